@@ -1,0 +1,182 @@
+"""CPU oracle: slow, plain FP64 reference implementation of the method.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this
+package; only the tests, the smoke check and the benchmark's CPU-baseline leg
+use it.  It shares no code with the HIP library (paper_2201_10058_amd).
+
+Contents:
+  genga_oracle.c  - C implementation (kick, pairs, rcrit, HC, drift, step,
+                    energy), loaded here through ctypes.
+  torch_ref.py    - plain PyTorch float64 CPU re-statement of the same maps,
+                    used with torch.autograd as the reference for the adjoint.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgenga_oracle.so")
+_lib = None
+
+OK = 0
+E_NONFINITE = -3
+E_NOCONV = -6
+
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.or_changeover_y.restype = _d
+    lib.or_changeover_y.argtypes = [_d]
+    lib.or_changeover_dy.restype = _d
+    lib.or_changeover_dy.argtypes = [_d]
+    lib.or_changeover.restype = _d
+    lib.or_changeover.argtypes = [_d, _d]
+    lib.or_rcrit.restype = None
+    lib.or_rcrit.argtypes = [_i64] + [_p] * 7 + [_d] * 4 + [_p]
+    lib.or_kick_acc.restype = ctypes.c_int
+    lib.or_kick_acc.argtypes = [_i64] + [_p] * 5 + [_d, _i64, _i64, ctypes.c_int] + [_p] * 3
+    lib.or_kick.restype = ctypes.c_int
+    lib.or_kick.argtypes = [_i64] + [_p] * 8 + [_d, _d]
+    lib.or_pairs.restype = _i64
+    lib.or_pairs.argtypes = [_i64] + [_p] * 4 + [_i64, _p, _p]
+    lib.or_hc.restype = None
+    lib.or_hc.argtypes = [_i64] + [_p] * 7 + [_d, _d]
+    lib.or_drift.restype = ctypes.c_int
+    lib.or_drift.argtypes = [_i64] + [_p] * 6 + [_d, _d]
+    lib.or_step.restype = _i64
+    lib.or_step.argtypes = [_i64] + [_p] * 8 + [_d] * 5 + [_i64, _p, _p, _p]
+    lib.or_energy.restype = _d
+    lib.or_energy.argtypes = [_i64] + [_p] * 7 + [_d, _d]
+    lib.or_num_threads.restype = ctypes.c_int
+    lib.or_set_num_threads.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def changeover_y(y: float) -> float:
+    return _load().or_changeover_y(float(y))
+
+
+def changeover_dy(y: float) -> float:
+    return _load().or_changeover_dy(float(y))
+
+
+def changeover(r: float, rho: float) -> float:
+    return _load().or_changeover(float(r), float(rho))
+
+
+def rcrit(x, y, z, vx, vy, vz, m, m_star, dt, n1, n2):
+    arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m)]
+    n = arrs[0].size
+    rc = np.empty(n)
+    _load().or_rcrit(n, *map(_ptr, arrs), float(m_star), float(dt), float(n1), float(n2), _ptr(rc))
+    return rc
+
+
+def kick_acc(x, y, z, m, rc, G, rows=None, precise=True):
+    """Accelerations for rows [i0, i1) (all rows by default).
+
+    Returns (ax, ay, az, status).
+    """
+    arrs = [_f64(a) for a in (x, y, z, m, rc)]
+    n = arrs[0].size
+    i0, i1 = (0, n) if rows is None else rows
+    k = max(i1 - i0, 0)
+    ax, ay, az = np.zeros(k), np.zeros(k), np.zeros(k)
+    st = _load().or_kick_acc(n, *map(_ptr, arrs), float(G), int(i0), int(i1), int(bool(precise)),
+                             _ptr(ax), _ptr(ay), _ptr(az))
+    return ax, ay, az, st
+
+
+def kick(state, rc, G, h):
+    """In-place v += h a (plain binary64 sums)."""
+    n = state["x"].size
+    return _load().or_kick(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                           _ptr(_f64(rc)), float(G), float(h))
+
+
+def pairs(x, y, z, rc, cap=None):
+    """Canonical close-encounter list (i < j, i asc, j asc) and true count."""
+    arrs = [_f64(a) for a in (x, y, z, rc)]
+    n = arrs[0].size
+    lib = _load()
+    if cap is None:
+        cnt = lib.or_pairs(n, *map(_ptr, arrs), 0, None, None)
+        cap = cnt
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    cnt = lib.or_pairs(n, *map(_ptr, arrs), int(cap), _ptr(pi), _ptr(pj))
+    k = min(cnt, cap)
+    return pi[:k].copy(), pj[:k].copy(), int(cnt)
+
+
+def hc(state, m_star, h):
+    n = state["x"].size
+    _load().or_hc(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                  float(m_star), float(h))
+
+
+def drift(state, mu, dt):
+    n = state["x"].size
+    return _load().or_drift(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz")),
+                            float(mu), float(dt))
+
+
+def step(state, G, m_star, dt, n1, n2, cap=None):
+    """One base step in place.  Returns (pi, pj, count, rc, status)."""
+    n = state["x"].size
+    lib = _load()
+    rc = np.empty(n)
+    if cap is None:
+        rc0 = rcrit(state["x"], state["y"], state["z"], state["vx"], state["vy"], state["vz"],
+                    state["m"], m_star, dt, n1, n2)
+        cap = pairs(state["x"], state["y"], state["z"], rc0, cap=0)[2]
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    st = ctypes.c_int(0)
+    cnt = lib.or_step(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                      _ptr(rc), float(G), float(m_star), float(dt), float(n1), float(n2),
+                      int(cap), _ptr(pi), _ptr(pj), ctypes.byref(st))
+    k = min(cnt, cap)
+    return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, st.value
+
+
+def energy(state, G, m_star):
+    n = state["x"].size
+    return _load().or_energy(n, *(_ptr(_f64(state[k])) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                             float(G), float(m_star))
+
+
+def num_threads() -> int:
+    return _load().or_num_threads()
+
+
+def set_num_threads(t: int) -> None:
+    _load().or_set_num_threads(int(t))
+
+
+def state_copy(d):
+    """Contiguous float64 copies of the state arrays of a workload dict."""
+    return {k: np.array(d[k], dtype=np.float64, copy=True) for k in ("x", "y", "z", "vx", "vy", "vz", "m")}

@@ -1,0 +1,438 @@
+/*
+ * CPU oracle for the changeover-weighted kick and its companions.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference against which the HIP library is checked.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant generator with the HIP library.
+ *
+ * Arithmetic is plain IEEE binary64, built with contraction disabled; the only
+ * fused multiply-adds are the explicit fma() calls of the pair predicate
+ * (squared separation), whose operation order is part of the predicate's
+ * definition so that the encounter list has exactly one correct answer.
+ *
+ * Sources (GENGA II, Grimm et al. 2022):
+ *   - Sect. 2, eqs. (H), (Ha), (Hb), (Hc): democratic heliocentric splitting;
+ *     the kick is the interaction part H_B, HC is the Sun part H_C, the drift
+ *     is the Keplerian part of H_A.
+ *   - Sect. 2, eq. (rcrit): critical radius r_crit,i = max(n1 R_H,i, n2 dt v_i).
+ *   - Sect. 6.2: the changeover acts for 0.1 < r/r_crit < 1 and has the form
+ *     of Chambers (1999) eq. 10.
+ *   - Appendix A: order of operations of one base step.
+ * Readings where the paper is silent are listed at each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_E_NONFINITE (-3)
+#define OR_E_NOCONV (-6)
+
+/* ------------------------------------------------------------------------ */
+/* Changeover function (Sect. 6.2, Chambers 1999 eq. 10).                    */
+/* y = (r - 0.1 rho) / (0.9 rho); K = 0 for y <= 0, 1 for y >= 1 and        */
+/* y^2 / (2y^2 - 2y + 1) between.  rho = 0 gives y = +inf, i.e. K = 1.       */
+/* ------------------------------------------------------------------------ */
+double or_changeover_y(double y)
+{
+    if (!(y > 0.0)) return 0.0;
+    if (y >= 1.0) return 1.0;
+    return (y * y) / (2.0 * y * y - 2.0 * y + 1.0);
+}
+
+/* dK/dy on the open band, zero outside. */
+double or_changeover_dy(double y)
+{
+    if (!(y > 0.0) || y >= 1.0) return 0.0;
+    double q = 2.0 * y * y - 2.0 * y + 1.0;
+    return 2.0 * y * (1.0 - y) / (q * q);
+}
+
+double or_changeover(double r, double rho)
+{
+    double y = (r - 0.1 * rho) / (0.9 * rho);
+    if (rho == 0.0) y = INFINITY;
+    return or_changeover_y(y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Critical radius, eq. (rcrit).  Reading: R_H,i = |x_i| (m_i / 3 m_star)^(1/3)
+ * with the heliocentric distance, and v_i = |v_i| of the democratic
+ * (barycentric) velocity held in the state.                                */
+/* ------------------------------------------------------------------------ */
+void or_rcrit(int64_t n, const double *x, const double *y, const double *z,
+              const double *vx, const double *vy, const double *vz, const double *m,
+              double m_star, double dt, double n1, double n2, double *rc)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double r = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+        double v = sqrt(vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+        double rh = r * cbrt(m[i] / (3.0 * m_star));
+        double a = n1 * rh;
+        double b = n2 * fabs(dt) * v;
+        rc[i] = a > b ? a : b;
+    }
+}
+
+/* Squared separation of the pair (i, j), the order fixed by definition:
+ * d = x_j - x_i per axis, r2 = fma(dz, dz, fma(dy, dy, dx*dx)).            */
+static double pair_r2(const double *x, const double *y, const double *z, int64_t i, int64_t j)
+{
+    double dx = x[j] - x[i];
+    double dy = y[j] - y[i];
+    double dz = z[j] - z[i];
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+/* Pair critical radius: rho_ij = max(rc_i, rc_j) (symmetric, so that the
+ * weighted forces obey Newton's third law).                                 */
+static double pair_rho(const double *rc, int64_t i, int64_t j)
+{
+    return rc[i] > rc[j] ? rc[i] : rc[j];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kick accelerations (interaction part H_B, Sect. 2 and Appendix A).       */
+/* a_i = G sum_{j != i} m_j K(r_ij; rho_ij) (x_j - x_i) / r_ij^3             */
+/* Reading: the changeover weights the Newtonian pair force, so that K F and
+ * (1 - K) F add up to F exactly (the direct solver takes the rest).          */
+/* Rows [i0, i1) are evaluated; j runs in ascending order.                   */
+/* precise = 0: plain binary64 sum (the timed CPU baseline).                  */
+/* precise = 1: terms and sum in long double with Neumaier compensation,     */
+/*              rounded once at the end (the accuracy reference).             */
+/* Returns OR_E_NONFINITE if two distinct bodies coincide.                   */
+/* ------------------------------------------------------------------------ */
+int or_kick_acc(int64_t n, const double *x, const double *y, const double *z,
+                const double *m, const double *rc, double G, int64_t i0, int64_t i1,
+                int precise, double *ax, double *ay, double *az)
+{
+    int status = OR_OK;
+    if (i0 < 0) i0 = 0;
+    if (i1 > n) i1 = n;
+#pragma omp parallel for schedule(dynamic, 16) reduction(min : status)
+    for (int64_t i = i0; i < i1; ++i) {
+        if (!precise) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                if (r2 == 0.0) { status = OR_E_NONFINITE; continue; }
+                double r = sqrt(r2);
+                double K = or_changeover(r, pair_rho(rc, i, j));
+                double s = G * m[j] * K / (r2 * r);
+                sx += s * dx; sy += s * dy; sz += s * dz;
+            }
+            ax[i - i0] = sx; ay[i - i0] = sy; az[i - i0] = sz;
+        } else {
+            long double S[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                long double d[3] = {(long double)x[j] - x[i], (long double)y[j] - y[i],
+                                    (long double)z[j] - z[i]};
+                long double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (r2 == 0.0L) { status = OR_E_NONFINITE; continue; }
+                long double r = sqrtl(r2);
+                long double rho = pair_rho(rc, i, j);
+                long double K;
+                if (rho == 0.0L) K = 1.0L;
+                else {
+                    long double yy = (r - 0.1L * rho) / (0.9L * rho);
+                    if (!(yy > 0.0L)) K = 0.0L;
+                    else if (yy >= 1.0L) K = 1.0L;
+                    else K = yy * yy / (2.0L * yy * yy - 2.0L * yy + 1.0L);
+                }
+                long double s = (long double)G * m[j] * K / (r2 * r);
+                for (int c = 0; c < 3; ++c) {
+                    long double t = s * d[c];
+                    long double u = S[c] + t;
+                    if (fabsl(S[c]) >= fabsl(t)) C[c] += (S[c] - u) + t;
+                    else C[c] += (t - u) + S[c];
+                    S[c] = u;
+                }
+            }
+            ax[i - i0] = (double)(S[0] + C[0]);
+            ay[i - i0] = (double)(S[1] + C[1]);
+            az[i - i0] = (double)(S[2] + C[2]);
+        }
+    }
+    return status;
+}
+
+/* v_i += h a_i for all bodies (plain path). */
+int or_kick(int64_t n, const double *x, const double *y, const double *z,
+            double *vx, double *vy, double *vz, const double *m, const double *rc,
+            double G, double h)
+{
+    double *a = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!a) return -1;
+    int st = or_kick_acc(n, x, y, z, m, rc, G, 0, n, 0, a, a + n, a + 2 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        vx[i] += h * a[i];
+        vy[i] += h * a[n + i];
+        vz[i] += h * a[2 * n + i];
+    }
+    free(a);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Close-encounter pairs (Sect. 2 and Appendix A: pairs closer than the     */
+/* critical radius go to the direct solver; Appendix B "exact reproducible   */
+/* results": the list is put in a fixed, sorted order).                      */
+/* Predicate: i < j and r2 < rho*rho with r2 as in pair_r2, strict '<'.      */
+/* Order: i ascending, then j ascending.  Writes at most cap pairs and       */
+/* returns the true count.  Brute force over all pairs.                      */
+/* ------------------------------------------------------------------------ */
+int64_t or_pairs(int64_t n, const double *x, const double *y, const double *z,
+                 const double *rc, int64_t cap, int32_t *pi, int32_t *pj)
+{
+    int64_t *cnt = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    if (!cnt) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = i + 1; j < n; ++j) {
+            double rho = pair_rho(rc, i, j);
+            if (pair_r2(x, y, z, i, j) < rho * rho) ++c;
+        }
+        cnt[i + 1] = c;
+    }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    int64_t total = cnt[n];
+    if (pi && pj) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t p = cnt[i];
+            if (p >= cap || cnt[i + 1] == cnt[i]) continue;
+            for (int64_t j = i + 1; j < n && p < cap; ++j) {
+                double rho = pair_rho(rc, i, j);
+                if (pair_r2(x, y, z, i, j) < rho * rho) {
+                    pi[p] = (int32_t)i;
+                    pj[p] = (int32_t)j;
+                    ++p;
+                }
+            }
+        }
+    }
+    free(cnt);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sun part H_C (eq. Hc): x_i += h P / m_star, P = sum_j m_j v_j.            */
+/* The momentum sum is accumulated in long double.                           */
+/* ------------------------------------------------------------------------ */
+void or_hc(int64_t n, double *x, double *y, double *z, const double *vx,
+           const double *vy, const double *vz, const double *m, double m_star, double h)
+{
+    long double P[3] = {0, 0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+        P[0] += (long double)m[j] * vx[j];
+        P[1] += (long double)m[j] * vy[j];
+        P[2] += (long double)m[j] * vz[j];
+    }
+    double px = (double)P[0], py = (double)P[1], pz = (double)P[2];
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] += h * px / m_star;
+        y[i] += h * py / m_star;
+        z[i] += h * pz / m_star;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Keplerian drift (the Kepler part of H_A, Sect. 2): every body moves on   */
+/* its two-body orbit about the star with mu = G m_star for a time dt.       */
+/* Formulation: Gauss f and g functions in the eccentric-anomaly change dE   */
+/* (elliptic) or the hyperbolic-anomaly change dF (hyperbolic), the classic  */
+/* textbook solution of the two-body problem.  Kepler's equation in dE is    */
+/* solved by Newton's method safeguarded with bisection on a bracket.        */
+/* Returns OR_E_NOCONV if a solve failed, OR_E_NONFINITE for r = 0.          */
+/* ------------------------------------------------------------------------ */
+static int kepler_one(double mu, double dt, double *X, double *V)
+{
+    double r0 = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    if (!(r0 > 0.0)) return OR_E_NONFINITE;
+    double v2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+    double u = X[0] * V[0] + X[1] * V[1] + X[2] * V[2];   /* r0 * dr/dt */
+    double alpha = 2.0 / r0 - v2 / mu;                     /* 1 / a */
+    double f, g, fd, gd;
+    if (dt == 0.0) return OR_OK;
+    if (alpha > 0.0) {
+        double a = 1.0 / alpha;
+        double n = sqrt(mu * alpha * alpha * alpha);
+        double ec = 1.0 - r0 * alpha;           /* e cos E0 */
+        double es = u / sqrt(mu * a);           /* e sin E0 */
+        double M = n * dt;
+        /* F(d) = d - ec sin d + es (1 - cos d) - M, F' = 1 - ec cos d + es sin d >= 1 - e */
+        double e = sqrt(ec * ec + es * es);
+        double lo = M - 2.0 * e - 1e-300, hi = M + 2.0 * e + 1e-300;
+        double d = M;
+        int ok = 0;
+        for (int it = 0; it < 200; ++it) {
+            double s = sin(d), c = cos(d);
+            double F = d - ec * s + es * (1.0 - c) - M;
+            double Fp = 1.0 - ec * c + es * s;
+            if (F > 0.0) hi = d; else lo = d;
+            double dn = d - F / Fp;
+            if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
+            double step = fabs(dn - d);
+            d = dn;
+            if (step <= 1e-15 * (1.0 + fabs(d))) { ok = 1; break; }
+        }
+        if (!ok) return OR_E_NOCONV;
+        double s = sin(d), c = cos(d);
+        double omc = 2.0 * sin(0.5 * d) * sin(0.5 * d);  /* 1 - cos d */
+        double r = a + (r0 - a) * c + sqrt(a) * (u / sqrt(mu)) * s;
+        f = 1.0 - (a / r0) * omc;
+        g = dt - (d - s) / n;
+        fd = -sqrt(mu * a) * s / (r * r0);
+        gd = 1.0 - (a / r) * omc;
+    } else if (alpha < 0.0) {
+        double a = 1.0 / alpha;                  /* negative */
+        double n = sqrt(mu * (-alpha) * (-alpha) * (-alpha));
+        double ec = 1.0 - r0 * alpha;            /* e cosh F0 */
+        double es = u / sqrt(-mu * a);           /* e sinh F0 */
+        double M = n * dt;
+        /* G(d) = ec sinh d + es (cosh d - 1) - d - M, increasing in d */
+        double d = (M >= 0.0 ? 1.0 : -1.0) * log(1.0 + fabs(M) / (ec > 1.0 ? ec : 1.0));
+        double lo = -1.0, hi = 1.0;
+        while (ec * sinh(lo) + es * (cosh(lo) - 1.0) - lo - M > 0.0) lo *= 2.0;
+        while (ec * sinh(hi) + es * (cosh(hi) - 1.0) - hi - M < 0.0) hi *= 2.0;
+        if (!(d > lo && d < hi)) d = 0.5 * (lo + hi);
+        int ok = 0;
+        for (int it = 0; it < 400; ++it) {
+            double sh = sinh(d), ch = cosh(d);
+            double F = ec * sh + es * (ch - 1.0) - d - M;
+            double Fp = ec * ch + es * sh - 1.0;
+            if (F > 0.0) hi = d; else lo = d;
+            double dn = d - F / Fp;
+            if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
+            double step = fabs(dn - d);
+            d = dn;
+            if (step <= 1e-15 * (1.0 + fabs(d))) { ok = 1; break; }
+        }
+        if (!ok) return OR_E_NOCONV;
+        double sh = sinh(d), ch = cosh(d);
+        double chm1 = 2.0 * sinh(0.5 * d) * sinh(0.5 * d);  /* cosh d - 1 */
+        double r = a + (r0 - a) * ch + sqrt(-a) * (u / sqrt(mu)) * sh;
+        f = 1.0 + (a / r0) * chm1;
+        g = dt - (sh - d) / n;
+        fd = -sqrt(-mu * a) * sh / (r * r0);
+        gd = 1.0 + (a / r) * chm1;
+    } else {
+        return OR_E_NOCONV;  /* exactly parabolic: not handled by this oracle */
+    }
+    double X1[3], V1[3];
+    for (int c = 0; c < 3; ++c) {
+        X1[c] = f * X[c] + g * V[c];
+        V1[c] = fd * X[c] + gd * V[c];
+    }
+    memcpy(X, X1, sizeof X1);
+    memcpy(V, V1, sizeof V1);
+    return OR_OK;
+}
+
+int or_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+             double *vz, double mu, double dt)
+{
+    int status = OR_OK;
+#pragma omp parallel for schedule(static) reduction(min : status)
+    for (int64_t i = 0; i < n; ++i) {
+        double X[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]};
+        int st = kepler_one(mu, dt, X, V);
+        if (st != OR_OK) status = st;
+        x[i] = X[0]; y[i] = X[1]; z[i] = X[2];
+        vx[i] = V[0]; vy[i] = V[1]; vz[i] = V[2];
+    }
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One base step without the direct solver (Appendix A):                    */
+/*   Rcrit(dt); Kick(dt/2) [+ encounter list]; HC(dt/2); FG(dt); HC(dt/2);    */
+/*   Kick(dt/2) with the same critical radii.                                 */
+/* Reading: the critical radii are computed once from the state at the      */
+/* start of the step and used by both half kicks; the encounter list is the  */
+/* one of the first half kick.  The (1 - K) part (grouping + Bulirsch-Stoer) */
+/* is not part of this step.  rc (length n) receives the radii used.         */
+/* ------------------------------------------------------------------------ */
+int64_t or_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                double *vz, const double *m, double *rc, double G, double m_star,
+                double dt, double n1, double n2, int64_t cap, int32_t *pi, int32_t *pj,
+                int *status)
+{
+    int st = OR_OK, s2;
+    or_rcrit(n, x, y, z, vx, vy, vz, m, m_star, dt, n1, n2, rc);
+    int64_t np = or_pairs(n, x, y, z, rc, cap, pi, pj);
+    s2 = or_kick(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt);
+    if (s2 < st) st = s2;
+    or_hc(n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    s2 = or_drift(n, x, y, z, vx, vy, vz, G * m_star, dt);
+    if (s2 < st) st = s2;
+    or_hc(n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    s2 = or_kick(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt);
+    if (s2 < st) st = s2;
+    if (status) *status = st;
+    return np;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Total energy in democratic coordinates (eqs. H, Ha, Hb, Hc):              */
+/* E = sum m v^2 / 2 + |sum m v|^2 / (2 m_star) - sum G m_star m / r_i        */
+/*     - sum_{i<j} G m_i m_j / r_ij  (the K-weighted parts add up to 1/r).   */
+/* Long double sums.                                                         */
+/* ------------------------------------------------------------------------ */
+double or_energy(int64_t n, const double *x, const double *y, const double *z,
+                 const double *vx, const double *vy, const double *vz, const double *m,
+                 double G, double m_star)
+{
+    long double T = 0, P[3] = {0, 0, 0}, U = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        T += 0.5L * m[i] * ((long double)vx[i] * vx[i] + (long double)vy[i] * vy[i] +
+                            (long double)vz[i] * vz[i]);
+        P[0] += (long double)m[i] * vx[i];
+        P[1] += (long double)m[i] * vy[i];
+        P[2] += (long double)m[i] * vz[i];
+        long double r = sqrtl((long double)x[i] * x[i] + (long double)y[i] * y[i] +
+                              (long double)z[i] * z[i]);
+        U -= (long double)G * m_star * m[i] / r;
+    }
+    long double W = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : W)
+    for (int64_t i = 0; i < n; ++i) {
+        long double wi = 0;
+        for (int64_t j = i + 1; j < n; ++j) {
+            long double dx = (long double)x[j] - x[i], dy = (long double)y[j] - y[i],
+                        dz = (long double)z[j] - z[i];
+            wi -= (long double)G * m[i] * m[j] / sqrtl(dx * dx + dy * dy + dz * dz);
+        }
+        W += wi;
+    }
+    long double Hc = (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) / (2.0L * m_star);
+    return (double)(T + Hc + U + W);
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
