@@ -1,0 +1,174 @@
+/*
+ * genga.h - C ABI of libgenga.so, the MI355X (gfx950) hot path of the hybrid
+ * symplectic N-body method of GENGA II (Grimm et al. 2022, arXiv 2201.10058).
+ *
+ * Method (paper Sect. 2, eqs. H, Ha, Hb, Hc and rcrit; Appendix A): bodies
+ * are held in democratic coordinates (heliocentric positions, barycentric
+ * velocities).  One base step is
+ *     Rcrit(dt); Kick(dt/2) + encounter pre-check; HC(dt/2); FG(dt);
+ *     HC(dt/2); Kick(dt/2).
+ * The kick is the interaction part H_B: every pair of bodies (not the star)
+ * exchanges Newtonian gravity weighted by the changeover function
+ * K(r_ij; rho_ij) of Sect. 6.2 (zero below 0.1 rho, one above rho, the
+ * smooth form of Chambers 1999 eq. 10 between), with rho_ij = max(rc_i, rc_j).
+ * Pairs closer than rho_ij form the close-encounter list that the direct
+ * solver would take (Sect. 2; list order fixed as in Appendix B, "exact
+ * reproducible results").  The direct solver itself is not part of this
+ * library.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array pointer is a DEVICE pointer owned by the caller
+ *   (contiguous, float64 structure-of-arrays of length n unless stated).  The
+ *   library never allocates device memory in a call: scratch space is the
+ *   caller's workspace `ws` of genga_workspace_bytes() bytes, 256-byte
+ *   aligned.  Host-side structs (genga_bodies, genga_params, genga_pairs) are
+ *   read during the call only and may be freed on return.
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *   enqueued asynchronously in order on that stream; results are valid after
+ *   the stream is synchronised.  Calls that share a workspace must be ordered
+ *   on one stream.
+ * Errors.  Argument errors are detected on the host and returned at once
+ *   (GENGA_E_INVAL), with nothing enqueued.  Errors found by kernels (encounter
+ *   list overflow, coincident bodies, non-finite results, invalid critical
+ *   radii, Kepler solver failure) set bits in a status word inside the
+ *   workspace; genga_read_status() synchronises the stream, returns the most
+ *   severe code and clears the word.  genga_step() reads it itself unless
+ *   GENGA_FLAG_NOSYNC is set.
+ * Determinism.  Every kernel is free of floating-point atomics; sums run in a
+ *   fixed order for a fixed launch configuration, so repeated calls with the
+ *   same inputs give bitwise identical results.  The encounter list is always
+ *   produced in canonical order (i ascending, then j ascending, i < j).
+ */
+#ifndef GENGA_H
+#define GENGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define GENGA_OK             0
+#define GENGA_E_INVAL       (-1) /* null pointer, n < 1, non-finite scalar, bad size  */
+#define GENGA_E_OVERFLOW    (-2) /* more encounter pairs than capacity (count is true) */
+#define GENGA_E_NONFINITE   (-3) /* two distinct bodies coincide, or a NaN/inf result  */
+#define GENGA_E_HIP         (-4) /* a HIP runtime call failed (genga_last_hip_error)   */
+#define GENGA_E_UNSUPPORTED (-5) /* option not available on this device               */
+#define GENGA_E_NOCONV      (-6) /* Kepler solver did not converge                     */
+#define GENGA_E_RCRIT       (-7) /* a critical radius is negative or NaN               */
+
+/* genga_params.precision */
+#define GENGA_FP64  0 /* all pair arithmetic in binary64                              */
+#define GENGA_MIXED 1 /* binary32 pair arithmetic on binary64 differences, binary64
+                         accumulation, binary64 encounter test (see genga_kick)       */
+
+/* genga_params.flags */
+#define GENGA_FLAG_NOSYNC 1 /* genga_step: do not synchronise nor read the status     */
+
+/* Bodies of one system, democratic coordinates, device SoA of length n.
+ * rc holds the critical radii r_crit,i (eq. rcrit); genga_rcrit writes it.    */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;    /* heliocentric positions [AU]                        */
+    double *vx, *vy, *vz; /* barycentric velocities [AU/day]                    */
+    double *m;            /* masses [solar masses]; the star is not an element  */
+    double *rc;           /* critical radii [AU], >= 0                          */
+} genga_bodies;
+
+/* Scalars of the method.  Units are the caller's; G must match them. */
+typedef struct {
+    double G;      /* gravitational constant                                    */
+    double m_star; /* central mass (H_A Kepler term and H_C)                    */
+    double dt;     /* base time step (eq. rcrit and genga_step)                 */
+    double n1;     /* Hill-radius factor of eq. rcrit (paper: 3)                */
+    double n2;     /* velocity factor of eq. rcrit (paper: 0.4)                 */
+    int precision; /* GENGA_FP64 or GENGA_MIXED                                 */
+    int flags;     /* GENGA_FLAG_*                                              */
+    int ipt;       /* kick rows per thread (1 or 2); 0 = library choice         */
+    int slices;    /* kick column slices; 0 = library choice                    */
+    void *prof_events[4]; /* optional hipEvent_t handles (timing): [0], [1] are
+                             recorded immediately before and after the main
+                             kernel of genga_kick and of the first half kick of
+                             genga_step; [2], [3] around the second half kick
+                             of genga_step.  NULL entries are skipped.        */
+} genga_params;
+
+/* Close-encounter list (device memory). */
+typedef struct {
+    int32_t *i, *j;   /* capacity entries each; pair k is (i[k], j[k]), i < j    */
+    int64_t capacity; /* entries available in i and j (may be 0)                 */
+    int64_t *count;   /* one device int64: receives the TRUE number of pairs     */
+} genga_pairs;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int genga_version(void);
+
+/* Text for a return code. */
+const char *genga_strerror(int code);
+
+/* The last hipError_t seen by the library on this thread (0 if none). */
+int genga_last_hip_error(void);
+
+/* Workspace size in bytes for systems of up to n bodies with these params.
+ * Returns 0 for n < 1. */
+size_t genga_workspace_bytes(int64_t n, const genga_params *p);
+
+/* Synchronise `stream`, return the most severe status recorded in the
+ * workspace since the last read (GENGA_OK if none) and clear it. */
+int genga_read_status(void *ws, void *stream);
+
+/* Clear the workspace status word (asynchronously, on `stream`). */
+int genga_clear_status(void *ws, void *stream);
+
+/* Critical radii, eq. (rcrit), paper Sect. 2:
+ *   rc_i = max(n1 * R_H,i, n2 * |dt| * |v_i|),
+ *   R_H,i = |x_i| * (m_i / (3 m_star))^(1/3).
+ * Reads x..vz, m; writes b->rc. */
+int genga_rcrit(const genga_bodies *b, const genga_params *p, void *ws, void *stream);
+
+/* Kick: the interaction part H_B (paper Sect. 2, eq. Hb; Appendix A).
+ *   a_i = G sum_{j != i} m_j K(r_ij; rho_ij) (x_j - x_i) / r_ij^3,
+ *   rho_ij = max(rc_i, rc_j),  v_i += h * a_i.
+ * h = 0 leaves the velocities untouched.  ax/ay/az (nullable, device, n)
+ * receive a.  pairs (nullable) receives the close-encounter list of the same
+ * positions: pairs with i < j and r_ij^2 < rho_ij^2, where
+ * r_ij^2 = fma(dz, dz, fma(dy, dy, dx * dx)) and d = x_j - x_i in binary64
+ * (the "close-encounter pre-check" of Appendix A), in canonical order.
+ * If the count exceeds capacity, the first `capacity` pairs are written, the
+ * true count is stored and the status records GENGA_E_OVERFLOW.
+ * precision GENGA_MIXED: differences d in binary64 rounded to binary32,
+ * binary32 distance and weight, binary32 partial sums over at most 64
+ * columns folded into binary64 accumulators; pairs inside rho_ij, and the
+ * encounter test, stay in binary64, so the list is identical to GENGA_FP64.
+ * Positions of two distinct bodies that coincide set GENGA_E_NONFINITE. */
+int genga_kick(const genga_bodies *b, const genga_params *p, double h,
+               double *ax, double *ay, double *az, genga_pairs *pairs, void *ws, void *stream);
+
+/* Close-encounter list alone (same predicate and order as genga_kick); used
+ * for the detection after the drift (Appendix A). */
+int genga_encounter_pairs(const genga_bodies *b, const genga_params *p, genga_pairs *pairs,
+                          void *ws, void *stream);
+
+/* HC, the Sun part H_C (eq. Hc):  x_i += h * P / m_star,  P = sum_j m_j v_j.
+ * P is summed in a fixed order. */
+int genga_hc(genga_bodies *b, const genga_params *p, double h, void *ws, void *stream);
+
+/* FG, the Keplerian part of H_A (Sect. 2): every body follows its two-body
+ * orbit about the star (mu = G m_star) for a time dt, by Gauss f and g
+ * functions in the universal anomaly (elliptic and hyperbolic orbits). */
+int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, void *stream);
+
+/* One base step of Appendix A without the direct solver:
+ *   rc <- Rcrit(x, v); Kick(dt/2) [+ pairs]; HC(dt/2); FG(dt); HC(dt/2);
+ *   Kick(dt/2) with the same rc.
+ * pairs (nullable) receives the list of the first half kick.  Unless
+ * GENGA_FLAG_NOSYNC, synchronises the stream and returns the status. */
+int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void *ws, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GENGA_H */

@@ -1,0 +1,217 @@
+// C ABI entry points of libgenga.so (declared in include/genga.h): argument
+// checking, workspace layout and kernel sequencing on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include "genga_internal.h"
+
+namespace genga {
+
+static thread_local int g_last_hip = 0;
+
+void set_hip_error(hipError_t e) { g_last_hip = (int)e; }
+
+static int hip_fail(hipError_t e)
+{
+    set_hip_error(e);
+    return GENGA_E_HIP;
+}
+
+static bool is_fin(double v) { return isfinite(v); }
+
+static int check_bodies(const genga_bodies *b, bool need_v, bool need_rc)
+{
+    if (!b || b->n < 1 || b->n > (int64_t)INT32_MAX) return GENGA_E_INVAL;
+    if (!b->x || !b->y || !b->z || !b->m) return GENGA_E_INVAL;
+    if (need_v && (!b->vx || !b->vy || !b->vz)) return GENGA_E_INVAL;
+    if (need_rc && !b->rc) return GENGA_E_INVAL;
+    return GENGA_OK;
+}
+
+static int check_params(const genga_params *p)
+{
+    if (!p) return GENGA_E_INVAL;
+    if (!is_fin(p->G) || p->G < 0.0) return GENGA_E_INVAL;
+    if (!is_fin(p->m_star) || !(p->m_star > 0.0)) return GENGA_E_INVAL;
+    if (!is_fin(p->dt) || !is_fin(p->n1) || !is_fin(p->n2)) return GENGA_E_INVAL;
+    if (p->n1 < 0.0 || p->n2 < 0.0) return GENGA_E_INVAL;
+    if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
+    if (p->ipt < 0 || p->ipt > 2 || p->slices < 0) return GENGA_E_INVAL;
+    return GENGA_OK;
+}
+
+static int check_pairs(const genga_pairs *q)
+{
+    if (!q) return GENGA_OK;
+    if (!q->count || q->capacity < 0) return GENGA_E_INVAL;
+    if (q->capacity > 0 && (!q->i || !q->j)) return GENGA_E_INVAL;
+    return GENGA_OK;
+}
+
+static int status_to_code(int32_t st)
+{
+    if (st & ST_RCRIT) return GENGA_E_RCRIT;
+    if (st & ST_NONFINITE) return GENGA_E_NONFINITE;
+    if (st & ST_NOCONV) return GENGA_E_NOCONV;
+    if (st & ST_OVERFLOW) return GENGA_E_OVERFLOW;
+    return GENGA_OK;
+}
+
+static int do_kick(const genga_bodies *b, const genga_params *p, double h, double *ax, double *ay,
+                   double *az, genga_pairs *pairs, bool forces, void *ws, void *stream,
+                   int ev_slot = 0)
+{
+    const KickCfg c = choose_kick_cfg(b->n, p);
+    const Layout L = make_layout(b->n, c);
+    KickLaunch k;
+    k.x = b->x; k.y = b->y; k.z = b->z; k.m = b->m; k.rc = b->rc;
+    k.vx = b->vx; k.vy = b->vy; k.vz = b->vz;
+    k.ax = ax; k.ay = ay; k.az = az;
+    k.n = b->n;
+    k.G = p->G;
+    k.h = h;
+    k.precision = p->precision;
+    k.forces = forces;
+    k.pairs = pairs;
+    k.ev0 = p->prof_events[ev_slot];
+    k.ev1 = p->prof_events[ev_slot + 1];
+    hipError_t e = launch_kick(k, c, L, (char *)ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return GENGA_OK;
+}
+
+}  // namespace genga
+
+using namespace genga;
+
+extern "C" {
+
+int genga_version(void) { return 100; }
+
+const char *genga_strerror(int code)
+{
+    switch (code) {
+    case GENGA_OK: return "ok";
+    case GENGA_E_INVAL: return "invalid argument";
+    case GENGA_E_OVERFLOW: return "encounter list longer than its capacity";
+    case GENGA_E_NONFINITE: return "coincident bodies or non-finite result";
+    case GENGA_E_HIP: return "HIP runtime error";
+    case GENGA_E_UNSUPPORTED: return "unsupported option";
+    case GENGA_E_NOCONV: return "Kepler solver did not converge";
+    case GENGA_E_RCRIT: return "negative or non-finite critical radius";
+    default: return "unknown error";
+    }
+}
+
+int genga_last_hip_error(void) { return g_last_hip; }
+
+size_t genga_workspace_bytes(int64_t n, const genga_params *p)
+{
+    if (n < 1) return 0;
+    const KickCfg c = choose_kick_cfg(n, p);
+    return make_layout(n, c).total;
+}
+
+int genga_read_status(void *ws, void *stream)
+{
+    if (!ws) return GENGA_E_INVAL;
+    int32_t st = 0;
+    hipError_t e = hipMemcpyAsync(&st, ws, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    if (st) {
+        e = launch_clear_status((char *)ws, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return status_to_code(st);
+}
+
+int genga_clear_status(void *ws, void *stream)
+{
+    if (!ws) return GENGA_E_INVAL;
+    hipError_t e = launch_clear_status((char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_rcrit(const genga_bodies *b, const genga_params *p, void *ws, void *stream)
+{
+    int r = check_bodies(b, true, true);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (!ws) return GENGA_E_INVAL;
+    hipError_t e = launch_rcrit(b, p, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_kick(const genga_bodies *b, const genga_params *p, double h, double *ax, double *ay,
+               double *az, genga_pairs *pairs, void *ws, void *stream)
+{
+    int r = check_bodies(b, h != 0.0, true);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if ((r = check_pairs(pairs))) return r;
+    if (!ws || !is_fin(h)) return GENGA_E_INVAL;
+    if ((ax || ay || az) && !(ax && ay && az)) return GENGA_E_INVAL;
+    if (p->precision == GENGA_MIXED) return GENGA_E_UNSUPPORTED;
+    return do_kick(b, p, h, ax, ay, az, pairs, true, ws, stream);
+}
+
+int genga_encounter_pairs(const genga_bodies *b, const genga_params *p, genga_pairs *pairs,
+                          void *ws, void *stream)
+{
+    int r = check_bodies(b, false, true);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (!pairs) return GENGA_E_INVAL;
+    if ((r = check_pairs(pairs))) return r;
+    if (!ws) return GENGA_E_INVAL;
+    return do_kick(b, p, 0.0, nullptr, nullptr, nullptr, pairs, false, ws, stream);
+}
+
+int genga_hc(genga_bodies *b, const genga_params *p, double h, void *ws, void *stream)
+{
+    int r = check_bodies(b, true, false);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (!ws || !is_fin(h)) return GENGA_E_INVAL;
+    const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
+    hipError_t e = launch_hc(b, p->m_star, h, L, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, void *stream)
+{
+    int r = check_bodies(b, true, false);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (!ws || !is_fin(dt)) return GENGA_E_INVAL;
+    hipError_t e = launch_drift(b, p->G * p->m_star, dt, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void *ws, void *stream)
+{
+    int r = check_bodies(b, true, true);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if ((r = check_pairs(pairs))) return r;
+    if (!ws) return GENGA_E_INVAL;
+    if (p->precision == GENGA_MIXED) return GENGA_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const double h = 0.5 * p->dt;
+    const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
+    hipError_t e = launch_rcrit(b, p, (char *)ws, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, pairs, true, ws, stream))) return r;
+    if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_drift(b, p->G * p->m_star, p->dt, (char *)ws, s)) != hipSuccess)
+        return hip_fail(e);
+    if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
+    if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2))) return r;
+    if (p->flags & GENGA_FLAG_NOSYNC) return GENGA_OK;
+    return genga_read_status(ws, stream);
+}
+
+}  // extern "C"

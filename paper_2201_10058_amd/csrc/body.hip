@@ -1,0 +1,137 @@
+// O(N) operators of the base step: critical radii (eq. rcrit), HC (eq. Hc)
+// and the Keplerian drift FG (Kepler part of eq. Ha), GENGA II Sect. 2 and
+// Appendix A.  One thread per body; reductions run in a fixed order.
+#include "genga_internal.h"
+#include "kepler.h"
+
+namespace genga {
+
+static_assert(KEPLER_NONFINITE == ST_NONFINITE && KEPLER_NOCONV == ST_NOCONV,
+              "Kepler codes are status bits");
+
+__global__ void k_clear_status(int32_t *status) { *status = 0; }
+
+// r_crit,i = max(n1 R_H,i, n2 |dt| |v_i|), R_H,i = |x_i| (m_i / 3 m_star)^(1/3)
+__global__ __launch_bounds__(RB) void k_rcrit(const double *x, const double *y, const double *z,
+                                              const double *vx, const double *vy, const double *vz,
+                                              const double *m, double *rc, int64_t n, double m_star,
+                                              double dt, double n1, double n2, int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    const double r = __builtin_sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+    const double v = __builtin_sqrt(vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    const double rh = r * cbrt(m[i] / (3.0 * m_star));
+    const double a = n1 * rh;
+    const double b = n2 * fabs(dt) * v;
+    const double out = a > b ? a : b;
+    if (!(out >= 0.0 && out < INFINITY)) atomicOr(status, ST_RCRIT);
+    rc[i] = out;
+}
+
+// Per-block momentum partials P_b = sum_{j in block} m_j v_j (fixed tree order).
+__global__ __launch_bounds__(RB) void k_momentum_partial(const double *vx, const double *vy,
+                                                         const double *vz, const double *m,
+                                                         int64_t n, double *hc)
+{
+    __shared__ double sm[3][RB];
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * RB + t;
+    const double mi = i < n ? m[i] : 0.0;
+    sm[0][t] = i < n ? mi * vx[i] : 0.0;
+    sm[1][t] = i < n ? mi * vy[i] : 0.0;
+    sm[2][t] = i < n ? mi * vz[i] : 0.0;
+    __syncthreads();
+    for (int h = RB / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sm[0][t] += sm[0][t + h];
+            sm[1][t] += sm[1][t + h];
+            sm[2][t] += sm[2][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 3) hc[(size_t)blockIdx.x * 3 + t] = sm[t][0];
+}
+
+// x_i += h P / m_star; every block reduces the partials in the same order.
+__global__ __launch_bounds__(RB) void k_hc_apply(double *x, double *y, double *z, int64_t n,
+                                                 const double *hc, int64_t nb, double h,
+                                                 double m_star)
+{
+    __shared__ double sm[3][RB];
+    const int t = threadIdx.x;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    for (int64_t b = t; b < nb; b += RB) {
+        p0 += hc[b * 3 + 0];
+        p1 += hc[b * 3 + 1];
+        p2 += hc[b * 3 + 2];
+    }
+    sm[0][t] = p0;
+    sm[1][t] = p1;
+    sm[2][t] = p2;
+    __syncthreads();
+    for (int hh = RB / 2; hh > 0; hh >>= 1) {
+        if (t < hh) {
+            sm[0][t] += sm[0][t + hh];
+            sm[1][t] += sm[1][t + hh];
+            sm[2][t] += sm[2][t + hh];
+        }
+        __syncthreads();
+    }
+    const int64_t i = (int64_t)blockIdx.x * RB + t;
+    if (i >= n) return;
+    x[i] += (h * sm[0][0]) / m_star;
+    y[i] += (h * sm[1][0]) / m_star;
+    z[i] += (h * sm[2][0]) / m_star;
+}
+
+__global__ __launch_bounds__(RB) void k_drift(double *x, double *y, double *z, double *vx,
+                                              double *vy, double *vz, int64_t n, double mu,
+                                              double dt, int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    double X = x[i], Y = y[i], Z = z[i], VX = vx[i], VY = vy[i], VZ = vz[i];
+    const int st = kepler_uv(mu, dt, X, Y, Z, VX, VY, VZ);
+    if (st) atomicOr(status, st);
+    x[i] = X; y[i] = Y; z[i] = Z;
+    vx[i] = VX; vy[i] = VY; vz[i] = VZ;
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_clear_status(char *ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, (int32_t *)ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_rcrit(const genga_bodies *b, const genga_params *p, char *ws, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((b->n + RB - 1) / RB);
+    hipLaunchKernelGGL(k_rcrit, dim3(nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx, b->vy, b->vz,
+                       b->m, b->rc, b->n, p->m_star, p->dt, p->n1, p->n2, (int32_t *)ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, char *ws,
+                     hipStream_t s)
+{
+    double *hc = (double *)(ws + L.hc);
+    hipLaunchKernelGGL(k_momentum_partial, dim3((unsigned)L.nb), dim3(RB), 0, s, b->vx, b->vy,
+                       b->vz, b->m, b->n, hc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hc_apply, dim3((unsigned)L.nb), dim3(RB), 0, s, b->x, b->y, b->z, b->n,
+                       hc, L.nb, h, m_star);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(genga_bodies *b, double mu, double dt, char *ws, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((b->n + RB - 1) / RB);
+    hipLaunchKernelGGL(k_drift, dim3(nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx, b->vy, b->vz,
+                       b->n, mu, dt, (int32_t *)ws);
+    return hipGetLastError();
+}
+
+}  // namespace genga

@@ -1,0 +1,546 @@
+// Changeover-weighted kick with fused close-encounter pair emission.
+//
+// Paper: GENGA II Sect. 2 (interaction part H_B of the democratic-heliocentric
+// splitting, eq. Hb; critical radius eq. rcrit), Sect. 6.2 (the changeover acts
+// on 0.1 < r/r_crit < 1 with the form of Chambers 1999 eq. 10), Appendix A
+// (kick with the close-encounter pre-check), Appendix B (fixed pair-list order
+// for exact reproducibility).
+//
+// Design for gfx950 (wave64, 256 CUs):
+//  * k_kick: grid (row blocks, column slices).  Each block stages TILE
+//    columns (x, y, z, m, rc^2) of its slice in LDS; every lane owns IPT rows
+//    and streams the tile with broadcast LDS reads.  Per interaction the fast
+//    path is 3 sub, 3 mul/fma for r^2, v_rsq_f64 with a third-order correction
+//    folded into m r^-3, 3 fma accumulations and two compares.  Pairs inside
+//    the pair critical radius (and the self pair) take a divergent slow path
+//    that evaluates K, records encounter pairs and detects coincident bodies.
+//  * Partial sums per slice go to the workspace; k_kick_reduce adds them in a
+//    fixed order (no atomics), applies v += h a and prepares the pair offsets.
+//  * Pair emission is atomic-free: each wave appends its pairs to a private
+//    staging segment with a ballot + mbcnt prefix; each pair carries its rank
+//    within its (row, slice).  k_scan_blocks and k_pairs_scatter turn counts
+//    into canonical positions (i ascending, j ascending).  A wave whose segment
+//    overflows is recomputed exactly by k_pairs_scatter.
+#include "genga_internal.h"
+
+namespace genga {
+
+struct KickDev {
+    const double *x, *y, *z, *m, *rc;
+    int64_t n;
+    int64_t npad;
+    int64_t slice_len;
+    double *part;      // [slices][3][npad]
+    int32_t *cnt;      // [slices][npad]
+    int32_t *stage;    // [nwaves][WSEG][3]
+    int32_t *wcount;   // [nwaves]
+    int32_t *status;
+    int emit;
+    double c15, c1875;   // 3/2 and 15/8
+};
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const unsigned lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64u - lane));
+}
+
+// Changeover weight K(y), y = (r - 0.1 rho) / (0.9 rho) (Chambers 1999 eq. 10).
+__device__ __forceinline__ double changeover_k(double r, double rho)
+{
+    const double yv = (r - 0.1 * rho) / (0.9 * rho);
+    if (!(yv > 0.0)) return 0.0;
+    if (yv >= 1.0) return 1.0;
+    const double y2 = yv * yv;
+    return y2 / (2.0 * y2 - 2.0 * yv + 1.0);
+}
+
+// max of two non-negative doubles in one v_max_f64 (the generic fmax adds
+// NaN-quieting canonicalisations; the critical radii are validated instead).
+__device__ __forceinline__ double vmax_f64(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Per-lane state of the kick: IPT rows per lane.
+template <int IPT>
+struct Rows {
+    double xi[IPT], yi[IPT], zi[IPT], rc2i[IPT];
+    double ax[IPT], ay[IPT], az[IPT];
+    int64_t ii[IPT];
+    int kc[IPT];
+};
+
+// Rare path of one interaction: self pair, coincident bodies, changeover band
+// (K < 1) and encounter-pair recording.  Returns the weight m_j K / r^3.
+template <int IPT, bool FORCES>
+__device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int q, int64_t jg,
+                                         double r2, double rc2j, double mj, int64_t wave_g,
+                                         volatile int *wcnt)
+{
+    bool emit = false;
+    double wk = 0.0;
+    if (jg != R.ii[q]) {
+        if (r2 == 0.0) {
+            atomicOr(a.status, ST_NONFINITE);
+        } else {
+            const double rho2 = R.rc2i[q] > rc2j ? R.rc2i[q] : rc2j;
+            emit = (r2 < rho2) && (jg > R.ii[q]);
+            if (FORCES) {
+                const double rci = a.rc[R.ii[q]];
+                const double rcj = a.rc[jg];
+                const double rho = rci > rcj ? rci : rcj;
+                const double r = __builtin_sqrt(r2);
+                wk = mj * changeover_k(r, rho) / (r2 * r);
+            }
+        }
+    }
+    if (a.emit) {
+        const uint64_t mask = __ballot(emit);
+        if (mask != 0ull) {
+            const int base = *wcnt;
+            if (emit) {
+                const int pos = base + __popcll(mask & lanemask_lt());
+                if (pos < WSEG) {
+                    int32_t *e3 = a.stage + ((size_t)wave_g * WSEG + pos) * 3;
+                    e3[0] = (int32_t)R.ii[q];
+                    e3[1] = (int32_t)jg;
+                    e3[2] = R.kc[q];
+                }
+                R.kc[q] += 1;
+            }
+            const uint64_t act = __ballot(1);
+            if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1) *wcnt = base + __popcll(mask);
+        }
+    }
+    return wk;
+}
+
+// One column j against the lane's rows (the hot loop body).
+template <int IPT, bool FORCES>
+__device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const double4 b,
+                                         const double rc2j, const int64_t jg, const double c15,
+                                         const double c1875, const int64_t wave_g,
+                                         volatile int *wcnt)
+{
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const double dx = b.x - R.xi[q];
+        const double dy = b.y - R.yi[q];
+        const double dz = b.z - R.zi[q];
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        // candidate: inside the pair critical radius, or the self pair
+        const bool cand = r2 <= vmax_f64(R.rc2i[q], rc2j);
+        double sc = 0.0;
+        if (FORCES) {
+            // m r^-3 from v_rsq_f64 (relative error e0 ~ 2^-23):
+            // with e = 1 - r2 y^2, r2^{-3/2} = y^3 (1 - e)^{-3/2}
+            //   = y^3 (1 + e (3/2 + 15/8 e) + O(e^3)).
+            const double yv = __builtin_amdgcn_rsq(r2);
+            const double y2 = yv * yv;
+            const double e = __builtin_fma(-r2, y2, 1.0);
+            const double y3 = y2 * yv;
+            const double p = __builtin_fma(e, c1875, c15);
+            const double my3 = b.w * y3;
+            const double t = my3 * e;
+            sc = __builtin_fma(t, p, my3);
+        }
+        if (cand) sc = slow_pair<IPT, FORCES>(a, R, q, jg, r2, rc2j, b.w, wave_g, wcnt);
+        if (FORCES) {
+            R.ax[q] = __builtin_fma(dx, sc, R.ax[q]);
+            R.ay[q] = __builtin_fma(dy, sc, R.ay[q]);
+            R.az[q] = __builtin_fma(dz, sc, R.az[q]);
+        }
+    }
+}
+
+template <int IPT, bool FORCES>
+__global__ __launch_bounds__(KB) void k_kick(KickDev a)
+{
+    __shared__ double4 s_xyzm[TILE];
+    __shared__ double s_rc2[TILE];
+    __shared__ int s_wcnt[KB / 64];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int64_t rowbase = (int64_t)blockIdx.x * (KB * IPT) + (int64_t)w * (64 * IPT);
+    const int s = blockIdx.y;
+    const int64_t j0 = (int64_t)s * a.slice_len;
+    const int64_t j1 = min(a.n, j0 + a.slice_len);
+    const int64_t wave_g = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (KB / 64) + w;
+    // An opaque zero (mbcnt of an empty mask) marks values as per-lane, so the
+    // compiler keeps the polynomial constants (not inline constants on gfx9)
+    // and the LDS tile address in VGPRs instead of re-materialising them in
+    // the hot loop.
+    const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+    const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
+    const double4 *t_xyzm = s_xyzm + vzero;
+    const double *t_rc2 = s_rc2 + vzero;
+
+    Rows<IPT> R;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        R.ii[q] = rowbase + q * 64 + lane;
+        if (R.ii[q] < a.n) {
+            R.xi[q] = a.x[R.ii[q]];
+            R.yi[q] = a.y[R.ii[q]];
+            R.zi[q] = a.z[R.ii[q]];
+            const double r = a.rc[R.ii[q]];
+            R.rc2i[q] = r * r;
+        } else {
+            // rows past the end: NaN positions never enter the slow path
+            R.xi[q] = R.yi[q] = R.zi[q] = __builtin_nan("");
+            R.rc2i[q] = 0.0;
+        }
+        R.ax[q] = R.ay[q] = R.az[q] = 0.0;
+        R.kc[q] = 0;
+    }
+    if (lane == 0) s_wcnt[w] = 0;
+    volatile int *wcnt = &s_wcnt[w];
+
+    for (int64_t t0 = j0; t0 < j1; t0 += TILE) {
+        __syncthreads();
+        for (int q = tid; q < TILE; q += KB) {
+            const int64_t jg = t0 + q;
+            if (jg < j1) {
+                const double rcj = a.rc[jg];
+                if (!(rcj >= 0.0 && rcj < INFINITY)) atomicOr(a.status, ST_RCRIT);
+                s_xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], a.m[jg]);
+                s_rc2[q] = rcj * rcj;
+            }
+        }
+        __syncthreads();
+        const int tn = (int)min((int64_t)TILE, j1 - t0);
+        if (tn == TILE) {
+            for (int jj = 0; jj < TILE; jj += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    interact<IPT, FORCES>(a, R, t_xyzm[jj + u], t_rc2[jj + u], t0 + jj + u, c15,
+                                          c1875, wave_g, wcnt);
+            }
+        } else {
+            for (int jj = 0; jj < tn; ++jj)
+                interact<IPT, FORCES>(a, R, t_xyzm[jj], t_rc2[jj], t0 + jj, c15, c1875, wave_g,
+                                      wcnt);
+        }
+    }
+
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (R.ii[q] < a.n) {
+            if (FORCES) {
+                a.part[((size_t)s * 3 + 0) * a.npad + R.ii[q]] = R.ax[q];
+                a.part[((size_t)s * 3 + 1) * a.npad + R.ii[q]] = R.ay[q];
+                a.part[((size_t)s * 3 + 2) * a.npad + R.ii[q]] = R.az[q];
+            }
+            if (a.emit) a.cnt[(size_t)s * a.npad + R.ii[q]] = R.kc[q];
+        }
+    }
+    if (a.emit && lane == 0) a.wcount[wave_g] = *wcnt;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of one int64 per thread (RB threads).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+template <int NT>
+__device__ int64_t block_excl_scan(int64_t v, int64_t *total, int64_t *smem /* NT/64 */)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t inc = wave_incl_scan(v);
+    if (lane == 63) smem[w] = inc;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) {
+        const int64_t t = smem[k];
+        if (k < w) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Sum the slice partials in slice order, apply v += h a, prepare pair offsets.
+struct ReduceDev {
+    const double *part;
+    int32_t *cnt;
+    int32_t *rowloc;
+    int64_t *bsum;
+    double *vx, *vy, *vz;
+    double *ax, *ay, *az;
+    int32_t *status;
+    int64_t n, npad;
+    int slices;
+    double G, h;
+    int forces, emit;
+};
+
+__global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
+{
+    __shared__ int64_t sm[RB / 64];
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    const bool valid = i < r.n;
+    if (r.forces && valid) {
+        double a3[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int s = 0; s < r.slices; ++s) acc += r.part[((size_t)s * 3 + c) * r.npad + i];
+            a3[c] = r.G * acc;
+        }
+        if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
+            atomicOr(r.status, ST_NONFINITE);
+        if (r.h != 0.0) {
+            r.vx[i] = __builtin_fma(r.h, a3[0], r.vx[i]);
+            r.vy[i] = __builtin_fma(r.h, a3[1], r.vy[i]);
+            r.vz[i] = __builtin_fma(r.h, a3[2], r.vz[i]);
+        }
+        if (r.ax) {
+            r.ax[i] = a3[0];
+            r.ay[i] = a3[1];
+            r.az[i] = a3[2];
+        }
+    }
+    if (r.emit) {
+        int64_t c = 0;
+        if (valid) {
+            for (int s = 0; s < r.slices; ++s) {
+                const int32_t t = r.cnt[(size_t)s * r.npad + i];
+                r.cnt[(size_t)s * r.npad + i] = (int32_t)c;
+                c += t;
+            }
+        }
+        int64_t tot;
+        const int64_t ex = block_excl_scan<RB>(c, &tot, sm);
+        if (valid) r.rowloc[i] = (int32_t)ex;
+        if (threadIdx.x == 0) r.bsum[blockIdx.x] = tot;
+    }
+}
+
+// Exclusive scan of the per-block pair counts (one block); writes the total.
+__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *bsum, int64_t nb, int64_t *count,
+                                                      int64_t capacity, int32_t *status)
+{
+    __shared__ int64_t sm[16];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t k = base + threadIdx.x;
+        const int64_t v = k < nb ? bsum[k] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan<1024>(v, &tot, sm);
+        if (k < nb) bsum[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        if (count) *count = carry;
+        if (carry > capacity) atomicOr(status, ST_OVERFLOW);
+    }
+}
+
+// Place staged pairs at their canonical positions; recompute overflowed waves.
+struct ScatterDev {
+    const double *x, *y, *z, *rc;
+    const int32_t *stage, *wcount, *cnt, *rowloc;
+    const int64_t *boff;
+    int32_t *pi, *pj;
+    int64_t capacity, n, npad, slice_len;
+    int gx, ipt;
+};
+
+__global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
+{
+    const int64_t wave_g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t blk = wave_g / (KB / 64);
+    const int w = (int)(wave_g % (KB / 64));
+    const int bx = (int)(blk % d.gx);
+    const int s = (int)(blk / d.gx);
+    const int nst = d.wcount[wave_g];
+    if (nst <= WSEG) {
+        for (int e = lane; e < nst; e += 64) {
+            const int32_t *e3 = d.stage + ((size_t)wave_g * WSEG + e) * 3;
+            const int64_t i = e3[0];
+            const int64_t pos = d.boff[i / RB] + d.rowloc[i] + d.cnt[(size_t)s * d.npad + i] + e3[2];
+            if (pos < d.capacity) {
+                d.pi[pos] = e3[0];
+                d.pj[pos] = e3[1];
+            }
+        }
+        return;
+    }
+    // staging overflowed: rebuild this wave's rows over its column slice
+    const int64_t rowbase = (int64_t)bx * (KB * d.ipt) + (int64_t)w * (64 * d.ipt);
+    const int64_t j0 = (int64_t)s * d.slice_len;
+    const int64_t j1 = min(d.n, j0 + d.slice_len);
+    for (int q = 0; q < d.ipt; ++q) {
+        const int64_t i = rowbase + q * 64 + lane;
+        if (i >= d.n) continue;
+        int64_t pos = d.boff[i / RB] + d.rowloc[i] + d.cnt[(size_t)s * d.npad + i];
+        const double xi = d.x[i], yi = d.y[i], zi = d.z[i];
+        const double rci = d.rc[i];
+        const double rc2i = rci * rci;
+        for (int64_t j = (j0 > i + 1 ? j0 : i + 1); j < j1; ++j) {
+            const double dx = d.x[j] - xi, dy = d.y[j] - yi, dz = d.z[j] - zi;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double rcj = d.rc[j];
+            const double rc2j = rcj * rcj;
+            const double rho2 = rc2i > rc2j ? rc2i : rc2j;
+            if (r2 < rho2) {
+                if (pos < d.capacity) {
+                    d.pi[pos] = (int32_t)i;
+                    d.pj[pos] = (int32_t)j;
+                }
+                ++pos;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
+{
+    KickCfg c;
+    c.ipt = (p && p->ipt > 0) ? p->ipt : 1;
+    if (c.ipt != 1 && c.ipt != 2) c.ipt = 1;
+    const int64_t rows_per_block = (int64_t)KB * c.ipt;
+    c.gx = (int)((n + rows_per_block - 1) / rows_per_block);
+    int64_t tiles = (n + TILE - 1) / TILE;
+    int slices;
+    if (p && p->slices > 0) {
+        slices = p->slices;
+    } else {
+        // aim for about 2048 blocks (8 per CU) so that j-slices hide latency
+        slices = (int)((2048 + c.gx - 1) / c.gx);
+        if (slices > 64) slices = 64;
+    }
+    if (slices < 1) slices = 1;
+    if (slices > tiles) slices = (int)tiles;
+    const int64_t tiles_per_slice = (tiles + slices - 1) / slices;
+    c.slice_len = tiles_per_slice * TILE;
+    c.slices = (int)((n + c.slice_len - 1) / c.slice_len);
+    c.nwaves = (int64_t)c.gx * c.slices * (KB / 64);
+    return c;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout make_layout(int64_t n, const KickCfg &c)
+{
+    Layout L;
+    L.npad = ((n + RB - 1) / RB) * RB;
+    L.nb = (n + RB - 1) / RB;
+    size_t off = 0;
+    L.status = off;
+    off += 256;
+    L.part = off;
+    off = align256(off + sizeof(double) * 3 * (size_t)c.slices * L.npad);
+    L.cnt = off;
+    off = align256(off + sizeof(int32_t) * (size_t)c.slices * L.npad);
+    L.rowloc = off;
+    off = align256(off + sizeof(int32_t) * (size_t)L.npad);
+    L.bsum = off;
+    off = align256(off + sizeof(int64_t) * (size_t)(L.nb + 1));
+    L.stage = off;
+    off = align256(off + sizeof(int32_t) * 3 * (size_t)WSEG * c.nwaves);
+    L.wcount = off;
+    off = align256(off + sizeof(int32_t) * (size_t)c.nwaves);
+    L.hc = off;
+    off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
+    L.total = off;
+    return L;
+}
+
+template <int IPT, bool F>
+static void launch_k(const KickDev &d, const KickCfg &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_kick<IPT, F>), dim3(c.gx, c.slices), dim3(KB), 0, s, d);
+}
+
+hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
+                       hipStream_t s)
+{
+    KickDev d;
+    d.x = k.x; d.y = k.y; d.z = k.z; d.m = k.m; d.rc = k.rc;
+    d.n = k.n;
+    d.npad = L.npad;
+    d.slice_len = c.slice_len;
+    d.part = (double *)(ws + L.part);
+    d.cnt = (int32_t *)(ws + L.cnt);
+    d.stage = (int32_t *)(ws + L.stage);
+    d.wcount = (int32_t *)(ws + L.wcount);
+    d.status = (int32_t *)(ws + L.status);
+    d.emit = k.pairs != nullptr;
+    d.c15 = 1.5;
+    d.c1875 = 1.875;
+
+    if (k.ev0) {
+        hipError_t e = hipEventRecord((hipEvent_t)k.ev0, s);
+        if (e != hipSuccess) return e;
+    }
+    if (k.forces) {
+        if (c.ipt == 2) launch_k<2, true>(d, c, s);
+        else launch_k<1, true>(d, c, s);
+    } else {
+        if (c.ipt == 2) launch_k<2, false>(d, c, s);
+        else launch_k<1, false>(d, c, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (k.ev1) {
+        e = hipEventRecord((hipEvent_t)k.ev1, s);
+        if (e != hipSuccess) return e;
+    }
+
+    ReduceDev r;
+    r.part = d.part; r.cnt = d.cnt;
+    r.rowloc = (int32_t *)(ws + L.rowloc);
+    r.bsum = (int64_t *)(ws + L.bsum);
+    r.vx = k.vx; r.vy = k.vy; r.vz = k.vz;
+    r.ax = k.ax; r.ay = k.ay; r.az = k.az;
+    r.status = d.status;
+    r.n = k.n; r.npad = L.npad; r.slices = c.slices;
+    r.G = k.G; r.h = k.h;
+    r.forces = k.forces;
+    r.emit = d.emit;
+    if (r.forces || r.emit) {
+        hipLaunchKernelGGL(k_kick_reduce, dim3((unsigned)L.nb), dim3(RB), 0, s, r);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (!d.emit) return hipSuccess;
+
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, r.bsum, L.nb, k.pairs->count,
+                       k.pairs->capacity, d.status);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    ScatterDev sd;
+    sd.x = k.x; sd.y = k.y; sd.z = k.z; sd.rc = k.rc;
+    sd.stage = d.stage; sd.wcount = d.wcount; sd.cnt = d.cnt; sd.rowloc = r.rowloc;
+    sd.boff = r.bsum;
+    sd.pi = k.pairs->i; sd.pj = k.pairs->j;
+    sd.capacity = k.pairs->capacity;
+    sd.n = k.n; sd.npad = L.npad; sd.slice_len = c.slice_len;
+    sd.gx = c.gx; sd.ipt = c.ipt;
+    hipLaunchKernelGGL(k_pairs_scatter, dim3((unsigned)c.nwaves), dim3(64), 0, s, sd);
+    return hipGetLastError();
+}
+
+}  // namespace genga

@@ -1,0 +1,270 @@
+"""Thin ctypes binding of libgenga.so (include/genga.h).
+
+Only argument marshalling happens here: torch tensors provide device memory
+and the current HIP stream; every step of the computation runs in the HIP
+kernels of libgenga.so.  The binding fails loudly if the library or a GPU is
+missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgenga.so")
+
+OK = 0
+E_INVAL = -1
+E_OVERFLOW = -2
+E_NONFINITE = -3
+E_HIP = -4
+E_UNSUPPORTED = -5
+E_NOCONV = -6
+E_RCRIT = -7
+
+FP64 = 0
+MIXED = 1
+FLAG_NOSYNC = 1
+
+_c_double_p = ctypes.c_void_p
+
+
+class Bodies(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in
+                                           ("x", "y", "z", "vx", "vy", "vz", "m", "rc")]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("m_star", ctypes.c_double), ("dt", ctypes.c_double),
+                ("n1", ctypes.c_double), ("n2", ctypes.c_double), ("precision", ctypes.c_int),
+                ("flags", ctypes.c_int), ("ipt", ctypes.c_int), ("slices", ctypes.c_int),
+                ("prof_events", ctypes.c_void_p * 4)]
+
+
+class Pairs(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_void_p), ("j", ctypes.c_void_p), ("capacity", ctypes.c_int64),
+                ("count", ctypes.c_void_p)]
+
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "genga_version": (ctypes.c_int, []),
+    "genga_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "genga_last_hip_error": (ctypes.c_int, []),
+    "genga_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.POINTER(Params)]),
+    "genga_read_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_clear_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_rcrit": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+    "genga_kick": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_encounter_pairs": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
+                                             ctypes.POINTER(Pairs), ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "genga_hc": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
+                                ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_drift": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_step": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
+                                  ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+class GengaError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = load().genga_strerror(code).decode() if _lib is not None else str(code)
+        if code == E_HIP:
+            msg += f" (hipError {load().genga_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{code}]" if what else f"{msg} [{code}]")
+
+
+def load(path: str = LIB_PATH):
+    """Load libgenga.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgenga.so not found at {path}; build it with "
+                           "`python -m paper_2201_10058_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise GengaError(code, what)
+
+
+def _require_gpu(t: torch.Tensor, dtype=torch.float64):
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return t.data_ptr()
+
+
+def _stream_ptr() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Config:
+    G: float
+    m_star: float = 1.0
+    dt: float = 6.0
+    n1: float = 3.0
+    n2: float = 0.4
+    precision: int = FP64
+    flags: int = 0
+    ipt: int = 0
+    slices: int = 0
+    events: tuple = field(default=(None, None, None, None))
+
+    def params(self) -> Params:
+        p = Params(self.G, self.m_star, self.dt, self.n1, self.n2, self.precision, self.flags,
+                   self.ipt, self.slices)
+        for k, e in enumerate(tuple(self.events)[:4]):
+            p.prof_events[k] = e
+        return p
+
+
+class State:
+    """Device SoA state of one system (float64 tensors on the GPU)."""
+
+    KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "rc")
+
+    def __init__(self, tensors: dict):
+        self.t = tensors
+        self.n = int(tensors["x"].numel())
+        for k in self.KEYS:
+            _require_gpu(tensors[k])
+            if tensors[k].numel() != self.n:
+                raise ValueError(f"{k} has {tensors[k].numel()} elements, expected {self.n}")
+
+    @classmethod
+    def from_numpy(cls, d: dict, device="cuda:0", rc=None):
+        t = {}
+        for k in ("x", "y", "z", "vx", "vy", "vz", "m"):
+            t[k] = torch.as_tensor(d[k], dtype=torch.float64).to(device).contiguous()
+        src = rc if rc is not None else d.get("rc")
+        if src is None:
+            t["rc"] = torch.zeros_like(t["x"])
+        else:
+            t["rc"] = torch.as_tensor(src, dtype=torch.float64).to(device).contiguous()
+        return cls(t)
+
+    def bodies(self) -> Bodies:
+        b = Bodies()
+        b.n = self.n
+        for k in self.KEYS:
+            setattr(b, k, self.t[k].data_ptr())
+        return b
+
+    def numpy(self) -> dict:
+        return {k: v.detach().cpu().numpy().copy() for k, v in self.t.items()}
+
+
+class PairList:
+    """Device encounter list with a given capacity."""
+
+    def __init__(self, capacity: int, device="cuda:0"):
+        self.capacity = int(capacity)
+        self.i = torch.zeros(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.j = torch.zeros(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def struct(self) -> Pairs:
+        return Pairs(self.i.data_ptr(), self.j.data_ptr(), self.capacity, self.count.data_ptr())
+
+    def result(self):
+        c = int(self.count.item())
+        k = min(c, self.capacity)
+        return self.i[:k].cpu().numpy(), self.j[:k].cpu().numpy(), c
+
+
+class Workspace:
+    """Caller-owned scratch for a system size and configuration."""
+
+    def __init__(self, n: int, cfg: Config, device="cuda:0"):
+        lib = load()
+        p = cfg.params()
+        nbytes = lib.genga_workspace_bytes(int(n), ctypes.byref(p))
+        if nbytes == 0:
+            raise GengaError(E_INVAL, "workspace size")
+        self.buf = torch.zeros(int(nbytes), dtype=torch.uint8, device=device)
+        self.nbytes = int(nbytes)
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+
+def read_status(ws: Workspace) -> int:
+    return load().genga_read_status(ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr()))
+
+
+def rcrit(state: State, cfg: Config, ws: Workspace):
+    b, p = state.bodies(), cfg.params()
+    _check(load().genga_rcrit(ctypes.byref(b), ctypes.byref(p), ctypes.c_void_p(ws.ptr),
+                              ctypes.c_void_p(_stream_ptr())), "genga_rcrit")
+
+
+def kick(state: State, cfg: Config, ws: Workspace, h: float, acc: bool = False,
+         pairs: PairList | None = None):
+    """v += h a (h may be 0); optionally return a (3, n) and fill pairs."""
+    b, p = state.bodies(), cfg.params()
+    a = None
+    ptrs = (None, None, None)
+    if acc:
+        a = torch.empty((3, state.n), dtype=torch.float64, device=state.t["x"].device)
+        ptrs = (a[0].data_ptr(), a[1].data_ptr(), a[2].data_ptr())
+    ps = pairs.struct() if pairs is not None else None
+    _check(load().genga_kick(ctypes.byref(b), ctypes.byref(p), float(h), ptrs[0], ptrs[1], ptrs[2],
+                             ctypes.byref(ps) if ps is not None else None, ctypes.c_void_p(ws.ptr),
+                             ctypes.c_void_p(_stream_ptr())), "genga_kick")
+    return a
+
+
+def encounter_pairs(state: State, cfg: Config, ws: Workspace, pairs: PairList):
+    b, p, ps = state.bodies(), cfg.params(), pairs.struct()
+    _check(load().genga_encounter_pairs(ctypes.byref(b), ctypes.byref(p), ctypes.byref(ps),
+                                        ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
+           "genga_encounter_pairs")
+
+
+def hc(state: State, cfg: Config, ws: Workspace, h: float):
+    b, p = state.bodies(), cfg.params()
+    _check(load().genga_hc(ctypes.byref(b), ctypes.byref(p), float(h), ctypes.c_void_p(ws.ptr),
+                           ctypes.c_void_p(_stream_ptr())), "genga_hc")
+
+
+def drift(state: State, cfg: Config, ws: Workspace, dt: float):
+    b, p = state.bodies(), cfg.params()
+    _check(load().genga_drift(ctypes.byref(b), ctypes.byref(p), float(dt), ctypes.c_void_p(ws.ptr),
+                              ctypes.c_void_p(_stream_ptr())), "genga_drift")
+
+
+def step(state: State, cfg: Config, ws: Workspace, pairs: PairList | None = None) -> int:
+    """One base step; returns the status code (raises on argument/HIP errors)."""
+    b, p = state.bodies(), cfg.params()
+    ps = pairs.struct() if pairs is not None else None
+    code = load().genga_step(ctypes.byref(b), ctypes.byref(p),
+                             ctypes.byref(ps) if ps is not None else None, ctypes.c_void_p(ws.ptr),
+                             ctypes.c_void_p(_stream_ptr()))
+    if code in (E_INVAL, E_HIP, E_UNSUPPORTED):
+        raise GengaError(code, "genga_step")
+    return code

@@ -1,0 +1,73 @@
+"""The C-ABI library loads on the CPU and exports every declared entry point.
+
+No compute call is made here (there is no GPU in the CPU test run); argument
+checks that return before any HIP call are exercised instead.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "genga.h")
+LIB = os.path.join(ROOT, "paper_2201_10058_amd", "libgenga.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(genga_[a-z0-9_]+)\s*\(", text)))
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        from paper_2201_10058_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("genga_kick", "genga_drift", "genga_encounter_pairs", "genga_step",
+                     "genga_rcrit", "genga_hc", "genga_workspace_bytes", "genga_read_status"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_signatures_cover_header():
+    from paper_2201_10058_amd import native
+    assert set(declared_functions()) <= set(native.SIGNATURES)
+
+
+def test_host_side_argument_errors():
+    from paper_2201_10058_amd import native
+    lib = native.load()
+    assert lib.genga_version() >= 100
+    assert lib.genga_strerror(native.E_OVERFLOW).decode().startswith("encounter list")
+    p = native.Config(G=2.959e-4).params()
+    assert lib.genga_workspace_bytes(0, ctypes.byref(p)) == 0
+    assert lib.genga_workspace_bytes(65536, ctypes.byref(p)) > 65536 * 8 * 3
+    # null bodies / workspace and invalid scalars fail before any device work
+    assert lib.genga_kick(None, ctypes.byref(p), 0.0, None, None, None, None, None, None) == native.E_INVAL
+    b = native.Bodies()
+    b.n = 0
+    assert lib.genga_rcrit(ctypes.byref(b), ctypes.byref(p), None, None) == native.E_INVAL
+    b.n = 10
+    assert lib.genga_step(ctypes.byref(b), ctypes.byref(p), None, None, None) == native.E_INVAL
+    bad = native.Config(G=float("nan")).params()
+    assert lib.genga_hc(ctypes.byref(b), ctypes.byref(bad), 1.0, None, None) == native.E_INVAL
+    assert lib.genga_read_status(None, None) == native.E_INVAL
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 2048, 65536, 4_000_000])
+def test_workspace_grows_with_n(n):
+    from paper_2201_10058_amd import native
+    lib = native.load()
+    p = native.Config(G=2.959e-4).params()
+    assert lib.genga_workspace_bytes(n, ctypes.byref(p)) >= 3 * 8 * n
