@@ -26,6 +26,7 @@ import time
 
 FLOP_PER_INTERACTION = 20
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X: 256 CU x 64 lanes x 2 flop x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak (packed FP32)
 METRIC = "pair interactions/s (Ginter/s) + % vector roofline, FP64 vs mixed at N=65536"
 
 
@@ -72,25 +73,34 @@ class HipEvents:
 
 
 def cpu_baseline(d, rc, G, target_s):
-    """Oracle plain FP64 kick on a bounded sample of rows of the same system."""
-    import numpy as np
+    """Oracle plain FP64 kick on a bounded sample of the same system.
+
+    The sample grows (first rows, then repeated full kicks) until one timed
+    pass takes about half of target_s.
+    """
     import oracle
     n = d["n"]
-    rows = 256
-    t_used = 0.0
+    rows, reps = 256, 1
     while True:
         t0 = time.perf_counter()
-        _, _, _, st = oracle.kick_acc(d["x"], d["y"], d["z"], d["m"], rc, G, rows=(0, rows),
-                                      precise=False)
+        for _ in range(reps):
+            oracle.kick_acc(d["x"], d["y"], d["z"], d["m"], rc, G, rows=(0, rows), precise=False)
         t_used = time.perf_counter() - t0
-        if t_used >= 0.3 * target_s or rows >= n:
+        if t_used >= 0.5 * target_s:
             break
-        rows = min(n, int(rows * max(2.0, min(8.0, 0.5 * target_s / max(t_used, 1e-3)))))
-    inter = rows * (n - 1)
+        grow = max(2.0, min(8.0, 0.6 * target_s / max(t_used, 1e-3)))
+        if rows < n:
+            rows = min(n, int(rows * grow))
+        elif reps < 64:
+            reps = min(64, int(reps * grow))
+        else:
+            break
+    inter = reps * rows * (n - 1)
+    what = (f"rows 0..{rows - 1}" if rows < n else f"{reps} full kick(s)")
     return {"value": inter / t_used / 1e9, "unit": "Ginter/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"plain FP64 kick, rows 0..{rows - 1} of the {n}-body disk "
-                      f"({inter:.3e} interactions, {t_used:.1f} s)"}
+            "sample": f"plain FP64 kick (oracle), {what} of the {n}-body disk: "
+                      f"{inter:.3e} interactions in {t_used:.1f} s"}
 
 
 def main():
@@ -117,45 +127,54 @@ def main():
     d = W.make_disk(spec)
     n = d["n"]
     G = d["G"]
-    st = N.State.from_numpy(d)
-    cfg = N.Config(G=G, m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
-                   flags=N.FLAG_NOSYNC, ipt=args.ipt, slices=args.slices)
-    ws = N.Workspace(n, cfg)
-    pairs = N.PairList(max(1 << 20, 8 * n))
-
-    for _ in range(args.warmup):
-        N.step(st, cfg, ws, pairs)
-    torch.cuda.synchronize()
-    code = N.read_status(ws)
-    if code != N.OK:
-        raise SystemExit(f"warm-up status: {code}")
-
     hip = HipEvents()
-    evs = [[hip.create() for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        cfg.events = tuple(evs[k])
-        N.step(st, cfg, ws, pairs)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    cfg.events = (None, None, None, None)
-    code = N.read_status(ws)
-    if code != N.OK:
-        raise SystemExit(f"timed-run status: {code}")
-    kick_ms = []
-    for e in evs:
-        kick_ms.append(hip.elapsed_ms(e[0], e[1]))
-        kick_ms.append(hip.elapsed_ms(e[2], e[3]))
-    for e in evs:
-        for h in e:
-            hip.destroy(h)
-    n_pairs = int(pairs.count.item())
+
+    def run(precision):
+        """Warm up, then time `steps` base steps; returns the measurements."""
+        st = N.State.from_numpy(d)
+        cfg = N.Config(G=G, m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                       precision=precision, flags=N.FLAG_NOSYNC, ipt=args.ipt, slices=args.slices)
+        ws = N.Workspace(n, cfg)
+        pairs = N.PairList(max(1 << 20, 8 * n))
+        for _ in range(args.warmup):
+            N.step(st, cfg, ws, pairs)
+        torch.cuda.synchronize()
+        code = N.read_status(ws)
+        if code != N.OK:
+            raise SystemExit(f"warm-up status: {code}")
+        evs = [[hip.create() for _ in range(4)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            cfg.events = tuple(evs[k])
+            N.step(st, cfg, ws, pairs)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        cfg.events = (None, None, None, None)
+        code = N.read_status(ws)
+        if code != N.OK:
+            raise SystemExit(f"timed-run status: {code}")
+        kick_ms = []
+        for e in evs:
+            kick_ms.append(hip.elapsed_ms(e[0], e[1]))
+            kick_ms.append(hip.elapsed_ms(e[2], e[3]))
+            for h in e:
+                hip.destroy(h)
+        return dict(elapsed=elapsed, kick_s=float(np.mean(kick_ms)) / 1e3,
+                    pairs=int(pairs.count.item()), rc=st.t["rc"])
+
+    r64 = run(N.FP64)
+    print(f"fp64 step done: {r64['elapsed'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
+          flush=True)
+    r32 = run(N.MIXED)
+    print(f"mixed step done: {r32['elapsed'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
+          flush=True)
 
     inter_step = 2.0 * n * (n - 1)
-    value = inter_step * args.steps / elapsed / 1e9
-    kick_s = float(np.mean(kick_ms)) / 1e3
-    achieved = FLOP_PER_INTERACTION * n * (n - 1) / kick_s / 1e12
+    value = inter_step * args.steps / r64["elapsed"] / 1e9
+    achieved = FLOP_PER_INTERACTION * n * (n - 1) / r64["kick_s"] / 1e12
+    achieved32 = FLOP_PER_INTERACTION * n * (n - 1) / r32["kick_s"] / 1e12
+    value32 = inter_step * args.steps / r32["elapsed"] / 1e9
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -163,24 +182,32 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "ms_per_step": round(r64["elapsed"] / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": spec.name, "n": n, "dt_days": d["dt"], "n1": d["n1"], "n2": d["n2"],
-                   "kicks_per_step": 2, "encounter_pairs_last_step": n_pairs,
+                   "kicks_per_step": 2, "encounter_pairs_last_step": r64["pairs"],
                    "ipt": args.ipt, "slices": args.slices},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_kick (FP64)", "kernel_ms": round(kick_s * 1e3, 4),
+                     "kernel": "k_kick<1, KM_F64>", "kernel_ms": round(r64["kick_s"] * 1e3, 4),
                      "flop_per_interaction": FLOP_PER_INTERACTION},
+        "mixed": {"value": round(value32, 3), "unit": "Ginter/s",
+                  "ms_per_step": round(r32["elapsed"] / args.steps * 1e3, 4),
+                  "kernel_ms": round(r32["kick_s"] * 1e3, 4),
+                  "achieved_tflops": round(achieved32, 3),
+                  "frac_fp32_vector_peak": round(achieved32 / FP32_VECTOR_PEAK_TFLOPS, 4),
+                  "speedup_vs_fp64_kernel": round(r64["kick_s"] / r32["kick_s"], 3),
+                  "encounter_pairs_last_step": r32["pairs"]},
     }
+    st_rc = r64["rc"]
     if not args.no_cpu_baseline:
         import oracle
-        rc = st.t["rc"].cpu().numpy()
+        rc = st_rc.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(d, rc, G, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

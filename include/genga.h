@@ -140,9 +140,10 @@ int genga_rcrit(const genga_bodies *b, const genga_params *p, void *ws, void *st
  * If the count exceeds capacity, the first `capacity` pairs are written, the
  * true count is stored and the status records GENGA_E_OVERFLOW.
  * precision GENGA_MIXED: differences d in binary64 rounded to binary32,
- * binary32 distance and weight, binary32 partial sums over at most 64
- * columns folded into binary64 accumulators; pairs inside rho_ij, and the
- * encounter test, stay in binary64, so the list is identical to GENGA_FP64.
+ * binary32 distance, weight and partial sums over 64 columns, folded into
+ * binary64 accumulators; every pair closer than 2 rho_ij (selected by a
+ * conservative binary32 test) is evaluated entirely in binary64, and the
+ * encounter test stays in binary64, so the list is identical to GENGA_FP64.
  * Positions of two distinct bodies that coincide set GENGA_E_NONFINITE. */
 int genga_kick(const genga_bodies *b, const genga_params *p, double h,
                double *ax, double *ay, double *az, genga_pairs *pairs, void *ws, void *stream);

@@ -154,7 +154,6 @@ int genga_kick(const genga_bodies *b, const genga_params *p, double h, double *a
     if ((r = check_pairs(pairs))) return r;
     if (!ws || !is_fin(h)) return GENGA_E_INVAL;
     if ((ax || ay || az) && !(ax && ay && az)) return GENGA_E_INVAL;
-    if (p->precision == GENGA_MIXED) return GENGA_E_UNSUPPORTED;
     return do_kick(b, p, h, ax, ay, az, pairs, true, ws, stream);
 }
 
@@ -198,7 +197,6 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if ((r = check_params(p))) return r;
     if ((r = check_pairs(pairs))) return r;
     if (!ws) return GENGA_E_INVAL;
-    if (p->precision == GENGA_MIXED) return GENGA_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const double h = 0.5 * p->dt;
     const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));

@@ -37,6 +37,7 @@ struct KickDev {
     int32_t *status;
     int emit;
     double c15, c1875;   // 3/2 and 15/8
+    double widen;        // mixed: squared widening of the binary32 pre-check radius
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt()
@@ -64,21 +65,31 @@ __device__ __forceinline__ double vmax_f64(double a, double b)
     return r;
 }
 
+// Kick variants sharing one kernel body.
+enum KickMode : int {
+    KM_F64 = 0,    // binary64 pair arithmetic
+    KM_MIXED = 1,  // binary32 pair arithmetic on binary64 differences
+    KM_PAIRS = 2,  // encounter list only (no forces)
+};
+
 // Per-lane state of the kick: IPT rows per lane.
 template <int IPT>
 struct Rows {
     double xi[IPT], yi[IPT], zi[IPT], rc2i[IPT];
     double ax[IPT], ay[IPT], az[IPT];
+    float rc2fi[IPT];            // mixed: widened binary32 pre-check radius
+    float axf[IPT], ayf[IPT], azf[IPT];  // mixed: binary32 partial sums
     int64_t ii[IPT];
     int kc[IPT];
 };
 
 // Rare path of one interaction: self pair, coincident bodies, changeover band
-// (K < 1) and encounter-pair recording.  Returns the weight m_j K / r^3.
+// (K < 1) and encounter-pair recording.  r2 is the exact binary64 squared
+// separation.  Returns the weight m_j K / r^3.
 template <int IPT, bool FORCES>
 __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int q, int64_t jg,
-                                         double r2, double rc2j, double mj, int64_t wave_g,
-                                         volatile int *wcnt)
+                                            double r2, double rc2j, double mj, int64_t wave_g,
+                                            volatile int *wcnt)
 {
     bool emit = false;
     double wk = 0.0;
@@ -87,13 +98,17 @@ __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int 
             atomicOr(a.status, ST_NONFINITE);
         } else {
             const double rho2 = R.rc2i[q] > rc2j ? R.rc2i[q] : rc2j;
-            emit = (r2 < rho2) && (jg > R.ii[q]);
+            const bool inside = r2 < rho2;
+            emit = inside && (jg > R.ii[q]);
             if (FORCES) {
-                const double rci = a.rc[R.ii[q]];
-                const double rcj = a.rc[jg];
-                const double rho = rci > rcj ? rci : rcj;
                 const double r = __builtin_sqrt(r2);
-                wk = mj * changeover_k(r, rho) / (r2 * r);
+                double K = 1.0;
+                if (inside) {
+                    const double rci = a.rc[R.ii[q]];
+                    const double rcj = a.rc[jg];
+                    K = changeover_k(r, rci > rcj ? rci : rcj);
+                }
+                wk = mj * K / (r2 * r);
             }
         }
     }
@@ -118,13 +133,72 @@ __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int 
     return wk;
 }
 
+__device__ __forceinline__ float vmax_f32(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// binary32 mass and pre-check radius packed in the fourth double of a tile entry
+__device__ __forceinline__ double pack_f32x2(float lo, float hi)
+{
+    return __hiloint2double(__float_as_int(hi), __float_as_int(lo));
+}
+
 // One column j against the lane's rows (the hot loop body).
-template <int IPT, bool FORCES>
+//   b = (x_j, y_j, z_j, m_j) for KM_F64 / KM_PAIRS, (x_j, y_j, z_j, {m_j, rc2f_j}) for KM_MIXED.
+template <int IPT, int MODE>
 __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const double4 b,
                                          const double rc2j, const int64_t jg, const double c15,
                                          const double c1875, const int64_t wave_g,
-                                         volatile int *wcnt)
+                                         volatile int *wcnt, const double *rc2j64,
+                                         const double *mj64)
 {
+    if (MODE == KM_MIXED) {
+        const float mjf = __int_as_float(__double2loint(b.w));
+        const float rc2fj = __int_as_float(__double2hiint(b.w));
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            const double dx = b.x - R.xi[q];
+            const double dy = b.y - R.yi[q];
+            const double dz = b.z - R.zi[q];
+            const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
+            const float r2f = __builtin_fmaf(dzf, dzf, __builtin_fmaf(dyf, dyf, dxf * dxf));
+            // conservative binary32 test for "closer than MIXED_NEAR rho_ij"
+            const bool near = r2f <= vmax_f32(R.rc2fi[q], rc2fj);
+            const float yv = __builtin_amdgcn_rsqf(r2f);
+            const float y2 = yv * yv;
+            float sc = mjf * (y2 * yv);
+            if (near) {
+                // near pairs are evaluated in binary64; those inside rho_ij
+                // (and the self pair) take the changeover / encounter path
+                sc = 0.0f;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                const double mj = *mj64;
+                const double rc2j = *rc2j64;
+                double wk;
+                if (r2 <= vmax_f64(R.rc2i[q], rc2j)) {
+                    wk = slow_pair<IPT, true>(a, R, q, jg, r2, rc2j, mj, wave_g, wcnt);
+                } else {
+                    const double y = __builtin_amdgcn_rsq(r2);
+                    const double yy = y * y;
+                    const double e = __builtin_fma(-r2, yy, 1.0);
+                    const double p = __builtin_fma(e, c1875, c15);
+                    const double my3 = mj * (yy * y);
+                    wk = __builtin_fma(my3 * e, p, my3);
+                }
+                R.ax[q] = __builtin_fma(dx, wk, R.ax[q]);
+                R.ay[q] = __builtin_fma(dy, wk, R.ay[q]);
+                R.az[q] = __builtin_fma(dz, wk, R.az[q]);
+            }
+            R.axf[q] = __builtin_fmaf(dxf, sc, R.axf[q]);
+            R.ayf[q] = __builtin_fmaf(dyf, sc, R.ayf[q]);
+            R.azf[q] = __builtin_fmaf(dzf, sc, R.azf[q]);
+        }
+        return;
+    }
+    constexpr bool FORCES = MODE == KM_F64;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const double dx = b.x - R.xi[q];
@@ -135,7 +209,7 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
         const bool cand = r2 <= vmax_f64(R.rc2i[q], rc2j);
         double sc = 0.0;
         if (FORCES) {
-            // m r^-3 from v_rsq_f64 (relative error e0 ~ 2^-23):
+            // m r^-3 from v_rsq_f64 (relative error e0 ~ 2^-24):
             // with e = 1 - r2 y^2, r2^{-3/2} = y^3 (1 - e)^{-3/2}
             //   = y^3 (1 + e (3/2 + 15/8 e) + O(e^3)).
             const double yv = __builtin_amdgcn_rsq(r2);
@@ -156,11 +230,34 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
     }
 }
 
-template <int IPT, bool FORCES>
+// Mixed mode: add the binary32 partial sums into the binary64 accumulators.
+template <int IPT, int MODE>
+__device__ __forceinline__ void fold(Rows<IPT> &R)
+{
+    if (MODE != KM_MIXED) return;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        R.ax[q] += (double)R.axf[q];
+        R.ay[q] += (double)R.ayf[q];
+        R.az[q] += (double)R.azf[q];
+        R.axf[q] = R.ayf[q] = R.azf[q] = 0.0f;
+    }
+}
+
+constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
+// Mixed mode: pairs closer than MIXED_NEAR rho_ij are summed in binary64.  The
+// largest binary32 terms are those of near neighbours; moving pairs inside
+// 3 rho to binary64 keeps the per-acceleration error of the 0.5-4 AU disks
+// below 1e-6 even for bodies whose net acceleration is 50-90 times smaller
+// than the sum of the magnitudes of its terms.
+constexpr double MIXED_NEAR = 3.0;
+
+template <int IPT, int MODE>
 __global__ __launch_bounds__(KB) void k_kick(KickDev a)
 {
     __shared__ double4 s_xyzm[TILE];
     __shared__ double s_rc2[TILE];
+    __shared__ double s_m[MODE == KM_MIXED ? TILE : 1];
     __shared__ int s_wcnt[KB / 64];
 
     const int tid = threadIdx.x;
@@ -179,6 +276,7 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
     const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
     const double4 *t_xyzm = s_xyzm + vzero;
     const double *t_rc2 = s_rc2 + vzero;
+    const double *t_m = s_m + vzero;
 
     Rows<IPT> R;
 #pragma unroll
@@ -195,7 +293,9 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
             R.xi[q] = R.yi[q] = R.zi[q] = __builtin_nan("");
             R.rc2i[q] = 0.0;
         }
+        R.rc2fi[q] = (float)(R.rc2i[q] * a.widen);
         R.ax[q] = R.ay[q] = R.az[q] = 0.0;
+        R.axf[q] = R.ayf[q] = R.azf[q] = 0.0f;
         R.kc[q] = 0;
     }
     if (lane == 0) s_wcnt[w] = 0;
@@ -208,7 +308,14 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
             if (jg < j1) {
                 const double rcj = a.rc[jg];
                 if (!(rcj >= 0.0 && rcj < INFINITY)) atomicOr(a.status, ST_RCRIT);
-                s_xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], a.m[jg]);
+                const double mj = a.m[jg];
+                if (MODE == KM_MIXED) {
+                    const float rc2f = (float)(rcj * rcj * a.widen);
+                    s_xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], pack_f32x2((float)mj, rc2f));
+                    s_m[q] = mj;
+                } else {
+                    s_xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], mj);
+                }
                 s_rc2[q] = rcj * rcj;
             }
         }
@@ -218,20 +325,25 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
             for (int jj = 0; jj < TILE; jj += 4) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    interact<IPT, FORCES>(a, R, t_xyzm[jj + u], t_rc2[jj + u], t0 + jj + u, c15,
-                                          c1875, wave_g, wcnt);
+                    interact<IPT, MODE>(a, R, t_xyzm[jj + u],
+                                        MODE == KM_MIXED ? 0.0 : t_rc2[jj + u], t0 + jj + u, c15,
+                                        c1875, wave_g, wcnt, t_rc2 + jj + u, t_m + jj + u);
+                if ((jj & (FOLD - 1)) == FOLD - 4) fold<IPT, MODE>(R);
             }
         } else {
-            for (int jj = 0; jj < tn; ++jj)
-                interact<IPT, FORCES>(a, R, t_xyzm[jj], t_rc2[jj], t0 + jj, c15, c1875, wave_g,
-                                      wcnt);
+            for (int jj = 0; jj < tn; ++jj) {
+                interact<IPT, MODE>(a, R, t_xyzm[jj], MODE == KM_MIXED ? 0.0 : t_rc2[jj], t0 + jj,
+                                    c15, c1875, wave_g, wcnt, t_rc2 + jj, t_m + jj);
+                if ((jj & (FOLD - 1)) == FOLD - 1) fold<IPT, MODE>(R);
+            }
+            fold<IPT, MODE>(R);
         }
     }
 
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         if (R.ii[q] < a.n) {
-            if (FORCES) {
+            if (MODE != KM_PAIRS) {
                 a.part[((size_t)s * 3 + 0) * a.npad + R.ii[q]] = R.ax[q];
                 a.part[((size_t)s * 3 + 1) * a.npad + R.ii[q]] = R.ay[q];
                 a.part[((size_t)s * 3 + 2) * a.npad + R.ii[q]] = R.az[q];
@@ -467,10 +579,18 @@ Layout make_layout(int64_t n, const KickCfg &c)
     return L;
 }
 
-template <int IPT, bool F>
+template <int IPT, int MODE>
 static void launch_k(const KickDev &d, const KickCfg &c, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_kick<IPT, F>), dim3(c.gx, c.slices), dim3(KB), 0, s, d);
+    hipLaunchKernelGGL((k_kick<IPT, MODE>), dim3(c.gx, c.slices), dim3(KB), 0, s, d);
+}
+
+template <int IPT>
+static void launch_mode(const KickDev &d, const KickCfg &c, int mode, hipStream_t s)
+{
+    if (mode == KM_MIXED) launch_k<IPT, KM_MIXED>(d, c, s);
+    else if (mode == KM_PAIRS) launch_k<IPT, KM_PAIRS>(d, c, s);
+    else launch_k<IPT, KM_F64>(d, c, s);
 }
 
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
@@ -489,18 +609,19 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     d.emit = k.pairs != nullptr;
     d.c15 = 1.5;
     d.c1875 = 1.875;
+    // Mixed mode evaluates every pair closer than MIXED_NEAR rho_ij in
+    // binary64: the binary32 test uses (MIXED_NEAR rho)^2 with a relative
+    // margin of 2^-14, far above the binary32 rounding of r^2 (< 2^-21), so
+    // no pair inside rho_ij can be missed.
+    d.widen = MIXED_NEAR * MIXED_NEAR * (1.0 + 0x1p-14);
 
     if (k.ev0) {
         hipError_t e = hipEventRecord((hipEvent_t)k.ev0, s);
         if (e != hipSuccess) return e;
     }
-    if (k.forces) {
-        if (c.ipt == 2) launch_k<2, true>(d, c, s);
-        else launch_k<1, true>(d, c, s);
-    } else {
-        if (c.ipt == 2) launch_k<2, false>(d, c, s);
-        else launch_k<1, false>(d, c, s);
-    }
+    const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
+    if (c.ipt == 2) launch_mode<2>(d, c, mode, s);
+    else launch_mode<1>(d, c, mode, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (k.ev1) {
