@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target duration of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -101,6 +103,77 @@ def cpu_baseline(d, rc, G, target_s):
             "kind": "oracle",
             "sample": f"plain FP64 kick (oracle), {what} of the {n}-body disk: "
                       f"{inter:.3e} interactions in {t_used:.1f} s"}
+
+
+def bench_batched(args, N, W, torch, np):
+    """The 512-system ensemble: one persistent kick per half step, the whole
+    step captured in a hipGraph, against 512 single-system steps."""
+    from paper_2201_10058_amd import autotune
+    d = W.make_batch()
+    G = d["G"]
+    bt = N.Batch(d["offsets"], d["m_star"], d["dt"], d["n1"], d["n2"])
+    st = N.State.from_numpy(d)
+    base = N.Config(G=G, flags=N.FLAG_NOSYNC)
+    # tile shape by the autotuner (rc from one plain step first)
+    ws0 = N.BatchWorkspace(bt, base)
+    N.step_batched(st, ws0, base)
+    torch.cuda.synchronize()
+    choice = autotune.tune_batched(st, bt, base)
+    cfg = N.Config(**{**base.__dict__, **choice})
+    ws = N.BatchWorkspace(bt, cfg)
+    pairs = N.PairList(1 << 22)
+    sizes = np.diff(d["offsets"])
+    inter = float(np.sum(sizes * (sizes - 1))) * 2.0       # per step (two kicks)
+    K = args.batch_steps
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    eager_s = timed(lambda: N.step_batched(st, ws, cfg, pairs), K)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        N.step_batched(st, ws, cfg, pairs)
+    graph_s = timed(g.replay, K)
+    code = N.read_status(ws)
+    if code != N.OK:
+        raise SystemExit(f"batched status: {code}")
+    # per-system launches (each system its own genga_step calls)
+    views, wss = [], []
+    for s_ in range(d["S"]):
+        lo, hi = int(d["offsets"][s_]), int(d["offsets"][s_ + 1])
+        views.append(N.system_view(st, lo, hi))
+        wss.append(N.Workspace(hi - lo, base))
+    cfgs = [N.Config(G=G, m_star=float(d["m_star"][k]), dt=float(d["dt"][k]), n1=float(d["n1"][k]),
+                     n2=float(d["n2"][k]), flags=N.FLAG_NOSYNC) for k in range(d["S"])]
+    pls = [N.PairList(max(16, 64 * int(sizes[k]))) for k in range(d["S"])]
+
+    def per_system():
+        for k in range(d["S"]):
+            N.step(views[k], cfgs[k], wss[k], pls[k])
+
+    per_sys_s = timed(per_system, max(2, K // 3))
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        per_system()
+    per_sys_graph_s = timed(g2.replay, K)
+    for w_ in wss:
+        if N.read_status(w_) != N.OK:
+            raise SystemExit("per-system status")
+    return {"systems": int(d["S"]), "bodies": int(d["offsets"][-1]),
+            "interactions_per_step": inter,
+            "value": round(inter / graph_s / 1e9, 3), "unit": "Ginter/s",
+            "graph_step_ms": round(graph_s * 1e3, 4), "eager_step_ms": round(eager_s * 1e3, 4),
+            "per_system_eager_step_ms": round(per_sys_s * 1e3, 4),
+            "per_system_graph_step_ms": round(per_sys_graph_s * 1e3, 4),
+            "speedup_vs_per_system_graph": round(per_sys_graph_s / graph_s, 3),
+            "speedup_vs_per_system_eager": round(per_sys_s / graph_s, 3),
+            "tile_shape": {**choice, "tiles": ws.info["tiles"], "grid": ws.info["grid"]}}
 
 
 def main():
@@ -205,6 +278,10 @@ def main():
                   "encounter_pairs_last_step": r32["pairs"]},
     }
     st_rc = r64["rc"]
+    if not args.no_batched:
+        out["batched"] = bench_batched(args, N, W, torch, np)
+        print(f"batched done: {out['batched']['graph_step_ms']} ms/step (graph)", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         import oracle
         rc = st_rc.cpu().numpy()

@@ -88,7 +88,10 @@ typedef struct {
     int precision; /* GENGA_FP64 or GENGA_MIXED                                 */
     int flags;     /* GENGA_FLAG_*                                              */
     int ipt;       /* kick rows per thread (1 or 2); 0 = library choice         */
-    int slices;    /* kick column slices; 0 = library choice                    */
+    int slices;    /* single system: kick column slices; 0 = library choice     */
+    int block;     /* batch: kick threads per block (64 or 256); 0 = 256         */
+    int tile_cols; /* batch: columns per kick tile (rounded up to 256); 0 = 1024 */
+    int grid;      /* batch: persistent kick blocks; 0 = library choice         */
     void *prof_events[4]; /* optional hipEvent_t handles (timing): [0], [1] are
                              recorded immediately before and after the main
                              kernel of genga_kick and of the first half kick of
@@ -168,6 +171,51 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
  * pairs (nullable) receives the list of the first half kick.  Unless
  * GENGA_FLAG_NOSYNC, synchronises the stream and returns the status. */
 int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void *ws, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched ensembles (the multi-simulation mode named in Sect. 10, not
+ * described by the paper): S independent systems, each advanced by the same
+ * operators as above, stored back to back in one genga_bodies (n = total).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t S;                /* number of systems, >= 1                              */
+    const int64_t *offsets;   /* HOST array of S + 1 body offsets: system s holds
+                                 bodies [offsets[s], offsets[s+1]); offsets[0] = 0,
+                                 every system non-empty                              */
+    const double *m_star;     /* DEVICE arrays of S values: central mass, time step */
+    const double *dt;         /*   and the factors n1, n2 of eq. (rcrit) per system  */
+    const double *n1;
+    const double *n2;
+} genga_batch;
+
+/* Workspace size for a batch with these params (0 if the batch is invalid). */
+size_t genga_batch_workspace_bytes(const genga_batch *bt, const genga_params *p);
+
+/* Write the batch plan into the workspace: kick tiles (rows of one system
+ * against a column range of the same system, sorted by decreasing cost),
+ * the body-to-system map and the column slices per system.  Copies from the
+ * host and synchronises the stream.  Call once per (batch layout, params,
+ * workspace) before the batched calls below; they read the plan. */
+int genga_batch_plan(const genga_batch *bt, const genga_params *p, void *ws, void *stream);
+
+/* Shape of the plan: out5 = {tiles, persistent blocks, threads per block,
+ * rows per thread, columns per tile}. */
+int genga_batch_info(const genga_batch *bt, const genga_params *p, int64_t *out5);
+
+/* Kick of every system in one persistent launch: for body i of system s,
+ * v_i += hfac * dt_s * a_i with a_i summed over the bodies of s only (the
+ * formula of genga_kick).  ax/ay/az (nullable) receive a.  pairs (nullable)
+ * receives one list for the whole batch with global body indices, in
+ * canonical order (which is also system order). */
+int genga_kick_batched(const genga_bodies *b, const genga_batch *bt, const genga_params *p,
+                       double hfac, double *ax, double *ay, double *az, genga_pairs *pairs,
+                       void *ws, void *stream);
+
+/* One base step (as genga_step) of every system with its own m_star, dt, n1,
+ * n2; p->G is shared.  The launch sequence is fixed, so the call can be
+ * captured in a hipGraph (with GENGA_FLAG_NOSYNC). */
+int genga_step_batched(genga_bodies *b, const genga_batch *bt, const genga_params *p,
+                       genga_pairs *pairs, void *ws, void *stream);
 
 #ifdef __cplusplus
 }

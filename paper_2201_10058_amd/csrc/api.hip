@@ -37,6 +37,7 @@ static int check_params(const genga_params *p)
     if (p->n1 < 0.0 || p->n2 < 0.0) return GENGA_E_INVAL;
     if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
     if (p->ipt < 0 || p->ipt > 2 || p->slices < 0) return GENGA_E_INVAL;
+    if (p->block < 0 || p->tile_cols < 0 || p->grid < 0) return GENGA_E_INVAL;
     return GENGA_OK;
 }
 
@@ -75,6 +76,11 @@ static int do_kick(const genga_bodies *b, const genga_params *p, double h, doubl
     k.pairs = pairs;
     k.ev0 = p->prof_events[ev_slot];
     k.ev1 = p->prof_events[ev_slot + 1];
+    k.hfac = 0.0;
+    k.tiles = nullptr;
+    k.sysid = nullptr;
+    k.sys_slices = nullptr;
+    k.sys_dt = nullptr;
     hipError_t e = launch_kick(k, c, L, (char *)ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return GENGA_OK;

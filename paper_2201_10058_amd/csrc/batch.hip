@@ -1,0 +1,264 @@
+// Batched ensembles: many independent systems of uneven size in one
+// persistent kick launch.  The paper names a multi-simulation mode (Sect. 10)
+// without describing it; here each system is an independent instance of the
+// base step of Appendix A and the systems share one launch per operator.
+//
+// Host side: a plan (tile list sorted by cost, body -> system map, column
+// slices per system) is written into the caller's workspace once; the
+// batched kick then walks that list with a persistent grid, so a step is a
+// fixed sequence of launches that can be captured in one hipGraph.
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "genga_internal.h"
+
+namespace genga {
+
+static int cu_count()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cached[dev] = v;
+    }
+    return cached[dev];
+}
+
+struct BatchShape {
+    KickCfg cfg;
+    int64_t ntot = 0;
+    int64_t cols = 0;     // columns per tile (multiple of TILE)
+};
+
+// Validate the batch and derive the launch shape (O(S) host work).
+static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape &sh)
+{
+    if (!bt || bt->S < 1 || !bt->offsets) return GENGA_E_INVAL;
+    if (!bt->m_star || !bt->dt || !bt->n1 || !bt->n2) return GENGA_E_INVAL;
+    if (bt->offsets[0] != 0) return GENGA_E_INVAL;
+    KickCfg &c = sh.cfg;
+    c.nt = (p && p->block == 64) ? 64 : KB;
+    if (p && p->block != 0 && p->block != 64 && p->block != KB) return GENGA_E_INVAL;
+    c.ipt = (p && p->ipt > 0) ? p->ipt : 1;
+    if (c.ipt != 1 && c.ipt != 2) return GENGA_E_INVAL;
+    int64_t cols = (p && p->tile_cols > 0) ? p->tile_cols : 1024;
+    cols = ((cols + TILE - 1) / TILE) * TILE;
+    sh.cols = cols;
+    const int64_t R = (int64_t)c.nt * c.ipt;
+    int64_t ntiles = 0;
+    int maxs = 1;
+    for (int64_t s = 0; s < bt->S; ++s) {
+        const int64_t ns = bt->offsets[s + 1] - bt->offsets[s];
+        if (ns < 1) return GENGA_E_INVAL;
+        const int64_t rb = (ns + R - 1) / R;
+        const int64_t nsl = (ns + cols - 1) / cols;
+        ntiles += rb * nsl;
+        if (nsl > maxs) maxs = (int)nsl;
+    }
+    sh.ntot = bt->offsets[bt->S];
+    if (sh.ntot > (int64_t)INT32_MAX) return GENGA_E_INVAL;
+    c.slices = maxs;
+    c.ntiles = ntiles;
+    c.nwaves = ntiles * (c.nt / 64);
+    const int per_cu = c.nt == 64 ? 16 : 4;
+    int64_t grid = (p && p->grid > 0) ? p->grid : (int64_t)cu_count() * per_cu;
+    if (grid > ntiles) grid = ntiles;
+    c.grid = (int)grid;
+    return GENGA_OK;
+}
+
+// Tile list (sorted by decreasing work, ties by position), body -> system map
+// and column slices per system.
+static void build_plan(const genga_batch *bt, const BatchShape &sh, std::vector<TileDesc> &tiles,
+                       std::vector<int32_t> &sysid, std::vector<int32_t> &slices)
+{
+    const int64_t R = (int64_t)sh.cfg.nt * sh.cfg.ipt;
+    tiles.clear();
+    tiles.reserve((size_t)sh.cfg.ntiles);
+    sysid.assign((size_t)sh.ntot, 0);
+    slices.assign((size_t)bt->S, 0);
+    for (int64_t s = 0; s < bt->S; ++s) {
+        const int64_t off = bt->offsets[s];
+        const int64_t ns = bt->offsets[s + 1] - off;
+        const int64_t nsl = (ns + sh.cols - 1) / sh.cols;
+        slices[(size_t)s] = (int32_t)nsl;
+        for (int64_t i = 0; i < ns; ++i) sysid[(size_t)(off + i)] = (int32_t)s;
+        for (int64_t r0 = 0; r0 < ns; r0 += R) {
+            for (int64_t k = 0; k < nsl; ++k) {
+                TileDesc t;
+                t.row0 = off + r0;
+                t.nrows = (int32_t)std::min(R, ns - r0);
+                t.slice = (int32_t)k;
+                t.col0 = off + k * sh.cols;
+                t.ncols = (int32_t)std::min(sh.cols, ns - k * sh.cols);
+                t.sys = (int32_t)s;
+                tiles.push_back(t);
+            }
+        }
+    }
+    std::stable_sort(tiles.begin(), tiles.end(), [](const TileDesc &a, const TileDesc &b) {
+        return (int64_t)a.nrows * a.ncols > (int64_t)b.nrows * b.ncols;
+    });
+}
+
+static BatchDev batch_dev(const genga_batch *bt, const Layout &L, char *ws)
+{
+    BatchDev bd;
+    bd.S = bt->S;
+    bd.offsets = (const int64_t *)(ws + L.offsets);
+    bd.sysid = (const int32_t *)(ws + L.sysid);
+    bd.sys_slices = (const int32_t *)(ws + L.sys_slices);
+    bd.tiles = (const TileDesc *)(ws + L.tiles);
+    bd.m_star = bt->m_star;
+    bd.dt = bt->dt;
+    bd.n1 = bt->n1;
+    bd.n2 = bt->n2;
+    bd.P = (double *)(ws + L.P);
+    return bd;
+}
+
+static int hip_err(hipError_t e)
+{
+    set_hip_error(e);
+    return GENGA_E_HIP;
+}
+
+static int kick_batched(const genga_bodies *b, const genga_batch *bt, const genga_params *p,
+                        double hfac, double *ax, double *ay, double *az, genga_pairs *pairs,
+                        bool forces, void *ws, void *stream, int ev_slot)
+{
+    BatchShape sh;
+    int r = batch_shape(bt, p, sh);
+    if (r) return r;
+    if (b->n != sh.ntot) return GENGA_E_INVAL;
+    const Layout L = make_layout(sh.ntot, sh.cfg, bt->S);
+    const BatchDev bd = batch_dev(bt, L, (char *)ws);
+    KickLaunch k;
+    k.x = b->x; k.y = b->y; k.z = b->z; k.m = b->m; k.rc = b->rc;
+    k.vx = b->vx; k.vy = b->vy; k.vz = b->vz;
+    k.ax = ax; k.ay = ay; k.az = az;
+    k.n = b->n;
+    k.G = p->G;
+    k.h = 0.0;
+    k.hfac = hfac;
+    k.precision = p->precision;
+    k.forces = forces;
+    k.pairs = pairs;
+    k.ev0 = p->prof_events[ev_slot];
+    k.ev1 = p->prof_events[ev_slot + 1];
+    k.tiles = bd.tiles;
+    k.sysid = bd.sysid;
+    k.sys_slices = bd.sys_slices;
+    k.sys_dt = bd.dt;
+    hipError_t e = launch_kick(k, sh.cfg, L, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_err(e);
+}
+
+}  // namespace genga
+
+using namespace genga;
+
+extern "C" {
+
+size_t genga_batch_workspace_bytes(const genga_batch *bt, const genga_params *p)
+{
+    BatchShape sh;
+    if (batch_shape(bt, p, sh)) return 0;
+    return make_layout(sh.ntot, sh.cfg, bt->S).total;
+}
+
+int genga_batch_plan(const genga_batch *bt, const genga_params *p, void *ws, void *stream)
+{
+    BatchShape sh;
+    int r = batch_shape(bt, p, sh);
+    if (r) return r;
+    if (!ws) return GENGA_E_INVAL;
+    const Layout L = make_layout(sh.ntot, sh.cfg, bt->S);
+    std::vector<TileDesc> tiles;
+    std::vector<int32_t> sysid, slices;
+    build_plan(bt, sh, tiles, sysid, slices);
+    char *w = (char *)ws;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(w + L.tiles, tiles.data(), tiles.size() * sizeof(TileDesc),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_err(e);
+    if ((e = hipMemcpyAsync(w + L.sysid, sysid.data(), sysid.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_err(e);
+    if ((e = hipMemcpyAsync(w + L.sys_slices, slices.data(), slices.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_err(e);
+    if ((e = hipMemcpyAsync(w + L.offsets, bt->offsets, (size_t)(bt->S + 1) * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_err(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e);
+    return GENGA_OK;
+}
+
+int genga_batch_info(const genga_batch *bt, const genga_params *p, int64_t *out5)
+{
+    BatchShape sh;
+    int r = batch_shape(bt, p, sh);
+    if (r) return r;
+    if (!out5) return GENGA_E_INVAL;
+    out5[0] = sh.cfg.ntiles;
+    out5[1] = sh.cfg.grid;
+    out5[2] = sh.cfg.nt;
+    out5[3] = sh.cfg.ipt;
+    out5[4] = sh.cols;
+    return GENGA_OK;
+}
+
+int genga_kick_batched(const genga_bodies *b, const genga_batch *bt, const genga_params *p,
+                       double hfac, double *ax, double *ay, double *az, genga_pairs *pairs,
+                       void *ws, void *stream)
+{
+    if (!b || !b->x || !b->y || !b->z || !b->m || !b->rc || !ws || !p) return GENGA_E_INVAL;
+    if (!std::isfinite(hfac) || !std::isfinite(p->G) || p->G < 0.0) return GENGA_E_INVAL;
+    if (hfac != 0.0 && (!b->vx || !b->vy || !b->vz)) return GENGA_E_INVAL;
+    if ((ax || ay || az) && !(ax && ay && az)) return GENGA_E_INVAL;
+    if (pairs && (!pairs->count || pairs->capacity < 0 || (pairs->capacity > 0 && (!pairs->i || !pairs->j))))
+        return GENGA_E_INVAL;
+    if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
+    return kick_batched(b, bt, p, hfac, ax, ay, az, pairs, true, ws, stream, 0);
+}
+
+int genga_step_batched(genga_bodies *b, const genga_batch *bt, const genga_params *p,
+                       genga_pairs *pairs, void *ws, void *stream)
+{
+    if (!b || !b->x || !b->y || !b->z || !b->m || !b->rc || !b->vx || !b->vy || !b->vz || !ws || !p)
+        return GENGA_E_INVAL;
+    if (!std::isfinite(p->G) || p->G < 0.0) return GENGA_E_INVAL;
+    if (pairs && (!pairs->count || pairs->capacity < 0 || (pairs->capacity > 0 && (!pairs->i || !pairs->j))))
+        return GENGA_E_INVAL;
+    if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
+    BatchShape sh;
+    int r = batch_shape(bt, p, sh);
+    if (r) return r;
+    if (b->n != sh.ntot) return GENGA_E_INVAL;
+    const Layout L = make_layout(sh.ntot, sh.cfg, bt->S);
+    const BatchDev bd = batch_dev(bt, L, (char *)ws);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = launch_rcrit_b(b, bd, (char *)ws, s)) != hipSuccess) return hip_err(e);
+    if ((r = kick_batched(b, bt, p, 0.5, nullptr, nullptr, nullptr, pairs, true, ws, stream, 0)))
+        return r;
+    if ((e = launch_hc_b(b, bd, 0.5, s)) != hipSuccess) return hip_err(e);
+    if ((e = launch_drift_b(b, bd, p->G, 1.0, (char *)ws, s)) != hipSuccess) return hip_err(e);
+    if ((e = launch_hc_b(b, bd, 0.5, s)) != hipSuccess) return hip_err(e);
+    if ((r = kick_batched(b, bt, p, 0.5, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2)))
+        return r;
+    if (p->flags & GENGA_FLAG_NOSYNC) return GENGA_OK;
+    return genga_read_status(ws, stream);
+}
+
+}  // extern "C"

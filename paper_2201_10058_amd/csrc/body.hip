@@ -99,6 +99,119 @@ __global__ __launch_bounds__(RB) void k_drift(double *x, double *y, double *z, d
 }
 
 // ---------------------------------------------------------------------------
+// Batched systems: body i belongs to system sysid[i]; per-system m_star, dt,
+// n1, n2 arrays.  hfac scales each system's dt (0.5 for a half step).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RB) void k_rcrit_b(const double *x, const double *y, const double *z,
+                                                const double *vx, const double *vy,
+                                                const double *vz, const double *m, double *rc,
+                                                int64_t n, const int32_t *sysid,
+                                                const double *m_star, const double *dt,
+                                                const double *n1, const double *n2,
+                                                int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    const int s = sysid[i];
+    const double r = __builtin_sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+    const double v = __builtin_sqrt(vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    const double rh = r * cbrt(m[i] / (3.0 * m_star[s]));
+    const double a = n1[s] * rh;
+    const double b = n2[s] * fabs(dt[s]) * v;
+    const double out = a > b ? a : b;
+    if (!(out >= 0.0 && out < INFINITY)) atomicOr(status, ST_RCRIT);
+    rc[i] = out;
+}
+
+// P_s = sum over the bodies of system s of m v; one block per system, fixed order.
+__global__ __launch_bounds__(RB) void k_momentum_sys(const double *vx, const double *vy,
+                                                     const double *vz, const double *m,
+                                                     const int64_t *offsets, double *P)
+{
+    __shared__ double sm[3][RB];
+    const int t = threadIdx.x;
+    const int64_t b = offsets[blockIdx.x], e = offsets[blockIdx.x + 1];
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    for (int64_t i = b + t; i < e; i += RB) {
+        p0 += m[i] * vx[i];
+        p1 += m[i] * vy[i];
+        p2 += m[i] * vz[i];
+    }
+    sm[0][t] = p0;
+    sm[1][t] = p1;
+    sm[2][t] = p2;
+    __syncthreads();
+    for (int h = RB / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sm[0][t] += sm[0][t + h];
+            sm[1][t] += sm[1][t + h];
+            sm[2][t] += sm[2][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 3) P[(size_t)blockIdx.x * 3 + t] = sm[t][0];
+}
+
+__global__ __launch_bounds__(RB) void k_hc_apply_b(double *x, double *y, double *z, int64_t n,
+                                                   const int32_t *sysid, const double *P,
+                                                   const double *m_star, const double *dt,
+                                                   double hfac)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    const int s = sysid[i];
+    const double h = hfac * dt[s];
+    x[i] += (h * P[(size_t)s * 3 + 0]) / m_star[s];
+    y[i] += (h * P[(size_t)s * 3 + 1]) / m_star[s];
+    z[i] += (h * P[(size_t)s * 3 + 2]) / m_star[s];
+}
+
+__global__ __launch_bounds__(RB) void k_drift_b(double *x, double *y, double *z, double *vx,
+                                                double *vy, double *vz, int64_t n,
+                                                const int32_t *sysid, double G,
+                                                const double *m_star, const double *dt,
+                                                double hfac, int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    const int s = sysid[i];
+    double X = x[i], Y = y[i], Z = z[i], VX = vx[i], VY = vy[i], VZ = vz[i];
+    const int st = kepler_uv(G * m_star[s], hfac * dt[s], X, Y, Z, VX, VY, VZ);
+    if (st) atomicOr(status, st);
+    x[i] = X; y[i] = Y; z[i] = Z;
+    vx[i] = VX; vy[i] = VY; vz[i] = VZ;
+}
+
+hipError_t launch_rcrit_b(const genga_bodies *b, const BatchDev &bd, char *ws, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((b->n + RB - 1) / RB);
+    hipLaunchKernelGGL(k_rcrit_b, dim3(nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx, b->vy, b->vz,
+                       b->m, b->rc, b->n, bd.sysid, bd.m_star, bd.dt, bd.n1, bd.n2, (int32_t *)ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_hc_b(genga_bodies *b, const BatchDev &bd, double hfac, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_momentum_sys, dim3((unsigned)bd.S), dim3(RB), 0, s, b->vx, b->vy, b->vz,
+                       b->m, bd.offsets, bd.P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((b->n + RB - 1) / RB);
+    hipLaunchKernelGGL(k_hc_apply_b, dim3(nb), dim3(RB), 0, s, b->x, b->y, b->z, b->n, bd.sysid,
+                       bd.P, bd.m_star, bd.dt, hfac);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift_b(genga_bodies *b, const BatchDev &bd, double G, double hfac, char *ws,
+                          hipStream_t s)
+{
+    const unsigned nb = (unsigned)((b->n + RB - 1) / RB);
+    hipLaunchKernelGGL(k_drift_b, dim3(nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx, b->vy, b->vz,
+                       b->n, bd.sysid, G, bd.m_star, bd.dt, hfac, (int32_t *)ws);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 hipError_t launch_clear_status(char *ws, hipStream_t s)
 {
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, (int32_t *)ws);

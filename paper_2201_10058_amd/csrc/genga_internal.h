@@ -22,46 +22,70 @@ constexpr int TILE = 256;    // columns staged in LDS per pass
 constexpr int WSEG = 128;    // staged encounter pairs per kick wave
 constexpr int RB = 256;      // rows per block of the O(N) kernels
 
-// Launch shape of the kick for a system of n bodies.
+// One kick tile: rows [row0, row0 + nrows) of one system against its columns
+// [col0, col0 + ncols); `slice` numbers the column ranges of that system.
+struct TileDesc {
+    int64_t row0;
+    int32_t nrows;
+    int32_t slice;
+    int64_t col0;
+    int32_t ncols;
+    int32_t sys;
+};
+
+// Launch shape of the kick.
 struct KickCfg {
+    int nt = KB;              // threads per block (64 or 256)
     int ipt = 1;              // rows per thread
-    int slices = 1;           // column slices (grid.y)
-    int64_t slice_len = 0;    // columns per slice, a multiple of TILE
-    int gx = 0;               // row blocks (grid.x)
-    int64_t nwaves = 0;       // kick waves in one launch
+    int slices = 1;           // column slices (single system: grid.y; batch: max per system)
+    int64_t slice_len = 0;    // single system: columns per slice, a multiple of TILE
+    int gx = 0;               // single system: row blocks (grid.x)
+    int64_t ntiles = 0;       // tiles in one launch
+    int64_t nwaves = 0;       // kick waves in one launch (ntiles * nt / 64)
+    int grid = 0;             // batch: persistent blocks
 };
 
 // Byte offsets of the workspace regions.
 struct Layout {
-    size_t status = 0;   // int32 status word (+ padding)
-    size_t part = 0;     // double [slices][3][npad]  partial accelerations
-    size_t cnt = 0;      // int32  [slices][npad]     per-slice pair counts
-    size_t rowloc = 0;   // int32  [npad]             row offset inside its 256-row block
-    size_t bsum = 0;     // int64  [nb + 1]           per-block pair counts / offsets
-    size_t stage = 0;    // int32  [nwaves][WSEG][3]  staged (i, j, rank)
-    size_t wcount = 0;   // int32  [nwaves]           staged pairs per wave
-    size_t hc = 0;       // double [nb][3]            momentum partials
+    size_t status = 0;     // int32 status word (+ padding)
+    size_t part = 0;       // double [slices][3][npad]  partial accelerations
+    size_t cnt = 0;        // int32  [slices][npad]     per-slice pair counts
+    size_t rowloc = 0;     // int32  [npad]             row offset inside its 256-row block
+    size_t bsum = 0;       // int64  [nb + 1]           per-block pair counts / offsets
+    size_t stage = 0;      // int32  [nwaves][WSEG][3]  staged (i, j, rank)
+    size_t wcount = 0;     // int32  [nwaves]           staged pairs per wave
+    size_t hc = 0;         // double [nb][3]            momentum partials
+    size_t P = 0;          // batch: double [S][3]      momentum per system
+    size_t tiles = 0;      // batch: TileDesc [ntiles]
+    size_t sysid = 0;      // batch: int32 [npad]
+    size_t sys_slices = 0; // batch: int32 [S]
+    size_t offsets = 0;    // batch: int64 [S + 1]
     size_t total = 0;
     int64_t npad = 0;
     int64_t nb = 0;
 };
 
 KickCfg choose_kick_cfg(int64_t n, const genga_params *p);
-Layout make_layout(int64_t n, const KickCfg &c);
+Layout make_layout(int64_t n, const KickCfg &c, int64_t S = 0);
 
 void set_hip_error(hipError_t e);
 
 // Kernel launchers (return hipError_t of the launch).
 struct KickLaunch {
     const double *x, *y, *z, *m, *rc;
-    double *vx, *vy, *vz;      // updated when h != 0
+    double *vx, *vy, *vz;      // updated when the step factor is non-zero
     double *ax, *ay, *az;      // optional outputs
     int64_t n;
-    double G, h;
+    double G, h;               // single system: v += h a
+    double hfac;               // batch: v += hfac * dt_s * a
     int precision;
     bool forces;               // false: encounter list only
     genga_pairs *pairs;        // optional
     void *ev0, *ev1;           // optional timing events around the main kernel
+    const TileDesc *tiles;     // batch: device tile list (else null)
+    const int32_t *sysid;      // batch: system of each body
+    const int32_t *sys_slices; // batch: column slices per system
+    const double *sys_dt;      // batch: time step per system
 };
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
                        hipStream_t s);
@@ -71,5 +95,21 @@ hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, 
                      hipStream_t s);
 hipError_t launch_drift(genga_bodies *b, double mu, double dt, char *ws, hipStream_t s);
 hipError_t launch_clear_status(char *ws, hipStream_t s);
+
+// Device view of a planned batch (pointers into the caller's arrays and the
+// workspace).
+struct BatchDev {
+    int64_t S;
+    const int64_t *offsets;     // device, S + 1 (workspace copy)
+    const int32_t *sysid;       // device, per body
+    const int32_t *sys_slices;  // device, per system
+    const TileDesc *tiles;      // device tile list
+    const double *m_star, *dt, *n1, *n2;  // caller's device arrays
+    double *P;                  // workspace: momentum per system (S x 3)
+};
+hipError_t launch_rcrit_b(const genga_bodies *b, const BatchDev &bd, char *ws, hipStream_t s);
+hipError_t launch_hc_b(genga_bodies *b, const BatchDev &bd, double hfac, hipStream_t s);
+hipError_t launch_drift_b(genga_bodies *b, const BatchDev &bd, double G, double hfac, char *ws,
+                          hipStream_t s);
 
 }  // namespace genga

@@ -7,15 +7,20 @@
 // for exact reproducibility).
 //
 // Design for gfx950 (wave64, 256 CUs):
-//  * k_kick: grid (row blocks, column slices).  Each block stages TILE
-//    columns (x, y, z, m, rc^2) of its slice in LDS; every lane owns IPT rows
-//    and streams the tile with broadcast LDS reads.  Per interaction the fast
-//    path is 3 sub, 3 mul/fma for r^2, v_rsq_f64 with a third-order correction
-//    folded into m r^-3, 3 fma accumulations and two compares.  Pairs inside
-//    the pair critical radius (and the self pair) take a divergent slow path
-//    that evaluates K, records encounter pairs and detects coincident bodies.
-//  * Partial sums per slice go to the workspace; k_kick_reduce adds them in a
-//    fixed order (no atomics), applies v += h a and prepares the pair offsets.
+//  * The work is cut into tiles: a block of rows of one system against a
+//    range of its columns.  A single system uses an implicit 2-D grid of tiles
+//    (row blocks x column slices); a batch of systems uses a host-built,
+//    cost-sorted tile list walked by a persistent grid.
+//  * Each block stages TILE columns (x, y, z, m, rc^2) in LDS; every lane
+//    owns IPT rows and streams the tile with broadcast LDS reads.  Per
+//    interaction the FP64 fast path is 3 sub, 3 mul/fma for r^2, v_rsq_f64
+//    with a correction folded into m r^-3, 3 fma accumulations and one
+//    compare against max(rc_i^2, rc_j^2).  Pairs inside the pair critical
+//    radius (and the self pair) take a divergent slow path that evaluates K,
+//    records encounter pairs and detects coincident bodies.
+//  * Partial sums per column slice go to the workspace; k_kick_reduce adds
+//    them in slice order (no atomics), applies v += h a and prepares the pair
+//    offsets.
 //  * Pair emission is atomic-free: each wave appends its pairs to a private
 //    staging segment with a ballot + mbcnt prefix; each pair carries its rank
 //    within its (row, slice).  k_scan_blocks and k_pairs_scatter turn counts
@@ -27,17 +32,21 @@ namespace genga {
 
 struct KickDev {
     const double *x, *y, *z, *m, *rc;
-    int64_t n;
+    int64_t n;            // bodies (all systems)
     int64_t npad;
-    int64_t slice_len;
-    double *part;      // [slices][3][npad]
-    int32_t *cnt;      // [slices][npad]
-    int32_t *stage;    // [nwaves][WSEG][3]
-    int32_t *wcount;   // [nwaves]
+    // tiles: explicit list (batched) or implicit (single system)
+    const TileDesc *tiles;
+    int64_t ntiles;
+    int gx;               // implicit: row blocks
+    int64_t slice_len;    // implicit: columns per slice
+    double *part;         // [slices][3][npad]
+    int32_t *cnt;         // [slices][npad]
+    int32_t *stage;       // [nwaves][WSEG][3]
+    int32_t *wcount;      // [nwaves]
     int32_t *status;
     int emit;
-    double c15, c1875;   // 3/2 and 15/8
-    double widen;        // mixed: squared widening of the binary32 pre-check radius
+    double c15, c1875;    // 3/2 and 15/8
+    double widen;         // mixed: squared widening of the binary32 pre-check radius
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt()
@@ -65,6 +74,35 @@ __device__ __forceinline__ double vmax_f64(double a, double b)
     return r;
 }
 
+__device__ __forceinline__ float vmax_f32(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// binary32 mass and pre-check radius packed in the fourth double of a tile entry
+__device__ __forceinline__ double pack_f32x2(float lo, float hi)
+{
+    return __hiloint2double(__float_as_int(hi), __float_as_int(lo));
+}
+
+// Tile t: from the list, or from the implicit (row block, slice) grid.
+template <int NT, int IPT>
+__device__ __forceinline__ TileDesc get_tile(const KickDev &a, int64_t t)
+{
+    if (a.tiles) return a.tiles[t];
+    TileDesc d;
+    const int64_t bx = t % a.gx, by = t / a.gx;
+    d.row0 = bx * (int64_t)(NT * IPT);
+    d.nrows = (int32_t)min((int64_t)(NT * IPT), a.n - d.row0);
+    d.slice = (int32_t)by;
+    d.col0 = by * a.slice_len;
+    d.ncols = (int32_t)min(a.slice_len, a.n - d.col0);
+    d.sys = 0;
+    return d;
+}
+
 // Kick variants sharing one kernel body.
 enum KickMode : int {
     KM_F64 = 0,    // binary64 pair arithmetic
@@ -77,7 +115,7 @@ template <int IPT>
 struct Rows {
     double xi[IPT], yi[IPT], zi[IPT], rc2i[IPT];
     double ax[IPT], ay[IPT], az[IPT];
-    float rc2fi[IPT];            // mixed: widened binary32 pre-check radius
+    float rc2fi[IPT];                    // mixed: widened binary32 pre-check radius
     float axf[IPT], ayf[IPT], azf[IPT];  // mixed: binary32 partial sums
     int64_t ii[IPT];
     int kc[IPT];
@@ -133,18 +171,13 @@ __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int 
     return wk;
 }
 
-__device__ __forceinline__ float vmax_f32(float a, float b)
-{
-    float r;
-    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-
-// binary32 mass and pre-check radius packed in the fourth double of a tile entry
-__device__ __forceinline__ double pack_f32x2(float lo, float hi)
-{
-    return __hiloint2double(__float_as_int(hi), __float_as_int(lo));
-}
+// Mixed mode: pairs closer than MIXED_NEAR rho_ij are summed in binary64.  The
+// largest binary32 terms are those of near neighbours; moving pairs inside
+// 3 rho to binary64 keeps the per-acceleration error of the 0.5-4 AU disks
+// below 1e-6 even for bodies whose net acceleration is 50-90 times smaller
+// than the sum of the magnitudes of its terms.
+constexpr double MIXED_NEAR = 3.0;
+constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
 
 // One column j against the lane's rows (the hot loop body).
 //   b = (x_j, y_j, z_j, m_j) for KM_F64 / KM_PAIRS, (x_j, y_j, z_j, {m_j, rc2f_j}) for KM_MIXED.
@@ -176,10 +209,10 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
                 sc = 0.0f;
                 const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
                 const double mj = *mj64;
-                const double rc2j = *rc2j64;
+                const double rc2j_ = *rc2j64;
                 double wk;
-                if (r2 <= vmax_f64(R.rc2i[q], rc2j)) {
-                    wk = slow_pair<IPT, true>(a, R, q, jg, r2, rc2j, mj, wave_g, wcnt);
+                if (r2 <= vmax_f64(R.rc2i[q], rc2j_)) {
+                    wk = slow_pair<IPT, true>(a, R, q, jg, r2, rc2j_, mj, wave_g, wcnt);
                 } else {
                     const double y = __builtin_amdgcn_rsq(r2);
                     const double yy = y * y;
@@ -244,45 +277,44 @@ __device__ __forceinline__ void fold(Rows<IPT> &R)
     }
 }
 
-constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
-// Mixed mode: pairs closer than MIXED_NEAR rho_ij are summed in binary64.  The
-// largest binary32 terms are those of near neighbours; moving pairs inside
-// 3 rho to binary64 keeps the per-acceleration error of the 0.5-4 AU disks
-// below 1e-6 even for bodies whose net acceleration is 50-90 times smaller
-// than the sum of the magnitudes of its terms.
-constexpr double MIXED_NEAR = 3.0;
+// Shared-memory tile of one block.
+struct KickSmem {
+    double4 xyzm[TILE];
+    double rc2[TILE];
+    double m[TILE];
+    int wcnt[4];
+};
 
-template <int IPT, int MODE>
-__global__ __launch_bounds__(KB) void k_kick(KickDev a)
+// All rows of tile `td` against its columns; writes the slice partials, the
+// per-row pair counts and the wave's staging count.
+template <int NT, int IPT, int MODE>
+__device__ __forceinline__ void process_tile(const KickDev &a, KickSmem &sm, const TileDesc &td,
+                                             int64_t tile_index)
 {
-    __shared__ double4 s_xyzm[TILE];
-    __shared__ double s_rc2[TILE];
-    __shared__ double s_m[MODE == KM_MIXED ? TILE : 1];
-    __shared__ int s_wcnt[KB / 64];
-
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
-    const int64_t rowbase = (int64_t)blockIdx.x * (KB * IPT) + (int64_t)w * (64 * IPT);
-    const int s = blockIdx.y;
-    const int64_t j0 = (int64_t)s * a.slice_len;
-    const int64_t j1 = min(a.n, j0 + a.slice_len);
-    const int64_t wave_g = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (KB / 64) + w;
+    const int64_t rowend = td.row0 + td.nrows;
+    const int64_t rowbase = td.row0 + (int64_t)w * (64 * IPT);
+    const int s = td.slice;
+    const int64_t j0 = td.col0;
+    const int64_t j1 = td.col0 + td.ncols;
+    const int64_t wave_g = tile_index * (NT / 64) + w;
     // An opaque zero (mbcnt of an empty mask) marks values as per-lane, so the
     // compiler keeps the polynomial constants (not inline constants on gfx9)
     // and the LDS tile address in VGPRs instead of re-materialising them in
     // the hot loop.
     const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
     const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
-    const double4 *t_xyzm = s_xyzm + vzero;
-    const double *t_rc2 = s_rc2 + vzero;
-    const double *t_m = s_m + vzero;
+    const double4 *t_xyzm = sm.xyzm + vzero;
+    const double *t_rc2 = sm.rc2 + vzero;
+    const double *t_m = sm.m + vzero;
 
     Rows<IPT> R;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         R.ii[q] = rowbase + q * 64 + lane;
-        if (R.ii[q] < a.n) {
+        if (R.ii[q] < rowend) {
             R.xi[q] = a.x[R.ii[q]];
             R.yi[q] = a.y[R.ii[q]];
             R.zi[q] = a.z[R.ii[q]];
@@ -298,12 +330,12 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
         R.axf[q] = R.ayf[q] = R.azf[q] = 0.0f;
         R.kc[q] = 0;
     }
-    if (lane == 0) s_wcnt[w] = 0;
-    volatile int *wcnt = &s_wcnt[w];
+    if (lane == 0) sm.wcnt[w] = 0;
+    volatile int *wcnt = &sm.wcnt[w];
 
     for (int64_t t0 = j0; t0 < j1; t0 += TILE) {
         __syncthreads();
-        for (int q = tid; q < TILE; q += KB) {
+        for (int q = tid; q < TILE; q += NT) {
             const int64_t jg = t0 + q;
             if (jg < j1) {
                 const double rcj = a.rc[jg];
@@ -311,12 +343,12 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
                 const double mj = a.m[jg];
                 if (MODE == KM_MIXED) {
                     const float rc2f = (float)(rcj * rcj * a.widen);
-                    s_xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], pack_f32x2((float)mj, rc2f));
-                    s_m[q] = mj;
+                    sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], pack_f32x2((float)mj, rc2f));
+                    sm.m[q] = mj;
                 } else {
-                    s_xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], mj);
+                    sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], mj);
                 }
-                s_rc2[q] = rcj * rcj;
+                sm.rc2[q] = rcj * rcj;
             }
         }
         __syncthreads();
@@ -342,7 +374,7 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
 
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        if (R.ii[q] < a.n) {
+        if (R.ii[q] < rowend) {
             if (MODE != KM_PAIRS) {
                 a.part[((size_t)s * 3 + 0) * a.npad + R.ii[q]] = R.ax[q];
                 a.part[((size_t)s * 3 + 1) * a.npad + R.ii[q]] = R.ay[q];
@@ -354,8 +386,29 @@ __global__ __launch_bounds__(KB) void k_kick(KickDev a)
     if (a.emit && lane == 0) a.wcount[wave_g] = *wcnt;
 }
 
+// One tile per block (single system: grid = row blocks x column slices).
+template <int NT, int IPT, int MODE>
+__global__ __launch_bounds__(NT) void k_kick(KickDev a)
+{
+    __shared__ KickSmem sm;
+    const int64_t t = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    process_tile<NT, IPT, MODE>(a, sm, get_tile<NT, IPT>(a, t), t);
+}
+
+// Persistent grid over a tile list (batched systems): block b takes tiles
+// b, b + G, b + 2G, ... of the cost-sorted list.
+template <int NT, int IPT, int MODE>
+__global__ __launch_bounds__(NT) void k_kick_persistent(KickDev a)
+{
+    __shared__ KickSmem sm;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        process_tile<NT, IPT, MODE>(a, sm, a.tiles[t], t);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan of one int64 per thread (RB threads).
+// Block-wide exclusive scan of one int64 per thread.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t wave_incl_scan(int64_t v)
 {
@@ -397,8 +450,11 @@ struct ReduceDev {
     double *ax, *ay, *az;
     int32_t *status;
     int64_t n, npad;
-    int slices;
-    double G, h;
+    int slices;                   // single system
+    const int32_t *sysid;         // batched: system of each body (else null)
+    const int32_t *sys_slices;    // batched: column slices per system
+    const double *sys_dt;         // batched: time step per system
+    double G, h, hfac;            // v += h a (single) or hfac * dt_s * a (batched)
     int forces, emit;
 };
 
@@ -407,20 +463,27 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     __shared__ int64_t sm[RB / 64];
     const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
     const bool valid = i < r.n;
+    int nsl = r.slices;
+    double h = r.h;
+    if (valid && r.sysid) {
+        const int sy = r.sysid[i];
+        nsl = r.sys_slices[sy];
+        h = r.hfac * r.sys_dt[sy];
+    }
     if (r.forces && valid) {
         double a3[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double acc = 0.0;
-            for (int s = 0; s < r.slices; ++s) acc += r.part[((size_t)s * 3 + c) * r.npad + i];
+            for (int s = 0; s < nsl; ++s) acc += r.part[((size_t)s * 3 + c) * r.npad + i];
             a3[c] = r.G * acc;
         }
         if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
             atomicOr(r.status, ST_NONFINITE);
-        if (r.h != 0.0) {
-            r.vx[i] = __builtin_fma(r.h, a3[0], r.vx[i]);
-            r.vy[i] = __builtin_fma(r.h, a3[1], r.vy[i]);
-            r.vz[i] = __builtin_fma(r.h, a3[2], r.vz[i]);
+        if (h != 0.0) {
+            r.vx[i] = __builtin_fma(h, a3[0], r.vx[i]);
+            r.vy[i] = __builtin_fma(h, a3[1], r.vy[i]);
+            r.vz[i] = __builtin_fma(h, a3[2], r.vz[i]);
         }
         if (r.ax) {
             r.ax[i] = a3[0];
@@ -431,7 +494,7 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     if (r.emit) {
         int64_t c = 0;
         if (valid) {
-            for (int s = 0; s < r.slices; ++s) {
+            for (int s = 0; s < nsl; ++s) {
                 const int32_t t = r.cnt[(size_t)s * r.npad + i];
                 r.cnt[(size_t)s * r.npad + i] = (int32_t)c;
                 c += t;
@@ -466,28 +529,29 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *bsum, int64_t nb,
 
 // Place staged pairs at their canonical positions; recompute overflowed waves.
 struct ScatterDev {
-    const double *x, *y, *z, *rc;
-    const int32_t *stage, *wcount, *cnt, *rowloc;
+    KickDev k;                      // tiles of the kick that staged the pairs
+    const int32_t *rowloc;
     const int64_t *boff;
     int32_t *pi, *pj;
-    int64_t capacity, n, npad, slice_len;
-    int gx, ipt;
+    int64_t capacity;
+    int nt, ipt;                    // kick block size and rows per thread
 };
 
-__global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
+template <int NT, int IPT>
+__device__ void scatter_wave(const ScatterDev &d, int64_t wave_g)
 {
-    const int64_t wave_g = blockIdx.x;
     const int lane = threadIdx.x;
-    const int64_t blk = wave_g / (KB / 64);
-    const int w = (int)(wave_g % (KB / 64));
-    const int bx = (int)(blk % d.gx);
-    const int s = (int)(blk / d.gx);
-    const int nst = d.wcount[wave_g];
+    const KickDev &a = d.k;
+    const int64_t t = wave_g / (NT / 64);
+    const int w = (int)(wave_g % (NT / 64));
+    const TileDesc td = get_tile<NT, IPT>(a, t);
+    const int s = td.slice;
+    const int nst = a.wcount[wave_g];
     if (nst <= WSEG) {
         for (int e = lane; e < nst; e += 64) {
-            const int32_t *e3 = d.stage + ((size_t)wave_g * WSEG + e) * 3;
+            const int32_t *e3 = a.stage + ((size_t)wave_g * WSEG + e) * 3;
             const int64_t i = e3[0];
-            const int64_t pos = d.boff[i / RB] + d.rowloc[i] + d.cnt[(size_t)s * d.npad + i] + e3[2];
+            const int64_t pos = d.boff[i / RB] + d.rowloc[i] + a.cnt[(size_t)s * a.npad + i] + e3[2];
             if (pos < d.capacity) {
                 d.pi[pos] = e3[0];
                 d.pj[pos] = e3[1];
@@ -495,21 +559,22 @@ __global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
         }
         return;
     }
-    // staging overflowed: rebuild this wave's rows over its column slice
-    const int64_t rowbase = (int64_t)bx * (KB * d.ipt) + (int64_t)w * (64 * d.ipt);
-    const int64_t j0 = (int64_t)s * d.slice_len;
-    const int64_t j1 = min(d.n, j0 + d.slice_len);
-    for (int q = 0; q < d.ipt; ++q) {
+    // staging overflowed: rebuild this wave's rows over its column range
+    const int64_t rowend = td.row0 + td.nrows;
+    const int64_t rowbase = td.row0 + (int64_t)w * (64 * IPT);
+    const int64_t j0 = td.col0;
+    const int64_t j1 = td.col0 + td.ncols;
+    for (int q = 0; q < IPT; ++q) {
         const int64_t i = rowbase + q * 64 + lane;
-        if (i >= d.n) continue;
-        int64_t pos = d.boff[i / RB] + d.rowloc[i] + d.cnt[(size_t)s * d.npad + i];
-        const double xi = d.x[i], yi = d.y[i], zi = d.z[i];
-        const double rci = d.rc[i];
+        if (i >= rowend) continue;
+        int64_t pos = d.boff[i / RB] + d.rowloc[i] + a.cnt[(size_t)s * a.npad + i];
+        const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+        const double rci = a.rc[i];
         const double rc2i = rci * rci;
         for (int64_t j = (j0 > i + 1 ? j0 : i + 1); j < j1; ++j) {
-            const double dx = d.x[j] - xi, dy = d.y[j] - yi, dz = d.z[j] - zi;
+            const double dx = a.x[j] - xi, dy = a.y[j] - yi, dz = a.z[j] - zi;
             const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-            const double rcj = d.rc[j];
+            const double rcj = a.rc[j];
             const double rc2j = rcj * rcj;
             const double rho2 = rc2i > rc2j ? rc2i : rc2j;
             if (r2 < rho2) {
@@ -523,6 +588,18 @@ __global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
     }
 }
 
+__global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
+{
+    const int64_t wave_g = blockIdx.x;
+    if (d.nt == 64) {
+        if (d.ipt == 2) scatter_wave<64, 2>(d, wave_g);
+        else scatter_wave<64, 1>(d, wave_g);
+    } else {
+        if (d.ipt == 2) scatter_wave<KB, 2>(d, wave_g);
+        else scatter_wave<KB, 1>(d, wave_g);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -531,15 +608,16 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
     KickCfg c;
     c.ipt = (p && p->ipt > 0) ? p->ipt : 1;
     if (c.ipt != 1 && c.ipt != 2) c.ipt = 1;
-    const int64_t rows_per_block = (int64_t)KB * c.ipt;
+    c.nt = KB;
+    const int64_t rows_per_block = (int64_t)c.nt * c.ipt;
     c.gx = (int)((n + rows_per_block - 1) / rows_per_block);
     int64_t tiles = (n + TILE - 1) / TILE;
     int slices;
     if (p && p->slices > 0) {
         slices = p->slices;
     } else {
-        // aim for about 2048 blocks (8 per CU) so that j-slices hide latency
-        slices = (int)((2048 + c.gx - 1) / c.gx);
+        // about 8192 blocks (32 per CU) so that column slices hide latency
+        slices = (int)((8192 + c.gx - 1) / c.gx);
         if (slices > 64) slices = 64;
     }
     if (slices < 1) slices = 1;
@@ -547,13 +625,14 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
     const int64_t tiles_per_slice = (tiles + slices - 1) / slices;
     c.slice_len = tiles_per_slice * TILE;
     c.slices = (int)((n + c.slice_len - 1) / c.slice_len);
-    c.nwaves = (int64_t)c.gx * c.slices * (KB / 64);
+    c.ntiles = (int64_t)c.gx * c.slices;
+    c.nwaves = c.ntiles * (c.nt / 64);
     return c;
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Layout make_layout(int64_t n, const KickCfg &c)
+Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
 {
     Layout L;
     L.npad = ((n + RB - 1) / RB) * RB;
@@ -575,22 +654,37 @@ Layout make_layout(int64_t n, const KickCfg &c)
     off = align256(off + sizeof(int32_t) * (size_t)c.nwaves);
     L.hc = off;
     off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
+    if (S > 0) {
+        L.P = off;
+        off = align256(off + sizeof(double) * 3 * (size_t)S);
+        L.tiles = off;
+        off = align256(off + sizeof(TileDesc) * (size_t)c.ntiles);
+        L.sysid = off;
+        off = align256(off + sizeof(int32_t) * (size_t)L.npad);
+        L.sys_slices = off;
+        off = align256(off + sizeof(int32_t) * (size_t)S);
+        L.offsets = off;
+        off = align256(off + sizeof(int64_t) * (size_t)(S + 1));
+    }
     L.total = off;
     return L;
 }
 
-template <int IPT, int MODE>
+template <int NT, int IPT, int MODE>
 static void launch_k(const KickDev &d, const KickCfg &c, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_kick<IPT, MODE>), dim3(c.gx, c.slices), dim3(KB), 0, s, d);
+    if (d.tiles)
+        hipLaunchKernelGGL((k_kick_persistent<NT, IPT, MODE>), dim3(c.grid), dim3(NT), 0, s, d);
+    else
+        hipLaunchKernelGGL((k_kick<NT, IPT, MODE>), dim3(c.gx, c.slices), dim3(NT), 0, s, d);
 }
 
-template <int IPT>
+template <int NT, int IPT>
 static void launch_mode(const KickDev &d, const KickCfg &c, int mode, hipStream_t s)
 {
-    if (mode == KM_MIXED) launch_k<IPT, KM_MIXED>(d, c, s);
-    else if (mode == KM_PAIRS) launch_k<IPT, KM_PAIRS>(d, c, s);
-    else launch_k<IPT, KM_F64>(d, c, s);
+    if (mode == KM_MIXED) launch_k<NT, IPT, KM_MIXED>(d, c, s);
+    else if (mode == KM_PAIRS) launch_k<NT, IPT, KM_PAIRS>(d, c, s);
+    else launch_k<NT, IPT, KM_F64>(d, c, s);
 }
 
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
@@ -600,6 +694,9 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     d.x = k.x; d.y = k.y; d.z = k.z; d.m = k.m; d.rc = k.rc;
     d.n = k.n;
     d.npad = L.npad;
+    d.tiles = k.tiles;
+    d.ntiles = c.ntiles;
+    d.gx = c.gx;
     d.slice_len = c.slice_len;
     d.part = (double *)(ws + L.part);
     d.cnt = (int32_t *)(ws + L.cnt);
@@ -620,8 +717,13 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
         if (e != hipSuccess) return e;
     }
     const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
-    if (c.ipt == 2) launch_mode<2>(d, c, mode, s);
-    else launch_mode<1>(d, c, mode, s);
+    if (c.nt == 64) {
+        if (c.ipt == 2) launch_mode<64, 2>(d, c, mode, s);
+        else launch_mode<64, 1>(d, c, mode, s);
+    } else {
+        if (c.ipt == 2) launch_mode<KB, 2>(d, c, mode, s);
+        else launch_mode<KB, 1>(d, c, mode, s);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (k.ev1) {
@@ -637,7 +739,10 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.ax = k.ax; r.ay = k.ay; r.az = k.az;
     r.status = d.status;
     r.n = k.n; r.npad = L.npad; r.slices = c.slices;
-    r.G = k.G; r.h = k.h;
+    r.sysid = k.sysid;
+    r.sys_slices = k.sys_slices;
+    r.sys_dt = k.sys_dt;
+    r.G = k.G; r.h = k.h; r.hfac = k.hfac;
     r.forces = k.forces;
     r.emit = d.emit;
     if (r.forces || r.emit) {
@@ -653,13 +758,13 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     if (e != hipSuccess) return e;
 
     ScatterDev sd;
-    sd.x = k.x; sd.y = k.y; sd.z = k.z; sd.rc = k.rc;
-    sd.stage = d.stage; sd.wcount = d.wcount; sd.cnt = d.cnt; sd.rowloc = r.rowloc;
+    sd.k = d;
+    sd.rowloc = r.rowloc;
     sd.boff = r.bsum;
     sd.pi = k.pairs->i; sd.pj = k.pairs->j;
     sd.capacity = k.pairs->capacity;
-    sd.n = k.n; sd.npad = L.npad; sd.slice_len = c.slice_len;
-    sd.gx = c.gx; sd.ipt = c.ipt;
+    sd.nt = c.nt;
+    sd.ipt = c.ipt;
     hipLaunchKernelGGL(k_pairs_scatter, dim3((unsigned)c.nwaves), dim3(64), 0, s, sd);
     return hipGetLastError();
 }

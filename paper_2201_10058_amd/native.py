@@ -41,7 +41,13 @@ class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("m_star", ctypes.c_double), ("dt", ctypes.c_double),
                 ("n1", ctypes.c_double), ("n2", ctypes.c_double), ("precision", ctypes.c_int),
                 ("flags", ctypes.c_int), ("ipt", ctypes.c_int), ("slices", ctypes.c_int),
+                ("block", ctypes.c_int), ("tile_cols", ctypes.c_int), ("grid", ctypes.c_int),
                 ("prof_events", ctypes.c_void_p * 4)]
+
+
+class BatchC(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int64), ("offsets", ctypes.c_void_p), ("m_star", ctypes.c_void_p),
+                ("dt", ctypes.c_void_p), ("n1", ctypes.c_void_p), ("n2", ctypes.c_void_p)]
 
 
 class Pairs(ctypes.Structure):
@@ -71,6 +77,18 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "genga_step": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
                                   ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(BatchC), ctypes.POINTER(Params)]),
+    "genga_batch_plan": (ctypes.c_int, [ctypes.POINTER(BatchC), ctypes.POINTER(Params),
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_batch_info": (ctypes.c_int, [ctypes.POINTER(BatchC), ctypes.POINTER(Params),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "genga_kick_batched": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(BatchC),
+                                          ctypes.POINTER(Params), ctypes.c_double, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Pairs),
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_step_batched": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(BatchC),
+                                          ctypes.POINTER(Params), ctypes.POINTER(Pairs),
+                                          ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -132,11 +150,14 @@ class Config:
     flags: int = 0
     ipt: int = 0
     slices: int = 0
+    block: int = 0
+    tile_cols: int = 0
+    grid: int = 0
     events: tuple = field(default=(None, None, None, None))
 
     def params(self) -> Params:
         p = Params(self.G, self.m_star, self.dt, self.n1, self.n2, self.precision, self.flags,
-                   self.ipt, self.slices)
+                   self.ipt, self.slices, self.block, self.tile_cols, self.grid)
         for k, e in enumerate(tuple(self.events)[:4]):
             p.prof_events[k] = e
         return p
@@ -268,3 +289,85 @@ def step(state: State, cfg: Config, ws: Workspace, pairs: PairList | None = None
     if code in (E_INVAL, E_HIP, E_UNSUPPORTED):
         raise GengaError(code, "genga_step")
     return code
+
+
+# ---------------------------------------------------------------------------
+# Batched ensembles
+# ---------------------------------------------------------------------------
+class Batch:
+    """S systems stored back to back; per-system parameters live on the GPU."""
+
+    def __init__(self, offsets, m_star, dt, n1, n2, device="cuda:0"):
+        import numpy as np
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)   # host
+        self.S = len(self.offsets) - 1
+        self.t = {k: torch.as_tensor(np.asarray(v, dtype=np.float64)).to(device).contiguous()
+                  for k, v in (("m_star", m_star), ("dt", dt), ("n1", n1), ("n2", n2))}
+        for v in self.t.values():
+            if v.numel() != self.S:
+                raise ValueError("per-system arrays must have S entries")
+
+    def struct(self) -> BatchC:
+        return BatchC(self.S, self.offsets.ctypes.data, self.t["m_star"].data_ptr(),
+                      self.t["dt"].data_ptr(), self.t["n1"].data_ptr(), self.t["n2"].data_ptr())
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets[-1])
+
+
+class BatchWorkspace:
+    """Workspace holding a batch plan (built at construction)."""
+
+    def __init__(self, batch: Batch, cfg: Config, device="cuda:0"):
+        lib = load()
+        self.bt = batch.struct()           # keeps the host offsets referenced
+        self._batch = batch
+        p = cfg.params()
+        nbytes = lib.genga_batch_workspace_bytes(ctypes.byref(self.bt), ctypes.byref(p))
+        if nbytes == 0:
+            raise GengaError(E_INVAL, "batch workspace size")
+        self.buf = torch.zeros(int(nbytes), dtype=torch.uint8, device=device)
+        self.nbytes = int(nbytes)
+        _check(lib.genga_batch_plan(ctypes.byref(self.bt), ctypes.byref(p), ctypes.c_void_p(self.ptr),
+                                    ctypes.c_void_p(_stream_ptr())), "genga_batch_plan")
+        info = (ctypes.c_int64 * 5)()
+        _check(lib.genga_batch_info(ctypes.byref(self.bt), ctypes.byref(p), info), "genga_batch_info")
+        self.info = dict(tiles=info[0], grid=info[1], block=info[2], ipt=info[3], tile_cols=info[4])
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+
+def kick_batched(state: State, ws: BatchWorkspace, cfg: Config, hfac: float, acc: bool = False,
+                 pairs: PairList | None = None):
+    b, p = state.bodies(), cfg.params()
+    a = None
+    ptrs = (None, None, None)
+    if acc:
+        a = torch.empty((3, state.n), dtype=torch.float64, device=state.t["x"].device)
+        ptrs = (a[0].data_ptr(), a[1].data_ptr(), a[2].data_ptr())
+    ps = pairs.struct() if pairs is not None else None
+    _check(load().genga_kick_batched(ctypes.byref(b), ctypes.byref(ws.bt), ctypes.byref(p), float(hfac),
+                                     ptrs[0], ptrs[1], ptrs[2],
+                                     ctypes.byref(ps) if ps is not None else None,
+                                     ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
+           "genga_kick_batched")
+    return a
+
+
+def step_batched(state: State, ws: BatchWorkspace, cfg: Config, pairs: PairList | None = None) -> int:
+    b, p = state.bodies(), cfg.params()
+    ps = pairs.struct() if pairs is not None else None
+    code = load().genga_step_batched(ctypes.byref(b), ctypes.byref(ws.bt), ctypes.byref(p),
+                                     ctypes.byref(ps) if ps is not None else None,
+                                     ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr()))
+    if code in (E_INVAL, E_HIP, E_UNSUPPORTED):
+        raise GengaError(code, "genga_step_batched")
+    return code
+
+
+def system_view(state: State, lo: int, hi: int) -> State:
+    """State of bodies [lo, hi) (views into the same device memory)."""
+    return State({k: v[lo:hi] for k, v in state.t.items()})

@@ -71,3 +71,28 @@ def test_workspace_grows_with_n(n):
     lib = native.load()
     p = native.Config(G=2.959e-4).params()
     assert lib.genga_workspace_bytes(n, ctypes.byref(p)) >= 3 * 8 * n
+
+
+def test_batch_plan_shape_on_host():
+    import numpy as np
+    from paper_2201_10058_amd import native as N
+    lib = N.load()
+    sizes = np.array([16, 300, 4096, 1000, 257])
+    offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    dummy = ctypes.c_void_p(8)   # never dereferenced by the host-side planner
+    bt = N.BatchC(len(sizes), offsets.ctypes.data, dummy, dummy, dummy, dummy)
+    for block, ipt, cols in ((256, 1, 1024), (64, 2, 512), (64, 1, 300)):
+        p = N.Config(G=2.959e-4, block=block, ipt=ipt, tile_cols=cols).params()
+        info = (ctypes.c_int64 * 5)()
+        assert lib.genga_batch_info(ctypes.byref(bt), ctypes.byref(p), info) == N.OK
+        c = -(-cols // 256) * 256
+        r = block * ipt
+        tiles = sum(-(-n // r) * -(-n // c) for n in sizes)
+        assert info[0] == tiles and info[2] == block and info[3] == ipt and info[4] == c
+        assert lib.genga_batch_workspace_bytes(ctypes.byref(bt), ctypes.byref(p)) > 24 * sizes.sum()
+    bad = offsets.copy()
+    bad[2] = bad[1]          # an empty system is rejected
+    btb = N.BatchC(len(sizes), bad.ctypes.data, dummy, dummy, dummy, dummy)
+    p = N.Config(G=2.959e-4).params()
+    assert lib.genga_batch_workspace_bytes(ctypes.byref(btb), ctypes.byref(p)) == 0

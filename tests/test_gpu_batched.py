@@ -1,0 +1,239 @@
+"""Batched ensembles: many systems in one persistent kick launch.
+
+Bar: every system's accelerations equal the oracle run on that system alone
+(<= 1e-12 relative, FP64) and its encounter pairs are bit-exact (with global
+indices); a hipGraph replay of the batched step equals the eager step bit for
+bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2201_10058_amd import autotune
+from paper_2201_10058_amd import native as N
+from paper_2201_10058_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+G = W.GAUSS_G
+SMALL_SIZES = [16, 17, 63, 64, 65, 100, 255, 256, 257, 300, 700, 1500, 2048, 3001]
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rc_batch(d):
+    rc = np.empty(d["x"].size)
+    for s in range(d["S"]):
+        lo, hi = d["offsets"][s], d["offsets"][s + 1]
+        rc[lo:hi] = oracle.rcrit(*(d[k][lo:hi] for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                                 d["m_star"][s], d["dt"][s], d["n1"][s], d["n2"][s])
+    return rc
+
+
+def _batch(d):
+    return N.Batch(d["offsets"], d["m_star"], d["dt"], d["n1"], d["n2"])
+
+
+def _oracle_system(d, rc, s, rows=None):
+    lo, hi = d["offsets"][s], d["offsets"][s + 1]
+    sl = {k: d[k][lo:hi] for k in ("x", "y", "z", "m")}
+    ax, ay, az, st = oracle.kick_acc(sl["x"], sl["y"], sl["z"], sl["m"], rc[lo:hi], G, rows=rows)
+    assert st == 0
+    pi, pj, cnt = oracle.pairs(sl["x"], sl["y"], sl["z"], rc[lo:hi])
+    return np.stack([ax, ay, az]), pi + lo, pj + lo, cnt
+
+
+@pytest.mark.parametrize("block,ipt,cols", [(256, 1, 1024), (64, 1, 256), (64, 2, 512), (256, 2, 2048)])
+def test_batched_kick_matches_oracle(dev, block, ipt, cols):
+    d = W.make_batch(sizes=SMALL_SIZES)
+    rc = _rc_batch(d)
+    st = N.State.from_numpy(d, rc=rc)
+    bt = _batch(d)
+    cfg = N.Config(G=G, block=block, ipt=ipt, tile_cols=cols)
+    ws = N.BatchWorkspace(bt, cfg)
+    _say("plan", ws.info)
+    pl = N.PairList(200000)
+    a = N.kick_batched(st, ws, cfg, 0.0, acc=True, pairs=pl)
+    torch.cuda.synchronize()
+    assert N.read_status(ws) == N.OK
+    a = a.cpu().numpy()
+    pi, pj, cnt = pl.result()
+    all_i, all_j = [], []
+    worst = 0.0
+    for s in range(d["S"]):
+        lo, hi = d["offsets"][s], d["offsets"][s + 1]
+        ref, opi, opj, ocnt = _oracle_system(d, rc, s)
+        err = np.linalg.norm(a[:, lo:hi] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        worst = max(worst, err.max())
+        all_i.append(opi); all_j.append(opj)
+    _say("worst rel err", worst)
+    assert worst <= 1e-12
+    oi, oj = np.concatenate(all_i), np.concatenate(all_j)
+    assert cnt == len(oi) and np.array_equal(pi, oi) and np.array_equal(pj, oj)
+
+
+def test_batched_step_matches_oracle_and_single(dev):
+    d = W.make_batch(sizes=SMALL_SIZES)
+    bt = _batch(d)
+    cfg = N.Config(G=G, block=64, ipt=1, tile_cols=512)
+    st = N.State.from_numpy(d)
+    ws = N.BatchWorkspace(bt, cfg)
+    pl = N.PairList(200000)
+    x0 = {c: d[c].copy() for c in "xyz"}
+    assert N.step_batched(st, ws, cfg, pl) == N.OK
+    out = st.numpy()
+    pi, pj, cnt = pl.result()
+    rc_used = out["rc"]
+    # pairs of the first half kick: oracle on the start positions and used radii
+    all_i, all_j = [], []
+    for s in range(d["S"]):
+        lo, hi = d["offsets"][s], d["offsets"][s + 1]
+        opi, opj, _ = oracle.pairs(x0["x"][lo:hi], x0["y"][lo:hi], x0["z"][lo:hi], rc_used[lo:hi])
+        all_i.append(opi + lo); all_j.append(opj + lo)
+    oi, oj = np.concatenate(all_i), np.concatenate(all_j)
+    assert cnt == len(oi) and np.array_equal(pi, oi) and np.array_equal(pj, oj)
+    # every system against the oracle step and against a single-system call
+    st1 = N.State.from_numpy(d)
+    for s in range(d["S"]):
+        lo, hi = int(d["offsets"][s]), int(d["offsets"][s + 1])
+        ref = {k: d[k][lo:hi].copy() for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
+        oracle.step(ref, G, d["m_star"][s], d["dt"][s], d["n1"][s], d["n2"][s])
+        sv = N.system_view(st1, lo, hi)
+        c1 = N.Config(G=G, m_star=d["m_star"][s], dt=d["dt"][s], n1=d["n1"][s], n2=d["n2"][s])
+        w1 = N.Workspace(hi - lo, c1)
+        assert N.step(sv, c1, w1) == N.OK
+        single = {k: v.cpu().numpy() for k, v in sv.t.items()}
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            scale = np.max(np.abs(ref[k]))
+            assert np.max(np.abs(out[k][lo:hi] - ref[k])) <= 1e-12 * scale, (s, k)
+            assert np.max(np.abs(out[k][lo:hi] - single[k])) <= 1e-12 * scale, (s, k)
+
+
+def test_batched_graph_replay_bitwise(dev):
+    d = W.make_batch(sizes=SMALL_SIZES[:10])
+    bt = _batch(d)
+    cfg = N.Config(G=G, flags=N.FLAG_NOSYNC, block=64, tile_cols=512)
+    st_g = N.State.from_numpy(d)
+    st_e = N.State.from_numpy(d)
+    ws_g = N.BatchWorkspace(bt, cfg)
+    ws_e = N.BatchWorkspace(bt, cfg)
+    pl_g = N.PairList(100000)
+    pl_e = N.PairList(100000)
+    # warm up on a side stream before capture
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tmp = N.State.from_numpy(d)
+        N.step_batched(tmp, N.BatchWorkspace(bt, cfg), cfg, N.PairList(100000))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        N.step_batched(st_g, ws_g, cfg, pl_g)
+    torch.cuda.synchronize()
+    # capture does not execute; reset the captured state to the start
+    for k in st_g.t:
+        st_g.t[k].copy_(st_e.t[k])
+    for rep in range(5):
+        g.replay()
+        N.step_batched(st_e, ws_e, cfg, pl_e)
+        junk = torch.randn(1000, device="cuda").sum()     # unrelated eager work
+        torch.cuda.synchronize()
+        assert N.read_status(ws_g) == N.OK and N.read_status(ws_e) == N.OK
+        for k in ("x", "y", "z", "vx", "vy", "vz", "rc"):
+            assert torch.equal(st_g.t[k], st_e.t[k]), (rep, k)
+        assert int(pl_g.count.item()) == int(pl_e.count.item())
+        c = min(int(pl_e.count.item()), pl_e.capacity)
+        assert torch.equal(pl_g.i[:c], pl_e.i[:c]) and torch.equal(pl_g.j[:c], pl_e.j[:c])
+        del junk
+
+
+def test_batched_full_ensemble_sampled(dev):
+    # the 512-system ensemble (log-uniform 16..4096 bodies): sampled systems
+    d = W.make_batch()
+    rc = _rc_batch(d)
+    st = N.State.from_numpy(d, rc=rc)
+    bt = _batch(d)
+    cfg = N.Config(G=G)
+    ws = N.BatchWorkspace(bt, cfg)
+    pl = N.PairList(4_000_000)
+    a = N.kick_batched(st, ws, cfg, 0.0, acc=True, pairs=pl)
+    torch.cuda.synchronize()
+    assert N.read_status(ws) == N.OK
+    a = a.cpu().numpy()
+    pi, pj, cnt = pl.result()
+    _say("ensemble bodies", d["x"].size, "pairs", cnt, "plan", ws.info)
+    rng = np.random.default_rng(0)
+    sizes = np.diff(d["offsets"])
+    pick = list(rng.choice(d["S"], 24, replace=False)) + [int(np.argmax(sizes)), int(np.argmin(sizes))]
+    for s in pick:
+        lo, hi = d["offsets"][s], d["offsets"][s + 1]
+        ref, opi, opj, ocnt = _oracle_system(d, rc, s)
+        err = np.linalg.norm(a[:, lo:hi] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert err.max() <= 1e-12, (s, err.max())
+        sel = (pi >= lo) & (pi < hi)
+        assert np.array_equal(pi[sel], opi) and np.array_equal(pj[sel], opj)
+    # global list is sorted and stays inside systems
+    assert np.all(np.diff(pi.astype(np.int64) * (1 << 32) + pj) > 0)
+    sys_i = np.searchsorted(d["offsets"], pi, side="right") - 1
+    sys_j = np.searchsorted(d["offsets"], pj, side="right") - 1
+    assert np.array_equal(sys_i, sys_j)
+
+
+def _magnitude_sums(d):
+    """sum_j |a_ij| per body (the scale binary32 pair arithmetic is relative to)."""
+    out = np.empty(d["x"].size)
+    for s in range(d["S"]):
+        lo, hi = d["offsets"][s], d["offsets"][s + 1]
+        X = np.stack([d[k][lo:hi] for k in "xyz"])
+        m = d["m"][lo:hi]
+        for i in range(hi - lo):
+            r2 = ((X - X[:, i:i + 1]) ** 2).sum(0)
+            r2[i] = np.inf
+            out[lo + i] = G * np.sum(m / r2)
+    return out
+
+
+def test_batched_mixed_precision(dev):
+    # Small systems have bodies whose net pull nearly cancels, so the relative
+    # bar of the 16k-65k disks (1e-6) does not apply body by body; the error is
+    # bounded instead against sum_j |a_ij|, and the encounter list is exact.
+    d = W.make_batch(sizes=SMALL_SIZES)
+    rc = _rc_batch(d)
+    st = N.State.from_numpy(d, rc=rc)
+    bt = _batch(d)
+    c64 = N.Config(G=G)
+    c32 = N.Config(G=G, precision=N.MIXED)
+    w64 = N.BatchWorkspace(bt, c64)
+    w32 = N.BatchWorkspace(bt, c32)
+    p64, p32 = N.PairList(200000), N.PairList(200000)
+    a64 = N.kick_batched(st, w64, c64, 0.0, acc=True, pairs=p64).cpu().numpy()
+    a32 = N.kick_batched(st, w32, c32, 0.0, acc=True, pairs=p32).cpu().numpy()
+    diff = np.linalg.norm(a32 - a64, axis=0)
+    rel = diff / np.linalg.norm(a64, axis=0)
+    norm = diff / _magnitude_sums(d)
+    _say("batched mixed: max rel", rel.max(), "p99 rel", np.quantile(rel, 0.99),
+         "max err / sum|a_ij|", norm.max())
+    assert norm.max() <= 1e-7
+    assert np.quantile(rel, 0.99) <= 1e-6
+    r64, r32 = p64.result(), p32.result()
+    assert r64[2] == r32[2] and np.array_equal(r64[0], r32[0]) and np.array_equal(r64[1], r32[1])
+
+
+def test_autotune_batched_choice_is_valid(dev, tmp_path, monkeypatch):
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
+    d = W.make_batch(sizes=SMALL_SIZES)
+    st = N.State.from_numpy(d, rc=_rc_batch(d))
+    bt = _batch(d)
+    cfg = N.Config(G=G)
+    choice = autotune.tune_batched(st, bt, cfg, candidates=[dict(block=64, ipt=1, tile_cols=512),
+                                                          dict(block=256, ipt=1, tile_cols=1024)])
+    assert choice in (dict(block=64, ipt=1, tile_cols=512), dict(block=256, ipt=1, tile_cols=1024))
+    assert autotune.tune_batched(st, bt, cfg) == choice        # served from the cache
+    c = N.Config(G=G, **choice)
+    a = N.kick_batched(st, N.BatchWorkspace(bt, c), c, 0.0, acc=True).cpu().numpy()
+    b = N.kick_batched(st, N.BatchWorkspace(bt, cfg), cfg, 0.0, acc=True).cpu().numpy()
+    assert np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)) <= 1e-13
