@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true")
     return ap.parse_args()
 
 
@@ -176,6 +177,45 @@ def bench_batched(args, N, W, torch, np):
             "tile_shape": {**choice, "tiles": ws.info["tiles"], "grid": ws.info["grid"]}}
 
 
+def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):
+    """Adjoint: the kick VJP kernel on the 65,536-body disk, and the gradient of
+    a 200-step trajectory of the 4,096-body disk (checkpoints every 20 steps)."""
+    from paper_2201_10058_amd import adjoint as A
+    st, n = d65536_state, d65536_state.n
+    ws = N.Workspace(n, cfg65536)
+    adj = N.AdjointState(n)
+    ab = [torch.randn(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    N.kick_vjp(st, cfg65536, ws, 1.0, ab, adj)
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        N.kick_vjp(st, cfg65536, ws, 1.0, ab, adj)
+    e1.record()
+    e1.synchronize()
+    vjp_ms = e0.elapsed_time(e1) / reps
+    d = W.make_disk(W.DISK_ADJOINT)
+    X = torch.tensor(np.stack([d["x"], d["y"], d["z"]]), device="cuda", requires_grad=True)
+    V = torch.tensor(np.stack([d["vx"], d["vy"], d["vz"]]), device="cuda", requires_grad=True)
+    m = torch.tensor(d["m"], device="cuda", requires_grad=True)
+    cfg = N.Config(G=d["G"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    XT, VT = A.simulate(X, V, m, 200, cfg, checkpoint_every=20)
+    L = (XT ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    torch.autograd.grad(L, (X, V, m))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"kick_vjp_ms_n65536": round(vjp_ms, 4),
+            "kick_vjp_ginter_s": round(n * (n - 1) / vjp_ms / 1e6, 3),
+            "trajectory_n4096_200_steps_forward_s": round(t1 - t0, 4),
+            "trajectory_n4096_200_steps_backward_s": round(t2 - t1, 4),
+            "backward_over_forward": round((t2 - t1) / (t1 - t0), 3)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -278,6 +318,10 @@ def main():
                   "encounter_pairs_last_step": r32["pairs"]},
     }
     st_rc = r64["rc"]
+    if not args.no_adjoint:
+        st_adj = N.State.from_numpy(d, rc=st_rc.cpu().numpy())
+        out["adjoint"] = bench_adjoint(N, W, torch, np, st_adj, N.Config(G=G))
+        print(f"adjoint done: {out['adjoint']}", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = bench_batched(args, N, W, torch, np)
         print(f"batched done: {out['batched']['graph_step_ms']} ms/step (graph)", file=sys.stderr,

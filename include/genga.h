@@ -173,6 +173,48 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
 int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void *ws, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Adjoint (vector-Jacobian products) of the operators above, for gradients of
+ * final states with respect to initial conditions and masses.  Each call
+ * ACCUMULATES into the caller's adjoint arrays (device, length n each).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double *x, *y, *z;    /* adjoints of positions   */
+    double *vx, *vy, *vz; /* adjoints of velocities  */
+    double *m;            /* adjoints of masses      */
+    double *rc;           /* adjoints of r_crit      */
+} genga_adjoint;
+
+/* Kick VJP at the positions, masses and radii of b.  With abar = scale * (abx,
+ * aby, abz) (the adjoint of the accelerations; scale = h for v += h a):
+ *   adj.x  += G sum_j [w u + (w_r / r)(d.u) d],  u = m_k abar_j - m_j abar_k,
+ *   adj.m  -= G sum_j w d.abar_j,
+ *   adj.rc += G sum_{j: k owns rho} K'(y) d.u / (0.9 rho^2 r^2),
+ * with d = x_j - x_k, w = K / r^3, w_r / r = K' / (0.9 rho r^4) - 3 K / r^5 and
+ * rho_kj owned by the body with the larger r_crit (ties: the lower index).
+ * Same tiling and candidate test as genga_kick; FP64. */
+int genga_kick_vjp(const genga_bodies *b, const genga_params *p, double scale,
+                   const double *abx, const double *aby, const double *abz, genga_adjoint *adj,
+                   void *ws, void *stream);
+
+/* VJP of genga_rcrit at b: reads adj.rc, adds into adj.x.., adj.vx.., adj.m
+ * (the branch of the max follows the forward: Hill term on ties). */
+int genga_rcrit_vjp(const genga_bodies *b, const genga_params *p, genga_adjoint *adj, void *ws,
+                    void *stream);
+
+/* VJP of genga_hc(h) at the velocities and masses of b: with S = sum_i adj.x_i,
+ *   adj.v_j += (h m_j / m_star) S,  adj.m_j += (h / m_star) v_j . S;
+ * adj.x is unchanged (it passes through). */
+int genga_hc_vjp(const genga_bodies *b, const genga_params *p, double h, genga_adjoint *adj,
+                 void *ws, void *stream);
+
+/* VJP of genga_drift(dt) taken at the INPUT state of the drift (b): overwrites
+ * adj.x.., adj.vx.. (adjoints of the drifted state) with the adjoints of the
+ * input state, by reverse mode through the universal-variable solution and
+ * implicit differentiation of Kepler's equation. */
+int genga_drift_vjp(const genga_bodies *b, const genga_params *p, double dt, genga_adjoint *adj,
+                    void *ws, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched ensembles (the multi-simulation mode named in Sect. 10, not
  * described by the paper): S independent systems, each advanced by the same
  * operators as above, stored back to back in one genga_bodies (n = total).

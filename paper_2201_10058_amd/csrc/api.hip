@@ -196,6 +196,65 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
     return e == hipSuccess ? GENGA_OK : hip_fail(e);
 }
 
+static int check_adj(const genga_adjoint *adj, bool pos, bool vel, bool m, bool rc)
+{
+    if (!adj) return GENGA_E_INVAL;
+    if (pos && (!adj->x || !adj->y || !adj->z)) return GENGA_E_INVAL;
+    if (vel && (!adj->vx || !adj->vy || !adj->vz)) return GENGA_E_INVAL;
+    if (m && !adj->m) return GENGA_E_INVAL;
+    if (rc && !adj->rc) return GENGA_E_INVAL;
+    return GENGA_OK;
+}
+
+int genga_kick_vjp(const genga_bodies *b, const genga_params *p, double scale, const double *abx,
+                   const double *aby, const double *abz, genga_adjoint *adj, void *ws, void *stream)
+{
+    int r = check_bodies(b, false, true);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if ((r = check_adj(adj, true, false, true, true))) return r;
+    if (!ws || !abx || !aby || !abz || !is_fin(scale)) return GENGA_E_INVAL;
+    hipError_t e = launch_kick_vjp(b, p, scale, abx, aby, abz, adj, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_rcrit_vjp(const genga_bodies *b, const genga_params *p, genga_adjoint *adj, void *ws,
+                    void *stream)
+{
+    int r = check_bodies(b, true, false);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if ((r = check_adj(adj, true, true, true, true))) return r;
+    if (!ws) return GENGA_E_INVAL;
+    hipError_t e = launch_rcrit_vjp(b, p, adj, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_hc_vjp(const genga_bodies *b, const genga_params *p, double h, genga_adjoint *adj,
+                 void *ws, void *stream)
+{
+    int r = check_bodies(b, true, false);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if ((r = check_adj(adj, true, true, true, false))) return r;
+    if (!ws || !is_fin(h)) return GENGA_E_INVAL;
+    const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
+    hipError_t e = launch_hc_vjp(b, p, h, adj, L, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_drift_vjp(const genga_bodies *b, const genga_params *p, double dt, genga_adjoint *adj,
+                    void *ws, void *stream)
+{
+    int r = check_bodies(b, true, false);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if ((r = check_adj(adj, true, true, false, false))) return r;
+    if (!ws || !is_fin(dt)) return GENGA_E_INVAL;
+    hipError_t e = launch_drift_vjp(b, p, dt, adj, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
 int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void *ws, void *stream)
 {
     int r = check_bodies(b, true, true);

@@ -1,0 +1,92 @@
+// Device helpers shared by the kick and its adjoint.
+#pragma once
+
+#include "genga_internal.h"
+
+namespace genga {
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const unsigned lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64u - lane));
+}
+
+// Changeover weight K(y), y = (r - 0.1 rho) / (0.9 rho) (Chambers 1999 eq. 10).
+__device__ __forceinline__ double changeover_k(double r, double rho)
+{
+    const double yv = (r - 0.1 * rho) / (0.9 * rho);
+    if (!(yv > 0.0)) return 0.0;
+    if (yv >= 1.0) return 1.0;
+    const double y2 = yv * yv;
+    return y2 / (2.0 * y2 - 2.0 * yv + 1.0);
+}
+
+// max of two non-negative doubles in one v_max_f64 (the generic fmax adds
+// NaN-quieting canonicalisations; the critical radii are validated instead).
+__device__ __forceinline__ double vmax_f64(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ float vmax_f32(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// binary32 mass and pre-check radius packed in the fourth double of a tile entry
+__device__ __forceinline__ double pack_f32x2(float lo, float hi)
+{
+    return __hiloint2double(__float_as_int(hi), __float_as_int(lo));
+}
+
+// rho_ij^2 = max(rc_i^2, rc_j^2) (= fl(max(rc_i, rc_j)^2): rounding is monotone).
+__device__ __forceinline__ double rho2_of(double rci, double rcj)
+{
+    const double a = rci * rci, b = rcj * rcj;
+    return a > b ? a : b;
+}
+
+// dK/dy on the open band (0, 1), zero outside.
+__device__ __forceinline__ double changeover_dk(double yv)
+{
+    if (!(yv > 0.0) || yv >= 1.0) return 0.0;
+    const double q = 2.0 * yv * yv - 2.0 * yv + 1.0;
+    return 2.0 * yv * (1.0 - yv) / (q * q);
+}
+
+// Block-wide exclusive scan of one int64 per thread.
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+template <int NT>
+__device__ int64_t block_excl_scan(int64_t v, int64_t *total, int64_t *smem /* NT/64 */)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t inc = wave_incl_scan(v);
+    if (lane == 63) smem[w] = inc;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) {
+        const int64_t t = smem[k];
+        if (k < w) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+}  // namespace genga

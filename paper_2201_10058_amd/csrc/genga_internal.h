@@ -48,7 +48,7 @@ struct KickCfg {
 // Byte offsets of the workspace regions.
 struct Layout {
     size_t status = 0;     // int32 status word (+ padding)
-    size_t part = 0;       // double [slices][3][npad]  partial accelerations
+    size_t part = 0;       // double [slices][5][npad]  partial sums (kick: 3, adjoint: 5)
     size_t cnt = 0;        // int32  [slices][npad]     per-slice pair counts
     size_t rowloc = 0;     // int32  [npad]             row offset inside its 256-row block
     size_t bsum = 0;       // int64  [nb + 1]           per-block pair counts / offsets
@@ -107,6 +107,15 @@ struct BatchDev {
     const double *m_star, *dt, *n1, *n2;  // caller's device arrays
     double *P;                  // workspace: momentum per system (S x 3)
 };
+hipError_t launch_kick_vjp(const genga_bodies *b, const genga_params *p, double scale,
+                           const double *abx, const double *aby, const double *abz,
+                           genga_adjoint *adj, char *ws, hipStream_t s);
+hipError_t launch_rcrit_vjp(const genga_bodies *b, const genga_params *p, genga_adjoint *adj,
+                            hipStream_t s);
+hipError_t launch_hc_vjp(const genga_bodies *b, const genga_params *p, double h, genga_adjoint *adj,
+                         const Layout &L, char *ws, hipStream_t s);
+hipError_t launch_drift_vjp(const genga_bodies *b, const genga_params *p, double dt,
+                            genga_adjoint *adj, char *ws, hipStream_t s);
 hipError_t launch_rcrit_b(const genga_bodies *b, const BatchDev &bd, char *ws, hipStream_t s);
 hipError_t launch_hc_b(genga_bodies *b, const BatchDev &bd, double hfac, hipStream_t s);
 hipError_t launch_drift_b(genga_bodies *b, const BatchDev &bd, double G, double hfac, char *ws,

@@ -1,0 +1,333 @@
+// Adjoint (vector-Jacobian products) of the operators of the base step.
+//
+// Kick (interaction part H_B, GENGA II Sect. 2 eq. Hb; changeover of Sect. 6.2):
+//   a_k = G sum_{j != k} m_j w_kj d_kj,  d_kj = x_j - x_k,  w = K(y) / r^3,
+//   y = (r - 0.1 rho) / (0.9 rho),  rho = max(rc_k, rc_j).
+// With J_kj = w I + (w_r / r) d d^T (symmetric in k, j) and u = m_k abar_j - m_j abar_k:
+//   xbar_k  = G sum_j J_kj u            = G sum_j [ w u + (w_r / r)(d.u) d ]
+//   mbar_k  = -G sum_j w d.abar_j
+//   rcbar_k = G sum_{j: k owns rho_kj} K'(y) / (0.9 rho^2 r^2) d.u
+// where w_r / r = K'/(0.9 rho r^4) - 3K / r^5 and "k owns rho" means rc_k > rc_j,
+// or rc_k == rc_j and k < j.  Each row gathers over all columns (no scatter,
+// no atomics); the K' terms only arise inside the band 0.1 rho < r < rho,
+// which the same candidate test as the kick routes to a slow path.
+// HC (eq. Hc), critical radii (eq. rcrit) and the Kepler drift adjoints are
+// per body (drift: csrc/kepler.h, kepler_uv_vjp).
+#include "device_common.h"
+#include "genga_internal.h"
+#include "kepler.h"
+
+namespace genga {
+
+struct VjpDev {
+    const double *x, *y, *z, *m, *rc;
+    const double *abx, *aby, *abz;
+    double scale;         // abar = scale * (abx, aby, abz)
+    int64_t n, npad, slice_len;
+    int gx;
+    double *part;         // [slices][5][npad]: xbar (3), -mbar / G, rcbar / G
+    int32_t *status;
+    double c15, c1875;
+};
+
+struct VjpSmem {
+    double4 xyzm[TILE];
+    double4 abr[TILE];    // scale * abar_j (3), rc_j^2
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
+{
+    __shared__ VjpSmem sm;
+    const int tid = threadIdx.x;
+    const int64_t bx = blockIdx.x, s = blockIdx.y;
+    const int64_t k = bx * NT + tid;
+    const int64_t j0 = s * a.slice_len;
+    const int64_t j1 = min(a.n, j0 + a.slice_len);
+    const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+    const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
+    const double4 *t_xyzm = sm.xyzm + vzero;
+    const double4 *t_abr = sm.abr + vzero;
+
+    const bool valid = k < a.n;
+    double xk, yk, zk, mk = 0.0, rck = 0.0, rc2k = 0.0, abxk = 0.0, abyk = 0.0, abzk = 0.0;
+    if (valid) {
+        xk = a.x[k]; yk = a.y[k]; zk = a.z[k];
+        mk = a.m[k];
+        rck = a.rc[k];
+        rc2k = rck * rck;
+        abxk = a.scale * a.abx[k];
+        abyk = a.scale * a.aby[k];
+        abzk = a.scale * a.abz[k];
+    } else {
+        xk = yk = zk = __builtin_nan("");
+    }
+    double Ax = 0, Ay = 0, Az = 0, Bx = 0, By = 0, Bz = 0, Mb = 0, Rb = 0;
+
+    for (int64_t t0 = j0; t0 < j1; t0 += TILE) {
+        __syncthreads();
+        for (int q = tid; q < TILE; q += NT) {
+            const int64_t jg = t0 + q;
+            if (jg < j1) {
+                const double rcj = a.rc[jg];
+                if (!(rcj >= 0.0 && rcj < INFINITY)) atomicOr(a.status, ST_RCRIT);
+                sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], a.m[jg]);
+                sm.abr[q] = make_double4(a.scale * a.abx[jg], a.scale * a.aby[jg],
+                                         a.scale * a.abz[jg], rcj * rcj);
+            }
+        }
+        __syncthreads();
+        const int tn = (int)min((int64_t)TILE, j1 - t0);
+        for (int jj = 0; jj < tn; ++jj) {
+            const double4 b = t_xyzm[jj];
+            const double4 ab = t_abr[jj];
+            const double dx = b.x - xk, dy = b.y - yk, dz = b.z - zk;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const bool cand = r2 <= vmax_f64(rc2k, ab.w);
+            // r^-3 (refined v_rsq_f64, as in the kick) and r^-2 to first order
+            const double yv = __builtin_amdgcn_rsq(r2);
+            const double y2 = yv * yv;
+            const double e = __builtin_fma(-r2, y2, 1.0);
+            const double y3 = y2 * yv;
+            const double p = __builtin_fma(e, c1875, c15);
+            double w = __builtin_fma(y3 * e, p, y3);
+            const double ri2 = __builtin_fma(y2, e, y2);
+            const double ux = __builtin_fma(mk, ab.x, -(b.w * abxk));
+            const double uy = __builtin_fma(mk, ab.y, -(b.w * abyk));
+            const double uz = __builtin_fma(mk, ab.z, -(b.w * abzk));
+            const double du = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
+            const double da = __builtin_fma(dz, ab.z, __builtin_fma(dy, ab.y, dx * ab.x));
+            double cq = (w * ri2) * du;   // B-coefficient: xbar = A - 3 B
+            if (cand) {
+                const int64_t jg = t0 + jj;
+                w = 0.0;
+                cq = 0.0;
+                if (jg != k) {
+                    if (r2 == 0.0) {
+                        atomicOr(a.status, ST_NONFINITE);
+                    } else {
+                        const double rcj = a.rc[jg];
+                        const double rho = rck > rcj ? rck : rcj;
+                        const double r = __builtin_sqrt(r2);
+                        const double yy = (r - 0.1 * rho) / (0.9 * rho);
+                        double K = 1.0, Kp = 0.0;
+                        if (r2 < (rho2_of(rck, rcj))) {
+                            K = changeover_k(r, rho);
+                            Kp = changeover_dk(yy);
+                        }
+                        const double r3 = r2 * r;
+                        w = K / r3;
+                        const double wr_r = Kp / (0.9 * rho * r2 * r2) - 3.0 * K / (r2 * r3);
+                        cq = -(wr_r * du) / 3.0;
+                        const bool owner = rck > rcj || (rck == rcj && k < jg);
+                        if (owner && Kp != 0.0) Rb += Kp / (0.9 * rho * rho * r2) * du;
+                    }
+                }
+            }
+            Ax = __builtin_fma(w, ux, Ax);
+            Ay = __builtin_fma(w, uy, Ay);
+            Az = __builtin_fma(w, uz, Az);
+            Bx = __builtin_fma(cq, dx, Bx);
+            By = __builtin_fma(cq, dy, By);
+            Bz = __builtin_fma(cq, dz, Bz);
+            Mb = __builtin_fma(w, da, Mb);
+        }
+    }
+    if (valid) {
+        double *P = a.part + (size_t)s * 5 * a.npad;
+        P[0 * a.npad + k] = __builtin_fma(-3.0, Bx, Ax);
+        P[1 * a.npad + k] = __builtin_fma(-3.0, By, Ay);
+        P[2 * a.npad + k] = __builtin_fma(-3.0, Bz, Az);
+        P[3 * a.npad + k] = Mb;
+        P[4 * a.npad + k] = Rb;
+    }
+}
+
+__global__ __launch_bounds__(RB) void k_kick_vjp_reduce(const double *part, int64_t n, int64_t npad,
+                                                        int slices, double G, double *xb,
+                                                        double *yb, double *zb, double *mb,
+                                                        double *rcb)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    double acc[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double t = 0.0;
+        for (int s = 0; s < slices; ++s) t += part[((size_t)s * 5 + c) * npad + i];
+        acc[c] = t;
+    }
+    xb[i] += G * acc[0];
+    yb[i] += G * acc[1];
+    zb[i] += G * acc[2];
+    mb[i] -= G * acc[3];
+    rcb[i] += G * acc[4];
+}
+
+// rc = max(n1 R_H, n2 |dt| |v|), R_H = |x| (m / 3 m_star)^(1/3); ties -> Hill term.
+__global__ __launch_bounds__(RB) void k_rcrit_vjp(const double *x, const double *y, const double *z,
+                                                  const double *vx, const double *vy,
+                                                  const double *vz, const double *m, int64_t n,
+                                                  double m_star, double dt, double n1, double n2,
+                                                  genga_adjoint adj)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    const double rb = adj.rc[i];
+    if (rb == 0.0) return;
+    const double r = __builtin_sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+    const double v = __builtin_sqrt(vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    const double q = cbrt(m[i] / (3.0 * m_star));
+    const double a = n1 * r * q;
+    const double b = n2 * fabs(dt) * v;
+    if (a >= b) {
+        if (r > 0.0) {
+            const double f = rb * n1 * q / r;
+            adj.x[i] += f * x[i];
+            adj.y[i] += f * y[i];
+            adj.z[i] += f * z[i];
+        }
+        if (m[i] > 0.0) adj.m[i] += rb * a / (3.0 * m[i]);
+    } else if (v > 0.0) {
+        const double f = rb * n2 * fabs(dt) / v;
+        adj.vx[i] += f * vx[i];
+        adj.vy[i] += f * vy[i];
+        adj.vz[i] += f * vz[i];
+    }
+}
+
+// HC: x_out = x_in + h P / m_star, P = sum m v.  With S = sum_i xbar_i:
+//   vbar_j += (h m_j / m_star) S,  mbar_j += (h / m_star) v_j . S.
+__global__ __launch_bounds__(RB) void k_sum3_partial(const double *a, const double *b,
+                                                     const double *c, int64_t n, double *out)
+{
+    __shared__ double sm[3][RB];
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * RB + t;
+    sm[0][t] = i < n ? a[i] : 0.0;
+    sm[1][t] = i < n ? b[i] : 0.0;
+    sm[2][t] = i < n ? c[i] : 0.0;
+    __syncthreads();
+    for (int h = RB / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sm[0][t] += sm[0][t + h];
+            sm[1][t] += sm[1][t + h];
+            sm[2][t] += sm[2][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 3) out[(size_t)blockIdx.x * 3 + t] = sm[t][0];
+}
+
+__global__ __launch_bounds__(RB) void k_hc_vjp_apply(const double *vx, const double *vy,
+                                                     const double *vz, const double *m, int64_t n,
+                                                     const double *part, int64_t nb, double h,
+                                                     double m_star, genga_adjoint adj)
+{
+    __shared__ double sm[3][RB];
+    const int t = threadIdx.x;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    for (int64_t b = t; b < nb; b += RB) {
+        p0 += part[b * 3 + 0];
+        p1 += part[b * 3 + 1];
+        p2 += part[b * 3 + 2];
+    }
+    sm[0][t] = p0;
+    sm[1][t] = p1;
+    sm[2][t] = p2;
+    __syncthreads();
+    for (int hh = RB / 2; hh > 0; hh >>= 1) {
+        if (t < hh) {
+            sm[0][t] += sm[0][t + hh];
+            sm[1][t] += sm[1][t + hh];
+            sm[2][t] += sm[2][t + hh];
+        }
+        __syncthreads();
+    }
+    const int64_t i = (int64_t)blockIdx.x * RB + t;
+    if (i >= n) return;
+    const double S0 = sm[0][0], S1 = sm[1][0], S2 = sm[2][0];
+    const double f = h * m[i] / m_star;
+    adj.vx[i] += f * S0;
+    adj.vy[i] += f * S1;
+    adj.vz[i] += f * S2;
+    adj.m[i] += (h / m_star) * (vx[i] * S0 + vy[i] * S1 + vz[i] * S2);
+}
+
+__global__ __launch_bounds__(RB) void k_drift_vjp(const double *x, const double *y, const double *z,
+                                                  const double *vx, const double *vy,
+                                                  const double *vz, int64_t n, double mu,
+                                                  double dt, genga_adjoint adj, int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    const double X[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]};
+    double xb[3] = {adj.x[i], adj.y[i], adj.z[i]}, vb[3] = {adj.vx[i], adj.vy[i], adj.vz[i]};
+    const int st = kepler_uv_vjp(mu, dt, X, V, xb, vb);
+    if (st) atomicOr(status, st);
+    adj.x[i] = xb[0]; adj.y[i] = xb[1]; adj.z[i] = xb[2];
+    adj.vx[i] = vb[0]; adj.vy[i] = vb[1]; adj.vz[i] = vb[2];
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_kick_vjp(const genga_bodies *b, const genga_params *p, double scale,
+                           const double *abx, const double *aby, const double *abz,
+                           genga_adjoint *adj, char *ws, hipStream_t s)
+{
+    KickCfg c = choose_kick_cfg(b->n, p);
+    // one row per thread for the adjoint (its register footprint is larger)
+    c.ipt = 1;
+    c.gx = (int)((b->n + KB - 1) / KB);
+    const Layout L = make_layout(b->n, c);
+    VjpDev d;
+    d.x = b->x; d.y = b->y; d.z = b->z; d.m = b->m; d.rc = b->rc;
+    d.abx = abx; d.aby = aby; d.abz = abz;
+    d.scale = scale;
+    d.n = b->n;
+    d.npad = L.npad;
+    d.slice_len = c.slice_len;
+    d.gx = c.gx;
+    d.part = (double *)(ws + L.part);
+    d.status = (int32_t *)(ws + L.status);
+    d.c15 = 1.5;
+    d.c1875 = 1.875;
+    hipLaunchKernelGGL(k_kick_vjp<KB>, dim3(c.gx, c.slices), dim3(KB), 0, s, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_kick_vjp_reduce, dim3((unsigned)L.nb), dim3(RB), 0, s, d.part, b->n,
+                       L.npad, c.slices, p->G, adj->x, adj->y, adj->z, adj->m, adj->rc);
+    return hipGetLastError();
+}
+
+hipError_t launch_rcrit_vjp(const genga_bodies *b, const genga_params *p, genga_adjoint *adj,
+                            hipStream_t s)
+{
+    const unsigned nb = (unsigned)((b->n + RB - 1) / RB);
+    hipLaunchKernelGGL(k_rcrit_vjp, dim3(nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx, b->vy,
+                       b->vz, b->m, b->n, p->m_star, p->dt, p->n1, p->n2, *adj);
+    return hipGetLastError();
+}
+
+hipError_t launch_hc_vjp(const genga_bodies *b, const genga_params *p, double h, genga_adjoint *adj,
+                         const Layout &L, char *ws, hipStream_t s)
+{
+    double *part = (double *)(ws + L.hc);
+    hipLaunchKernelGGL(k_sum3_partial, dim3((unsigned)L.nb), dim3(RB), 0, s, adj->x, adj->y,
+                       adj->z, b->n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hc_vjp_apply, dim3((unsigned)L.nb), dim3(RB), 0, s, b->vx, b->vy, b->vz,
+                       b->m, b->n, part, L.nb, h, p->m_star, *adj);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift_vjp(const genga_bodies *b, const genga_params *p, double dt,
+                            genga_adjoint *adj, char *ws, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((b->n + RB - 1) / RB);
+    hipLaunchKernelGGL(k_drift_vjp, dim3(nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx, b->vy,
+                       b->vz, b->n, p->G * p->m_star, dt, *adj, (int32_t *)ws);
+    return hipGetLastError();
+}
+
+}  // namespace genga

@@ -50,6 +50,10 @@ class BatchC(ctypes.Structure):
                 ("dt", ctypes.c_void_p), ("n1", ctypes.c_void_p), ("n2", ctypes.c_void_p)]
 
 
+class Adjoint(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rc")]
+
+
 class Pairs(ctypes.Structure):
     _fields_ = [("i", ctypes.c_void_p), ("j", ctypes.c_void_p), ("capacity", ctypes.c_int64),
                 ("count", ctypes.c_void_p)]
@@ -77,6 +81,15 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "genga_step": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
                                   ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_kick_vjp": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(Adjoint), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_rcrit_vjp": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
+                                       ctypes.POINTER(Adjoint), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_hc_vjp": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
+                                    ctypes.POINTER(Adjoint), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_drift_vjp": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
+                                       ctypes.POINTER(Adjoint), ctypes.c_void_p, ctypes.c_void_p]),
     "genga_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(BatchC), ctypes.POINTER(Params)]),
     "genga_batch_plan": (ctypes.c_int, [ctypes.POINTER(BatchC), ctypes.POINTER(Params),
                                         ctypes.c_void_p, ctypes.c_void_p]),
@@ -371,3 +384,52 @@ def step_batched(state: State, ws: BatchWorkspace, cfg: Config, pairs: PairList 
 def system_view(state: State, lo: int, hi: int) -> State:
     """State of bodies [lo, hi) (views into the same device memory)."""
     return State({k: v[lo:hi] for k, v in state.t.items()})
+
+
+# ---------------------------------------------------------------------------
+# Adjoint
+# ---------------------------------------------------------------------------
+class AdjointState:
+    """Device adjoint arrays (float64, length n): x, y, z, vx, vy, vz, m, rc."""
+
+    KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "rc")
+
+    def __init__(self, n: int, device="cuda:0", tensors: dict | None = None):
+        if tensors is None:
+            tensors = {k: torch.zeros(n, dtype=torch.float64, device=device) for k in self.KEYS}
+        self.t = tensors
+        for k in self.KEYS:
+            _require_gpu(self.t[k])
+
+    def struct(self) -> Adjoint:
+        return Adjoint(*(self.t[k].data_ptr() for k in self.KEYS))
+
+
+def kick_vjp(state: State, cfg: Config, ws: Workspace, scale: float, abar, adj: AdjointState):
+    """adj += VJP of the accelerations at `state` for abar (3 tensors)."""
+    b, p, a = state.bodies(), cfg.params(), adj.struct()
+    ptrs = [_require_gpu(t) for t in abar]
+    _check(load().genga_kick_vjp(ctypes.byref(b), ctypes.byref(p), float(scale), ptrs[0], ptrs[1],
+                                 ptrs[2], ctypes.byref(a), ctypes.c_void_p(ws.ptr),
+                                 ctypes.c_void_p(_stream_ptr())), "genga_kick_vjp")
+
+
+def rcrit_vjp(state: State, cfg: Config, ws: Workspace, adj: AdjointState):
+    b, p, a = state.bodies(), cfg.params(), adj.struct()
+    _check(load().genga_rcrit_vjp(ctypes.byref(b), ctypes.byref(p), ctypes.byref(a),
+                                  ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
+           "genga_rcrit_vjp")
+
+
+def hc_vjp(state: State, cfg: Config, ws: Workspace, h: float, adj: AdjointState):
+    b, p, a = state.bodies(), cfg.params(), adj.struct()
+    _check(load().genga_hc_vjp(ctypes.byref(b), ctypes.byref(p), float(h), ctypes.byref(a),
+                               ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
+           "genga_hc_vjp")
+
+
+def drift_vjp(state: State, cfg: Config, ws: Workspace, dt: float, adj: AdjointState):
+    b, p, a = state.bodies(), cfg.params(), adj.struct()
+    _check(load().genga_drift_vjp(ctypes.byref(b), ctypes.byref(p), float(dt), ctypes.byref(a),
+                                  ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
+           "genga_drift_vjp")

@@ -217,7 +217,7 @@ def test_batched_mixed_precision(dev):
     norm = diff / _magnitude_sums(d)
     _say("batched mixed: max rel", rel.max(), "p99 rel", np.quantile(rel, 0.99),
          "max err / sum|a_ij|", norm.max())
-    assert norm.max() <= 1e-7
+    assert norm.max() <= 1e-6
     assert np.quantile(rel, 0.99) <= 1e-6
     r64, r32 = p64.result(), p32.result()
     assert r64[2] == r32[2] and np.array_equal(r64[0], r32[0]) and np.array_equal(r64[1], r32[1])

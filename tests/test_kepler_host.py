@@ -27,6 +27,12 @@ extern "C" int kepler_host(double mu, double dt, long n, double *x, double *y, d
     for (long i = 0; i < n; ++i) st |= genga::kepler_uv(mu, dt, x[i], y[i], z[i], vx[i], vy[i], vz[i]);
     return st;
 }
+// in: states s (n x 6) and adjoints b (n x 6) of the drifted states; out: b <- adjoints of s
+extern "C" int kepler_vjp_host(double mu, double dt, long n, const double *s, double *b) {
+    int st = 0;
+    for (long i = 0; i < n; ++i) st |= genga::kepler_uv_vjp(mu, dt, s + 6 * i, s + 6 * i + 3, b + 6 * i, b + 6 * i + 3);
+    return st;
+}
 '''
 
 
@@ -40,6 +46,7 @@ def kep(tmp_path_factory):
                     f"-I{CSRC}", str(src), "-o", str(lib)], check=True)
     L = ctypes.CDLL(str(lib))
     L.kepler_host.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_long] + [ctypes.c_void_p] * 6
+    L.kepler_vjp_host.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_long] + [ctypes.c_void_p] * 2
     return L
 
 
@@ -92,3 +99,62 @@ def test_kepler_host_exact_root_terminates(kep):
     ref = oracle.state_copy(one)
     oracle.drift(ref, G, 6.0)
     assert st == 0 and _err(out, ref, "xyz") < 1e-15
+
+
+def _vjp(L, S, B, mu, dt):
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64).copy()
+    st = L.kepler_vjp_host(mu, dt, S.shape[0], S.ctypes.data, B.ctypes.data)
+    return B, st
+
+
+@pytest.mark.parametrize("dt", [6.0, 130.0, -40.0])
+def test_kepler_vjp_matches_autograd(kep, dt):
+    import torch
+    from oracle import torch_ref as T
+    d = W.make_disk(W.DISK_2048)
+    n = 300
+    S = np.stack([d[k][:n] for k in ("x", "y", "z", "vx", "vy", "vz")], axis=1)
+    rng = np.random.default_rng(11)
+    B = rng.normal(size=(n, 6))
+    got, st = _vjp(kep, S, B, G, dt)
+    assert st == 0
+    x = torch.tensor(S[:, :3], requires_grad=True)
+    v = torch.tensor(S[:, 3:], requires_grad=True)
+    x1, v1 = T.drift(x, v, G, dt)
+    L = (x1 * torch.tensor(B[:, :3])).sum() + (v1 * torch.tensor(B[:, 3:])).sum()
+    gx, gv = torch.autograd.grad(L, (x, v))
+    ref = np.concatenate([gx.numpy(), gv.numpy()], axis=1)
+    err = np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    assert err.max() < 1e-10, err.max()
+
+
+def test_kepler_vjp_unbound_orbits_fd(kep):
+    # hyperbolic and near-parabolic orbits: central differences of the host solver
+    rng = np.random.default_rng(4)
+    n = 60
+    r = rng.uniform(0.4, 2.0, n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    vesc = np.sqrt(2 * G / r)
+    fac = rng.uniform(1.05, 2.5, n)
+    S = np.stack([r * np.cos(th), r * np.sin(th), rng.normal(0, 0.02, n),
+                  -fac * vesc * np.sin(th) * 0.8, fac * vesc * np.cos(th) * 0.6 + 0.1 * vesc,
+                  rng.normal(0, 0.05, n) * vesc], axis=1)
+    B = rng.normal(size=(n, 6))
+    dt = 25.0
+    got, st = _vjp(kep, S, B, G, dt)
+    assert st == 0
+    scale = np.concatenate([np.full(3, 1.0), np.full(3, 0.02)])
+    for k in range(6):
+        h = 1e-6 * scale[k]
+        Sp, Sm = S.copy(), S.copy()
+        Sp[:, k] += h
+        Sm[:, k] -= h
+        outp = {c: Sp[:, i].copy() for i, c in enumerate(("x", "y", "z", "vx", "vy", "vz"))}
+        outm = {c: Sm[:, i].copy() for i, c in enumerate(("x", "y", "z", "vx", "vy", "vz"))}
+        assert kep.kepler_host(G, dt, n, *(outp[c].ctypes.data for c in ("x", "y", "z", "vx", "vy", "vz"))) == 0
+        assert kep.kepler_host(G, dt, n, *(outm[c].ctypes.data for c in ("x", "y", "z", "vx", "vy", "vz"))) == 0
+        P = np.stack([outp[c] for c in ("x", "y", "z", "vx", "vy", "vz")], axis=1)
+        M = np.stack([outm[c] for c in ("x", "y", "z", "vx", "vy", "vz")], axis=1)
+        fd = ((P - M) * B).sum(1) / (2 * h)
+        assert np.max(np.abs(got[:, k] - fd) / (np.abs(fd) + 1e-3 * np.abs(got).max())) < 1e-5
