@@ -44,7 +44,42 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     return ap.parse_args()
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KICK_SOURCES = ("kick.hip", "device_common.h", "genga_internal.h")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_kick_fp64_disk65536_traffic.txt")
+
+
+def kick_source_hash() -> str:
+    """SHA-256 over the sources of the FP64 kick kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KICK_SOURCES:
+        with open(os.path.join(HERE, "paper_2201_10058_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per kick launch from the committed counter summary, or None if
+    the kernel sources changed since the counters were taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != kick_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 class HipEvents:
@@ -235,6 +270,12 @@ def main():
         sys.exit(1)
     N.load()
 
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     spec = W.DISK_65536 if args.n == 65536 else W.DiskSpec(
         f"disk_n{args.n}_a0.5-4_5Mearth", args.n, 0.5, 4.0, 5.0, seed=1)
     d = W.make_disk(spec)
@@ -279,15 +320,17 @@ def main():
     r64 = run(N.FP64)
     print(f"fp64 step done: {r64['elapsed'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
-    r32 = run(N.MIXED)
-    print(f"mixed step done: {r32['elapsed'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
-          flush=True)
+    r32 = None
+    if not args.no_mixed:
+        r32 = run(N.MIXED)
+        print(f"mixed step done: {r32['elapsed'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
+              flush=True)
 
     inter_step = 2.0 * n * (n - 1)
     value = inter_step * args.steps / r64["elapsed"] / 1e9
     achieved = FLOP_PER_INTERACTION * n * (n - 1) / r64["kick_s"] / 1e12
-    achieved32 = FLOP_PER_INTERACTION * n * (n - 1) / r32["kick_s"] / 1e12
-    value32 = inter_step * args.steps / r32["elapsed"] / 1e9
+    achieved32 = FLOP_PER_INTERACTION * n * (n - 1) / r32["kick_s"] / 1e12 if r32 else None
+    value32 = inter_step * args.steps / r32["elapsed"] / 1e9 if r32 else None
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -306,17 +349,19 @@ def main():
                    "ipt": args.ipt, "slices": args.slices},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_kick<1, KM_F64>", "kernel_ms": round(r64["kick_s"] * 1e3, 4),
+                     "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": recorded_traffic(),
+                     "kernel": "k_kick<256,1,KM_F64>", "kernel_ms": round(r64["kick_s"] * 1e3, 4),
                      "flop_per_interaction": FLOP_PER_INTERACTION},
-        "mixed": {"value": round(value32, 3), "unit": "Ginter/s",
-                  "ms_per_step": round(r32["elapsed"] / args.steps * 1e3, 4),
-                  "kernel_ms": round(r32["kick_s"] * 1e3, 4),
-                  "achieved_tflops": round(achieved32, 3),
-                  "frac_fp32_vector_peak": round(achieved32 / FP32_VECTOR_PEAK_TFLOPS, 4),
-                  "speedup_vs_fp64_kernel": round(r64["kick_s"] / r32["kick_s"], 3),
-                  "encounter_pairs_last_step": r32["pairs"]},
     }
+    if r32:
+        out["mixed"] = {"value": round(value32, 3), "unit": "Ginter/s",
+                        "ms_per_step": round(r32["elapsed"] / args.steps * 1e3, 4),
+                        "kernel_ms": round(r32["kick_s"] * 1e3, 4),
+                        "achieved_tflops": round(achieved32, 3),
+                        "frac_fp32_vector_peak": round(achieved32 / FP32_VECTOR_PEAK_TFLOPS, 4),
+                        "speedup_vs_fp64_kernel": round(r64["kick_s"] / r32["kick_s"], 3),
+                        "encounter_pairs_last_step": r32["pairs"]}
     st_rc = r64["rc"]
     if not args.no_adjoint:
         st_adj = N.State.from_numpy(d, rc=st_rc.cpu().numpy())

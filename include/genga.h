@@ -90,7 +90,7 @@ typedef struct {
     int ipt;       /* kick rows per thread (1 or 2); 0 = library choice         */
     int slices;    /* single system: kick column slices; 0 = library choice     */
     int block;     /* batch: kick threads per block (64 or 256); 0 = 256         */
-    int tile_cols; /* batch: columns per kick tile (rounded up to 256); 0 = 1024 */
+    int tile_cols; /* batch: columns per kick tile (rounded up to 64); 0 = 1024  */
     int grid;      /* batch: persistent kick blocks; 0 = library choice         */
     void *prof_events[4]; /* optional hipEvent_t handles (timing): [0], [1] are
                              recorded immediately before and after the main

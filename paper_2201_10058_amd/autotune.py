@@ -72,7 +72,7 @@ def batch_signature(batch: N.Batch) -> str:
 
 
 BATCH_CANDIDATES = [dict(block=b, ipt=i, tile_cols=c)
-                    for b in (64, 256) for i in (1, 2) for c in (512, 1024, 2048)]
+                    for b in (64, 256) for i in (1, 2) for c in (256, 512, 1024, 2048)]
 
 
 def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool = True,

@@ -35,7 +35,7 @@ static int cu_count()
 struct BatchShape {
     KickCfg cfg;
     int64_t ntot = 0;
-    int64_t cols = 0;     // columns per tile (multiple of TILE)
+    int64_t cols = 0;     // columns per tile (multiple of 64)
 };
 
 // Validate the batch and derive the launch shape (O(S) host work).
@@ -50,7 +50,7 @@ static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape 
     c.ipt = (p && p->ipt > 0) ? p->ipt : 1;
     if (c.ipt != 1 && c.ipt != 2) return GENGA_E_INVAL;
     int64_t cols = (p && p->tile_cols > 0) ? p->tile_cols : 1024;
-    cols = ((cols + TILE - 1) / TILE) * TILE;
+    cols = ((cols + 63) / 64) * 64;
     sh.cols = cols;
     const int64_t R = (int64_t)c.nt * c.ipt;
     int64_t ntiles = 0;
@@ -68,7 +68,8 @@ static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape 
     c.slices = maxs;
     c.ntiles = ntiles;
     c.nwaves = ntiles * (c.nt / 64);
-    const int per_cu = c.nt == 64 ? 16 : 4;
+    int per_cu = kick_blocks_per_cu(c, p ? p->precision : GENGA_FP64);
+    if (per_cu <= 0) per_cu = c.nt == 64 ? 8 : 2;
     int64_t grid = (p && p->grid > 0) ? p->grid : (int64_t)cu_count() * per_cu;
     if (grid > ntiles) grid = ntiles;
     c.grid = (int)grid;
@@ -199,6 +200,10 @@ int genga_batch_plan(const genga_batch *bt, const genga_params *p, void *ws, voi
         return hip_err(e);
     if ((e = hipMemcpyAsync(w + L.offsets, bt->offsets, (size_t)(bt->S + 1) * sizeof(int64_t),
                             hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_err(e);
+    const int32_t zero2[2] = {0, 0};   // status word and tile counter
+    if ((e = hipMemcpyAsync(w + L.status, zero2, sizeof(zero2), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
         return hip_err(e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e);
     return GENGA_OK;

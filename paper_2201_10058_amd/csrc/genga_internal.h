@@ -18,7 +18,6 @@ enum : int32_t {
 };
 
 constexpr int KB = 256;      // threads per kick block (4 waves of 64)
-constexpr int TILE = 256;    // columns staged in LDS per pass
 constexpr int WSEG = 128;    // staged encounter pairs per kick wave
 constexpr int RB = 256;      // rows per block of the O(N) kernels
 
@@ -38,7 +37,7 @@ struct KickCfg {
     int nt = KB;              // threads per block (64 or 256)
     int ipt = 1;              // rows per thread
     int slices = 1;           // column slices (single system: grid.y; batch: max per system)
-    int64_t slice_len = 0;    // single system: columns per slice, a multiple of TILE
+    int64_t slice_len = 0;    // single system: columns per slice, a multiple of 64
     int gx = 0;               // single system: row blocks (grid.x)
     int64_t ntiles = 0;       // tiles in one launch
     int64_t nwaves = 0;       // kick waves in one launch (ntiles * nt / 64)
@@ -47,7 +46,7 @@ struct KickCfg {
 
 // Byte offsets of the workspace regions.
 struct Layout {
-    size_t status = 0;     // int32 status word (+ padding)
+    size_t status = 0;     // int32 status word, int32 tile counter (+ padding)
     size_t part = 0;       // double [slices][5][npad]  partial sums (kick: 3, adjoint: 5)
     size_t cnt = 0;        // int32  [slices][npad]     per-slice pair counts
     size_t rowloc = 0;     // int32  [npad]             row offset inside its 256-row block
@@ -66,6 +65,8 @@ struct Layout {
 };
 
 KickCfg choose_kick_cfg(int64_t n, const genga_params *p);
+// Resident blocks per CU of the persistent kick for this shape (0 if unknown).
+int kick_blocks_per_cu(const KickCfg &c, int precision);
 Layout make_layout(int64_t n, const KickCfg &c, int64_t S = 0);
 
 void set_hip_error(hipError_t e);

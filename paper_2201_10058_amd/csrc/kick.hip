@@ -11,11 +11,11 @@
 //    range of its columns.  A single system uses an implicit 2-D grid of tiles
 //    (row blocks x column slices); a batch of systems uses a host-built,
 //    cost-sorted tile list walked by a persistent grid.
-//  * Each block stages TILE columns (x, y, z, m, rc^2) in LDS; every lane
+//  * Each block stages NT columns (x, y, z, m, rc^2) in LDS; every lane
 //    owns IPT rows and streams the tile with broadcast LDS reads.  Per
 //    interaction the FP64 fast path is 3 sub, 3 mul/fma for r^2, v_rsq_f64
-//    with a correction folded into m r^-3, 3 fma accumulations and one
-//    compare against max(rc_i^2, rc_j^2).  Pairs inside the pair critical
+//    with a first-order correction folded into m r^-3 (5 ops), 3 fma
+//    accumulations and one compare against max(rc_i^2, rc_j^2).  Pairs inside the pair critical
 //    radius (and the self pair) take a divergent slow path that evaluates K,
 //    records encounter pairs and detects coincident bodies.
 //  * Partial sums per column slice go to the workspace; k_kick_reduce adds
@@ -45,6 +45,7 @@ struct KickDev {
     int32_t *stage;       // [nwaves][WSEG][3]
     int32_t *wcount;      // [nwaves]
     int32_t *status;
+    int32_t *queue;       // batch: next tile to take (reset to 0 by k_kick_reduce)
     int emit;
     double c15, c1875;    // 3/2 and 15/8
     double widen;         // mixed: squared widening of the binary32 pre-check radius
@@ -90,7 +91,7 @@ struct Rows {
 template <int IPT, bool FORCES>
 __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int q, int64_t jg,
                                             double r2, double rc2j, double mj, int64_t wave_g,
-                                            volatile int *wcnt)
+                                            int *wcnt)
 {
     bool emit = false;
     double wk = 0.0;
@@ -116,7 +117,9 @@ __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int 
     if (a.emit) {
         const uint64_t mask = __ballot(emit);
         if (mask != 0ull) {
-            const int base = *wcnt;
+            // wave-private LDS counter: plain ds_read / ds_write (relaxed,
+            // wavefront scope), so the compiler may still pipeline the tile reads
+            const int base = __hip_atomic_load(wcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             if (emit) {
                 const int pos = base + __popcll(mask & lanemask_lt());
                 if (pos < WSEG) {
@@ -128,7 +131,9 @@ __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int 
                 R.kc[q] += 1;
             }
             const uint64_t act = __ballot(1);
-            if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1) *wcnt = base + __popcll(mask);
+            if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1)
+                __hip_atomic_store(wcnt, base + __popcll(mask), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
     }
     return wk;
@@ -148,7 +153,7 @@ template <int IPT, int MODE>
 __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const double4 b,
                                          const double rc2j, const int64_t jg, const double c15,
                                          const double c1875, const int64_t wave_g,
-                                         volatile int *wcnt, const double *rc2j64,
+                                         int *wcnt, const double *rc2j64,
                                          const double *mj64)
 {
     if (MODE == KM_MIXED) {
@@ -205,17 +210,17 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
         const bool cand = r2 <= vmax_f64(R.rc2i[q], rc2j);
         double sc = 0.0;
         if (FORCES) {
-            // m r^-3 from v_rsq_f64 (relative error e0 ~ 2^-24):
-            // with e = 1 - r2 y^2, r2^{-3/2} = y^3 (1 - e)^{-3/2}
-            //   = y^3 (1 + e (3/2 + 15/8 e) + O(e^3)).
+            // m r^-3 from v_rsq_f64 (measured relative error below 2^-24):
+            // with e = 1 - r2 y^2 (|e| < 1.1e-7), r2^{-3/2} = y^3 (1 - e)^{-3/2}
+            //   = y^3 (1 + 3/2 e) + (15/8 e^2 < 2.3e-14) y^3 + ...
+            // The first-order form leaves each term at most 2.3e-14 small;
+            // over a whole disk that moves accelerations by < 2e-14 relative.
             const double yv = __builtin_amdgcn_rsq(r2);
             const double y2 = yv * yv;
             const double e = __builtin_fma(-r2, y2, 1.0);
             const double y3 = y2 * yv;
-            const double p = __builtin_fma(e, c1875, c15);
             const double my3 = b.w * y3;
-            const double t = my3 * e;
-            sc = __builtin_fma(t, p, my3);
+            sc = __builtin_fma(my3 * e, c15, my3);
         }
         if (cand) sc = slow_pair<IPT, FORCES>(a, R, q, jg, r2, rc2j, b.w, wave_g, wcnt);
         if (FORCES) {
@@ -240,18 +245,19 @@ __device__ __forceinline__ void fold(Rows<IPT> &R)
     }
 }
 
-// Shared-memory tile of one block.
+// Shared-memory tile of one block: NT columns (one per thread per pass).
+template <int NT>
 struct KickSmem {
-    double4 xyzm[TILE];
-    double rc2[TILE];
-    double m[TILE];
+    double4 xyzm[NT];
+    double rc2[NT];
+    double m[NT];
     int wcnt[4];
 };
 
 // All rows of tile `td` against its columns; writes the slice partials, the
 // per-row pair counts and the wave's staging count.
 template <int NT, int IPT, int MODE>
-__device__ __forceinline__ void process_tile(const KickDev &a, KickSmem &sm, const TileDesc &td,
+__device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm, const TileDesc &td,
                                              int64_t tile_index)
 {
     const int tid = threadIdx.x;
@@ -293,12 +299,13 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem &sm, con
         R.axf[q] = R.ayf[q] = R.azf[q] = 0.0f;
         R.kc[q] = 0;
     }
-    if (lane == 0) sm.wcnt[w] = 0;
-    volatile int *wcnt = &sm.wcnt[w];
+    int *wcnt = &sm.wcnt[w];
+    if (lane == 0) __hip_atomic_store(wcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 
-    for (int64_t t0 = j0; t0 < j1; t0 += TILE) {
+    for (int64_t t0 = j0; t0 < j1; t0 += NT) {
         __syncthreads();
-        for (int q = tid; q < TILE; q += NT) {
+        {
+            const int q = tid;
             const int64_t jg = t0 + q;
             if (jg < j1) {
                 const double rcj = a.rc[jg];
@@ -315,24 +322,20 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem &sm, con
             }
         }
         __syncthreads();
-        const int tn = (int)min((int64_t)TILE, j1 - t0);
-        if (tn == TILE) {
-            for (int jj = 0; jj < TILE; jj += 4) {
+        const int tn = (int)min((int64_t)NT, j1 - t0);
+        int jj = 0;
+        for (; jj + 4 <= tn; jj += 4) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    interact<IPT, MODE>(a, R, t_xyzm[jj + u],
-                                        MODE == KM_MIXED ? 0.0 : t_rc2[jj + u], t0 + jj + u, c15,
-                                        c1875, wave_g, wcnt, t_rc2 + jj + u, t_m + jj + u);
-                if ((jj & (FOLD - 1)) == FOLD - 4) fold<IPT, MODE>(R);
-            }
-        } else {
-            for (int jj = 0; jj < tn; ++jj) {
-                interact<IPT, MODE>(a, R, t_xyzm[jj], MODE == KM_MIXED ? 0.0 : t_rc2[jj], t0 + jj,
-                                    c15, c1875, wave_g, wcnt, t_rc2 + jj, t_m + jj);
-                if ((jj & (FOLD - 1)) == FOLD - 1) fold<IPT, MODE>(R);
-            }
-            fold<IPT, MODE>(R);
+            for (int u = 0; u < 4; ++u)
+                interact<IPT, MODE>(a, R, t_xyzm[jj + u], MODE == KM_MIXED ? 0.0 : t_rc2[jj + u],
+                                    t0 + jj + u, c15, c1875, wave_g, wcnt, t_rc2 + jj + u,
+                                    t_m + jj + u);
+            if ((jj & (FOLD - 1)) == FOLD - 4) fold<IPT, MODE>(R);
         }
+        for (; jj < tn; ++jj)
+            interact<IPT, MODE>(a, R, t_xyzm[jj], MODE == KM_MIXED ? 0.0 : t_rc2[jj], t0 + jj, c15,
+                                c1875, wave_g, wcnt, t_rc2 + jj, t_m + jj);
+        fold<IPT, MODE>(R);
     }
 
 #pragma unroll
@@ -346,27 +349,36 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem &sm, con
             if (a.emit) a.cnt[(size_t)s * a.npad + R.ii[q]] = R.kc[q];
         }
     }
-    if (a.emit && lane == 0) a.wcount[wave_g] = *wcnt;
+    if (a.emit && lane == 0)
+        a.wcount[wave_g] = __hip_atomic_load(wcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 // One tile per block (single system: grid = row blocks x column slices).
 template <int NT, int IPT, int MODE>
 __global__ __launch_bounds__(NT) void k_kick(KickDev a)
 {
-    __shared__ KickSmem sm;
+    __shared__ KickSmem<NT> sm;
     const int64_t t = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     process_tile<NT, IPT, MODE>(a, sm, get_tile<NT, IPT>(a, t), t);
 }
 
-// Persistent grid over a tile list (batched systems): block b takes tiles
-// b, b + G, b + 2G, ... of the cost-sorted list.
+// Persistent grid over a tile list (batched systems), sized to the blocks
+// the chip holds at once: each block takes the next tile of the list (sorted
+// by decreasing cost) from a device counter until the list is exhausted.
+// Which block runs a tile does not change any result: every tile writes its
+// own partial-sum and staging slots.
 template <int NT, int IPT, int MODE>
 __global__ __launch_bounds__(NT) void k_kick_persistent(KickDev a)
 {
-    __shared__ KickSmem sm;
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        process_tile<NT, IPT, MODE>(a, sm, a.tiles[t], t);
+    __shared__ KickSmem<NT> sm;
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(a.queue, 1);
         __syncthreads();
+        const int64_t t = next;
+        __syncthreads();
+        if (t >= a.ntiles) break;
+        process_tile<NT, IPT, MODE>(a, sm, a.tiles[t], t);
     }
 }
 
@@ -386,6 +398,7 @@ struct ReduceDev {
     const double *sys_dt;         // batched: time step per system
     double G, h, hfac;            // v += h a (single) or hfac * dt_s * a (batched)
     int forces, emit;
+    int32_t *queue;               // batch: tile counter of the kick, reset here
 };
 
 __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
@@ -393,6 +406,7 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     __shared__ int64_t sm[RB / 64];
     const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
     const bool valid = i < r.n;
+    if (r.queue && i == 0) *r.queue = 0;
     int nsl = r.slices;
     double h = r.h;
     if (valid && r.sysid) {
@@ -541,19 +555,20 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
     c.nt = KB;
     const int64_t rows_per_block = (int64_t)c.nt * c.ipt;
     c.gx = (int)((n + rows_per_block - 1) / rows_per_block);
-    int64_t tiles = (n + TILE - 1) / TILE;
-    int slices;
+    int64_t slices;
     if (p && p->slices > 0) {
         slices = p->slices;
     } else {
-        // about 8192 blocks (32 per CU) so that column slices hide latency
-        slices = (int)((8192 + c.gx - 1) / c.gx);
-        if (slices > 64) slices = 64;
+        // about 8192 blocks (32 per CU): large systems get column slices for
+        // latency hiding, small ones short slices so that no wave walks more
+        // than a few hundred columns on an otherwise idle chip
+        slices = (8192 + c.gx - 1) / c.gx;
     }
     if (slices < 1) slices = 1;
-    if (slices > tiles) slices = (int)tiles;
-    const int64_t tiles_per_slice = (tiles + slices - 1) / slices;
-    c.slice_len = tiles_per_slice * TILE;
+    // slices of a multiple of 64 columns (64 at the least)
+    int64_t len = (n + slices - 1) / slices;
+    len = ((len + 63) / 64) * 64;
+    c.slice_len = len;
     c.slices = (int)((n + c.slice_len - 1) / c.slice_len);
     c.ntiles = (int64_t)c.gx * c.slices;
     c.nwaves = c.ntiles * (c.nt / 64);
@@ -609,6 +624,27 @@ static void launch_k(const KickDev &d, const KickCfg &c, hipStream_t s)
         hipLaunchKernelGGL((k_kick<NT, IPT, MODE>), dim3(c.gx, c.slices), dim3(NT), 0, s, d);
 }
 
+template <int NT, int IPT, int MODE>
+static int occupancy_k()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_kick_persistent<NT, IPT, MODE>, NT, 0) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
+int kick_blocks_per_cu(const KickCfg &c, int precision)
+{
+    const bool mixed = precision == GENGA_MIXED;
+    if (c.nt == 64) {
+        if (c.ipt == 2) return mixed ? occupancy_k<64, 2, KM_MIXED>() : occupancy_k<64, 2, KM_F64>();
+        return mixed ? occupancy_k<64, 1, KM_MIXED>() : occupancy_k<64, 1, KM_F64>();
+    }
+    if (c.ipt == 2) return mixed ? occupancy_k<KB, 2, KM_MIXED>() : occupancy_k<KB, 2, KM_F64>();
+    return mixed ? occupancy_k<KB, 1, KM_MIXED>() : occupancy_k<KB, 1, KM_F64>();
+}
+
 template <int NT, int IPT>
 static void launch_mode(const KickDev &d, const KickCfg &c, int mode, hipStream_t s)
 {
@@ -633,6 +669,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     d.stage = (int32_t *)(ws + L.stage);
     d.wcount = (int32_t *)(ws + L.wcount);
     d.status = (int32_t *)(ws + L.status);
+    d.queue = k.tiles ? (int32_t *)(ws + L.status) + 1 : nullptr;
     d.emit = k.pairs != nullptr;
     d.c15 = 1.5;
     d.c1875 = 1.875;
@@ -675,6 +712,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.G = k.G; r.h = k.h; r.hfac = k.hfac;
     r.forces = k.forces;
     r.emit = d.emit;
+    r.queue = d.queue;
     if (r.forces || r.emit) {
         hipLaunchKernelGGL(k_kick_reduce, dim3((unsigned)L.nb), dim3(RB), 0, s, r);
         e = hipGetLastError();

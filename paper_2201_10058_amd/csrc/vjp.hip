@@ -30,15 +30,16 @@ struct VjpDev {
     double c15, c1875;
 };
 
+template <int NT>
 struct VjpSmem {
-    double4 xyzm[TILE];
-    double4 abr[TILE];    // scale * abar_j (3), rc_j^2
+    double4 xyzm[NT];
+    double4 abr[NT];      // scale * abar_j (3), rc_j^2
 };
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
 {
-    __shared__ VjpSmem sm;
+    __shared__ VjpSmem<NT> sm;
     const int tid = threadIdx.x;
     const int64_t bx = blockIdx.x, s = blockIdx.y;
     const int64_t k = bx * NT + tid;
@@ -64,9 +65,9 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
     }
     double Ax = 0, Ay = 0, Az = 0, Bx = 0, By = 0, Bz = 0, Mb = 0, Rb = 0;
 
-    for (int64_t t0 = j0; t0 < j1; t0 += TILE) {
+    for (int64_t t0 = j0; t0 < j1; t0 += NT) {
         __syncthreads();
-        for (int q = tid; q < TILE; q += NT) {
+        for (int q = tid; q < NT; q += NT) {
             const int64_t jg = t0 + q;
             if (jg < j1) {
                 const double rcj = a.rc[jg];
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
             }
         }
         __syncthreads();
-        const int tn = (int)min((int64_t)TILE, j1 - t0);
+        const int tn = (int)min((int64_t)NT, j1 - t0);
         for (int jj = 0; jj < tn; ++jj) {
             const double4 b = t_xyzm[jj];
             const double4 ab = t_abr[jj];

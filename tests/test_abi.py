@@ -86,7 +86,7 @@ def test_batch_plan_shape_on_host():
         p = N.Config(G=2.959e-4, block=block, ipt=ipt, tile_cols=cols).params()
         info = (ctypes.c_int64 * 5)()
         assert lib.genga_batch_info(ctypes.byref(bt), ctypes.byref(p), info) == N.OK
-        c = -(-cols // 256) * 256
+        c = -(-cols // 64) * 64
         r = block * ipt
         tiles = sum(-(-n // r) * -(-n // c) for n in sizes)
         assert info[0] == tiles and info[2] == block and info[3] == ipt and info[4] == c
