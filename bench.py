@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the mixed-precision error and energy-drift report")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -139,6 +141,51 @@ def cpu_baseline(d, rc, G, target_s):
             "kind": "oracle",
             "sample": f"plain FP64 kick (oracle), {what} of the {n}-body disk: "
                       f"{inter:.3e} interactions in {t_used:.1f} s"}
+
+
+def mixed_accuracy(N, W, torch, np):
+    """Mixed-precision kick against the FP64 kick on the three mixed-precision
+    disks (16,384 / 32,768 / 65,536 bodies): relative error per acceleration."""
+    out = {}
+    for n_, spec in sorted(W.DISK_MIXED.items()):
+        d = W.make_disk(spec)
+        st = N.State.from_numpy(d)
+        cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"])
+        ws = N.Workspace(n_, cfg)
+        N.rcrit(st, cfg, ws)
+        a64 = N.kick(st, cfg, ws, 0.0, acc=True)
+        a32 = N.kick(st, N.Config(**{**cfg.__dict__, "precision": N.MIXED}), ws, 0.0, acc=True)
+        torch.cuda.synchronize()
+        if N.read_status(ws) != N.OK:
+            raise SystemExit("mixed accuracy status")
+        rel = ((a32 - a64).norm(dim=0) / a64.norm(dim=0)).cpu().numpy()
+        out[f"n{n_}"] = {"max_rel_err": float(rel.max()), "p99_rel_err": float(np.quantile(rel, 0.99))}
+    return out
+
+
+def energy_drift(N, W, torch, np, steps=10_000, every=1000):
+    """Relative energy drift (E(t) - E(0)) / |E(0)| of the FP64 and mixed steps
+    on the 16,384-body disk over `steps` steps, energies in binary64."""
+    d = W.make_disk(W.DISK_MIXED[16384])
+    drift = {}
+    for name, prec in (("fp64", N.FP64), ("mixed", N.MIXED)):
+        st = N.State.from_numpy(d)
+        cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                       precision=prec, flags=N.FLAG_NOSYNC)
+        ws = N.Workspace(st.n, cfg)
+        Es = [N.energy(st, cfg, ws).clone()]
+        for k in range(steps):
+            N.step(st, cfg, ws)
+            if (k + 1) % every == 0:
+                Es.append(N.energy(st, cfg, ws).clone())
+        if N.read_status(ws) != N.OK:
+            raise SystemExit("energy drift status")
+        E = torch.stack(Es).cpu().numpy()[:, 0]
+        drift[name] = (E - E[0]) / abs(E[0])
+    return {"steps": steps, "n": int(d["n"]),
+            "fp64_max_abs_drift": float(np.max(np.abs(drift["fp64"]))),
+            "mixed_max_abs_drift": float(np.max(np.abs(drift["mixed"]))),
+            "max_abs_mixed_minus_fp64": float(np.max(np.abs(drift["mixed"] - drift["fp64"])))}
 
 
 def bench_batched(args, N, W, torch, np):
@@ -362,6 +409,11 @@ def main():
                         "frac_fp32_vector_peak": round(achieved32 / FP32_VECTOR_PEAK_TFLOPS, 4),
                         "speedup_vs_fp64_kernel": round(r64["kick_s"] / r32["kick_s"], 3),
                         "encounter_pairs_last_step": r32["pairs"]}
+        if not args.no_accuracy:
+            out["mixed"]["accuracy_vs_fp64"] = mixed_accuracy(N, W, torch, np)
+            out["mixed"]["energy_drift"] = energy_drift(N, W, torch, np)
+            print(f"mixed accuracy done: {out['mixed']['accuracy_vs_fp64']} "
+                  f"{out['mixed']['energy_drift']}", file=sys.stderr, flush=True)
     st_rc = r64["rc"]
     if not args.no_adjoint:
         st_adj = N.State.from_numpy(d, rc=st_rc.cpu().numpy())

@@ -172,6 +172,19 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
  * GENGA_FLAG_NOSYNC, synchronises the stream and returns the status. */
 int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void *ws, void *stream);
 
+/* Energy bookkeeping in binary64: the Hamiltonian of the democratic
+ * heliocentric splitting (Sect. 2, eqs. H, Ha, Hb, Hc), whose parts the
+ * changeover only redistributes (K + (1 - K) = 1), so none of them involves rc:
+ *   T   = sum_i m_i |v_i|^2 / 2,
+ *   U_* = -G m_star sum_i m_i / |x_i|,
+ *   U   = -G sum_{i<j} m_i m_j / r_ij,
+ *   C   = |sum_i m_i v_i|^2 / (2 m_star).
+ * Writes out[0..4] = (T + U_* + U + C, T, U_*, U, C), `out` a device array
+ * of 5 doubles.  Reads x..vz, m.  Asynchronous; two coincident bodies set
+ * GENGA_E_NONFINITE in the workspace status.  ws: genga_workspace_bytes(n, p). */
+int genga_energy(const genga_bodies *b, const genga_params *p, double *out, void *ws,
+                 void *stream);
+
 /* ------------------------------------------------------------------------
  * Adjoint (vector-Jacobian products) of the operators above, for gradients of
  * final states with respect to initial conditions and masses.  Each call

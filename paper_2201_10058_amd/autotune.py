@@ -75,15 +75,26 @@ BATCH_CANDIDATES = [dict(block=b, ipt=i, tile_cols=c)
                     for b in (64, 256) for i in (1, 2) for c in (256, 512, 1024, 2048)]
 
 
+def _batch_candidates() -> list:
+    """Tile shapes, each with the library's occupancy-sized persistent grid
+    (grid = 0) and with a grid of 32 waves per CU."""
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    out = []
+    for c in BATCH_CANDIDATES:
+        out.append({**c, "grid": 0})
+        out.append({**c, "grid": cus * (32 * 64 // c["block"])})
+    return out
+
+
 def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool = True,
                  candidates=None, reps: int = 3) -> dict:
-    """Pick (block, ipt, tile_cols) for the batched kick; returns the choice."""
-    key = f"batch:{_arch()}:p{cfg.precision}:{batch_signature(batch)}"
+    """Pick (block, ipt, tile_cols, grid) for the batched kick; returns the choice."""
+    key = f"batch2:{_arch()}:p{cfg.precision}:{batch_signature(batch)}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key]["choice"]
     results = []
-    for cand in candidates or BATCH_CANDIDATES:
+    for cand in candidates or _batch_candidates():
         c = N.Config(**{**cfg.__dict__, **cand, "flags": N.FLAG_NOSYNC})
         ws = N.BatchWorkspace(batch, c)
         ms = _time(lambda: N.kick_batched(state, ws, c, 0.0), reps)

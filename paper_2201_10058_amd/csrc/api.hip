@@ -196,6 +196,19 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
     return e == hipSuccess ? GENGA_OK : hip_fail(e);
 }
 
+int genga_energy(const genga_bodies *b, const genga_params *p, double *out, void *ws,
+                 void *stream)
+{
+    int r = check_bodies(b, true, false);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (!ws || !out) return GENGA_E_INVAL;
+    const KickCfg c = choose_kick_cfg(b->n, p);
+    const Layout L = make_layout(b->n, c);
+    hipError_t e = launch_energy(b, p, out, c, L, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
 static int check_adj(const genga_adjoint *adj, bool pos, bool vel, bool m, bool rc)
 {
     if (!adj) return GENGA_E_INVAL;

@@ -96,6 +96,8 @@ hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, 
                      hipStream_t s);
 hipError_t launch_drift(genga_bodies *b, double mu, double dt, char *ws, hipStream_t s);
 hipError_t launch_clear_status(char *ws, hipStream_t s);
+hipError_t launch_energy(const genga_bodies *b, const genga_params *p, double *out,
+                         const KickCfg &c, const Layout &L, char *ws, hipStream_t s);
 
 // Device view of a planned batch (pointers into the caller's arrays and the
 // workspace).

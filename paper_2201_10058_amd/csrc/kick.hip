@@ -48,6 +48,7 @@ struct KickDev {
     int32_t *queue;       // batch: next tile to take (reset to 0 by k_kick_reduce)
     int emit;
     double c15, c1875;    // 3/2 and 15/8
+    double c53;           // 5/3
     double widen;         // mixed: squared widening of the binary32 pre-check radius
 };
 
@@ -148,11 +149,12 @@ constexpr double MIXED_NEAR = 3.0;
 constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
 
 // One column j against the lane's rows (the hot loop body).
-//   b = (x_j, y_j, z_j, m_j) for KM_F64 / KM_PAIRS, (x_j, y_j, z_j, {m_j, rc2f_j}) for KM_MIXED.
+//   b = (x_j, y_j, z_j, 3/2 m_j) for KM_F64, (x_j, y_j, z_j, m_j) for KM_PAIRS,
+//   (x_j, y_j, z_j, {m_j, rc2f_j}) for KM_MIXED; *mj64 = m_j.
 template <int IPT, int MODE>
 __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const double4 b,
                                          const double rc2j, const int64_t jg, const double c15,
-                                         const double c1875, const int64_t wave_g,
+                                         const double c1875, const double c53, const int64_t wave_g,
                                          int *wcnt, const double *rc2j64,
                                          const double *mj64)
 {
@@ -215,14 +217,16 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
             //   = y^3 (1 + 3/2 e) + (15/8 e^2 < 2.3e-14) y^3 + ...
             // The first-order form leaves each term at most 2.3e-14 small;
             // over a whole disk that moves accelerations by < 2e-14 relative.
+            // It is evaluated as (3/2 m) y^3 (5/3 - r2 y^2), with 3/2 m staged
+            // in the tile, which takes one instruction less than
+            // m y^3 + 3/2 e m y^3.
             const double yv = __builtin_amdgcn_rsq(r2);
             const double y2 = yv * yv;
-            const double e = __builtin_fma(-r2, y2, 1.0);
+            const double p = __builtin_fma(-r2, y2, c53);
             const double y3 = y2 * yv;
-            const double my3 = b.w * y3;
-            sc = __builtin_fma(my3 * e, c15, my3);
+            sc = (b.w * y3) * p;
         }
-        if (cand) sc = slow_pair<IPT, FORCES>(a, R, q, jg, r2, rc2j, b.w, wave_g, wcnt);
+        if (cand) sc = slow_pair<IPT, FORCES>(a, R, q, jg, r2, rc2j, *mj64, wave_g, wcnt);
         if (FORCES) {
             R.ax[q] = __builtin_fma(dx, sc, R.ax[q]);
             R.ay[q] = __builtin_fma(dy, sc, R.ay[q]);
@@ -275,6 +279,7 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
     // the hot loop.
     const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
     const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
+    const double c53 = a.c53 + (double)vzero;
     const double4 *t_xyzm = sm.xyzm + vzero;
     const double *t_rc2 = sm.rc2 + vzero;
     const double *t_m = sm.m + vzero;
@@ -316,7 +321,9 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
                     sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], pack_f32x2((float)mj, rc2f));
                     sm.m[q] = mj;
                 } else {
-                    sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], mj);
+                    sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg],
+                                              MODE == KM_F64 ? 1.5 * mj : mj);
+                    sm.m[q] = mj;
                 }
                 sm.rc2[q] = rcj * rcj;
             }
@@ -328,13 +335,13 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 interact<IPT, MODE>(a, R, t_xyzm[jj + u], MODE == KM_MIXED ? 0.0 : t_rc2[jj + u],
-                                    t0 + jj + u, c15, c1875, wave_g, wcnt, t_rc2 + jj + u,
+                                    t0 + jj + u, c15, c1875, c53, wave_g, wcnt, t_rc2 + jj + u,
                                     t_m + jj + u);
             if ((jj & (FOLD - 1)) == FOLD - 4) fold<IPT, MODE>(R);
         }
         for (; jj < tn; ++jj)
             interact<IPT, MODE>(a, R, t_xyzm[jj], MODE == KM_MIXED ? 0.0 : t_rc2[jj], t0 + jj, c15,
-                                c1875, wave_g, wcnt, t_rc2 + jj, t_m + jj);
+                                c1875, c53, wave_g, wcnt, t_rc2 + jj, t_m + jj);
         fold<IPT, MODE>(R);
     }
 
@@ -672,6 +679,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     d.queue = k.tiles ? (int32_t *)(ws + L.status) + 1 : nullptr;
     d.emit = k.pairs != nullptr;
     d.c15 = 1.5;
+    d.c53 = 5.0 / 3.0;
     d.c1875 = 1.875;
     // Mixed mode evaluates every pair closer than MIXED_NEAR rho_ij in
     // binary64: the binary32 test uses (MIXED_NEAR rho)^2 with a relative

@@ -11,6 +11,10 @@
 // or rc_k == rc_j and k < j.  Each row gathers over all columns (no scatter,
 // no atomics); the K' terms only arise inside the band 0.1 rho < r < rho,
 // which the same candidate test as the kick routes to a slow path.
+// The row sums are gathered as
+//   sum_j w u = m_k sum_j w abar_j - abar_k sum_j w m_j,
+//   d.u = m_k d.abar_j - m_j d.abar_k,
+// so no per-pair u is formed.
 // HC (eq. Hc), critical radii (eq. rcrit) and the Kepler drift adjoints are
 // per body (drift: csrc/kepler.h, kepler_uv_vjp).
 #include "device_common.h"
@@ -27,15 +31,25 @@ struct VjpDev {
     int gx;
     double *part;         // [slices][5][npad]: xbar (3), -mbar / G, rcbar / G
     int32_t *status;
-    double c15, c1875;
+    double c53, c75;      // 5/3 and 7/5
 };
 
 template <int NT>
 struct VjpSmem {
-    double4 xyzm[NT];
-    double4 abr[NT];      // scale * abar_j (3), rc_j^2
+    double4 xyzm[NT];     // x_j, y_j, z_j, 3/2 m_j
+    double4 abr[NT];      // 3/2 scale * abar_j (3), rc_j^2
 };
 
+// Fast-path weights to first order in e = 1 - r2 y^2 (y = v_rsq_f64(r2),
+// |e| < 1.1e-7; the neglected second-order terms are below 6e-14 relative):
+//   r^-3 = y^3 (1 + 3/2 e) = 3/2 y^3 (5/3 - r2 y^2)
+//   r^-5 = y^5 (1 + 5/2 e) = 5/2 y^5 (7/5 - r2 y^2).
+// Column values are staged times 3/2 (M_j = 3/2 m_j, AB_j = 3/2 abar_j), so
+// with w = y^3 (5/3 - r2 y^2) = r^-3 / (3/2) the products w AB_j, w M_j and
+// w d.AB_j are the exact terms, du = m_k d.AB_j - M_j d.abar_k = 3/2 d.u, and
+// c = y^5 (7/5 - r2 y^2) du = 3/5 r^-5 d.u, whose sum B enters xbar as -5 B
+// (the fast-path w_r / r is -3 r^-5).  The slow path stores w and c in the
+// same units.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
 {
@@ -46,7 +60,7 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
     const int64_t j0 = s * a.slice_len;
     const int64_t j1 = min(a.n, j0 + a.slice_len);
     const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
-    const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
+    const double c53 = a.c53 + (double)vzero, c75 = a.c75 + (double)vzero;
     const double4 *t_xyzm = sm.xyzm + vzero;
     const double4 *t_abr = sm.abr + vzero;
 
@@ -63,18 +77,21 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
     } else {
         xk = yk = zk = __builtin_nan("");
     }
-    double Ax = 0, Ay = 0, Az = 0, Bx = 0, By = 0, Bz = 0, Mb = 0, Rb = 0;
+    // (3/2-scaled) sums: SA = sum w abar_j, SW = sum w m_j, Mb = sum w d.abar_j,
+    // B = sum c d; xbar = mk SA - abar_k SW - 5 B (scales undone at the end).
+    double SAx = 0, SAy = 0, SAz = 0, SW = 0, Bx = 0, By = 0, Bz = 0, Mb = 0, Rb = 0;
 
     for (int64_t t0 = j0; t0 < j1; t0 += NT) {
         __syncthreads();
-        for (int q = tid; q < NT; q += NT) {
-            const int64_t jg = t0 + q;
+        {
+            const int64_t jg = t0 + tid;
             if (jg < j1) {
                 const double rcj = a.rc[jg];
                 if (!(rcj >= 0.0 && rcj < INFINITY)) atomicOr(a.status, ST_RCRIT);
-                sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], a.m[jg]);
-                sm.abr[q] = make_double4(a.scale * a.abx[jg], a.scale * a.aby[jg],
-                                         a.scale * a.abz[jg], rcj * rcj);
+                const double sc = 1.5 * a.scale;
+                sm.xyzm[tid] = make_double4(a.x[jg], a.y[jg], a.z[jg], 1.5 * a.m[jg]);
+                sm.abr[tid] = make_double4(sc * a.abx[jg], sc * a.aby[jg], sc * a.abz[jg],
+                                           rcj * rcj);
             }
         }
         __syncthreads();
@@ -85,20 +102,16 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
             const double dx = b.x - xk, dy = b.y - yk, dz = b.z - zk;
             const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
             const bool cand = r2 <= vmax_f64(rc2k, ab.w);
-            // r^-3 (refined v_rsq_f64, as in the kick) and r^-2 to first order
             const double yv = __builtin_amdgcn_rsq(r2);
             const double y2 = yv * yv;
-            const double e = __builtin_fma(-r2, y2, 1.0);
+            const double p3 = __builtin_fma(-r2, y2, c53);
+            const double p5 = __builtin_fma(-r2, y2, c75);
             const double y3 = y2 * yv;
-            const double p = __builtin_fma(e, c1875, c15);
-            double w = __builtin_fma(y3 * e, p, y3);
-            const double ri2 = __builtin_fma(y2, e, y2);
-            const double ux = __builtin_fma(mk, ab.x, -(b.w * abxk));
-            const double uy = __builtin_fma(mk, ab.y, -(b.w * abyk));
-            const double uz = __builtin_fma(mk, ab.z, -(b.w * abzk));
-            const double du = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
+            double w = y3 * p3;                       // r^-3 / (3/2)
             const double da = __builtin_fma(dz, ab.z, __builtin_fma(dy, ab.y, dx * ab.x));
-            double cq = (w * ri2) * du;   // B-coefficient: xbar = A - 3 B
+            const double db = __builtin_fma(dz, abzk, __builtin_fma(dy, abyk, dx * abxk));
+            const double du = __builtin_fma(mk, da, -(b.w * db));   // 3/2 d.u
+            double cq = ((y3 * y2) * p5) * du;                      // 3/5 r^-5 d.u
             if (cand) {
                 const int64_t jg = t0 + jj;
                 w = 0.0;
@@ -117,28 +130,32 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
                             Kp = changeover_dk(yy);
                         }
                         const double r3 = r2 * r;
-                        w = K / r3;
+                        // fast-path units: w = (K / r^3) / (3/2) and
+                        // -5 c = (w_r / r) d.u with du = 3/2 d.u
+                        w = K / r3 / 1.5;
                         const double wr_r = Kp / (0.9 * rho * r2 * r2) - 3.0 * K / (r2 * r3);
-                        cq = -(wr_r * du) / 3.0;
+                        cq = -(wr_r * du) / 7.5;
                         const bool owner = rck > rcj || (rck == rcj && k < jg);
-                        if (owner && Kp != 0.0) Rb += Kp / (0.9 * rho * rho * r2) * du;
+                        if (owner && Kp != 0.0) Rb += Kp / (0.9 * rho * rho * r2) * (du / 1.5);
                     }
                 }
             }
-            Ax = __builtin_fma(w, ux, Ax);
-            Ay = __builtin_fma(w, uy, Ay);
-            Az = __builtin_fma(w, uz, Az);
+            SAx = __builtin_fma(w, ab.x, SAx);
+            SAy = __builtin_fma(w, ab.y, SAy);
+            SAz = __builtin_fma(w, ab.z, SAz);
+            SW = __builtin_fma(w, b.w, SW);
+            Mb = __builtin_fma(w, da, Mb);
             Bx = __builtin_fma(cq, dx, Bx);
             By = __builtin_fma(cq, dy, By);
             Bz = __builtin_fma(cq, dz, Bz);
-            Mb = __builtin_fma(w, da, Mb);
         }
     }
     if (valid) {
+        // xbar = m_k sum w abar_j - abar_k sum w m_j + sum (w_r / r) d.u d
         double *P = a.part + (size_t)s * 5 * a.npad;
-        P[0 * a.npad + k] = __builtin_fma(-3.0, Bx, Ax);
-        P[1 * a.npad + k] = __builtin_fma(-3.0, By, Ay);
-        P[2 * a.npad + k] = __builtin_fma(-3.0, Bz, Az);
+        P[0 * a.npad + k] = __builtin_fma(-5.0, Bx, __builtin_fma(mk, SAx, -(abxk * SW)));
+        P[1 * a.npad + k] = __builtin_fma(-5.0, By, __builtin_fma(mk, SAy, -(abyk * SW)));
+        P[2 * a.npad + k] = __builtin_fma(-5.0, Bz, __builtin_fma(mk, SAz, -(abzk * SW)));
         P[3 * a.npad + k] = Mb;
         P[4 * a.npad + k] = Rb;
     }
@@ -290,8 +307,8 @@ hipError_t launch_kick_vjp(const genga_bodies *b, const genga_params *p, double 
     d.gx = c.gx;
     d.part = (double *)(ws + L.part);
     d.status = (int32_t *)(ws + L.status);
-    d.c15 = 1.5;
-    d.c1875 = 1.875;
+    d.c53 = 5.0 / 3.0;
+    d.c75 = 7.0 / 5.0;
     hipLaunchKernelGGL(k_kick_vjp<KB>, dim3(c.gx, c.slices), dim3(KB), 0, s, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

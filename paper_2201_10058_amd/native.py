@@ -81,6 +81,8 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "genga_step": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
                                   ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_energy": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "genga_kick_vjp": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.POINTER(Adjoint), ctypes.c_void_p, ctypes.c_void_p]),
@@ -302,6 +304,18 @@ def step(state: State, cfg: Config, ws: Workspace, pairs: PairList | None = None
     if code in (E_INVAL, E_HIP, E_UNSUPPORTED):
         raise GengaError(code, "genga_step")
     return code
+
+
+def energy(state: State, cfg: Config, ws: Workspace, out=None):
+    """Energy parts (E, T, U_*, U, C) as a float64 device tensor of 5
+    (asynchronous; read the status afterwards for coincident bodies)."""
+    if out is None:
+        out = torch.empty(5, dtype=torch.float64, device=state.t["x"].device)
+    b, p = state.bodies(), cfg.params()
+    _check(load().genga_energy(ctypes.byref(b), ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
+                               ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
+           "genga_energy")
+    return out
 
 
 # ---------------------------------------------------------------------------

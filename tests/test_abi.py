@@ -63,6 +63,7 @@ def test_host_side_argument_errors():
     bad = native.Config(G=float("nan")).params()
     assert lib.genga_hc(ctypes.byref(b), ctypes.byref(bad), 1.0, None, None) == native.E_INVAL
     assert lib.genga_read_status(None, None) == native.E_INVAL
+    assert lib.genga_energy(ctypes.byref(b), ctypes.byref(p), None, None, None) == native.E_INVAL
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 2048, 65536, 4_000_000])
