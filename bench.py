@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 2,048-body eager vs hipGraph step timing")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the mixed-precision error and energy-drift report")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -143,15 +145,12 @@ def cpu_baseline(d, rc, G, target_s):
                       f"{inter:.3e} interactions in {t_used:.1f} s"}
 
 
-def mixed_accuracy(N, W, torch, np):
+def mixed_accuracy(N, W, torch, np, checkpoints=(0, 10, 100, 1000)):
     """Mixed-precision kick against the FP64 kick on the three mixed-precision
-    disks (16,384 / 32,768 / 65,536 bodies): relative error per acceleration."""
-    out = {}
-    for n_, spec in sorted(W.DISK_MIXED.items()):
-        d = W.make_disk(spec)
-        st = N.State.from_numpy(d)
-        cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"])
-        ws = N.Workspace(n_, cfg)
+    disks (16,384 / 32,768 / 65,536 bodies) at t = 0, and on the 16,384-body
+    disk also after 10, 100 and 1000 mixed-precision steps (both kicks on the
+    state the mixed run reached): relative error per acceleration."""
+    def compare(st, cfg, ws):
         N.rcrit(st, cfg, ws)
         a64 = N.kick(st, cfg, ws, 0.0, acc=True)
         a32 = N.kick(st, N.Config(**{**cfg.__dict__, "precision": N.MIXED}), ws, 0.0, acc=True)
@@ -159,7 +158,24 @@ def mixed_accuracy(N, W, torch, np):
         if N.read_status(ws) != N.OK:
             raise SystemExit("mixed accuracy status")
         rel = ((a32 - a64).norm(dim=0) / a64.norm(dim=0)).cpu().numpy()
-        out[f"n{n_}"] = {"max_rel_err": float(rel.max()), "p99_rel_err": float(np.quantile(rel, 0.99))}
+        return {"max": float(rel.max()), "p99": float(np.quantile(rel, 0.99)),
+                "p50": float(np.quantile(rel, 0.5))}
+
+    out = {}
+    for n_, spec in sorted(W.DISK_MIXED.items()):
+        d = W.make_disk(spec)
+        st = N.State.from_numpy(d)
+        cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"])
+        ws = N.Workspace(n_, cfg)
+        out[f"n{n_}_t0"] = compare(st, cfg, ws)
+        if n_ == 16384:
+            mcfg = N.Config(**{**cfg.__dict__, "precision": N.MIXED, "flags": N.FLAG_NOSYNC})
+            done = 0
+            for t in checkpoints[1:]:
+                for _ in range(t - done):
+                    N.step(st, mcfg, ws)
+                done = t
+                out[f"n{n_}_t{t}"] = compare(st, cfg, ws)
     return out
 
 
@@ -188,6 +204,50 @@ def energy_drift(N, W, torch, np, steps=10_000, every=1000):
             "max_abs_mixed_minus_fp64": float(np.max(np.abs(drift["mixed"] - drift["fp64"])))}
 
 
+def bench_small(N, W, torch, np, steps=100):
+    """The 2,048-body disk (a launch-bound size): base steps issued one by
+    one against the same step captured once in a hipGraph and replayed."""
+    d = W.make_disk(W.DISK_2048)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                   flags=N.FLAG_NOSYNC)
+    ws = N.Workspace(st.n, cfg)
+    pairs = N.PairList(1 << 16)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    eager = timed(lambda: N.step(st, cfg, ws, pairs))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        N.step(st, cfg, ws, pairs)
+    graph = timed(g.replay)
+    if N.read_status(ws) != N.OK:
+        raise SystemExit("small-system status")
+    inter = 2.0 * st.n * (st.n - 1)
+    return {"workload": W.DISK_2048.name, "n": st.n, "steps": steps,
+            "eager_step_us": round(eager * 1e6, 2), "graph_step_us": round(graph * 1e6, 2),
+            "eager_ginter_s": round(inter / eager / 1e9, 3),
+            "graph_ginter_s": round(inter / graph / 1e9, 3)}
+
+
+def pair_list_sha256(pairs) -> str:
+    """SHA-256 of the canonical list (int32 i then int32 j, little endian)."""
+    import hashlib
+    pi, pj, _ = pairs.result()
+    h = hashlib.sha256()
+    h.update(pi.astype("<i4").tobytes())
+    h.update(pj.astype("<i4").tobytes())
+    return h.hexdigest()
+
+
 def bench_batched(args, N, W, torch, np):
     """The 512-system ensemble: one persistent kick per half step, the whole
     step captured in a hipGraph, against 512 single-system steps."""
@@ -202,6 +262,7 @@ def bench_batched(args, N, W, torch, np):
     N.step_batched(st, ws0, base)
     torch.cuda.synchronize()
     choice = autotune.tune_batched(st, bt, base)
+    tune_ms = choice.pop("ms")
     cfg = N.Config(**{**base.__dict__, **choice})
     ws = N.BatchWorkspace(bt, cfg)
     pairs = N.PairList(1 << 22)
@@ -256,7 +317,8 @@ def bench_batched(args, N, W, torch, np):
             "per_system_graph_step_ms": round(per_sys_graph_s * 1e3, 4),
             "speedup_vs_per_system_graph": round(per_sys_graph_s / graph_s, 3),
             "speedup_vs_per_system_eager": round(per_sys_s / graph_s, 3),
-            "tile_shape": {**choice, "tiles": ws.info["tiles"], "grid": ws.info["grid"]}}
+            "tile_shape": {**choice, "tiles": ws.info["tiles"], "grid": ws.info["grid"],
+                           "autotuned_kick_ms": round(tune_ms, 4)}}
 
 
 def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):
@@ -362,7 +424,9 @@ def main():
             for h in e:
                 hip.destroy(h)
         return dict(elapsed=elapsed, kick_s=float(np.mean(kick_ms)) / 1e3,
-                    pairs=int(pairs.count.item()), rc=st.t["rc"])
+                    kick_ms_median=float(np.median(kick_ms)), kick_ms_min=float(np.min(kick_ms)),
+                    pairs=int(pairs.count.item()), pairs_sha256=pair_list_sha256(pairs),
+                    rc=st.t["rc"])
 
     r64 = run(N.FP64)
     print(f"fp64 step done: {r64['elapsed'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
@@ -393,12 +457,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "n": n, "dt_days": d["dt"], "n1": d["n1"], "n2": d["n2"],
                    "kicks_per_step": 2, "encounter_pairs_last_step": r64["pairs"],
+                   "encounter_pairs_sha256_last_step": r64["pairs_sha256"],
                    "ipt": args.ipt, "slices": args.slices},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic(),
                      "kernel": "k_kick<256,1,KM_F64>", "kernel_ms": round(r64["kick_s"] * 1e3, 4),
+                     "kernel_ms_median": round(r64["kick_ms_median"], 4),
+                     "kernel_ms_min": round(r64["kick_ms_min"], 4),
                      "flop_per_interaction": FLOP_PER_INTERACTION},
     }
     if r32:
@@ -408,12 +475,16 @@ def main():
                         "achieved_tflops": round(achieved32, 3),
                         "frac_fp32_vector_peak": round(achieved32 / FP32_VECTOR_PEAK_TFLOPS, 4),
                         "speedup_vs_fp64_kernel": round(r64["kick_s"] / r32["kick_s"], 3),
-                        "encounter_pairs_last_step": r32["pairs"]}
+                        "encounter_pairs_last_step": r32["pairs"],
+                        "encounter_pairs_sha256_last_step": r32["pairs_sha256"]}
         if not args.no_accuracy:
             out["mixed"]["accuracy_vs_fp64"] = mixed_accuracy(N, W, torch, np)
             out["mixed"]["energy_drift"] = energy_drift(N, W, torch, np)
             print(f"mixed accuracy done: {out['mixed']['accuracy_vs_fp64']} "
                   f"{out['mixed']['energy_drift']}", file=sys.stderr, flush=True)
+    if not args.no_small:
+        out["small_system"] = bench_small(N, W, torch, np)
+        print(f"small system done: {out['small_system']}", file=sys.stderr, flush=True)
     st_rc = r64["rc"]
     if not args.no_adjoint:
         st_adj = N.State.from_numpy(d, rc=st_rc.cpu().numpy())

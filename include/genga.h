@@ -272,6 +272,41 @@ int genga_kick_batched(const genga_bodies *b, const genga_batch *bt, const genga
 int genga_step_batched(genga_bodies *b, const genga_batch *bt, const genga_params *p,
                        genga_pairs *pairs, void *ws, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Self-tuning of launch shapes (GENGA II tunes its kernel parameters at
+ * start-up by timing them, Sect. 8).  Candidate shapes are timed with hipEvents
+ * (median of 3 after one warm-up) on the caller's own bodies with a zero step
+ * factor, so positions and velocities are not modified (the kick's status
+ * checks still run).  The fastest shape is written into *p.  With cache_path
+ * non-null the choice is first looked up in, and after tuning appended to, a
+ * plain-text file: one line "key block ipt tile_cols grid slices ms" per
+ * problem, key = kind, device architecture, precision and problem signature
+ * (N rounded up to a power of two; or S, total N and a histogram of the system
+ * sizes); the last line of a key wins.  ms_out (nullable) receives the time
+ * of one kick with the chosen shape.  Synchronises the stream.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace for genga_autotune_batched: the largest any candidate needs. */
+size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga_params *p);
+
+/* Batched kick.  Candidates: block {64, 256} x rows per thread {1, 2} x
+ * tile_cols {256, 512, 1024, 2048} x grid {library choice, 32 waves per CU}.
+ * Writes p->block, p->ipt, p->tile_cols, p->grid (p->slices = 0).  On return
+ * ws holds the plan of the chosen shape (as after genga_batch_plan).
+ * ws_bytes >= genga_autotune_batched_workspace_bytes(bt, p), else candidates
+ * that do not fit are skipped.  GENGA_E_UNSUPPORTED if no candidate ran. */
+int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_params *p,
+                           void *ws, size_t ws_bytes, const char *cache_path, double *ms_out,
+                           void *stream);
+
+/* Workspace for genga_autotune: the largest any candidate needs. */
+size_t genga_autotune_workspace_bytes(int64_t n, const genga_params *p);
+
+/* Single-system kick.  Candidates: rows per thread {1, 2} x column slices
+ * {library choice, 8, 16, 32, 64}.  Writes p->ipt and p->slices. */
+int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_bytes,
+                   const char *cache_path, double *ms_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

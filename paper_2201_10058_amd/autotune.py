@@ -1,18 +1,15 @@
-"""Self-tuning of kick launch shapes (cf. the self-tuning kernel parameters of
-GENGA II, Sect. 8): candidate shapes are timed on the caller's own inputs and
-the fastest is kept, cached in a JSON file keyed by device architecture,
-precision and problem signature.
-
-Timing runs the kick with a zero step factor and no encounter list, so the
-caller's state is not modified.
+"""Self-tuning of kick launch shapes (cf. the start-up self-tuning of kernel
+parameters in GENGA II, Sect. 8): a thin binding of the native autotuner of
+libgenga.so (genga_autotune_batched, genga_autotune).  Candidate shapes are
+timed on the caller's own inputs with a zero step factor, so the state is not
+modified; the choice is cached in a plain-text file keyed by device
+architecture, precision and problem signature.
 """
 from __future__ import annotations
 
-import json
+import ctypes
 import os
-import statistics
 
-import numpy as np
 import torch
 
 from . import native as N
@@ -20,117 +17,51 @@ from . import native as N
 CACHE_ENV = "GENGA_TUNE_CACHE"
 
 
-def _cache_path() -> str:
+def cache_path() -> str:
+    """$GENGA_TUNE_CACHE, else ~/.cache/genga_mi355x/autotune.txt."""
     p = os.environ.get(CACHE_ENV)
-    if p:
-        return p
-    return os.path.join(os.path.expanduser("~"), ".cache", "genga_mi355x", "autotune.json")
-
-
-def _load_cache() -> dict:
+    if not p:
+        p = os.path.join(os.path.expanduser("~"), ".cache", "genga_mi355x", "autotune.txt")
     try:
-        with open(_cache_path()) as f:
-            return json.load(f)
-    except (OSError, ValueError):
-        return {}
-
-
-def _store_cache(c: dict) -> None:
-    path = _cache_path()
-    try:
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        with open(path + ".tmp", "w") as f:
-            json.dump(c, f, indent=1, sort_keys=True)
-        os.replace(path + ".tmp", path)
+        os.makedirs(os.path.dirname(p), exist_ok=True)
     except OSError:
         pass
+    return p
 
 
-def _arch() -> str:
-    props = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return getattr(props, "gcnArchName", props.name).split(":")[0]
+def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool = True) -> dict:
+    """Pick (block, ipt, tile_cols, grid) for the batched kick; returns the choice
+    (with the time of one kick in "ms")."""
+    lib = N.load()
+    bt = batch.struct()
+    p = cfg.params()
+    nbytes = lib.genga_autotune_batched_workspace_bytes(ctypes.byref(bt), ctypes.byref(p))
+    if nbytes == 0:
+        raise N.GengaError(N.E_INVAL, "genga_autotune_batched_workspace_bytes")
+    ws = torch.zeros(int(nbytes), dtype=torch.uint8, device=state.t["x"].device)
+    ms = ctypes.c_double(0.0)
+    path = cache_path().encode() if use_cache else None
+    b = state.bodies()
+    N._check(lib.genga_autotune_batched(ctypes.byref(b), ctypes.byref(bt), ctypes.byref(p),
+                                        ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(int(nbytes)),
+                                        path, ctypes.byref(ms), ctypes.c_void_p(N._stream_ptr())),
+             "genga_autotune_batched")
+    return dict(block=p.block, ipt=p.ipt, tile_cols=p.tile_cols, grid=p.grid, ms=ms.value)
 
 
-def _time(fn, reps: int = 3) -> float:
-    fn()
-    ts = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        fn()
-        e1.record()
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    return statistics.median(ts)
-
-
-def batch_signature(batch: N.Batch) -> str:
-    sizes = np.diff(batch.offsets)
-    hist = np.histogram(np.log2(sizes), bins=8, range=(0, 16))[0]
-    return f"S{batch.S}-N{batch.n}-h{'.'.join(map(str, hist))}"
-
-
-BATCH_CANDIDATES = [dict(block=b, ipt=i, tile_cols=c)
-                    for b in (64, 256) for i in (1, 2) for c in (256, 512, 1024, 2048)]
-
-
-def _batch_candidates() -> list:
-    """Tile shapes, each with the library's occupancy-sized persistent grid
-    (grid = 0) and with a grid of 32 waves per CU."""
-    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
-    out = []
-    for c in BATCH_CANDIDATES:
-        out.append({**c, "grid": 0})
-        out.append({**c, "grid": cus * (32 * 64 // c["block"])})
-    return out
-
-
-def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool = True,
-                 candidates=None, reps: int = 3) -> dict:
-    """Pick (block, ipt, tile_cols, grid) for the batched kick; returns the choice."""
-    key = f"batch2:{_arch()}:p{cfg.precision}:{batch_signature(batch)}"
-    cache = _load_cache() if use_cache else {}
-    if key in cache:
-        return cache[key]["choice"]
-    results = []
-    for cand in candidates or _batch_candidates():
-        c = N.Config(**{**cfg.__dict__, **cand, "flags": N.FLAG_NOSYNC})
-        ws = N.BatchWorkspace(batch, c)
-        ms = _time(lambda: N.kick_batched(state, ws, c, 0.0), reps)
-        results.append((ms, cand))
-        del ws
-    results.sort(key=lambda r: r[0])
-    choice = dict(results[0][1])
-    if use_cache:
-        cache[key] = {"choice": choice, "ms": results[0][0],
-                      "tried": [{"ms": m, **c} for m, c in results]}
-        _store_cache(cache)
-    return choice
-
-
-SINGLE_CANDIDATES = [dict(ipt=i, slices=s) for i in (1, 2) for s in (8, 16, 32, 64)]
-
-
-def tune_single(state: N.State, cfg: N.Config, use_cache: bool = True, candidates=None,
-                reps: int = 3) -> dict:
+def tune_single(state: N.State, cfg: N.Config, use_cache: bool = True) -> dict:
     """Pick (ipt, slices) for the single-system kick of this size."""
-    bucket = 1 << max(0, int(np.ceil(np.log2(max(state.n, 1)))))
-    key = f"single:{_arch()}:p{cfg.precision}:N{bucket}"
-    cache = _load_cache() if use_cache else {}
-    if key in cache:
-        return cache[key]["choice"]
-    results = []
-    for cand in candidates or SINGLE_CANDIDATES:
-        c = N.Config(**{**cfg.__dict__, **cand})
-        ws = N.Workspace(state.n, c)
-        ms = _time(lambda: N.kick(state, c, ws, 0.0), reps)
-        results.append((ms, cand))
-        del ws
-    results.sort(key=lambda r: r[0])
-    choice = dict(results[0][1])
-    if use_cache:
-        cache[key] = {"choice": choice, "ms": results[0][0],
-                      "tried": [{"ms": m, **c} for m, c in results]}
-        _store_cache(cache)
-    return choice
+    lib = N.load()
+    p = cfg.params()
+    nbytes = lib.genga_autotune_workspace_bytes(state.n, ctypes.byref(p))
+    if nbytes == 0:
+        raise N.GengaError(N.E_INVAL, "genga_autotune_workspace_bytes")
+    ws = torch.zeros(int(nbytes), dtype=torch.uint8, device=state.t["x"].device)
+    ms = ctypes.c_double(0.0)
+    path = cache_path().encode() if use_cache else None
+    b = state.bodies()
+    N._check(lib.genga_autotune(ctypes.byref(b), ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()),
+                                ctypes.c_size_t(int(nbytes)), path, ctypes.byref(ms),
+                                ctypes.c_void_p(N._stream_ptr())),
+             "genga_autotune")
+    return dict(ipt=p.ipt, slices=p.slices, ms=ms.value)

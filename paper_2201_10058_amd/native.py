@@ -101,6 +101,16 @@ SIGNATURES = {
                                           ctypes.POINTER(Params), ctypes.c_double, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Pairs),
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_autotune_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(BatchC),
+                                                                 ctypes.POINTER(Params)]),
+    "genga_autotune_batched": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(BatchC),
+                                              ctypes.POINTER(Params), ctypes.c_void_p,
+                                              ctypes.c_size_t, ctypes.c_char_p,
+                                              ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "genga_autotune_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.POINTER(Params)]),
+    "genga_autotune": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_char_p,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "genga_step_batched": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(BatchC),
                                           ctypes.POINTER(Params), ctypes.POINTER(Pairs),
                                           ctypes.c_void_p, ctypes.c_void_p]),

@@ -224,16 +224,40 @@ def test_batched_mixed_precision(dev):
 
 
 def test_autotune_batched_choice_is_valid(dev, tmp_path, monkeypatch):
-    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv(autotune.CACHE_ENV, str(cache))
     d = W.make_batch(sizes=SMALL_SIZES)
     st = N.State.from_numpy(d, rc=_rc_batch(d))
+    x0 = st.t["x"].clone(), st.t["vx"].clone()
     bt = _batch(d)
     cfg = N.Config(G=G)
-    choice = autotune.tune_batched(st, bt, cfg, candidates=[dict(block=64, ipt=1, tile_cols=512),
-                                                          dict(block=256, ipt=1, tile_cols=1024)])
-    assert choice in (dict(block=64, ipt=1, tile_cols=512), dict(block=256, ipt=1, tile_cols=1024))
-    assert autotune.tune_batched(st, bt, cfg) == choice        # served from the cache
-    c = N.Config(G=G, **choice)
+    choice = autotune.tune_batched(st, bt, cfg)
+    _say("autotuned batched shape", choice)
+    assert choice["block"] in (64, 256) and choice["ipt"] in (1, 2)
+    assert choice["tile_cols"] in (256, 512, 1024, 2048) and choice["grid"] >= 0
+    assert choice["ms"] > 0.0
+    # the state is untouched (zero step factor)
+    assert torch.equal(st.t["x"], x0[0]) and torch.equal(st.t["vx"], x0[1])
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("batch:")
+    again = autotune.tune_batched(st, bt, cfg)                  # served from the cache
+    assert again == choice
+    assert len(cache.read_text().splitlines()) == 1
+    shape = {k: choice[k] for k in ("block", "ipt", "tile_cols", "grid")}
+    c = N.Config(G=G, **shape)
     a = N.kick_batched(st, N.BatchWorkspace(bt, c), c, 0.0, acc=True).cpu().numpy()
     b = N.kick_batched(st, N.BatchWorkspace(bt, cfg), cfg, 0.0, acc=True).cpu().numpy()
     assert np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)) <= 1e-13
+
+
+def test_autotune_single_choice_is_valid(dev, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv(autotune.CACHE_ENV, str(cache))
+    d = W.make_disk(W.DISK_2048)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=G)
+    choice = autotune.tune_single(st, cfg)
+    _say("autotuned single shape", choice)
+    assert choice["ipt"] in (1, 2) and choice["slices"] in (0, 8, 16, 32, 64)
+    assert autotune.tune_single(st, cfg) == choice
+    assert cache.read_text().splitlines()[0].startswith("single:")
