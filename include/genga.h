@@ -144,9 +144,14 @@ int genga_rcrit(const genga_bodies *b, const genga_params *p, void *ws, void *st
  * true count is stored and the status records GENGA_E_OVERFLOW.
  * precision GENGA_MIXED: differences d in binary64 rounded to binary32,
  * binary32 distance, weight and partial sums over 64 columns, folded into
- * binary64 accumulators; every pair closer than 2 rho_ij (selected by a
+ * binary64 accumulators; every pair closer than 3 rho_ij (selected by a
  * conservative binary32 test) is evaluated entirely in binary64, and the
  * encounter test stays in binary64, so the list is identical to GENGA_FP64.
+ * A row whose binary32 terms add up in magnitude (sum m_j / r_ij^2) to more
+ * than 10 times the magnitude of their sum is evaluated again entirely in
+ * binary64 (strong cancellation would otherwise magnify the binary32 term
+ * errors); after the call the third int32 of the workspace holds the number
+ * of such rows.
  * Positions of two distinct bodies that coincide set GENGA_E_NONFINITE. */
 int genga_kick(const genga_bodies *b, const genga_params *p, double h,
                double *ax, double *ay, double *az, genga_pairs *pairs, void *ws, void *stream);
@@ -306,6 +311,22 @@ size_t genga_autotune_workspace_bytes(int64_t n, const genga_params *p);
  * {library choice, 8, 16, 32, 64}.  Writes p->ipt and p->slices. */
 int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_bytes,
                    const char *cache_path, double *ms_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the scratch buffer genga_probe_issue_rates needs on this device. */
+size_t genga_probe_issue_rates_bytes(void);
+
+/* Sustained issue cost, in cycles of a 2.4 GHz clock per wave64 instruction
+ * and per SIMD, of the vector instructions the kick is built from:
+ * cycles[0..5] = v_fma_f64, v_mul_f64, v_add_f64, v_rsq_f64, v_fma_f32,
+ * v_rsq_f32.  Each is timed (best of 3) on 8 independent chains per lane with
+ * 8 waves per SIMD, so latency is hidden.  These costs give the instruction-
+ * issue ceiling of the kick that its roofline fraction is compared with.
+ * buf: device scratch of genga_probe_issue_rates_bytes(); synchronises. */
+int genga_probe_issue_rates(double *cycles, void *buf, size_t buf_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -81,6 +81,7 @@ static int do_kick(const genga_bodies *b, const genga_params *p, double h, doubl
     k.sysid = nullptr;
     k.sys_slices = nullptr;
     k.sys_dt = nullptr;
+    k.sys_off = nullptr;
     hipError_t e = launch_kick(k, c, L, (char *)ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return GENGA_OK;

@@ -159,6 +159,7 @@ static int kick_batched(const genga_bodies *b, const genga_batch *bt, const geng
     k.sysid = bd.sysid;
     k.sys_slices = bd.sys_slices;
     k.sys_dt = bd.dt;
+    k.sys_off = bd.offsets;
     hipError_t e = launch_kick(k, sh.cfg, L, (char *)ws, (hipStream_t)stream);
     return e == hipSuccess ? GENGA_OK : hip_err(e);
 }

@@ -46,7 +46,7 @@ struct KickCfg {
 
 // Byte offsets of the workspace regions.
 struct Layout {
-    size_t status = 0;     // int32 status word, int32 tile counter (+ padding)
+    size_t status = 0;     // int32 status word, tile counter, refine count (+ padding)
     size_t part = 0;       // double [slices][5][npad]  partial sums (kick: 3, adjoint: 5)
     size_t cnt = 0;        // int32  [slices][npad]     per-slice pair counts
     size_t rowloc = 0;     // int32  [npad]             row offset inside its 256-row block
@@ -54,6 +54,7 @@ struct Layout {
     size_t stage = 0;      // int32  [nwaves][WSEG][3]  staged (i, j, rank)
     size_t wcount = 0;     // int32  [nwaves]           staged pairs per wave
     size_t hc = 0;         // double [nb][3]            momentum partials
+    size_t rlist = 0;      // int32  [npad]             mixed: rows to evaluate in binary64
     size_t P = 0;          // batch: double [S][3]      momentum per system
     size_t tiles = 0;      // batch: TileDesc [ntiles]
     size_t sysid = 0;      // batch: int32 [npad]
@@ -87,6 +88,7 @@ struct KickLaunch {
     const int32_t *sysid;      // batch: system of each body
     const int32_t *sys_slices; // batch: column slices per system
     const double *sys_dt;      // batch: time step per system
+    const int64_t *sys_off;    // batch: device offsets of the systems
 };
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
                        hipStream_t s);

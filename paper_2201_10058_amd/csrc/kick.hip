@@ -27,6 +27,8 @@
 //    into canonical positions (i ascending, j ascending).  A wave whose segment
 //    overflows is recomputed exactly by k_pairs_scatter.
 #include "genga_internal.h"
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace genga {
@@ -40,12 +42,13 @@ struct KickDev {
     int64_t ntiles;
     int gx;               // implicit: row blocks
     int64_t slice_len;    // implicit: columns per slice
-    double *part;         // [slices][3][npad]
+    double *part;         // [slices][3][npad] (mixed: [slices][4][npad], 4th = sum m/r^2)
     int32_t *cnt;         // [slices][npad]
     int32_t *stage;       // [nwaves][WSEG][3]
     int32_t *wcount;      // [nwaves]
     int32_t *status;
     int32_t *queue;       // batch: next tile to take (reset to 0 by k_kick_reduce)
+    int32_t *refine_cnt;  // mixed: rows listed for binary64 evaluation (reset here)
     int emit;
     double c15, c1875;    // 3/2 and 15/8
     double c53;           // 5/3
@@ -82,6 +85,8 @@ struct Rows {
     double ax[IPT], ay[IPT], az[IPT];
     float rc2fi[IPT];                    // mixed: widened binary32 pre-check radius
     float axf[IPT], ayf[IPT], azf[IPT];  // mixed: binary32 partial sums
+    float magf[IPT];                     // mixed: binary32 partial sum of m_j / r^2 (far pairs)
+    double mag[IPT];                     // mixed: its binary64 accumulator
     int64_t ii[IPT];
     int kc[IPT];
 };
@@ -146,6 +151,11 @@ __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int 
 // below 1e-6 even for bodies whose net acceleration is 50-90 times smaller
 // than the sum of the magnitudes of its terms.
 constexpr double MIXED_NEAR = 3.0;
+// Rows whose binary32 terms sum (in magnitude) to more than MIXED_KAPPA times
+// the magnitude of their total are evaluated again in binary64: the binary32
+// terms carry relative errors of a few 2^-24, so without this the error of a
+// strongly cancelling row grows with that ratio.
+constexpr double MIXED_KAPPA = 10.0;
 constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
 
 // One column j against the lane's rows (the hot loop body).
@@ -173,10 +183,12 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
             const float yv = __builtin_amdgcn_rsqf(r2f);
             const float y2 = yv * yv;
             float sc = mjf * (y2 * yv);
+            float mt = mjf;   // magnitude m_j / r^2 of the binary32 terms
             if (near) {
                 // near pairs are evaluated in binary64; those inside rho_ij
                 // (and the self pair) take the changeover / encounter path
                 sc = 0.0f;
+                mt = 0.0f;
                 const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
                 const double mj = *mj64;
                 const double rc2j_ = *rc2j64;
@@ -198,6 +210,7 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
             R.axf[q] = __builtin_fmaf(dxf, sc, R.axf[q]);
             R.ayf[q] = __builtin_fmaf(dyf, sc, R.ayf[q]);
             R.azf[q] = __builtin_fmaf(dzf, sc, R.azf[q]);
+            R.magf[q] = __builtin_fmaf(mt, y2, R.magf[q]);
         }
         return;
     }
@@ -245,7 +258,8 @@ __device__ __forceinline__ void fold(Rows<IPT> &R)
         R.ax[q] += (double)R.axf[q];
         R.ay[q] += (double)R.ayf[q];
         R.az[q] += (double)R.azf[q];
-        R.axf[q] = R.ayf[q] = R.azf[q] = 0.0f;
+        R.mag[q] += (double)R.magf[q];
+        R.axf[q] = R.ayf[q] = R.azf[q] = R.magf[q] = 0.0f;
     }
 }
 
@@ -300,8 +314,8 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
             R.rc2i[q] = 0.0;
         }
         R.rc2fi[q] = (float)(R.rc2i[q] * a.widen);
-        R.ax[q] = R.ay[q] = R.az[q] = 0.0;
-        R.axf[q] = R.ayf[q] = R.azf[q] = 0.0f;
+        R.ax[q] = R.ay[q] = R.az[q] = R.mag[q] = 0.0;
+        R.axf[q] = R.ayf[q] = R.azf[q] = R.magf[q] = 0.0f;
         R.kc[q] = 0;
     }
     int *wcnt = &sm.wcnt[w];
@@ -349,9 +363,11 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
     for (int q = 0; q < IPT; ++q) {
         if (R.ii[q] < rowend) {
             if (MODE != KM_PAIRS) {
-                a.part[((size_t)s * 3 + 0) * a.npad + R.ii[q]] = R.ax[q];
-                a.part[((size_t)s * 3 + 1) * a.npad + R.ii[q]] = R.ay[q];
-                a.part[((size_t)s * 3 + 2) * a.npad + R.ii[q]] = R.az[q];
+                constexpr int PS = MODE == KM_MIXED ? 4 : 3;
+                a.part[((size_t)s * PS + 0) * a.npad + R.ii[q]] = R.ax[q];
+                a.part[((size_t)s * PS + 1) * a.npad + R.ii[q]] = R.ay[q];
+                a.part[((size_t)s * PS + 2) * a.npad + R.ii[q]] = R.az[q];
+                if (MODE == KM_MIXED) a.part[((size_t)s * PS + 3) * a.npad + R.ii[q]] = R.mag[q];
             }
             if (a.emit) a.cnt[(size_t)s * a.npad + R.ii[q]] = R.kc[q];
         }
@@ -366,6 +382,7 @@ __global__ __launch_bounds__(NT) void k_kick(KickDev a)
 {
     __shared__ KickSmem<NT> sm;
     const int64_t t = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (MODE == KM_MIXED && t == 0 && threadIdx.x == 0) *a.refine_cnt = 0;
     process_tile<NT, IPT, MODE>(a, sm, get_tile<NT, IPT>(a, t), t);
 }
 
@@ -379,6 +396,7 @@ __global__ __launch_bounds__(NT) void k_kick_persistent(KickDev a)
 {
     __shared__ KickSmem<NT> sm;
     __shared__ int next;
+    if (MODE == KM_MIXED && blockIdx.x == 0 && threadIdx.x == 0) *a.refine_cnt = 0;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(a.queue, 1);
         __syncthreads();
@@ -406,6 +424,9 @@ struct ReduceDev {
     double G, h, hfac;            // v += h a (single) or hfac * dt_s * a (batched)
     int forces, emit;
     int32_t *queue;               // batch: tile counter of the kick, reset here
+    int pstride;                  // partial values per row and slice (3; mixed 4)
+    double kappa2;                // mixed: square of the refinement threshold (else 0)
+    int32_t *refine_list, *refine_cnt;
 };
 
 __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
@@ -426,20 +447,36 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double acc = 0.0;
-            for (int s = 0; s < nsl; ++s) acc += r.part[((size_t)s * 3 + c) * r.npad + i];
-            a3[c] = r.G * acc;
+            for (int s = 0; s < nsl; ++s) acc += r.part[((size_t)s * r.pstride + c) * r.npad + i];
+            a3[c] = acc;
         }
-        if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
-            atomicOr(r.status, ST_NONFINITE);
-        if (h != 0.0) {
-            r.vx[i] = __builtin_fma(h, a3[0], r.vx[i]);
-            r.vy[i] = __builtin_fma(h, a3[1], r.vy[i]);
-            r.vz[i] = __builtin_fma(h, a3[2], r.vz[i]);
+        bool refine = false;
+        if (r.kappa2 > 0.0) {
+            // mixed: a row whose binary32 terms are large against their sum
+            // (sum_j m_j / r^2 > kappa |sum_j m_j d / r^3|) is evaluated
+            // again in binary64 by k_kick_refine
+            double mag = 0.0;
+            for (int s = 0; s < nsl; ++s) mag += r.part[((size_t)s * r.pstride + 3) * r.npad + i];
+            const double a2 = a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2];
+            refine = !(mag * mag <= r.kappa2 * a2);
         }
-        if (r.ax) {
-            r.ax[i] = a3[0];
-            r.ay[i] = a3[1];
-            r.az[i] = a3[2];
+        if (refine) {
+            r.refine_list[atomicAdd(r.refine_cnt, 1)] = (int32_t)i;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a3[c] *= r.G;
+            if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
+                atomicOr(r.status, ST_NONFINITE);
+            if (h != 0.0) {
+                r.vx[i] = __builtin_fma(h, a3[0], r.vx[i]);
+                r.vy[i] = __builtin_fma(h, a3[1], r.vy[i]);
+                r.vz[i] = __builtin_fma(h, a3[2], r.vz[i]);
+            }
+            if (r.ax) {
+                r.ax[i] = a3[0];
+                r.ay[i] = a3[1];
+                r.az[i] = a3[2];
+            }
         }
     }
     if (r.emit) {
@@ -455,6 +492,107 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
         const int64_t ex = block_excl_scan<RB>(c, &tot, sm);
         if (valid) r.rowloc[i] = (int32_t)ex;
         if (threadIdx.x == 0) r.bsum[blockIdx.x] = tot;
+    }
+}
+
+// Mixed mode: binary64 kick of the rows listed by k_kick_reduce, one block
+// per row (threads stride over the row's columns, then a fixed-order block
+// sum), with the arithmetic of the binary64 kick.  The grid is fixed (the
+// row count is read on the device), so the launch can be captured.
+struct RefineDev {
+    const double *x, *y, *z, *m, *rc;
+    double *vx, *vy, *vz;
+    double *ax, *ay, *az;
+    int64_t n;
+    const int32_t *list, *count;
+    const int32_t *sysid;          // batched (else null)
+    const int64_t *sys_off;        // batched: system offsets
+    const double *sys_dt;          // batched: time step per system
+    double G, h, hfac;
+    double c53;
+    int32_t *status;
+};
+
+constexpr int FB = 256;   // threads per refine block
+
+__global__ __launch_bounds__(FB) void k_kick_refine(RefineDev a)
+{
+    __shared__ double sm[3][FB / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+    const double c53 = a.c53 + (double)vzero;
+    const int cnt = *a.count;
+    for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
+        const int64_t i = a.list[p];
+        int64_t c0 = 0, c1 = a.n;
+        double h = a.h;
+        if (a.sysid) {
+            const int sy = a.sysid[i];
+            c0 = a.sys_off[sy];
+            c1 = a.sys_off[sy + 1];
+            h = a.hfac * a.sys_dt[sy];
+        }
+        const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
+        const double rc2i = rci * rci;
+        double sx = 0.0, sy_ = 0.0, sz = 0.0;
+        for (int64_t j = c0 + threadIdx.x; j < c1; j += FB) {
+            const double dx = a.x[j] - xi, dy = a.y[j] - yi, dz = a.z[j] - zi;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double rcj = a.rc[j];
+            const double mj = a.m[j];
+            double wk;
+            if (r2 <= vmax_f64(rc2i, rcj * rcj)) {
+                wk = 0.0;
+                if (j != i && r2 > 0.0) {
+                    const double r = __builtin_sqrt(r2);
+                    double K = 1.0;
+                    if (r2 < rho2_of(rci, rcj)) K = changeover_k(r, rci > rcj ? rci : rcj);
+                    wk = mj * K / (r2 * r);
+                }
+                // coincident bodies are reported by the main kick
+            } else {
+                const double yv = __builtin_amdgcn_rsq(r2);
+                const double y2 = yv * yv;
+                const double q = __builtin_fma(-r2, y2, c53);
+                wk = ((1.5 * mj) * (y2 * yv)) * q;
+            }
+            sx = __builtin_fma(dx, wk, sx);
+            sy_ = __builtin_fma(dy, wk, sy_);
+            sz = __builtin_fma(dz, wk, sz);
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            sx += __shfl_xor(sx, off);
+            sy_ += __shfl_xor(sy_, off);
+            sz += __shfl_xor(sz, off);
+        }
+        if (lane == 0) {
+            sm[0][w] = sx;
+            sm[1][w] = sy_;
+            sm[2][w] = sz;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a3[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double t = 0.0;
+                for (int k = 0; k < FB / 64; ++k) t += sm[c][k];
+                a3[c] = a.G * t;
+            }
+            if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
+                atomicOr(a.status, ST_NONFINITE);
+            if (h != 0.0) {
+                a.vx[i] = __builtin_fma(h, a3[0], a.vx[i]);
+                a.vy[i] = __builtin_fma(h, a3[1], a.vy[i]);
+                a.vz[i] = __builtin_fma(h, a3[2], a.vz[i]);
+            }
+            if (a.ax) {
+                a.ax[i] = a3[0];
+                a.ay[i] = a3[1];
+                a.az[i] = a3[2];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -606,6 +744,8 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     off = align256(off + sizeof(int32_t) * (size_t)c.nwaves);
     L.hc = off;
     off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
+    L.rlist = off;
+    off = align256(off + sizeof(int32_t) * (size_t)L.npad);
     if (S > 0) {
         L.P = off;
         off = align256(off + sizeof(double) * 3 * (size_t)S);
@@ -677,6 +817,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     d.wcount = (int32_t *)(ws + L.wcount);
     d.status = (int32_t *)(ws + L.status);
     d.queue = k.tiles ? (int32_t *)(ws + L.status) + 1 : nullptr;
+    d.refine_cnt = (int32_t *)(ws + L.status) + 2;
     d.emit = k.pairs != nullptr;
     d.c15 = 1.5;
     d.c53 = 5.0 / 3.0;
@@ -692,6 +833,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
         if (e != hipSuccess) return e;
     }
     const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
+    const bool refine = mode == KM_MIXED;
     if (c.nt == 64) {
         if (c.ipt == 2) launch_mode<64, 2>(d, c, mode, s);
         else launch_mode<64, 1>(d, c, mode, s);
@@ -701,7 +843,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (k.ev1) {
+    if (k.ev1 && !refine) {
         e = hipEventRecord((hipEvent_t)k.ev1, s);
         if (e != hipSuccess) return e;
     }
@@ -721,10 +863,38 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.forces = k.forces;
     r.emit = d.emit;
     r.queue = d.queue;
+    r.pstride = refine ? 4 : 3;
+    r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
+    r.refine_list = (int32_t *)(ws + L.rlist);
+    r.refine_cnt = d.refine_cnt;
     if (r.forces || r.emit) {
         hipLaunchKernelGGL(k_kick_reduce, dim3((unsigned)L.nb), dim3(RB), 0, s, r);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+    }
+    if (refine) {
+        RefineDev f;
+        f.x = k.x; f.y = k.y; f.z = k.z; f.m = k.m; f.rc = k.rc;
+        f.vx = k.vx; f.vy = k.vy; f.vz = k.vz;
+        f.ax = k.ax; f.ay = k.ay; f.az = k.az;
+        f.n = k.n;
+        f.list = r.refine_list;
+        f.count = r.refine_cnt;
+        f.sysid = k.sysid;
+        f.sys_off = k.sys_off;
+        f.sys_dt = k.sys_dt;
+        f.G = k.G; f.h = k.h; f.hfac = k.hfac;
+        f.c53 = 5.0 / 3.0;
+        f.status = d.status;
+        // enough blocks for a few percent of the rows at one row per block
+        const int64_t blocks = std::min<int64_t>(std::max<int64_t>(k.n, 1), 2048);
+        hipLaunchKernelGGL(k_kick_refine, dim3((unsigned)blocks), dim3(FB), 0, s, f);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (k.ev1) {
+            e = hipEventRecord((hipEvent_t)k.ev1, s);
+            if (e != hipSuccess) return e;
+        }
     }
     if (!d.emit) return hipSuccess;
 

@@ -104,3 +104,68 @@ def test_mixed_step_pairs_match_oracle(dev):
         pi, pj, cnt = pl.result()
         opi, opj, ocnt = oracle.pairs(x0["x"], x0["y"], x0["z"], st.t["rc"].cpu().numpy())
         assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
+
+
+def _refined_rows(ws) -> int:
+    # the third int32 of the workspace: rows of the last mixed kick that were
+    # evaluated again in binary64 (documented with genga_kick)
+    return int(ws.buf[:12].view(torch.int32)[2].item())
+
+
+def test_mixed_refines_cancelling_rows(dev):
+    # a body close to the centre of a ring of 4,096 equal masses: its terms
+    # cancel almost completely (sum |a_ij| / |a_i| ~ 10^3), so the binary32
+    # sum alone could not reach 1e-6; the kick must evaluate it in binary64
+    ring = W.make_ring(4096)
+    d = {k: np.append(ring[k], v) for k, v in
+         (("x", 1e-3), ("y", 2e-3), ("z", 1e-4), ("vx", 0.0), ("vy", 0.0), ("vz", 0.0),
+          ("m", 1e-9), ("rc", 1e-3))}
+    n = d["x"].size
+    st = N.State.from_numpy(d, rc=d["rc"])
+    cfg = N.Config(G=G, precision=N.MIXED)
+    ws = N.Workspace(n, cfg)
+    a = N.kick(st, cfg, ws, 0.0, acc=True).cpu().numpy()
+    assert N.read_status(ws) == N.OK
+    refined = _refined_rows(ws)
+    ax, ay, az, _ = oracle.kick_acc(d["x"], d["y"], d["z"], d["m"], d["rc"], G, precise=True)
+    ref = np.stack([ax, ay, az])
+    err = _rel(a, ref)
+    mags = G * d["m"][:-1] / np.sum((np.stack([d[c][:-1] for c in "xyz"]) -
+                                    np.array([[d[c][-1]] for c in "xyz"])) ** 2, axis=0)
+    kappa = mags.sum() / np.linalg.norm(ref[:, -1])
+    _say("ring + centre body: kappa", kappa, "centre error", err[-1], "max", err.max(),
+         "refined rows", refined)
+    assert kappa > 100
+    assert refined >= 1
+    assert err[-1] <= 1e-9
+    assert err.max() <= MIXED_TOL
+
+
+def test_mixed_evolved_disk16384(dev):
+    # after 100 mixed-precision steps the disk holds bodies with stronger
+    # cancellation than the initial state; every body against the FP64 kick
+    # on the same state, the worst ones against the oracle
+    d = W.make_disk(W.DISK_MIXED[16384])
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=G, m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"], precision=N.MIXED,
+                   flags=N.FLAG_NOSYNC)
+    ws = N.Workspace(st.n, cfg)
+    for _ in range(100):
+        N.step(st, cfg, ws)
+    assert N.read_status(ws) == N.OK
+    N.rcrit(st, cfg, ws)
+    a32 = N.kick(st, cfg, ws, 0.0, acc=True).cpu().numpy()
+    refined = _refined_rows(ws)
+    c64 = N.Config(**{**cfg.__dict__, "precision": N.FP64})
+    a64 = N.kick(st, c64, ws, 0.0, acc=True).cpu().numpy()
+    assert N.read_status(ws) == N.OK
+    err = _rel(a32, a64)
+    _say(f"evolved mixed: max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e} refined rows {refined}")
+    assert err.max() <= MIXED_TOL
+    s = st.numpy()
+    rc = st.t["rc"].cpu().numpy()
+    for r in np.argsort(err)[::-1][:8]:
+        ax, ay, az, _ = oracle.kick_acc(s["x"], s["y"], s["z"], s["m"], rc, G, rows=(int(r), int(r) + 1),
+                                        precise=True)
+        ref = np.array([ax[0], ay[0], az[0]])
+        assert np.linalg.norm(a32[:, r] - ref) <= MIXED_TOL * np.linalg.norm(ref)

@@ -295,3 +295,29 @@ def test_kick_disk65536_sampled(dev, ipt):
     assert np.max(np.abs(P)) <= 1e-13 * (d["m"] * np.abs(a)).sum()
     opi, opj, ocnt = oracle.pairs(d["x"], d["y"], d["z"], rc)
     assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
+
+
+def test_step_pairs_disk65536_every_100_steps(dev):
+    # 1000 base steps of the 65,536-body disk; every 100 steps the encounter
+    # list of the step (first half kick, positions the step starts from) is
+    # compared with the oracle's brute force on the same positions and r_crit
+    d = W.make_disk(W.DISK_65536)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=G, m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"], flags=N.FLAG_NOSYNC)
+    ws = N.Workspace(st.n, cfg)
+    pl = N.PairList(1 << 20)
+    checked = 0
+    for k in range(1000):
+        if k % 100 == 0:
+            x0 = {c: st.t[c].cpu().numpy().copy() for c in "xyz"}
+        N.step(st, cfg, ws, pl)
+        if k % 100 == 0:
+            assert N.read_status(ws) == N.OK
+            pi, pj, cnt = pl.result()
+            rc = st.t["rc"].cpu().numpy()
+            opi, opj, ocnt = oracle.pairs(x0["x"], x0["y"], x0["z"], rc, cap=1 << 20)
+            _say(f"step {k}: {cnt} pairs, oracle {ocnt}")
+            assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
+            checked += 1
+    assert N.read_status(ws) == N.OK
+    assert checked == 10
