@@ -365,7 +365,12 @@ def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):
     V = torch.tensor(np.stack([d["vx"], d["vy"], d["vz"]]), device="cuda", requires_grad=True)
     m = torch.tensor(d["m"], device="cuda", requires_grad=True)
     cfg = N.Config(G=d["G"])
+    # warm-up: one short differentiated trajectory
+    XT, _ = A.simulate(X, V, m, 20, cfg, checkpoint_every=20)
+    torch.autograd.grad((XT ** 2).sum(), (X, V, m))
     torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     t0 = time.perf_counter()
     XT, VT = A.simulate(X, V, m, 200, cfg, checkpoint_every=20)
     L = (XT ** 2).sum()
@@ -374,11 +379,14 @@ def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):
     torch.autograd.grad(L, (X, V, m))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    peak = torch.cuda.max_memory_allocated() - base
     return {"kick_vjp_ms_n65536": round(vjp_ms, 4),
             "kick_vjp_ginter_s": round(n * (n - 1) / vjp_ms / 1e6, 3),
             "trajectory_n4096_200_steps_forward_s": round(t1 - t0, 4),
             "trajectory_n4096_200_steps_backward_s": round(t2 - t1, 4),
-            "backward_over_forward": round((t2 - t1) / (t1 - t0), 3)}
+            "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+            "checkpoint_every": 20,
+            "peak_device_bytes_forward_backward": int(peak)}
 
 
 def main():

@@ -21,6 +21,20 @@ __device__ __forceinline__ double changeover_k(double r, double rho)
     return y2 / (2.0 * y2 - 2.0 * yv + 1.0);
 }
 
+// K(y) of the same changeover on a precomputed y: the division by
+// 2y^2 - 2y + 1 (in [1/2, 1] on the band) by v_rcp_f64 and two Newton steps.
+__device__ __forceinline__ double changeover_of_y(double yv)
+{
+    if (!(yv > 0.0)) return 0.0;
+    if (yv >= 1.0) return 1.0;
+    const double y2 = yv * yv;
+    const double q = __builtin_fma(2.0, y2 - yv, 1.0);
+    double t = __builtin_amdgcn_rcp(q);
+    t = __builtin_fma(t, __builtin_fma(-q, t, 1.0), t);
+    t = __builtin_fma(t, __builtin_fma(-q, t, 1.0), t);
+    return y2 * t;
+}
+
 // max of two non-negative doubles in one v_max_f64 (the generic fmax adds
 // NaN-quieting canonicalisations; the critical radii are validated instead).
 __device__ __forceinline__ double vmax_f64(double a, double b)

@@ -82,6 +82,7 @@ enum KickMode : int {
 template <int IPT>
 struct Rows {
     double xi[IPT], yi[IPT], zi[IPT], rc2i[IPT];
+    double iri[IPT];                     // 1 / rc_i
     double ax[IPT], ay[IPT], az[IPT];
     float rc2fi[IPT];                    // mixed: widened binary32 pre-check radius
     float axf[IPT], ayf[IPT], azf[IPT];  // mixed: binary32 partial sums
@@ -93,11 +94,15 @@ struct Rows {
 
 // Rare path of one interaction: self pair, coincident bodies, changeover band
 // (K < 1) and encounter-pair recording.  r2 is the exact binary64 squared
-// separation.  Returns the weight m_j K / r^3.
+// separation, rc2j = rc_j^2 and irj = 1 / rc_j.  Returns the weight
+// m_j K / r^3.  1/r comes from v_rsq_f64 with one Newton correction
+// (relative error below 5e-15); with 1/rho = min(1/rc_i, 1/rc_j) (division
+// is monotone, so this is exactly fl(1 / max(rc_i, rc_j))) the band variable
+// is y = (r/rho) / 0.9 - 1/9.  No global memory is read on this path.
 template <int IPT, bool FORCES>
 __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int q, int64_t jg,
-                                            double r2, double rc2j, double mj, int64_t wave_g,
-                                            int *wcnt)
+                                            double r2, double rc2j, double irj, double mj,
+                                            int64_t wave_g, int *wcnt)
 {
     bool emit = false;
     double wk = 0.0;
@@ -109,14 +114,15 @@ __device__ __forceinline__ double slow_pair(const KickDev &a, Rows<IPT> &R, int 
             const bool inside = r2 < rho2;
             emit = inside && (jg > R.ii[q]);
             if (FORCES) {
-                const double r = __builtin_sqrt(r2);
+                const double y = __builtin_amdgcn_rsq(r2);
+                const double e = __builtin_fma(-r2, y * y, 1.0);
+                const double yc = __builtin_fma(y * e, 0.5, y);
                 double K = 1.0;
                 if (inside) {
-                    const double rci = a.rc[R.ii[q]];
-                    const double rcj = a.rc[jg];
-                    K = changeover_k(r, rci > rcj ? rci : rcj);
+                    const double irho = R.iri[q] < irj ? R.iri[q] : irj;
+                    K = changeover_of_y(__builtin_fma((r2 * yc) * irho, 1.0 / 0.9, -1.0 / 9.0));
                 }
-                wk = mj * K / (r2 * r);
+                wk = (mj * K) * (yc * yc * yc);
             }
         }
     }
@@ -166,7 +172,7 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
                                          const double rc2j, const int64_t jg, const double c15,
                                          const double c1875, const double c53, const int64_t wave_g,
                                          int *wcnt, const double *rc2j64,
-                                         const double *mj64)
+                                         const double *mj64, const double *irj64)
 {
     if (MODE == KM_MIXED) {
         const float mjf = __int_as_float(__double2loint(b.w));
@@ -181,12 +187,12 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
             // conservative binary32 test for "closer than MIXED_NEAR rho_ij"
             const bool near = r2f <= vmax_f32(R.rc2fi[q], rc2fj);
             const float yv = __builtin_amdgcn_rsqf(r2f);
-            const float y2 = yv * yv;
-            float sc = mjf * (y2 * yv);
-            float mt = mjf;   // magnitude m_j / r^2 of the binary32 terms
+            float mt = mjf * (yv * yv);   // magnitude m_j / r^2 of the binary32 term
+            float sc = mt * yv;
             if (near) {
                 // near pairs are evaluated in binary64; those inside rho_ij
-                // (and the self pair) take the changeover / encounter path
+                // (and the self pair, whose binary32 values are infinite)
+                // take the changeover / encounter path
                 sc = 0.0f;
                 mt = 0.0f;
                 const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
@@ -194,7 +200,7 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
                 const double rc2j_ = *rc2j64;
                 double wk;
                 if (r2 <= vmax_f64(R.rc2i[q], rc2j_)) {
-                    wk = slow_pair<IPT, true>(a, R, q, jg, r2, rc2j_, mj, wave_g, wcnt);
+                    wk = slow_pair<IPT, true>(a, R, q, jg, r2, rc2j_, *irj64, mj, wave_g, wcnt);
                 } else {
                     const double y = __builtin_amdgcn_rsq(r2);
                     const double yy = y * y;
@@ -210,7 +216,7 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
             R.axf[q] = __builtin_fmaf(dxf, sc, R.axf[q]);
             R.ayf[q] = __builtin_fmaf(dyf, sc, R.ayf[q]);
             R.azf[q] = __builtin_fmaf(dzf, sc, R.azf[q]);
-            R.magf[q] = __builtin_fmaf(mt, y2, R.magf[q]);
+            R.magf[q] += mt;
         }
         return;
     }
@@ -239,7 +245,7 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
             const double y3 = y2 * yv;
             sc = (b.w * y3) * p;
         }
-        if (cand) sc = slow_pair<IPT, FORCES>(a, R, q, jg, r2, rc2j, *mj64, wave_g, wcnt);
+        if (cand) sc = slow_pair<IPT, FORCES>(a, R, q, jg, r2, rc2j, *irj64, *mj64, wave_g, wcnt);
         if (FORCES) {
             R.ax[q] = __builtin_fma(dx, sc, R.ax[q]);
             R.ay[q] = __builtin_fma(dy, sc, R.ay[q]);
@@ -269,6 +275,7 @@ struct KickSmem {
     double4 xyzm[NT];
     double rc2[NT];
     double m[NT];
+    double irc[NT];     // 1 / rc_j
     int wcnt[4];
 };
 
@@ -297,6 +304,7 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
     const double4 *t_xyzm = sm.xyzm + vzero;
     const double *t_rc2 = sm.rc2 + vzero;
     const double *t_m = sm.m + vzero;
+    const double *t_irc = sm.irc + vzero;
 
     Rows<IPT> R;
 #pragma unroll
@@ -308,10 +316,12 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
             R.zi[q] = a.z[R.ii[q]];
             const double r = a.rc[R.ii[q]];
             R.rc2i[q] = r * r;
+            R.iri[q] = 1.0 / r;
         } else {
             // rows past the end: NaN positions never enter the slow path
             R.xi[q] = R.yi[q] = R.zi[q] = __builtin_nan("");
             R.rc2i[q] = 0.0;
+            R.iri[q] = 0.0;
         }
         R.rc2fi[q] = (float)(R.rc2i[q] * a.widen);
         R.ax[q] = R.ay[q] = R.az[q] = R.mag[q] = 0.0;
@@ -340,6 +350,7 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
                     sm.m[q] = mj;
                 }
                 sm.rc2[q] = rcj * rcj;
+                if (MODE != KM_PAIRS) sm.irc[q] = 1.0 / rcj;
             }
         }
         __syncthreads();
@@ -350,12 +361,12 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
             for (int u = 0; u < 4; ++u)
                 interact<IPT, MODE>(a, R, t_xyzm[jj + u], MODE == KM_MIXED ? 0.0 : t_rc2[jj + u],
                                     t0 + jj + u, c15, c1875, c53, wave_g, wcnt, t_rc2 + jj + u,
-                                    t_m + jj + u);
+                                    t_m + jj + u, t_irc + jj + u);
             if ((jj & (FOLD - 1)) == FOLD - 4) fold<IPT, MODE>(R);
         }
         for (; jj < tn; ++jj)
             interact<IPT, MODE>(a, R, t_xyzm[jj], MODE == KM_MIXED ? 0.0 : t_rc2[jj], t0 + jj, c15,
-                                c1875, c53, wave_g, wcnt, t_rc2 + jj, t_m + jj);
+                                c1875, c53, wave_g, wcnt, t_rc2 + jj, t_m + jj, t_irc + jj);
         fold<IPT, MODE>(R);
     }
 

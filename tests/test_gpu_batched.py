@@ -241,9 +241,10 @@ def test_autotune_batched_choice_is_valid(dev, tmp_path, monkeypatch):
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and lines[0].startswith("batch:")
     again = autotune.tune_batched(st, bt, cfg)                  # served from the cache
-    assert again == choice
-    assert len(cache.read_text().splitlines()) == 1
     shape = {k: choice[k] for k in ("block", "ipt", "tile_cols", "grid")}
+    assert {k: again[k] for k in shape} == shape
+    assert again["ms"] == pytest.approx(choice["ms"], rel=1e-5)
+    assert len(cache.read_text().splitlines()) == 1
     c = N.Config(G=G, **shape)
     a = N.kick_batched(st, N.BatchWorkspace(bt, c), c, 0.0, acc=True).cpu().numpy()
     b = N.kick_batched(st, N.BatchWorkspace(bt, cfg), cfg, 0.0, acc=True).cpu().numpy()
@@ -259,5 +260,6 @@ def test_autotune_single_choice_is_valid(dev, tmp_path, monkeypatch):
     choice = autotune.tune_single(st, cfg)
     _say("autotuned single shape", choice)
     assert choice["ipt"] in (1, 2) and choice["slices"] in (0, 8, 16, 32, 64)
-    assert autotune.tune_single(st, cfg) == choice
+    again = autotune.tune_single(st, cfg)
+    assert (again["ipt"], again["slices"]) == (choice["ipt"], choice["slices"])
     assert cache.read_text().splitlines()[0].startswith("single:")

@@ -162,6 +162,8 @@ def test_mixed_evolved_disk16384(dev):
     err = _rel(a32, a64)
     _say(f"evolved mixed: max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e} refined rows {refined}")
     assert err.max() <= MIXED_TOL
+    # the refinement is for the strongly cancelling few, not the bulk
+    assert 0 < refined < st.n // 10
     s = st.numpy()
     rc = st.t["rc"].cpu().numpy()
     for r in np.argsort(err)[::-1][:8]:
