@@ -35,6 +35,30 @@ __device__ __forceinline__ double changeover_of_y(double yv)
     return y2 * t;
 }
 
+// K(y) and dK/dy = 2y(1 - y) / q^2, q = 2y^2 - 2y + 1, with one reciprocal
+// of q (v_rcp_f64 and two Newton steps); both zero below the band, K = 1 and
+// dK/dy = 0 above it.
+__device__ __forceinline__ void changeover_kdk_of_y(double yv, double &K, double &dK)
+{
+    if (!(yv > 0.0)) {
+        K = 0.0;
+        dK = 0.0;
+        return;
+    }
+    if (yv >= 1.0) {
+        K = 1.0;
+        dK = 0.0;
+        return;
+    }
+    const double y2 = yv * yv;
+    const double q = __builtin_fma(2.0, y2 - yv, 1.0);
+    double t = __builtin_amdgcn_rcp(q);
+    t = __builtin_fma(t, __builtin_fma(-q, t, 1.0), t);
+    t = __builtin_fma(t, __builtin_fma(-q, t, 1.0), t);
+    K = y2 * t;
+    dK = (2.0 * (yv - y2)) * (t * t);
+}
+
 // max of two non-negative doubles in one v_max_f64 (the generic fmax adds
 // NaN-quieting canonicalisations; the critical radii are validated instead).
 __device__ __forceinline__ double vmax_f64(double a, double b)
@@ -62,14 +86,6 @@ __device__ __forceinline__ double rho2_of(double rci, double rcj)
 {
     const double a = rci * rci, b = rcj * rcj;
     return a > b ? a : b;
-}
-
-// dK/dy on the open band (0, 1), zero outside.
-__device__ __forceinline__ double changeover_dk(double yv)
-{
-    if (!(yv > 0.0) || yv >= 1.0) return 0.0;
-    const double q = 2.0 * yv * yv - 2.0 * yv + 1.0;
-    return 2.0 * yv * (1.0 - yv) / (q * q);
 }
 
 // Block-wide exclusive scan of one int64 per thread.

@@ -506,10 +506,11 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     }
 }
 
-// Mixed mode: binary64 kick of the rows listed by k_kick_reduce, one block
-// per row (threads stride over the row's columns, then a fixed-order block
-// sum), with the arithmetic of the binary64 kick.  The grid is fixed (the
-// row count is read on the device), so the launch can be captured.
+// Mixed mode: binary64 kick of the rows listed by k_kick_reduce, with the
+// arithmetic of the binary64 kick.  Batched systems: one block per row
+// (threads stride over the row's system, then a fixed-order block sum).
+// Single system: k_refine_tiles / k_refine_apply below.  The grids are fixed
+// (the row count is read on the device), so the launches can be captured.
 struct RefineDev {
     const double *x, *y, *z, *m, *rc;
     double *vx, *vy, *vz;
@@ -604,6 +605,120 @@ __global__ __launch_bounds__(FB) void k_kick_refine(RefineDev a)
             }
         }
         __syncthreads();
+    }
+}
+
+// Single system: tiles of 256 listed rows x a column slice, columns staged in
+// LDS as in the kick, so the listed rows cost what they would in the binary64
+// kick.  The number of slices is chosen on the device from the row count so
+// that the partial sums ([row][slice][3], by list position) fit the partial-
+// sum region of the workspace (cap doubles); each slice is a multiple of 64
+// columns.
+constexpr int RT = KB;        // listed rows per refine tile
+constexpr int RMAXS = 128;    // most column slices of the refinement
+
+__device__ __forceinline__ void refine_shape(int cnt, int64_t n, int64_t cap, int &S, int64_t &len)
+{
+    int64_t sl = cap / (3 * (int64_t)(cnt > 0 ? cnt : 1));
+    sl = sl < RMAXS ? sl : RMAXS;
+    sl = sl > 1 ? sl : 1;
+    len = (((n + sl - 1) / sl) + 63) / 64 * 64;
+    S = (int)((n + len - 1) / len);
+}
+
+__global__ __launch_bounds__(RT) void k_refine_tiles(KickDev a, const int32_t *list,
+                                                     const int32_t *count, int64_t cap)
+{
+    __shared__ KickSmem<RT> sm;
+    const int tid = threadIdx.x;
+    const int cnt = *count;
+    int S;
+    int64_t len;
+    refine_shape(cnt, a.n, cap, S, len);
+    const int64_t items = (int64_t)((cnt + RT - 1) / RT) * S;
+    const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+    const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
+    const double c53 = a.c53 + (double)vzero;
+    const double4 *t_xyzm = sm.xyzm + vzero;
+    const double *t_rc2 = sm.rc2 + vzero;
+    const double *t_m = sm.m + vzero;
+    const double *t_irc = sm.irc + vzero;
+    for (int64_t t = blockIdx.x; t < items; t += gridDim.x) {
+        const int64_t pos = (t / S) * RT + tid;
+        const int s = (int)(t % S);
+        Rows<1> R;
+        R.ii[0] = -1;
+        R.xi[0] = R.yi[0] = R.zi[0] = __builtin_nan("");
+        R.rc2i[0] = 0.0;
+        R.iri[0] = 0.0;
+        if (pos < cnt) {
+            const int64_t i = list[pos];
+            R.ii[0] = i;
+            R.xi[0] = a.x[i];
+            R.yi[0] = a.y[i];
+            R.zi[0] = a.z[i];
+            const double r = a.rc[i];
+            R.rc2i[0] = r * r;
+            R.iri[0] = 1.0 / r;
+        }
+        R.ax[0] = R.ay[0] = R.az[0] = 0.0;
+        R.kc[0] = 0;
+        const int64_t j0 = (int64_t)s * len;
+        const int64_t j1 = j0 + len < a.n ? j0 + len : a.n;
+        for (int64_t t0 = j0; t0 < j1; t0 += RT) {
+            __syncthreads();
+            const int64_t jg = t0 + tid;
+            if (jg < j1) {
+                const double mj = a.m[jg], rcj = a.rc[jg];
+                sm.xyzm[tid] = make_double4(a.x[jg], a.y[jg], a.z[jg], 1.5 * mj);
+                sm.m[tid] = mj;
+                sm.rc2[tid] = rcj * rcj;
+                sm.irc[tid] = 1.0 / rcj;
+            }
+            __syncthreads();
+            const int tn = (int)(j1 - t0 < RT ? j1 - t0 : RT);
+            for (int jj = 0; jj < tn; ++jj)
+                interact<1, KM_F64>(a, R, t_xyzm[jj], t_rc2[jj], t0 + jj, c15, c1875, c53, 0,
+                                    nullptr, t_rc2 + jj, t_m + jj, t_irc + jj);
+        }
+        if (pos < cnt) {
+            double *P = a.part + ((size_t)pos * S + s) * 3;
+            P[0] = R.ax[0];
+            P[1] = R.ay[0];
+            P[2] = R.az[0];
+        }
+    }
+}
+
+// Sum each listed row's slices in order and apply v += h a.
+__global__ __launch_bounds__(RB) void k_refine_apply(RefineDev f, const double *part, int64_t cap)
+{
+    const int cnt = *f.count;
+    int S;
+    int64_t len;
+    refine_shape(cnt, f.n, cap, S, len);
+    for (int64_t pos = (int64_t)blockIdx.x * RB + threadIdx.x; pos < cnt;
+         pos += (int64_t)gridDim.x * RB) {
+        const int64_t i = f.list[pos];
+        double a3[3] = {0.0, 0.0, 0.0};
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a3[c] += part[((size_t)pos * S + s) * 3 + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a3[c] *= f.G;
+        if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
+            atomicOr(f.status, ST_NONFINITE);
+        if (f.h != 0.0) {
+            f.vx[i] = __builtin_fma(f.h, a3[0], f.vx[i]);
+            f.vy[i] = __builtin_fma(f.h, a3[1], f.vy[i]);
+            f.vz[i] = __builtin_fma(f.h, a3[2], f.vz[i]);
+        }
+        if (f.ax) {
+            f.ax[i] = a3[0];
+            f.ay[i] = a3[1];
+            f.az[i] = a3[2];
+        }
     }
 }
 
@@ -897,9 +1012,22 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
         f.G = k.G; f.h = k.h; f.hfac = k.hfac;
         f.c53 = 5.0 / 3.0;
         f.status = d.status;
-        // enough blocks for a few percent of the rows at one row per block
-        const int64_t blocks = std::min<int64_t>(std::max<int64_t>(k.n, 1), 2048);
-        hipLaunchKernelGGL(k_kick_refine, dim3((unsigned)blocks), dim3(FB), 0, s, f);
+        if (k.sysid) {
+            // enough blocks for a few percent of the rows at one row per block
+            const int64_t blocks = std::min<int64_t>(std::max<int64_t>(k.n, 1), 2048);
+            hipLaunchKernelGGL(k_kick_refine, dim3((unsigned)blocks), dim3(FB), 0, s, f);
+        } else {
+            // the main kick's partial sums are consumed: reuse their region
+            const int64_t cap = 5 * (int64_t)c.slices * L.npad;
+            KickDev rd = d;
+            rd.emit = 0;
+            hipLaunchKernelGGL(k_refine_tiles, dim3(2048), dim3(RT), 0, s, rd, f.list, f.count,
+                               cap);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_refine_apply, dim3((unsigned)std::min<int64_t>(L.nb, 1024)),
+                               dim3(RB), 0, s, f, d.part, cap);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (k.ev1) {

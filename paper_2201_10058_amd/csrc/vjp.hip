@@ -38,6 +38,7 @@ template <int NT>
 struct VjpSmem {
     double4 xyzm[NT];     // x_j, y_j, z_j, 3/2 m_j
     double4 abr[NT];      // 3/2 scale * abar_j (3), rc_j^2
+    double rc[NT];        // rc_j
 };
 
 // Fast-path weights to first order in e = 1 - r2 y^2 (y = v_rsq_f64(r2),
@@ -63,6 +64,7 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
     const double c53 = a.c53 + (double)vzero, c75 = a.c75 + (double)vzero;
     const double4 *t_xyzm = sm.xyzm + vzero;
     const double4 *t_abr = sm.abr + vzero;
+    const double *t_rc = sm.rc + vzero;
 
     const bool valid = k < a.n;
     double xk, yk, zk, mk = 0.0, rck = 0.0, rc2k = 0.0, abxk = 0.0, abyk = 0.0, abzk = 0.0;
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
                 sm.xyzm[tid] = make_double4(a.x[jg], a.y[jg], a.z[jg], 1.5 * a.m[jg]);
                 sm.abr[tid] = make_double4(sc * a.abx[jg], sc * a.aby[jg], sc * a.abz[jg],
                                            rcj * rcj);
+                sm.rc[tid] = rcj;
             }
         }
         __syncthreads();
@@ -120,23 +123,33 @@ __global__ __launch_bounds__(NT) void k_kick_vjp(VjpDev a)
                     if (r2 == 0.0) {
                         atomicOr(a.status, ST_NONFINITE);
                     } else {
-                        const double rcj = a.rc[jg];
-                        const double rho = rck > rcj ? rck : rcj;
-                        const double r = __builtin_sqrt(r2);
-                        const double yy = (r - 0.1 * rho) / (0.9 * rho);
-                        double K = 1.0, Kp = 0.0;
-                        if (r2 < (rho2_of(rck, rcj))) {
-                            K = changeover_k(r, rho);
-                            Kp = changeover_dk(yy);
+                        // as in the kick's rare path: 1/r from one corrected
+                        // v_rsq_f64, 1/rho by v_rcp_f64 and Newton steps, no
+                        // IEEE division and no global memory access
+                        const double rcj = t_rc[jj];
+                        const double y0 = __builtin_amdgcn_rsq(r2);
+                        const double e0 = __builtin_fma(-r2, y0 * y0, 1.0);
+                        const double yc = __builtin_fma(y0 * e0, 0.5, y0);    // 1 / r
+                        const double yc2 = yc * yc, yc3 = yc2 * yc;
+                        double K = 1.0, Kp = 0.0, irho = 0.0;
+                        if (r2 < rho2_of(rck, rcj)) {
+                            const double rho = rck > rcj ? rck : rcj;
+                            irho = __builtin_amdgcn_rcp(rho);
+                            irho = __builtin_fma(irho, __builtin_fma(-rho, irho, 1.0), irho);
+                            irho = __builtin_fma(irho, __builtin_fma(-rho, irho, 1.0), irho);
+                            changeover_kdk_of_y(
+                                __builtin_fma((r2 * yc) * irho, 1.0 / 0.9, -1.0 / 9.0), K, Kp);
                         }
-                        const double r3 = r2 * r;
                         // fast-path units: w = (K / r^3) / (3/2) and
-                        // -5 c = (w_r / r) d.u with du = 3/2 d.u
-                        w = K / r3 / 1.5;
-                        const double wr_r = Kp / (0.9 * rho * r2 * r2) - 3.0 * K / (r2 * r3);
-                        cq = -(wr_r * du) / 7.5;
+                        // -5 c = (w_r / r) d.u with du = 3/2 d.u, where
+                        // w_r / r = K' / (0.9 rho r^4) - 3 K / r^5
+                        w = (K * yc3) * (2.0 / 3.0);
+                        const double wr_r =
+                            (Kp * (irho * (1.0 / 0.9))) * (yc2 * yc2) - (3.0 * K) * (yc3 * yc2);
+                        cq = -(wr_r * du) * (1.0 / 7.5);
                         const bool owner = rck > rcj || (rck == rcj && k < jg);
-                        if (owner && Kp != 0.0) Rb += Kp / (0.9 * rho * rho * r2) * (du / 1.5);
+                        if (owner && Kp != 0.0)
+                            Rb += ((Kp * (irho * irho)) * (1.0 / 0.9)) * yc2 * (du * (2.0 / 3.0));
                     }
                 }
             }
