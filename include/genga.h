@@ -22,7 +22,9 @@
  *   (contiguous, float64 structure-of-arrays of length n unless stated).  The
  *   library never allocates device memory in a call: scratch space is the
  *   caller's workspace `ws` of genga_workspace_bytes() bytes, 256-byte
- *   aligned.  Host-side structs (genga_bodies, genga_params, genga_pairs) are
+ *   aligned; a new workspace is zero-filled by the caller (or passed to
+ *   genga_clear_status) before its first use, so that its status word starts
+ *   clear.  Host-side structs (genga_bodies, genga_params, genga_pairs) are
  *   read during the call only and may be freed on return.
  * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Work is
  *   enqueued asynchronously in order on that stream; results are valid after

@@ -55,6 +55,8 @@ struct Layout {
     size_t wcount = 0;     // int32  [nwaves]           staged pairs per wave
     size_t hc = 0;         // double [nb][3]            momentum partials
     size_t rlist = 0;      // int32  [npad]             mixed: rows to evaluate in binary64
+    size_t perm = 0;       // int32  [npad]             bodies in order of r_crit
+    size_t cursor = 0;     // int32  [4096]             bucket offsets of that order
     size_t P = 0;          // batch: double [S][3]      momentum per system
     size_t tiles = 0;      // batch: TileDesc [ntiles]
     size_t sysid = 0;      // batch: int32 [npad]
@@ -89,6 +91,8 @@ struct KickLaunch {
     const int32_t *sys_slices; // batch: column slices per system
     const double *sys_dt;      // batch: time step per system
     const int64_t *sys_off;    // batch: device offsets of the systems
+    bool perm_build = true;    // one system: build the r_crit order of the rows first
+                               // (false: reuse the order already in the workspace)
 };
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
                        hipStream_t s);

@@ -171,3 +171,47 @@ def test_mixed_evolved_disk16384(dev):
                                         precise=True)
         ref = np.array([ax[0], ay[0], az[0]])
         assert np.linalg.norm(a32[:, r] - ref) <= MIXED_TOL * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_step_graph_replay_bitwise(dev, precision):
+    # the single-system step captured once in a hipGraph and replayed, against
+    # the same step issued eagerly; the mixed step includes the refinement of
+    # cancelling rows, whose count lives on the device
+    prec = N.FP64 if precision == "fp64" else N.MIXED
+    d = W.make_disk(W.DISK_MIXED[16384])
+    cfg = N.Config(G=G, m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"], precision=prec,
+                   flags=N.FLAG_NOSYNC)
+    st_g, st_e = N.State.from_numpy(d), N.State.from_numpy(d)
+    ws_g, ws_e = N.Workspace(st_g.n, cfg), N.Workspace(st_e.n, cfg)
+    pl_g, pl_e = N.PairList(1 << 18), N.PairList(1 << 18)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tmp = N.State.from_numpy(d)
+        N.step(tmp, cfg, N.Workspace(tmp.n, cfg), N.PairList(1 << 18))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        N.step(st_g, cfg, ws_g, pl_g)
+    torch.cuda.synchronize()
+    for k in st_g.t:
+        st_g.t[k].copy_(st_e.t[k])
+    refined = []
+    for rep in range(4):
+        g.replay()
+        N.step(st_e, cfg, ws_e, pl_e)
+        junk = torch.randn(1000, device="cuda").sum()     # unrelated eager work
+        torch.cuda.synchronize()
+        refined.append(_refined_rows(ws_e))
+        assert N.read_status(ws_g) == N.OK and N.read_status(ws_e) == N.OK
+        for k in ("x", "y", "z", "vx", "vy", "vz", "rc"):
+            assert torch.equal(st_g.t[k], st_e.t[k]), (rep, k)
+        assert int(pl_g.count.item()) == int(pl_e.count.item())
+        c = min(int(pl_e.count.item()), pl_e.capacity)
+        assert torch.equal(pl_g.i[:c], pl_e.i[:c]) and torch.equal(pl_g.j[:c], pl_e.j[:c])
+        del junk
+    _say(precision, "rows refined in binary64 per replayed step", refined)
+    if prec == N.MIXED:
+        assert min(refined) > 0
