@@ -82,6 +82,7 @@ static int do_kick(const genga_bodies *b, const genga_params *p, double h, doubl
     k.sys_slices = nullptr;
     k.sys_dt = nullptr;
     k.sys_off = nullptr;
+    k.row_order = b->n >= ROW_ORDER_MIN_N && !(p->flags & GENGA_FLAG_BODY_ORDER);
     k.perm_build = perm_build;
     hipError_t e = launch_kick(k, c, L, (char *)ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);

@@ -59,6 +59,23 @@ __device__ __forceinline__ void changeover_kdk_of_y(double yv, double &K, double
     dK = (2.0 * (yv - y2)) * (t * t);
 }
 
+// sum_{s < ns} p[s * stride] in slice order; the loads of 8 slices are issued
+// before their additions, whose order is unchanged.
+__device__ __forceinline__ double ordered_sum(const double *p, size_t stride, int ns)
+{
+    double acc = 0.0;
+    int s = 0;
+    for (; s + 8 <= ns; s += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[(size_t)(s + k) * stride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+    }
+    for (; s < ns; ++s) acc += p[(size_t)s * stride];
+    return acc;
+}
+
 // max of two non-negative doubles in one v_max_f64 (the generic fmax adds
 // NaN-quieting canonicalisations; the critical radii are validated instead).
 __device__ __forceinline__ double vmax_f64(double a, double b)

@@ -79,8 +79,7 @@ __global__ __launch_bounds__(RB) void k_energy_rows(const double *x, const doubl
     const int64_t i = (int64_t)blockIdx.x * RB + t;
     double v[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
-        double p = 0.0;
-        for (int s = 0; s < slices; ++s) p += phi[(size_t)s * npad + i];
+        const double p = ordered_sum(phi + i, (size_t)npad, slices);
         const double mi = m[i];
         const double v2 = vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
         const double r = __builtin_sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);

@@ -68,6 +68,8 @@ struct Layout {
 };
 
 KickCfg choose_kick_cfg(int64_t n, const genga_params *p);
+// Systems of at least this many bodies take the binary64 kick in r_crit order.
+constexpr int64_t ROW_ORDER_MIN_N = 16384;
 // Resident blocks per CU of the persistent kick for this shape (0 if unknown).
 int kick_blocks_per_cu(const KickCfg &c, int precision);
 Layout make_layout(int64_t n, const KickCfg &c, int64_t S = 0);
@@ -91,7 +93,8 @@ struct KickLaunch {
     const int32_t *sys_slices; // batch: column slices per system
     const double *sys_dt;      // batch: time step per system
     const int64_t *sys_off;    // batch: device offsets of the systems
-    bool perm_build = true;    // one system: build the r_crit order of the rows first
+    bool row_order = false;    // one system, binary64 or pairs only: rows in r_crit order
+    bool perm_build = true;    // with row_order: build that order first
                                // (false: reuse the order already in the workspace)
 };
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,

@@ -419,14 +419,13 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
 }
 
 // One tile per block (single system: grid = row blocks x column slices).
-template <int NT, int IPT, int MODE>
+template <int NT, int IPT, int MODE, bool SORTED>
 __global__ __launch_bounds__(NT) void k_kick(KickDev a)
 {
     __shared__ KickSmem<NT> sm;
     const int64_t t = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (MODE == KM_MIXED && t == 0 && threadIdx.x == 0) *a.refine_cnt = 0;
-    // one system: binary64 and pair-only kicks walk the rows in r_crit order
-    process_tile<NT, IPT, MODE, MODE != KM_MIXED>(a, sm, get_tile<NT, IPT>(a, t), t);
+    process_tile<NT, IPT, MODE, SORTED>(a, sm, get_tile<NT, IPT>(a, t), t);
 }
 
 // Persistent grid over a tile list (batched systems), sized to the blocks
@@ -489,17 +488,15 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
         double a3[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double acc = 0.0;
-            for (int s = 0; s < nsl; ++s) acc += r.part[((size_t)s * r.pstride + c) * r.npad + i];
-            a3[c] = acc;
+            a3[c] = ordered_sum(r.part + (size_t)c * r.npad + i, (size_t)r.pstride * r.npad, nsl);
         }
         bool refine = false;
         if (r.kappa2 > 0.0) {
             // mixed: a row whose binary32 terms are large against their sum
             // (sum_j m_j / r^2 > kappa |sum_j m_j d / r^3|) is evaluated
             // again in binary64 by k_kick_refine
-            double mag = 0.0;
-            for (int s = 0; s < nsl; ++s) mag += r.part[((size_t)s * r.pstride + 3) * r.npad + i];
+            const double mag =
+                ordered_sum(r.part + (size_t)3 * r.npad + i, (size_t)r.pstride * r.npad, nsl);
             const double a2 = a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2];
             refine = !(mag * mag <= r.kappa2 * a2);
         }
@@ -525,7 +522,18 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     if (r.emit) {
         int64_t c = 0;
         if (valid) {
-            for (int s = 0; s < nsl; ++s) {
+            int s = 0;
+            for (; s + 8 <= nsl; s += 8) {
+                int32_t t[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) t[k] = r.cnt[(size_t)(s + k) * r.npad + i];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    r.cnt[(size_t)(s + k) * r.npad + i] = (int32_t)c;
+                    c += t[k];
+                }
+            }
+            for (; s < nsl; ++s) {
                 const int32_t t = r.cnt[(size_t)s * r.npad + i];
                 r.cnt[(size_t)s * r.npad + i] = (int32_t)c;
                 c += t;
@@ -977,8 +985,11 @@ static void launch_k(const KickDev &d, const KickCfg &c, hipStream_t s)
 {
     if (d.tiles)
         hipLaunchKernelGGL((k_kick_persistent<NT, IPT, MODE>), dim3(c.grid), dim3(NT), 0, s, d);
+    else if (MODE != KM_MIXED && d.perm)
+        hipLaunchKernelGGL((k_kick<NT, IPT, MODE, MODE != KM_MIXED>), dim3(c.gx, c.slices),
+                           dim3(NT), 0, s, d);
     else
-        hipLaunchKernelGGL((k_kick<NT, IPT, MODE>), dim3(c.gx, c.slices), dim3(NT), 0, s, d);
+        hipLaunchKernelGGL((k_kick<NT, IPT, MODE, false>), dim3(c.gx, c.slices), dim3(NT), 0, s, d);
 }
 
 template <int NT, int IPT, int MODE>
@@ -1041,7 +1052,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
     const bool refine = mode == KM_MIXED;
     d.perm = nullptr;
-    if (!k.tiles && mode != KM_MIXED) {
+    if (!k.tiles && mode != KM_MIXED && k.row_order) {
         int32_t *perm = (int32_t *)(ws + L.perm);
         d.perm = perm;
         if (k.perm_build) {

@@ -184,9 +184,7 @@ __global__ __launch_bounds__(RB) void k_kick_vjp_reduce(const double *part, int6
     double acc[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        double t = 0.0;
-        for (int s = 0; s < slices; ++s) t += part[((size_t)s * 5 + c) * npad + i];
-        acc[c] = t;
+        acc[c] = ordered_sum(part + (size_t)c * npad + i, (size_t)5 * npad, slices);
     }
     xb[i] += G * acc[0];
     yb[i] += G * acc[1];
