@@ -69,10 +69,6 @@ extern "C" {
 
 /* genga_params.flags */
 #define GENGA_FLAG_NOSYNC 1 /* genga_step: do not synchronise nor read the status     */
-#define GENGA_FLAG_BODY_ORDER 2 /* binary64 / pair-only kick of one system with at least
-                                   16384 bodies: keep the rows in body order instead of
-                                   walking them in order of r_crit (a faster gate of the
-                                   rare path; results are identical either way)      */
 
 /* Bodies of one system, democratic coordinates, device SoA of length n.
  * rc holds the critical radii r_crit,i (eq. rcrit); genga_rcrit writes it.    */

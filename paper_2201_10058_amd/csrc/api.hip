@@ -60,7 +60,7 @@ static int status_to_code(int32_t st)
 
 static int do_kick(const genga_bodies *b, const genga_params *p, double h, double *ax, double *ay,
                    double *az, genga_pairs *pairs, bool forces, void *ws, void *stream,
-                   int ev_slot = 0, bool perm_build = true)
+                   int ev_slot = 0)
 {
     const KickCfg c = choose_kick_cfg(b->n, p);
     const Layout L = make_layout(b->n, c);
@@ -82,8 +82,6 @@ static int do_kick(const genga_bodies *b, const genga_params *p, double h, doubl
     k.sys_slices = nullptr;
     k.sys_dt = nullptr;
     k.sys_off = nullptr;
-    k.row_order = b->n >= ROW_ORDER_MIN_N && !(p->flags & GENGA_FLAG_BODY_ORDER);
-    k.perm_build = perm_build;
     hipError_t e = launch_kick(k, c, L, (char *)ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return GENGA_OK;
@@ -288,9 +286,7 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if ((e = launch_drift(b, p->G * p->m_star, p->dt, (char *)ws, s)) != hipSuccess)
         return hip_fail(e);
     if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
-    // same rc as the first half kick: reuse its r_crit order of the rows
-    if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2, false)))
-        return r;
+    if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2))) return r;
     if (p->flags & GENGA_FLAG_NOSYNC) return GENGA_OK;
     return genga_read_status(ws, stream);
 }

@@ -55,8 +55,6 @@ struct Layout {
     size_t wcount = 0;     // int32  [nwaves]           staged pairs per wave
     size_t hc = 0;         // double [nb][3]            momentum partials
     size_t rlist = 0;      // int32  [npad]             mixed: rows to evaluate in binary64
-    size_t perm = 0;       // int32  [npad]             bodies in order of r_crit
-    size_t cursor = 0;     // int32  [4096]             bucket offsets of that order
     size_t P = 0;          // batch: double [S][3]      momentum per system
     size_t tiles = 0;      // batch: TileDesc [ntiles]
     size_t sysid = 0;      // batch: int32 [npad]
@@ -68,8 +66,6 @@ struct Layout {
 };
 
 KickCfg choose_kick_cfg(int64_t n, const genga_params *p);
-// Systems of at least this many bodies take the binary64 kick in r_crit order.
-constexpr int64_t ROW_ORDER_MIN_N = 16384;
 // Resident blocks per CU of the persistent kick for this shape (0 if unknown).
 int kick_blocks_per_cu(const KickCfg &c, int precision);
 Layout make_layout(int64_t n, const KickCfg &c, int64_t S = 0);
@@ -93,9 +89,6 @@ struct KickLaunch {
     const int32_t *sys_slices; // batch: column slices per system
     const double *sys_dt;      // batch: time step per system
     const int64_t *sys_off;    // batch: device offsets of the systems
-    bool row_order = false;    // one system, binary64 or pairs only: rows in r_crit order
-    bool perm_build = true;    // with row_order: build that order first
-                               // (false: reuse the order already in the workspace)
 };
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
                        hipStream_t s);

@@ -49,7 +49,6 @@ struct KickDev {
     int32_t *status;
     int32_t *queue;       // batch: next tile to take (reset to 0 by k_kick_reduce)
     int32_t *refine_cnt;  // mixed: rows listed for binary64 evaluation (reset here)
-    const int32_t *perm;  // single system, binary64: rows in order of r_crit (row slot -> body)
     int emit;
     double c15, c1875;    // 3/2 and 15/8
     double c53;           // 5/3
@@ -170,7 +169,7 @@ constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
 // One column j against the lane's rows (the hot loop body).
 //   b = (x_j, y_j, z_j, 3/2 m_j) for KM_F64, (x_j, y_j, z_j, m_j) for KM_PAIRS,
 //   (x_j, y_j, z_j, {m_j, rc2f_j}) for KM_MIXED; *mj64 = m_j.
-template <int IPT, int MODE, bool SORTED = false>
+template <int IPT, int MODE>
 __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const double4 b,
                                          const double rc2j, const int64_t jg, const double c15,
                                          const double c1875, const double c53, const int64_t wave_g,
@@ -228,10 +227,8 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
         const double dy = b.y - R.yi[q];
         const double dz = b.z - R.zi[q];
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        // candidate: inside the pair critical radius, or the self pair.
-        // SORTED: rc2j holds max(rc_j^2, largest rc_i^2 of the block's rows),
-        // a conservative gate of one compare
-        const bool cand = SORTED ? r2 <= rc2j : r2 <= vmax_f64(R.rc2i[q], rc2j);
+        // candidate: inside the pair critical radius, or the self pair
+        const bool cand = r2 <= vmax_f64(R.rc2i[q], rc2j);
         double sc = 0.0;
         if (FORCES) {
             // m r^-3 from v_rsq_f64 (measured relative error below 2^-24):
@@ -280,17 +277,12 @@ struct KickSmem {
     double rc2[NT];
     double m[NT];
     double irc[NT];     // 1 / rc_j
-    double thr[NT];     // rows in r_crit order: max(rc_j^2, largest rc_i^2 of the block)
-    double tmax[NT / 64];
     int wcnt[4];
 };
 
 // All rows of tile `td` against its columns; writes the slice partials, the
-// per-row pair counts and the wave's staging count.  SORTED: row slot k holds
-// body perm[k] (bodies in order of r_crit), so the rows of a block have
-// nearly equal r_crit and one compare against max(rc_j^2, largest rc_i^2 of
-// the block) is a tight conservative gate for the rare path.
-template <int NT, int IPT, int MODE, bool SORTED = false>
+// per-row pair counts and the wave's staging count.
+template <int NT, int IPT, int MODE>
 __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm, const TileDesc &td,
                                              int64_t tile_index)
 {
@@ -315,13 +307,12 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
     const double *t_m = sm.m + vzero;
     const double *t_irc = sm.irc + vzero;
 
-    const double *t_thr = sm.thr + vzero;
 
     Rows<IPT> R;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int64_t slot = rowbase + q * 64 + lane;
-        R.ii[q] = slot < rowend ? (SORTED ? (int64_t)a.perm[slot] : slot) : -1;
+        R.ii[q] = slot < rowend ? slot : -1;
         if (R.ii[q] >= 0) {
             R.xi[q] = a.x[R.ii[q]];
             R.yi[q] = a.y[R.ii[q]];
@@ -342,16 +333,6 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
     }
     int *wcnt = &sm.wcnt[w];
     if (lane == 0) __hip_atomic_store(wcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    if (SORTED) {
-        double mx = R.rc2i[0];
-#pragma unroll
-        for (int q = 1; q < IPT; ++q) mx = R.rc2i[q] > mx ? R.rc2i[q] : mx;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double o = __shfl_xor(mx, off);
-            mx = o > mx ? o : mx;
-        }
-        if (lane == 0) sm.tmax[w] = mx;   // read after the column loop's first barrier
-    }
 
     for (int64_t t0 = j0; t0 < j1; t0 += NT) {
         __syncthreads();
@@ -373,12 +354,7 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
                 }
                 sm.rc2[q] = rcj * rcj;
                 if (MODE != KM_PAIRS) sm.irc[q] = 1.0 / rcj;
-                if (SORTED) {
-                    double tb = sm.tmax[0];
-#pragma unroll
-                    for (int k = 1; k < NT / 64; ++k) tb = sm.tmax[k] > tb ? sm.tmax[k] : tb;
-                    sm.thr[q] = rcj * rcj > tb ? rcj * rcj : tb;
-                }
+
             }
         }
         __syncthreads();
@@ -387,17 +363,14 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
         for (; jj + 4 <= tn; jj += 4) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                interact<IPT, MODE, SORTED>(
-                    a, R, t_xyzm[jj + u],
-                    MODE == KM_MIXED ? 0.0 : (SORTED ? t_thr[jj + u] : t_rc2[jj + u]), t0 + jj + u,
-                    c15, c1875, c53, wave_g, wcnt, t_rc2 + jj + u, t_m + jj + u, t_irc + jj + u);
+                interact<IPT, MODE>(a, R, t_xyzm[jj + u], MODE == KM_MIXED ? 0.0 : t_rc2[jj + u],
+                                    t0 + jj + u, c15, c1875, c53, wave_g, wcnt, t_rc2 + jj + u,
+                                    t_m + jj + u, t_irc + jj + u);
             if ((jj & (FOLD - 1)) == FOLD - 4) fold<IPT, MODE>(R);
         }
         for (; jj < tn; ++jj)
-            interact<IPT, MODE, SORTED>(a, R, t_xyzm[jj],
-                                        MODE == KM_MIXED ? 0.0 : (SORTED ? t_thr[jj] : t_rc2[jj]),
-                                        t0 + jj, c15, c1875, c53, wave_g, wcnt, t_rc2 + jj,
-                                        t_m + jj, t_irc + jj);
+            interact<IPT, MODE>(a, R, t_xyzm[jj], MODE == KM_MIXED ? 0.0 : t_rc2[jj], t0 + jj, c15,
+                                c1875, c53, wave_g, wcnt, t_rc2 + jj, t_m + jj, t_irc + jj);
         fold<IPT, MODE>(R);
     }
 
@@ -419,13 +392,13 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
 }
 
 // One tile per block (single system: grid = row blocks x column slices).
-template <int NT, int IPT, int MODE, bool SORTED>
+template <int NT, int IPT, int MODE>
 __global__ __launch_bounds__(NT) void k_kick(KickDev a)
 {
     __shared__ KickSmem<NT> sm;
     const int64_t t = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (MODE == KM_MIXED && t == 0 && threadIdx.x == 0) *a.refine_cnt = 0;
-    process_tile<NT, IPT, MODE, SORTED>(a, sm, get_tile<NT, IPT>(a, t), t);
+    process_tile<NT, IPT, MODE>(a, sm, get_tile<NT, IPT>(a, t), t);
 }
 
 // Persistent grid over a tile list (batched systems), sized to the blocks
@@ -730,34 +703,42 @@ __global__ __launch_bounds__(RT) void k_refine_tiles(KickDev a, const int32_t *l
     }
 }
 
-// Sum each listed row's slices in order and apply v += h a.
+// Sum each listed row's slices and apply v += h a: one wave per listed row,
+// lanes take slices l, l + 64, then a fixed xor-butterfly combines the lanes.
 __global__ __launch_bounds__(RB) void k_refine_apply(RefineDev f, const double *part, int64_t cap)
 {
     const int cnt = *f.count;
     int S;
     int64_t len;
     refine_shape(cnt, f.n, cap, S, len);
-    for (int64_t pos = (int64_t)blockIdx.x * RB + threadIdx.x; pos < cnt;
-         pos += (int64_t)gridDim.x * RB) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (RB / 64);
+    for (int64_t pos = (int64_t)blockIdx.x * (RB / 64) + (threadIdx.x >> 6); pos < cnt; pos += nw) {
         const int64_t i = f.list[pos];
         double a3[3] = {0.0, 0.0, 0.0};
-        for (int s = 0; s < S; ++s) {
+        for (int s = lane; s < S; s += 64) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) a3[c] += part[((size_t)pos * S + s) * 3 + c];
         }
+        for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a3[c] *= f.G;
-        if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
-            atomicOr(f.status, ST_NONFINITE);
-        if (f.h != 0.0) {
-            f.vx[i] = __builtin_fma(f.h, a3[0], f.vx[i]);
-            f.vy[i] = __builtin_fma(f.h, a3[1], f.vy[i]);
-            f.vz[i] = __builtin_fma(f.h, a3[2], f.vz[i]);
+            for (int c = 0; c < 3; ++c) a3[c] += __shfl_xor(a3[c], off);
         }
-        if (f.ax) {
-            f.ax[i] = a3[0];
-            f.ay[i] = a3[1];
-            f.az[i] = a3[2];
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a3[c] *= f.G;
+            if (!(isfinite(a3[0]) && isfinite(a3[1]) && isfinite(a3[2])))
+                atomicOr(f.status, ST_NONFINITE);
+            if (f.h != 0.0) {
+                f.vx[i] = __builtin_fma(f.h, a3[0], f.vx[i]);
+                f.vy[i] = __builtin_fma(f.h, a3[1], f.vy[i]);
+                f.vz[i] = __builtin_fma(f.h, a3[2], f.vz[i]);
+            }
+            if (f.ax) {
+                f.ax[i] = a3[0];
+                f.ay[i] = a3[1];
+                f.az[i] = a3[2];
+            }
         }
     }
 }
@@ -822,7 +803,7 @@ __device__ void scatter_wave(const ScatterDev &d, int64_t wave_g)
     for (int q = 0; q < IPT; ++q) {
         const int64_t slot = rowbase + q * 64 + lane;
         if (slot >= rowend) continue;
-        const int64_t i = a.perm ? (int64_t)a.perm[slot] : slot;
+        const int64_t i = slot;
         int64_t pos = d.boff[i / RB] + d.rowloc[i] + a.cnt[(size_t)s * a.npad + i];
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
         const double rci = a.rc[i];
@@ -854,53 +835,6 @@ __global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
         if (d.ipt == 2) scatter_wave<KB, 2>(d, wave_g);
         else scatter_wave<KB, 1>(d, wave_g);
     }
-}
-
-// Rows in order of r_crit (one system, binary64 and pair-only kicks): a bucket
-// sort on the exponent and the top 6 mantissa bits of rc (4096 buckets, each
-// 1.1 % wide).  The order inside a bucket is left to the atomics: every row's
-// sums are the same whichever block and lane hold it, and the rare path gives
-// a lane outside rho_ij the fast path's own weight, so results do not depend
-// on it.
-constexpr int NBUCK = 4096;
-
-__device__ __forceinline__ int rc_bucket(double rc)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(rc);
-    const int k = ((int)((b >> 52) & 0x7ff) - 1023 + 32) * 64 + (int)((b >> 46) & 63);
-    return k < 0 ? 0 : (k > NBUCK - 1 ? NBUCK - 1 : k);
-}
-
-// One block: histogram of the buckets in LDS, then their exclusive prefix.
-__global__ __launch_bounds__(1024) void k_rc_hist_scan(const double *rc, int64_t n, int32_t *cursor)
-{
-    __shared__ int32_t hist[NBUCK];
-    __shared__ int64_t sm[1024 / 64];
-    for (int b = threadIdx.x; b < NBUCK; b += 1024) hist[b] = 0;
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += 1024) atomicAdd(&hist[rc_bucket(rc[i])], 1);
-    __syncthreads();
-    int32_t c[NBUCK / 1024];
-    int64_t v = 0;
-#pragma unroll
-    for (int k = 0; k < NBUCK / 1024; ++k) {
-        c[k] = hist[threadIdx.x * (NBUCK / 1024) + k];
-        v += c[k];
-    }
-    int64_t tot;
-    int64_t run = block_excl_scan<1024>(v, &tot, sm);
-#pragma unroll
-    for (int k = 0; k < NBUCK / 1024; ++k) {
-        cursor[threadIdx.x * (NBUCK / 1024) + k] = (int32_t)run;
-        run += c[k];
-    }
-}
-
-__global__ __launch_bounds__(RB) void k_rc_scatter(const double *rc, int64_t n, int32_t *cursor,
-                                                   int32_t *perm)
-{
-    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
-    if (i < n) perm[atomicAdd(&cursor[rc_bucket(rc[i])], 1)] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -960,10 +894,6 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
     L.rlist = off;
     off = align256(off + sizeof(int32_t) * (size_t)L.npad);
-    L.perm = off;
-    off = align256(off + sizeof(int32_t) * (size_t)L.npad);
-    L.cursor = off;
-    off = align256(off + sizeof(int32_t) * (size_t)NBUCK);
     if (S > 0) {
         L.P = off;
         off = align256(off + sizeof(double) * 3 * (size_t)S);
@@ -985,11 +915,8 @@ static void launch_k(const KickDev &d, const KickCfg &c, hipStream_t s)
 {
     if (d.tiles)
         hipLaunchKernelGGL((k_kick_persistent<NT, IPT, MODE>), dim3(c.grid), dim3(NT), 0, s, d);
-    else if (MODE != KM_MIXED && d.perm)
-        hipLaunchKernelGGL((k_kick<NT, IPT, MODE, MODE != KM_MIXED>), dim3(c.gx, c.slices),
-                           dim3(NT), 0, s, d);
     else
-        hipLaunchKernelGGL((k_kick<NT, IPT, MODE, false>), dim3(c.gx, c.slices), dim3(NT), 0, s, d);
+        hipLaunchKernelGGL((k_kick<NT, IPT, MODE>), dim3(c.gx, c.slices), dim3(NT), 0, s, d);
 }
 
 template <int NT, int IPT, int MODE>
@@ -1051,20 +978,6 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
 
     const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
     const bool refine = mode == KM_MIXED;
-    d.perm = nullptr;
-    if (!k.tiles && mode != KM_MIXED && k.row_order) {
-        int32_t *perm = (int32_t *)(ws + L.perm);
-        d.perm = perm;
-        if (k.perm_build) {
-            int32_t *cursor = (int32_t *)(ws + L.cursor);
-            hipLaunchKernelGGL(k_rc_hist_scan, dim3(1), dim3(1024), 0, s, k.rc, k.n, cursor);
-            hipError_t e0 = hipGetLastError();
-            if (e0 != hipSuccess) return e0;
-            hipLaunchKernelGGL(k_rc_scatter, dim3((unsigned)L.nb), dim3(RB), 0, s, k.rc, k.n,
-                               cursor, perm);
-            if ((e0 = hipGetLastError()) != hipSuccess) return e0;
-        }
-    }
     if (k.ev0) {
         hipError_t e0 = hipEventRecord((hipEvent_t)k.ev0, s);
         if (e0 != hipSuccess) return e0;

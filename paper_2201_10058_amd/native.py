@@ -28,7 +28,6 @@ E_RCRIT = -7
 FP64 = 0
 MIXED = 1
 FLAG_NOSYNC = 1
-FLAG_BODY_ORDER = 2
 
 _c_double_p = ctypes.c_void_p
 

@@ -322,22 +322,3 @@ def test_step_pairs_disk65536_every_100_steps(dev):
     assert N.read_status(ws) == N.OK
     assert checked == 10
 
-
-def test_row_order_is_bitwise_neutral(dev):
-    # systems of >= 16384 bodies walk the rows in r_crit order; forcing body
-    # order must give the same accelerations and pair list bit for bit
-    d = W.make_disk(W.DISK_MIXED[16384])
-    rc = _disk_rc(d)
-    out = []
-    for flags in (0, N.FLAG_BODY_ORDER):
-        a, (pi, pj, cnt), code, _ = _run_kick(d, rc, N.Config(G=G, flags=flags))
-        assert code == N.OK
-        st = N.State.from_numpy(d, rc=rc)
-        cfg = N.Config(G=G, flags=flags)
-        pl = N.PairList(cnt)
-        N.encounter_pairs(st, cfg, N.Workspace(st.n, cfg), pl)
-        out.append((a, pi, pj, cnt, pl.result()))
-    (a0, i0, j0, c0, e0), (a1, i1, j1, c1, e1) = out
-    assert np.array_equal(a0, a1)
-    assert c0 == c1 and np.array_equal(i0, i1) and np.array_equal(j0, j1)
-    assert e0[2] == e1[2] == c0 and np.array_equal(e0[0], e1[0]) and np.array_equal(e0[1], e1[1])
