@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--n", type=int, default=65536, help="bodies (default: the 65,536-body disk)")
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--slices", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target duration of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -236,27 +236,6 @@ def bench_small(N, W, torch, np, steps=100):
             "eager_step_us": round(eager * 1e6, 2), "graph_step_us": round(graph * 1e6, 2),
             "eager_ginter_s": round(inter / eager / 1e9, 3),
             "graph_ginter_s": round(inter / graph / 1e9, 3)}
-
-
-# VALU instructions per interaction of the binary64 fast path (the hot loop of
-# k_kick<256,1,KM_F64>): d 3 add; r^2 1 mul + 2 fma; gate max + compare;
-# m r^-3 4 mul + 1 fma around one rsq; accumulation 3 fma.
-KICK_MIX = {"v_add_f64": 5, "v_mul_f64": 5, "v_fma_f64": 6, "v_rsq_f64": 1}
-
-
-def issue_ceiling(N, torch):
-    """Instruction-issue ceiling of the FP64 kick from the measured sustained
-    cost of each instruction (max and compare priced as an add)."""
-    rates = N.probe_issue_rates()
-    cyc = sum(k * rates[op] for op, k in KICK_MIX.items())
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    ginter = cus * 4 * 64 * 2.4e9 / cyc / 1e9
-    return {"cycles_per_wave_instruction": {k: round(v, 3) for k, v in rates.items()},
-            "kick_instruction_mix": KICK_MIX,
-            "cycles_per_64_interactions": round(cyc, 2),
-            "ceiling_ginter_s": round(ginter, 1),
-            "ceiling_tflops": round(ginter * FLOP_PER_INTERACTION / 1e3, 3),
-            "ceiling_frac_of_peak": round(ginter * FLOP_PER_INTERACTION / 1e3 / FP64_VECTOR_PEAK_TFLOPS, 4)}
 
 
 def pair_list_sha256(pairs) -> str:
@@ -511,9 +490,6 @@ def main():
             out["mixed"]["energy_drift"] = energy_drift(N, W, torch, np)
             print(f"mixed accuracy done: {out['mixed']['accuracy_vs_fp64']} "
                   f"{out['mixed']['energy_drift']}", file=sys.stderr, flush=True)
-    ceil_ = issue_ceiling(N, torch)
-    ceil_["kernel_frac_of_ceiling"] = round(n * (n - 1) / r64["kick_s"] / 1e9 / ceil_["ceiling_ginter_s"], 4)
-    out["roofline"]["issue_ceiling"] = ceil_
     if not args.no_small:
         out["small_system"] = bench_small(N, W, torch, np)
         print(f"small system done: {out['small_system']}", file=sys.stderr, flush=True)

@@ -314,22 +314,6 @@ size_t genga_autotune_workspace_bytes(int64_t n, const genga_params *p);
 int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_bytes,
                    const char *cache_path, double *ms_out, void *stream);
 
-/* ------------------------------------------------------------------------
- * Diagnostics.
- * ------------------------------------------------------------------------ */
-
-/* Bytes of the scratch buffer genga_probe_issue_rates needs on this device. */
-size_t genga_probe_issue_rates_bytes(void);
-
-/* Sustained issue cost, in cycles of a 2.4 GHz clock per wave64 instruction
- * and per SIMD, of the vector instructions the kick is built from:
- * cycles[0..5] = v_fma_f64, v_mul_f64, v_add_f64, v_rsq_f64, v_fma_f32,
- * v_rsq_f32.  Each is timed (best of 3) on 8 independent chains per lane with
- * 8 waves per SIMD, so latency is hidden.  These costs give the instruction-
- * issue ceiling of the kick that its roofline fraction is compared with.
- * buf: device scratch of genga_probe_issue_rates_bytes(); synchronises. */
-int genga_probe_issue_rates(double *cycles, void *buf, size_t buf_bytes, void *stream);
-
 #ifdef __cplusplus
 }
 #endif

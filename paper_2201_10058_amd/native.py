@@ -111,9 +111,6 @@ SIGNATURES = {
     "genga_autotune": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_void_p,
                                       ctypes.c_size_t, ctypes.c_char_p,
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
-    "genga_probe_issue_rates_bytes": (ctypes.c_size_t, []),
-    "genga_probe_issue_rates": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
-                                               ctypes.c_size_t, ctypes.c_void_p]),
     "genga_step_batched": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(BatchC),
                                           ctypes.POINTER(Params), ctypes.POINTER(Pairs),
                                           ctypes.c_void_p, ctypes.c_void_p]),
@@ -329,20 +326,6 @@ def energy(state: State, cfg: Config, ws: Workspace, out=None):
                                ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
            "genga_energy")
     return out
-
-
-ISSUE_OPS = ("v_fma_f64", "v_mul_f64", "v_add_f64", "v_rsq_f64", "v_fma_f32", "v_rsq_f32")
-
-
-def probe_issue_rates(device="cuda:0") -> dict:
-    """Sustained cycles (at 2.4 GHz) per wave64 instruction and SIMD."""
-    lib = load()
-    nbytes = int(lib.genga_probe_issue_rates_bytes())
-    buf = torch.zeros(nbytes, dtype=torch.uint8, device=device)
-    out = (ctypes.c_double * len(ISSUE_OPS))()
-    _check(lib.genga_probe_issue_rates(out, ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(nbytes),
-                                       ctypes.c_void_p(_stream_ptr())), "genga_probe_issue_rates")
-    return {k: float(out[i]) for i, k in enumerate(ISSUE_OPS)}
 
 
 # ---------------------------------------------------------------------------
