@@ -247,13 +247,17 @@ def test_drift_hyperbolic_and_eccentric(dev):
 # Step
 # ---------------------------------------------------------------------------
 def test_step_matches_oracle_and_pairs_per_step(dev):
+    # the 2,048-body disk for 100 base steps of 6 days: the encounter list of
+    # every step is bit-exact against the oracle's brute force on the GPU's
+    # own positions and r_crit, and the final state follows the oracle's own
+    # 100-step trajectory (a 1e-15 perturbation grows to ~1e-13 in 100 steps)
     d = W.make_disk(W.DISK_2048)
     st = N.State.from_numpy(d)
     cfg = N.Config(G=G)
     ws = N.Workspace(st.n, cfg)
     ref = oracle.state_copy(d)
     pl = N.PairList(20000)
-    for k in range(10):
+    for k in range(100):
         x0 = {c: st.t[c].cpu().numpy().copy() for c in ("x", "y", "z")}
         code = N.step(st, cfg, ws, pl)
         assert code == N.OK
@@ -267,8 +271,8 @@ def test_step_matches_oracle_and_pairs_per_step(dev):
     vel = np.stack([out[c] for c in ("vx", "vy", "vz")]); rvel = np.stack([ref[c] for c in ("vx", "vy", "vz")])
     ep = np.max(np.abs(pos - rpos)) / np.max(np.abs(rpos))
     ev = np.max(np.abs(vel - rvel)) / np.max(np.abs(rvel))
-    _say("10 steps", ep, ev)
-    assert ep < 1e-12 and ev < 1e-12
+    _say("100 steps", ep, ev)
+    assert ep < 1e-11 and ev < 1e-11
 
 
 # ---------------------------------------------------------------------------
