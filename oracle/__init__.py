@@ -48,6 +48,13 @@ def _load():
     lib.or_rcrit.argtypes = [_i64] + [_p] * 7 + [_d] * 4 + [_p]
     lib.or_kick_acc.restype = ctypes.c_int
     lib.or_kick_acc.argtypes = [_i64] + [_p] * 5 + [_d, _i64, _i64, ctypes.c_int] + [_p] * 3
+    lib.or_kick_acc_tp.restype = ctypes.c_int
+    lib.or_kick_acc_tp.argtypes = ([_i64] + [_p] * 5 + [_d, _i64, ctypes.c_int, _i64, _i64, ctypes.c_int]
+                                   + [_p] * 3)
+    lib.or_pairs_tp.restype = _i64
+    lib.or_pairs_tp.argtypes = [_i64] + [_p] * 4 + [_i64, ctypes.c_int, _i64, _p, _p]
+    lib.or_step_tp.restype = _i64
+    lib.or_step_tp.argtypes = [_i64] + [_p] * 8 + [_d] * 5 + [_i64, ctypes.c_int, _i64, _p, _p, _p]
     lib.or_kick.restype = ctypes.c_int
     lib.or_kick.argtypes = [_i64] + [_p] * 8 + [_d, _d]
     lib.or_pairs.restype = _i64
@@ -108,6 +115,47 @@ def kick_acc(x, y, z, m, rc, G, rows=None, precise=True):
     st = _load().or_kick_acc(n, *map(_ptr, arrs), float(G), int(i0), int(i1), int(bool(precise)),
                              _ptr(ax), _ptr(ay), _ptr(az))
     return ax, ay, az, st
+
+
+def kick_acc_tp(x, y, z, m, rc, G, nm, mode, rows=None, precise=True):
+    """Accelerations in test-particle mode `mode` (bodies [0, nm) massive)."""
+    arrs = [_f64(a) for a in (x, y, z, m, rc)]
+    n = arrs[0].size
+    i0, i1 = (0, n) if rows is None else rows
+    k = max(i1 - i0, 0)
+    ax, ay, az = np.zeros(k), np.zeros(k), np.zeros(k)
+    st = _load().or_kick_acc_tp(n, *map(_ptr, arrs), float(G), int(nm), int(mode), int(i0), int(i1),
+                                int(bool(precise)), _ptr(ax), _ptr(ay), _ptr(az))
+    return ax, ay, az, st
+
+
+def pairs_tp(x, y, z, rc, nm, mode, cap=None):
+    """Canonical close-encounter list in test-particle mode `mode`."""
+    arrs = [_f64(a) for a in (x, y, z, rc)]
+    n = arrs[0].size
+    lib = _load()
+    if cap is None:
+        cap = lib.or_pairs_tp(n, *map(_ptr, arrs), int(nm), int(mode), 0, None, None)
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    cnt = lib.or_pairs_tp(n, *map(_ptr, arrs), int(nm), int(mode), int(cap), _ptr(pi), _ptr(pj))
+    k = min(cnt, cap)
+    return pi[:k].copy(), pj[:k].copy(), int(cnt)
+
+
+def step_tp(state, G, m_star, dt, n1, n2, nm, mode, cap=1 << 20):
+    """One base step in place in test-particle mode `mode`.
+    Returns (pi, pj, count, rc, status)."""
+    n = state["x"].size
+    rc = np.empty(n)
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    st = ctypes.c_int(0)
+    cnt = _load().or_step_tp(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                             _ptr(rc), float(G), float(m_star), float(dt), float(n1), float(n2),
+                             int(nm), int(mode), int(cap), _ptr(pi), _ptr(pj), ctypes.byref(st))
+    k = min(cnt, cap)
+    return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, st.value
 
 
 def kick(state, rc, G, h):

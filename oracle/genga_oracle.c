@@ -108,9 +108,26 @@ static double pair_rho(const double *rc, int64_t i, int64_t j)
 /*              rounded once at the end (the accuracy reference).             */
 /* Returns OR_E_NONFINITE if two distinct bodies coincide.                   */
 /* ------------------------------------------------------------------------ */
-int or_kick_acc(int64_t n, const double *x, const double *y, const double *z,
-                const double *m, const double *rc, double G, int64_t i0, int64_t i1,
-                int precise, double *ax, double *ay, double *az)
+/* ------------------------------------------------------------------------ */
+/* Test-particle modes (Sect. 8, semi-active test particles).  Bodies       */
+/* [0, nm) are massive, [nm, n) are test particles.                          */
+/*   mode 0: every body acts on every other (fully interactive).             */
+/*   mode 1: test particles feel the massive bodies; massive bodies feel     */
+/*           only each other.                                                 */
+/*   mode 2 (semi-active): as mode 1, but test particles also act on the     */
+/*           massive bodies, as in the fully interactive mode.                */
+/* Test particles never act on each other.  Does body j act on body i?       */
+/* ------------------------------------------------------------------------ */
+static int tp_acts(int mode, int64_t nm, int64_t i, int64_t j)
+{
+    if (mode == 0 || j < nm) return 1;
+    if (i >= nm) return 0;
+    return mode == 2;
+}
+
+int or_kick_acc_tp(int64_t n, const double *x, const double *y, const double *z,
+                   const double *m, const double *rc, double G, int64_t nm, int mode,
+                   int64_t i0, int64_t i1, int precise, double *ax, double *ay, double *az)
 {
     int status = OR_OK;
     if (i0 < 0) i0 = 0;
@@ -120,7 +137,7 @@ int or_kick_acc(int64_t n, const double *x, const double *y, const double *z,
         if (!precise) {
             double sx = 0.0, sy = 0.0, sz = 0.0;
             for (int64_t j = 0; j < n; ++j) {
-                if (j == i) continue;
+                if (j == i || !tp_acts(mode, nm, i, j)) continue;
                 double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
                 double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 if (r2 == 0.0) { status = OR_E_NONFINITE; continue; }
@@ -133,7 +150,7 @@ int or_kick_acc(int64_t n, const double *x, const double *y, const double *z,
         } else {
             long double S[3] = {0, 0, 0}, C[3] = {0, 0, 0};
             for (int64_t j = 0; j < n; ++j) {
-                if (j == i) continue;
+                if (j == i || !tp_acts(mode, nm, i, j)) continue;
                 long double d[3] = {(long double)x[j] - x[i], (long double)y[j] - y[i],
                                     (long double)z[j] - z[i]};
                 long double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -165,14 +182,21 @@ int or_kick_acc(int64_t n, const double *x, const double *y, const double *z,
     return status;
 }
 
-/* v_i += h a_i for all bodies (plain path). */
-int or_kick(int64_t n, const double *x, const double *y, const double *z,
-            double *vx, double *vy, double *vz, const double *m, const double *rc,
-            double G, double h)
+int or_kick_acc(int64_t n, const double *x, const double *y, const double *z,
+                const double *m, const double *rc, double G, int64_t i0, int64_t i1,
+                int precise, double *ax, double *ay, double *az)
+{
+    return or_kick_acc_tp(n, x, y, z, m, rc, G, n, 0, i0, i1, precise, ax, ay, az);
+}
+
+/* v_i += h a_i for all bodies (plain path), in test-particle mode `mode`. */
+static int kick_tp(int64_t n, const double *x, const double *y, const double *z, double *vx,
+                   double *vy, double *vz, const double *m, const double *rc, double G, double h,
+                   int64_t nm, int mode)
 {
     double *a = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     if (!a) return -1;
-    int st = or_kick_acc(n, x, y, z, m, rc, G, 0, n, 0, a, a + n, a + 2 * n);
+    int st = or_kick_acc_tp(n, x, y, z, m, rc, G, nm, mode, 0, n, 0, a, a + n, a + 2 * n);
     for (int64_t i = 0; i < n; ++i) {
         vx[i] += h * a[i];
         vy[i] += h * a[n + i];
@@ -180,6 +204,14 @@ int or_kick(int64_t n, const double *x, const double *y, const double *z,
     }
     free(a);
     return st;
+}
+
+/* v_i += h a_i for all bodies (plain path). */
+int or_kick(int64_t n, const double *x, const double *y, const double *z,
+            double *vx, double *vy, double *vz, const double *m, const double *rc,
+            double G, double h)
+{
+    return kick_tp(n, x, y, z, vx, vy, vz, m, rc, G, h, n, 0);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -190,14 +222,22 @@ int or_kick(int64_t n, const double *x, const double *y, const double *z,
 /* Order: i ascending, then j ascending.  Writes at most cap pairs and       */
 /* returns the true count.  Brute force over all pairs.                      */
 /* ------------------------------------------------------------------------ */
-int64_t or_pairs(int64_t n, const double *x, const double *y, const double *z,
-                 const double *rc, int64_t cap, int32_t *pi, int32_t *pj)
+/* Test-particle modes 1 and 2: only pairs with a massive first body       */
+/* (i < nm) are listed; two test particles never form a pair.               */
+int64_t or_pairs_tp(int64_t n, const double *x, const double *y, const double *z,
+                    const double *rc, int64_t nm, int mode, int64_t cap, int32_t *pi,
+                    int32_t *pj)
 {
     int64_t *cnt = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
     if (!cnt) return -1;
+    const int64_t nrow = mode == 0 ? n : (nm < n ? nm : n);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; ++i) {
         int64_t c = 0;
+        if (i >= nrow) {
+            cnt[i + 1] = 0;
+            continue;
+        }
         for (int64_t j = i + 1; j < n; ++j) {
             double rho = pair_rho(rc, i, j);
             if (pair_r2(x, y, z, i, j) < rho * rho) ++c;
@@ -208,7 +248,7 @@ int64_t or_pairs(int64_t n, const double *x, const double *y, const double *z,
     int64_t total = cnt[n];
     if (pi && pj) {
 #pragma omp parallel for schedule(dynamic, 64)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t i = 0; i < nrow; ++i) {
             int64_t p = cnt[i];
             if (p >= cap || cnt[i + 1] == cnt[i]) continue;
             for (int64_t j = i + 1; j < n && p < cap; ++j) {
@@ -225,15 +265,23 @@ int64_t or_pairs(int64_t n, const double *x, const double *y, const double *z,
     return total;
 }
 
+int64_t or_pairs(int64_t n, const double *x, const double *y, const double *z,
+                 const double *rc, int64_t cap, int32_t *pi, int32_t *pj)
+{
+    return or_pairs_tp(n, x, y, z, rc, n, 0, cap, pi, pj);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sun part H_C (eq. Hc): x_i += h P / m_star, P = sum_j m_j v_j.            */
 /* The momentum sum is accumulated in long double.                           */
 /* ------------------------------------------------------------------------ */
-void or_hc(int64_t n, double *x, double *y, double *z, const double *vx,
-           const double *vy, const double *vz, const double *m, double m_star, double h)
+/* nsum: P sums bodies [0, nsum) (test-particle mode 1: the massive ones,   */
+/* since its test particles act on nothing); every body is shifted.          */
+static void hc_n(int64_t n, int64_t nsum, double *x, double *y, double *z, const double *vx,
+                 const double *vy, const double *vz, const double *m, double m_star, double h)
 {
     long double P[3] = {0, 0, 0};
-    for (int64_t j = 0; j < n; ++j) {
+    for (int64_t j = 0; j < nsum; ++j) {
         P[0] += (long double)m[j] * vx[j];
         P[1] += (long double)m[j] * vy[j];
         P[2] += (long double)m[j] * vz[j];
@@ -244,6 +292,12 @@ void or_hc(int64_t n, double *x, double *y, double *z, const double *vx,
         y[i] += h * py / m_star;
         z[i] += h * pz / m_star;
     }
+}
+
+void or_hc(int64_t n, double *x, double *y, double *z, const double *vx,
+           const double *vy, const double *vz, const double *m, double m_star, double h)
+{
+    hc_n(n, n, x, y, z, vx, vy, vz, m, m_star, h);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -363,24 +417,34 @@ int or_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
 /* one of the first half kick.  The (1 - K) part (grouping + Bulirsch-Stoer) */
 /* is not part of this step.  rc (length n) receives the radii used.         */
 /* ------------------------------------------------------------------------ */
+int64_t or_step_tp(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                   double *vz, const double *m, double *rc, double G, double m_star,
+                   double dt, double n1, double n2, int64_t nm, int mode, int64_t cap,
+                   int32_t *pi, int32_t *pj, int *status)
+{
+    int st = OR_OK, s2;
+    const int64_t nsum = mode == 1 ? (nm < n ? nm : n) : n;
+    or_rcrit(n, x, y, z, vx, vy, vz, m, m_star, dt, n1, n2, rc);
+    int64_t np = or_pairs_tp(n, x, y, z, rc, nm, mode, cap, pi, pj);
+    s2 = kick_tp(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt, nm, mode);
+    if (s2 < st) st = s2;
+    hc_n(n, nsum, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    s2 = or_drift(n, x, y, z, vx, vy, vz, G * m_star, dt);
+    if (s2 < st) st = s2;
+    hc_n(n, nsum, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    s2 = kick_tp(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt, nm, mode);
+    if (s2 < st) st = s2;
+    if (status) *status = st;
+    return np;
+}
+
 int64_t or_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
                 double *vz, const double *m, double *rc, double G, double m_star,
                 double dt, double n1, double n2, int64_t cap, int32_t *pi, int32_t *pj,
                 int *status)
 {
-    int st = OR_OK, s2;
-    or_rcrit(n, x, y, z, vx, vy, vz, m, m_star, dt, n1, n2, rc);
-    int64_t np = or_pairs(n, x, y, z, rc, cap, pi, pj);
-    s2 = or_kick(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt);
-    if (s2 < st) st = s2;
-    or_hc(n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
-    s2 = or_drift(n, x, y, z, vx, vy, vz, G * m_star, dt);
-    if (s2 < st) st = s2;
-    or_hc(n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
-    s2 = or_kick(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt);
-    if (s2 < st) st = s2;
-    if (status) *status = st;
-    return np;
+    return or_step_tp(n, x, y, z, vx, vy, vz, m, rc, G, m_star, dt, n1, n2, n, 0, cap, pi, pj,
+                      status);
 }
 
 /* ------------------------------------------------------------------------ */

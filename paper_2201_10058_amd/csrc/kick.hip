@@ -852,10 +852,12 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
     if (p && p->slices > 0) {
         slices = p->slices;
     } else {
-        // about 8192 blocks (32 per CU): large systems get column slices for
-        // latency hiding, small ones short slices so that no wave walks more
-        // than a few hundred columns on an otherwise idle chip
-        slices = (8192 + c.gx - 1) / c.gx;
+        // about 12288 blocks (48 per CU, ~10 waves of resident blocks): large
+        // systems get column slices for latency hiding and a short tail, small
+        // ones short slices so that no wave walks more than a few hundred
+        // columns on an otherwise idle chip (measured at 65,536 bodies: 32,
+        // 40, 48, 64 slices give 2.70, 2.65, 2.64, 2.66 ms)
+        slices = (12288 + c.gx - 1) / c.gx;
     }
     if (slices < 1) slices = 1;
     // slices of a multiple of 64 columns (64 at the least)
