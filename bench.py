@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-tp", action="store_true",
+                    help="skip the test-particle mode timings")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 2,048-body eager vs hipGraph step timing")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -236,6 +238,36 @@ def bench_small(N, W, torch, np, steps=100):
             "eager_step_us": round(eager * 1e6, 2), "graph_step_us": round(graph * 1e6, 2),
             "eager_ginter_s": round(inter / eager / 1e9, 3),
             "graph_ginter_s": round(inter / graph / 1e9, 3)}
+
+
+def bench_tp(N, W, torch, np, steps=20):
+    """Test-particle modes on the 65,536-body zero-inclination disk with 16
+    massive bodies (the setup of the paper's test-particle timings): step time
+    and interactions per second, counting the force terms each mode has."""
+    d = W.make_tp_disk(65536, 16)
+    n, nm = d["n"], d["n_massive"]
+    out = {"workload": d["name"], "n": n, "n_massive": nm}
+    for mode in (1, 2):
+        st = N.State.from_numpy(d)
+        cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                       flags=N.FLAG_NOSYNC, tp_mode=mode, n_massive=nm)
+        ws = N.Workspace(n, cfg)
+        pairs = N.PairList(1 << 16)
+        for _ in range(3):
+            N.step(st, cfg, ws, pairs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            N.step(st, cfg, ws, pairs)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / steps
+        if N.read_status(ws) != N.OK:
+            raise SystemExit("test-particle status")
+        terms = nm * (n - 1) + (n - nm) * nm if mode == 2 else nm * (nm - 1) + (n - nm) * nm
+        out[f"tp{mode}"] = {"step_us": round(dt_s * 1e6, 2),
+                            "ginter_s": round(2.0 * terms / dt_s / 1e9, 3),
+                            "encounter_pairs_last_step": int(pairs.count.item())}
+    return out
 
 
 def pair_list_sha256(pairs) -> str:
@@ -490,6 +522,9 @@ def main():
             out["mixed"]["energy_drift"] = energy_drift(N, W, torch, np)
             print(f"mixed accuracy done: {out['mixed']['accuracy_vs_fp64']} "
                   f"{out['mixed']['energy_drift']}", file=sys.stderr, flush=True)
+    if not args.no_tp:
+        out["test_particles"] = bench_tp(N, W, torch, np)
+        print(f"test particles done: {out['test_particles']}", file=sys.stderr, flush=True)
     if not args.no_small:
         out["small_system"] = bench_small(N, W, torch, np)
         print(f"small system done: {out['small_system']}", file=sys.stderr, flush=True)

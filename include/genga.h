@@ -99,6 +99,19 @@ typedef struct {
                              kernel of genga_kick and of the first half kick of
                              genga_step; [2], [3] around the second half kick
                              of genga_step.  NULL entries are skipped.        */
+    int tp_mode;   /* test-particle mode (Sect. 8): bodies [0, n_massive) are
+                      massive, [n_massive, n) test particles, which never act
+                      on each other.  0: every body acts on every other (the
+                      default; n_massive ignored).  1: test particles feel the
+                      massive bodies but act on nothing (they are left out of
+                      the HC momentum too).  2 (semi-active): as 1, but test
+                      particles act on the massive bodies as in mode 0.  The
+                      encounter list then holds the pairs whose first body is
+                      massive.  Modes 1 and 2 run in the binary64 single-system
+                      genga_kick, genga_encounter_pairs, genga_hc and genga_step;
+                      elsewhere they return GENGA_E_UNSUPPORTED.              */
+    int reserved;  /* 0                                                          */
+    int64_t n_massive; /* number of massive bodies (0 <= n_massive <= n)        */
 } genga_params;
 
 /* Close-encounter list (device memory). */

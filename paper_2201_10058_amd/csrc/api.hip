@@ -38,7 +38,25 @@ static int check_params(const genga_params *p)
     if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
     if (p->ipt < 0 || p->ipt > 2 || p->slices < 0) return GENGA_E_INVAL;
     if (p->block < 0 || p->tile_cols < 0 || p->grid < 0) return GENGA_E_INVAL;
+    if (p->tp_mode < 0 || p->tp_mode > 2 || p->n_massive < 0) return GENGA_E_INVAL;
     return GENGA_OK;
+}
+
+// Test-particle modes: n_massive <= n; only the binary64 single-system kick,
+// pair list and step support them.
+static int check_tp(const genga_bodies *b, const genga_params *p, bool supported)
+{
+    if (p->tp_mode == 0) return GENGA_OK;
+    if (p->n_massive > b->n) return GENGA_E_INVAL;
+    if (!supported || p->precision != GENGA_FP64) return GENGA_E_UNSUPPORTED;
+    return GENGA_OK;
+}
+
+// Bodies whose momentum enters HC: in test-particle mode 1 the test particles
+// act on no body, so only the massive ones.
+static int64_t hc_count(const genga_bodies *b, const genga_params *p)
+{
+    return p->tp_mode == 1 ? p->n_massive : b->n;
 }
 
 static int check_pairs(const genga_pairs *q)
@@ -161,6 +179,7 @@ int genga_kick(const genga_bodies *b, const genga_params *p, double h, double *a
     if ((r = check_pairs(pairs))) return r;
     if (!ws || !is_fin(h)) return GENGA_E_INVAL;
     if ((ax || ay || az) && !(ax && ay && az)) return GENGA_E_INVAL;
+    if ((r = check_tp(b, p, true))) return r;
     return do_kick(b, p, h, ax, ay, az, pairs, true, ws, stream);
 }
 
@@ -173,6 +192,7 @@ int genga_encounter_pairs(const genga_bodies *b, const genga_params *p, genga_pa
     if (!pairs) return GENGA_E_INVAL;
     if ((r = check_pairs(pairs))) return r;
     if (!ws) return GENGA_E_INVAL;
+    if (p->tp_mode != 0 && p->n_massive > b->n) return GENGA_E_INVAL;
     return do_kick(b, p, 0.0, nullptr, nullptr, nullptr, pairs, false, ws, stream);
 }
 
@@ -182,8 +202,9 @@ int genga_hc(genga_bodies *b, const genga_params *p, double h, void *ws, void *s
     if (r) return r;
     if ((r = check_params(p))) return r;
     if (!ws || !is_fin(h)) return GENGA_E_INVAL;
+    if (p->tp_mode != 0 && p->n_massive > b->n) return GENGA_E_INVAL;
     const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
-    hipError_t e = launch_hc(b, p->m_star, h, L, (char *)ws, (hipStream_t)stream);
+    hipError_t e = launch_hc(b, p->m_star, h, L, (char *)ws, (hipStream_t)stream, hc_count(b, p));
     return e == hipSuccess ? GENGA_OK : hip_fail(e);
 }
 
@@ -203,6 +224,7 @@ int genga_energy(const genga_bodies *b, const genga_params *p, double *out, void
     int r = check_bodies(b, true, false);
     if (r) return r;
     if ((r = check_params(p))) return r;
+    if (p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     if (!ws || !out) return GENGA_E_INVAL;
     const KickCfg c = choose_kick_cfg(b->n, p);
     const Layout L = make_layout(b->n, c);
@@ -226,6 +248,7 @@ int genga_kick_vjp(const genga_bodies *b, const genga_params *p, double scale, c
     int r = check_bodies(b, false, true);
     if (r) return r;
     if ((r = check_params(p))) return r;
+    if (p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     if ((r = check_adj(adj, true, false, true, true))) return r;
     if (!ws || !abx || !aby || !abz || !is_fin(scale)) return GENGA_E_INVAL;
     hipError_t e = launch_kick_vjp(b, p, scale, abx, aby, abz, adj, (char *)ws, (hipStream_t)stream);
@@ -238,6 +261,7 @@ int genga_rcrit_vjp(const genga_bodies *b, const genga_params *p, genga_adjoint 
     int r = check_bodies(b, true, false);
     if (r) return r;
     if ((r = check_params(p))) return r;
+    if (p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     if ((r = check_adj(adj, true, true, true, true))) return r;
     if (!ws) return GENGA_E_INVAL;
     hipError_t e = launch_rcrit_vjp(b, p, adj, (hipStream_t)stream);
@@ -250,6 +274,7 @@ int genga_hc_vjp(const genga_bodies *b, const genga_params *p, double h, genga_a
     int r = check_bodies(b, true, false);
     if (r) return r;
     if ((r = check_params(p))) return r;
+    if (p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     if ((r = check_adj(adj, true, true, true, false))) return r;
     if (!ws || !is_fin(h)) return GENGA_E_INVAL;
     const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
@@ -263,6 +288,7 @@ int genga_drift_vjp(const genga_bodies *b, const genga_params *p, double dt, gen
     int r = check_bodies(b, true, false);
     if (r) return r;
     if ((r = check_params(p))) return r;
+    if (p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     if ((r = check_adj(adj, true, true, false, false))) return r;
     if (!ws || !is_fin(dt)) return GENGA_E_INVAL;
     hipError_t e = launch_drift_vjp(b, p, dt, adj, (char *)ws, (hipStream_t)stream);
@@ -276,16 +302,19 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if ((r = check_params(p))) return r;
     if ((r = check_pairs(pairs))) return r;
     if (!ws) return GENGA_E_INVAL;
+    if ((r = check_tp(b, p, true))) return r;
     hipStream_t s = (hipStream_t)stream;
     const double h = 0.5 * p->dt;
     const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
     hipError_t e = launch_rcrit(b, p, (char *)ws, s);
     if (e != hipSuccess) return hip_fail(e);
     if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, pairs, true, ws, stream))) return r;
-    if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s, hc_count(b, p))) != hipSuccess)
+        return hip_fail(e);
     if ((e = launch_drift(b, p->G * p->m_star, p->dt, (char *)ws, s)) != hipSuccess)
         return hip_fail(e);
-    if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s, hc_count(b, p))) != hipSuccess)
+        return hip_fail(e);
     if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2))) return r;
     if (p->flags & GENGA_FLAG_NOSYNC) return GENGA_OK;
     return genga_read_status(ws, stream);

@@ -44,6 +44,7 @@ static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape 
     if (!bt || bt->S < 1 || !bt->offsets) return GENGA_E_INVAL;
     if (!bt->m_star || !bt->dt || !bt->n1 || !bt->n2) return GENGA_E_INVAL;
     if (bt->offsets[0] != 0) return GENGA_E_INVAL;
+    if (p && p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     KickCfg &c = sh.cfg;
     c.nt = (p && p->block == 64) ? 64 : KB;
     if (p && p->block != 0 && p->block != 64 && p->block != KB) return GENGA_E_INVAL;

@@ -227,11 +227,11 @@ hipError_t launch_rcrit(const genga_bodies *b, const genga_params *p, char *ws, 
 }
 
 hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, char *ws,
-                     hipStream_t s)
+                     hipStream_t s, int64_t nsum)
 {
     double *hc = (double *)(ws + L.hc);
     hipLaunchKernelGGL(k_momentum_partial, dim3((unsigned)L.nb), dim3(RB), 0, s, b->vx, b->vy,
-                       b->vz, b->m, b->n, hc);
+                       b->vz, b->m, nsum, hc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hc_apply, dim3((unsigned)L.nb), dim3(RB), 0, s, b->x, b->y, b->z, b->n,

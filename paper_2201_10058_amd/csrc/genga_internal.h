@@ -42,6 +42,15 @@ struct KickCfg {
     int64_t ntiles = 0;       // tiles in one launch
     int64_t nwaves = 0;       // kick waves in one launch (ntiles * nt / 64)
     int grid = 0;             // batch: persistent blocks
+    int gy = 0;               // single system: grid.y of the launch (grid.x = gx)
+    // single system in a test-particle mode (tp = 1 or 2): rows [0, nm) are
+    // the massive bodies (gx_m row blocks, s_m slices of len_m over all
+    // columns), rows [nm, n) the test particles (gx_t row blocks, s_t slices
+    // of len_t over the massive columns); tiles are numbered massive first
+    int tp = 0;
+    int64_t nm = 0;
+    int gx_m = 0, s_m = 0, gx_t = 0, s_t = 0;
+    int64_t len_m = 0, len_t = 0;
 };
 
 // Byte offsets of the workspace regions.
@@ -94,8 +103,9 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
                        hipStream_t s);
 
 hipError_t launch_rcrit(const genga_bodies *b, const genga_params *p, char *ws, hipStream_t s);
+// x_i += h P / m_star for every body, P summed over bodies [0, nsum).
 hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, char *ws,
-                     hipStream_t s);
+                     hipStream_t s, int64_t nsum);
 hipError_t launch_drift(genga_bodies *b, double mu, double dt, char *ws, hipStream_t s);
 hipError_t launch_clear_status(char *ws, hipStream_t s);
 hipError_t launch_energy(const genga_bodies *b, const genga_params *p, double *out,

@@ -42,6 +42,10 @@ struct KickDev {
     int64_t ntiles;
     int gx;               // implicit: row blocks
     int64_t slice_len;    // implicit: columns per slice
+    int tp;               // implicit, test-particle mode 1 or 2 (0: all bodies interact)
+    int64_t nm;           // test-particle modes: bodies [0, nm) are massive
+    int gx_m, s_m, gx_t;  // test-particle modes: massive / test-particle tiling
+    int64_t len_m, len_t;
     double *part;         // [slices][3][npad] (mixed: [slices][4][npad], 4th = sum m/r^2)
     int32_t *cnt;         // [slices][npad]
     int32_t *stage;       // [nwaves][WSEG][3]
@@ -61,13 +65,35 @@ __device__ __forceinline__ TileDesc get_tile(const KickDev &a, int64_t t)
 {
     if (a.tiles) return a.tiles[t];
     TileDesc d;
+    d.sys = 0;
+    if (a.tp) {
+        // massive rows against every column, then test-particle rows against
+        // the massive columns only
+        const int64_t tm = (int64_t)a.gx_m * a.s_m;
+        if (t < tm) {
+            const int64_t bx = t % a.gx_m, by = t / a.gx_m;
+            d.row0 = bx * (int64_t)(NT * IPT);
+            d.nrows = (int32_t)min((int64_t)(NT * IPT), a.nm - d.row0);
+            d.slice = (int32_t)by;
+            d.col0 = by * a.len_m;
+            d.ncols = (int32_t)min(a.len_m, a.n - d.col0);
+        } else {
+            const int64_t u = t - tm;
+            const int64_t bx = u % a.gx_t, by = u / a.gx_t;
+            d.row0 = a.nm + bx * (int64_t)(NT * IPT);
+            d.nrows = (int32_t)min((int64_t)(NT * IPT), a.n - d.row0);
+            d.slice = (int32_t)by;
+            d.col0 = by * a.len_t;
+            d.ncols = (int32_t)min(a.len_t, a.nm - d.col0);
+        }
+        return d;
+    }
     const int64_t bx = t % a.gx, by = t / a.gx;
     d.row0 = bx * (int64_t)(NT * IPT);
     d.nrows = (int32_t)min((int64_t)(NT * IPT), a.n - d.row0);
     d.slice = (int32_t)by;
     d.col0 = by * a.slice_len;
     d.ncols = (int32_t)min(a.slice_len, a.n - d.col0);
-    d.sys = 0;
     return d;
 }
 
@@ -342,7 +368,9 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
             if (jg < j1) {
                 const double rcj = a.rc[jg];
                 if (!(rcj >= 0.0 && rcj < INFINITY)) atomicOr(a.status, ST_RCRIT);
-                const double mj = a.m[jg];
+                // test-particle mode 1: a test particle acts on no body (it is
+                // still tested for encounters with the massive rows)
+                const double mj = (a.tp == 1 && jg >= a.nm) ? 0.0 : a.m[jg];
                 if (MODE == KM_MIXED) {
                     const float rc2f = (float)(rcj * rcj * a.widen);
                     sm.xyzm[q] = make_double4(a.x[jg], a.y[jg], a.z[jg], pack_f32x2((float)mj, rc2f));
@@ -438,6 +466,9 @@ struct ReduceDev {
     const double *sys_dt;         // batched: time step per system
     double G, h, hfac;            // v += h a (single) or hfac * dt_s * a (batched)
     int forces, emit;
+    int tp;                       // test-particle mode: rows [0, nm) use s_m slices, the rest s_t
+    int64_t nm;
+    int s_m, s_t;
     int32_t *queue;               // batch: tile counter of the kick, reset here
     int pstride;                  // partial values per row and slice (3; mixed 4)
     double kappa2;                // mixed: square of the refinement threshold (else 0)
@@ -451,6 +482,7 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     const bool valid = i < r.n;
     if (r.queue && i == 0) *r.queue = 0;
     int nsl = r.slices;
+    if (r.tp) nsl = i < r.nm ? r.s_m : r.s_t;
     double h = r.h;
     if (valid && r.sysid) {
         const int sy = r.sysid[i];
@@ -866,6 +898,36 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
     c.slice_len = len;
     c.slices = (int)((n + c.slice_len - 1) / c.slice_len);
     c.ntiles = (int64_t)c.gx * c.slices;
+    c.gy = c.slices;
+    if (p && p->tp_mode != 0 && p->n_massive < n) {
+        // test particles: massive rows x all columns, test-particle rows x
+        // massive columns, each class with about half of the blocks
+        const int64_t nm = p->n_massive > 0 ? p->n_massive : 0;
+        c.tp = p->tp_mode;
+        c.nm = nm;
+        c.gx_m = (int)((nm + rows_per_block - 1) / rows_per_block);
+        c.gx_t = (int)((n - nm + rows_per_block - 1) / rows_per_block);
+        auto split = [](int64_t cols, int gxc, int &sc, int64_t &len) {
+            if (cols <= 0 || gxc <= 0) {
+                sc = 0;
+                len = 64;
+                return;
+            }
+            int64_t want = (6144 + gxc - 1) / gxc;
+            const int64_t most = (cols + 63) / 64;
+            if (want > most) want = most;
+            if (want < 1) want = 1;
+            len = (((cols + want - 1) / want) + 63) / 64 * 64;
+            sc = (int)((cols + len - 1) / len);
+        };
+        split(n, c.gx_m, c.s_m, c.len_m);
+        split(nm, c.gx_t, c.s_t, c.len_t);
+        c.ntiles = (int64_t)c.gx_m * c.s_m + (int64_t)c.gx_t * c.s_t;
+        c.slices = c.s_m > c.s_t ? c.s_m : c.s_t;
+        if (c.slices < 1) c.slices = 1;
+        c.gx = (int)c.ntiles;    // one-dimensional launch over the tile numbers
+        c.gy = 1;
+    }
     c.nwaves = c.ntiles * (c.nt / 64);
     return c;
 }
@@ -918,7 +980,7 @@ static void launch_k(const KickDev &d, const KickCfg &c, hipStream_t s)
     if (d.tiles)
         hipLaunchKernelGGL((k_kick_persistent<NT, IPT, MODE>), dim3(c.grid), dim3(NT), 0, s, d);
     else
-        hipLaunchKernelGGL((k_kick<NT, IPT, MODE>), dim3(c.gx, c.slices), dim3(NT), 0, s, d);
+        hipLaunchKernelGGL((k_kick<NT, IPT, MODE>), dim3(c.gx, c.gy), dim3(NT), 0, s, d);
 }
 
 template <int NT, int IPT, int MODE>
@@ -961,6 +1023,13 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     d.ntiles = c.ntiles;
     d.gx = c.gx;
     d.slice_len = c.slice_len;
+    d.tp = c.tp;
+    d.nm = c.nm;
+    d.gx_m = c.gx_m;
+    d.s_m = c.s_m;
+    d.gx_t = c.gx_t;
+    d.len_m = c.len_m;
+    d.len_t = c.len_t;
     d.part = (double *)(ws + L.part);
     d.cnt = (int32_t *)(ws + L.cnt);
     d.stage = (int32_t *)(ws + L.stage);
@@ -984,7 +1053,9 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
         hipError_t e0 = hipEventRecord((hipEvent_t)k.ev0, s);
         if (e0 != hipSuccess) return e0;
     }
-    if (c.nt == 64) {
+    if (c.ntiles == 0) {
+        // (test-particle mode without massive bodies: nothing acts on anything)
+    } else if (c.nt == 64) {
         if (c.ipt == 2) launch_mode<64, 2>(d, c, mode, s);
         else launch_mode<64, 1>(d, c, mode, s);
     } else {
@@ -1013,6 +1084,10 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.forces = k.forces;
     r.emit = d.emit;
     r.queue = d.queue;
+    r.tp = c.tp;
+    r.nm = c.nm;
+    r.s_m = c.s_m;
+    r.s_t = c.s_t;
     r.pstride = refine ? 4 : 3;
     r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
     r.refine_list = (int32_t *)(ws + L.rlist);
@@ -1074,6 +1149,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     sd.capacity = k.pairs->capacity;
     sd.nt = c.nt;
     sd.ipt = c.ipt;
+    if (c.nwaves == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs_scatter, dim3((unsigned)c.nwaves), dim3(64), 0, s, sd);
     return hipGetLastError();
 }

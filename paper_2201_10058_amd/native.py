@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
                 ("n1", ctypes.c_double), ("n2", ctypes.c_double), ("precision", ctypes.c_int),
                 ("flags", ctypes.c_int), ("ipt", ctypes.c_int), ("slices", ctypes.c_int),
                 ("block", ctypes.c_int), ("tile_cols", ctypes.c_int), ("grid", ctypes.c_int),
-                ("prof_events", ctypes.c_void_p * 4)]
+                ("prof_events", ctypes.c_void_p * 4), ("tp_mode", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("n_massive", ctypes.c_int64)]
 
 
 class BatchC(ctypes.Structure):
@@ -179,12 +180,16 @@ class Config:
     tile_cols: int = 0
     grid: int = 0
     events: tuple = field(default=(None, None, None, None))
+    tp_mode: int = 0
+    n_massive: int = 0
 
     def params(self) -> Params:
         p = Params(self.G, self.m_star, self.dt, self.n1, self.n2, self.precision, self.flags,
                    self.ipt, self.slices, self.block, self.tile_cols, self.grid)
         for k, e in enumerate(tuple(self.events)[:4]):
             p.prof_events[k] = e
+        p.tp_mode = self.tp_mode
+        p.n_massive = self.n_massive
         return p
 
 

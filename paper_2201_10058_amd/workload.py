@@ -106,8 +106,9 @@ def elements_to_state(a, e, inc, Omega, omega, M, mu):
     return pos, vel
 
 
-def make_disk(spec: DiskSpec) -> dict:
-    """Return a dict of contiguous float64 arrays x,y,z,vx,vy,vz,m,R plus scalars."""
+def make_disk(spec: DiskSpec, masses=None) -> dict:
+    """Return a dict of contiguous float64 arrays x,y,z,vx,vy,vz,m,R plus scalars
+    (equal masses m_total/N unless `masses` [solar masses] is given)."""
     n = spec.n
     rng = np.random.default_rng(spec.seed)
     a = rng.uniform(spec.a_min, spec.a_max, n)
@@ -116,7 +117,10 @@ def make_disk(spec: DiskSpec) -> dict:
     Omega = rng.uniform(0.0, 2.0 * math.pi, n)
     omega = rng.uniform(0.0, 2.0 * math.pi, n)
     M = rng.uniform(0.0, 2.0 * math.pi, n)
-    m = np.full(n, spec.m_total_earth * M_EARTH / n)
+    if masses is None:
+        m = np.full(n, spec.m_total_earth * M_EARTH / n)
+    else:
+        m = np.ascontiguousarray(masses, dtype=np.float64)
     mu = GAUSS_G * (spec.m_star + m)
     pos, vel = elements_to_state(a, e, inc, Omega, omega, M, mu)
     # democratic coordinates: heliocentric positions, barycentric velocities
@@ -129,6 +133,22 @@ def make_disk(spec: DiskSpec) -> dict:
     out.update(n=n, G=GAUSS_G, m_star=spec.m_star, dt=spec.dt, n1=spec.n1, n2=spec.n2,
                name=spec.name)
     return out
+
+
+def make_tp_disk(n: int = 65536, n_massive: int = 16, seed: int = 30,
+                 m_massive_earth: float = 1.0, tp_total_earth: float = 5.0) -> dict:
+    """The test-particle setup of Sect. 8: a disk between 0.5 and 4 AU with
+    zero inclination, whose first `n_massive` bodies are massive (reading:
+    m_massive_earth Earth masses each; the paper gives no value) and the rest
+    test particles sharing tp_total_earth Earth masses (used by the
+    semi-active mode)."""
+    spec = DiskSpec(f"tpdisk_n{n}_m{n_massive}_a0.5-4_i0", n, 0.5, 4.0, tp_total_earth, seed=seed,
+                    sigma_i=0.0)
+    m = np.full(n, tp_total_earth * M_EARTH / max(n - n_massive, 1))
+    m[:n_massive] = m_massive_earth * M_EARTH
+    d = make_disk(spec, masses=m)
+    d["n_massive"] = n_massive
+    return d
 
 
 def batch_sizes(n_systems: int = 512, n_lo: int = 16, n_hi: int = 4096, seed: int = 3) -> np.ndarray:

@@ -64,6 +64,23 @@ def test_host_side_argument_errors():
     assert lib.genga_hc(ctypes.byref(b), ctypes.byref(bad), 1.0, None, None) == native.E_INVAL
     assert lib.genga_read_status(None, None) == native.E_INVAL
     assert lib.genga_energy(ctypes.byref(b), ctypes.byref(p), None, None, None) == native.E_INVAL
+    # test-particle modes: checked on the host before any device work
+    fake = ctypes.c_void_p(256)     # never dereferenced by the host-side checks
+    for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rc"):
+        setattr(b, k, fake)
+    b.n = 10
+    bad_tp = native.Config(G=2.959e-4, tp_mode=3).params()
+    assert lib.genga_kick(ctypes.byref(b), ctypes.byref(bad_tp), 0.0, None, None, None, None, fake,
+                          None) == native.E_INVAL
+    too_many = native.Config(G=2.959e-4, tp_mode=1, n_massive=11).params()
+    assert lib.genga_kick(ctypes.byref(b), ctypes.byref(too_many), 0.0, None, None, None, None, fake,
+                          None) == native.E_INVAL
+    mixed_tp = native.Config(G=2.959e-4, tp_mode=2, n_massive=5, precision=native.MIXED).params()
+    assert lib.genga_kick(ctypes.byref(b), ctypes.byref(mixed_tp), 0.0, None, None, None, None, fake,
+                          None) == native.E_UNSUPPORTED
+    tp = native.Config(G=2.959e-4, tp_mode=2, n_massive=5).params()
+    assert lib.genga_kick_vjp(ctypes.byref(b), ctypes.byref(tp), 1.0, fake, fake, fake, None, fake,
+                              None) in (native.E_INVAL, native.E_UNSUPPORTED)
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 2048, 65536, 4_000_000])

@@ -1,0 +1,119 @@
+"""Test-particle modes 1 and 2 (Sect. 8) of the binary64 kick, pair list and
+step against the oracle's test-particle functions (pinned in test_oracle_tp.py).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2201_10058_amd import native as N
+from paper_2201_10058_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+G = W.GAUSS_G
+ACC_TOL = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _cloud(n, nm, seed, rc_scale=0.3):
+    d = dict(W.random_cloud(n, seed=seed, rc_scale=rc_scale))
+    m = d["m"].copy()
+    m[:nm] *= 50.0
+    d["m"] = m
+    return d
+
+
+def _kick(d, rc, nm, mode, ipt=0):
+    st = N.State.from_numpy(d, rc=rc)
+    cfg = N.Config(G=G, tp_mode=mode, n_massive=nm, ipt=ipt)
+    ws = N.Workspace(st.n, cfg)
+    cap = max(16, oracle.pairs_tp(d["x"], d["y"], d["z"], rc, nm, mode, cap=0)[2])
+    pl = N.PairList(cap)
+    a = N.kick(st, cfg, ws, 0.0, acc=True, pairs=pl)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), pl.result(), N.read_status(ws)
+
+
+def _check(d, rc, nm, mode, ipt=0):
+    a, (pi, pj, cnt), code = _kick(d, rc, nm, mode, ipt)
+    assert code == N.OK
+    ax, ay, az, st = oracle.kick_acc_tp(d["x"], d["y"], d["z"], d["m"], rc, G, nm, mode, precise=True)
+    ref = np.stack([ax, ay, az])
+    scale = np.linalg.norm(ref, axis=0)
+    nz = scale > 0
+    err = np.zeros(ref.shape[1])
+    err[nz] = np.linalg.norm(a - ref, axis=0)[nz] / scale[nz]
+    assert np.all(a[:, ~nz] == 0.0)
+    opi, opj, ocnt = oracle.pairs_tp(d["x"], d["y"], d["z"], rc, nm, mode)
+    _say(f"tp{mode} n={rc.size} nm={nm}: max rel err {err.max():.3e}, pairs {cnt}")
+    assert err.max() <= ACC_TOL
+    assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("n,nm,ipt", [(600, 37, 1), (257, 256, 2), (1000, 1, 1), (300, 300, 1)])
+def test_tp_kick_random(dev, mode, n, nm, ipt):
+    d = _cloud(n, nm, seed=n + nm)
+    _check(d, d["rc"], nm, mode, ipt)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_tp_kick_disk(dev, mode):
+    d = W.make_tp_disk(4096, 16, seed=31)
+    rc = oracle.rcrit(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["m"], 1.0, 6.0, 3.0, 0.4)
+    _check(d, rc, 16, mode)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_tp_no_massive_body(dev, mode):
+    d = _cloud(500, 0, seed=77)
+    a, (pi, pj, cnt), code = _kick(d, d["rc"], 0, mode)
+    assert code == N.OK and cnt == 0
+    assert not np.any(a)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_tp_step_matches_oracle(dev, mode):
+    d = W.make_tp_disk(2048, 16, seed=32)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=G, tp_mode=mode, n_massive=16)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(d)
+    pl = N.PairList(1 << 16)
+    for _ in range(10):
+        x0 = {c: st.t[c].cpu().numpy().copy() for c in "xyz"}
+        assert N.step(st, cfg, ws, pl) == N.OK
+        pi, pj, cnt = pl.result()
+        rc = st.t["rc"].cpu().numpy()
+        opi, opj, ocnt = oracle.pairs_tp(x0["x"], x0["y"], x0["z"], rc, 16, mode)
+        assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
+        oracle.step_tp(ref, G, 1.0, 6.0, 3.0, 0.4, 16, mode)
+    out = st.numpy()
+    for keys in (("x", "y", "z"), ("vx", "vy", "vz")):
+        g = np.stack([out[k] for k in keys])
+        r = np.stack([ref[k] for k in keys])
+        e = np.max(np.abs(g - r)) / np.max(np.abs(r))
+        _say(f"tp{mode} 10 steps {keys[0]}: {e:.3e}")
+        assert e < 1e-12
+
+
+def test_tp_unsupported_combinations(dev):
+    d = _cloud(300, 10, seed=5)
+    st = N.State.from_numpy(d, rc=d["rc"])
+    cfg = N.Config(G=G, tp_mode=2, n_massive=10, precision=N.MIXED)
+    ws = N.Workspace(st.n, cfg)
+    with pytest.raises(N.GengaError) as e:
+        N.kick(st, cfg, ws, 0.0)
+    assert e.value.code == N.E_UNSUPPORTED
+    cfg = N.Config(G=G, tp_mode=2, n_massive=10)
+    with pytest.raises(N.GengaError) as e:
+        N.energy(st, cfg, ws)
+    assert e.value.code == N.E_UNSUPPORTED
+    cfg = N.Config(G=G, tp_mode=1, n_massive=301)
+    with pytest.raises(N.GengaError) as e:
+        N.kick(st, cfg, ws, 0.0)
+    assert e.value.code == N.E_INVAL
