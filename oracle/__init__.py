@@ -55,6 +55,9 @@ def _load():
     lib.or_pairs_tp.argtypes = [_i64] + [_p] * 4 + [_i64, ctypes.c_int, _i64, _p, _p]
     lib.or_step_tp.restype = _i64
     lib.or_step_tp.argtypes = [_i64] + [_p] * 8 + [_d] * 5 + [_i64, ctypes.c_int, _i64, _p, _p, _p]
+    lib.or_step_levels.restype = _i64
+    lib.or_step_levels.argtypes = ([_i64] + [_p] * 8 + [_d] * 5
+                                   + [ctypes.c_int, ctypes.c_int, _i64, _p, _p, _p, _p])
     lib.or_kick.restype = ctypes.c_int
     lib.or_kick.argtypes = [_i64] + [_p] * 8 + [_d, _d]
     lib.or_pairs.restype = _i64
@@ -156,6 +159,25 @@ def step_tp(state, G, m_star, dt, n1, n2, nm, mode, cap=1 << 20):
                              int(nm), int(mode), int(cap), _ptr(pi), _ptr(pj), ctypes.byref(st))
     k = min(cnt, cap)
     return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, st.value
+
+
+def step_levels(state, G, m_star, dt, n1, n2, levels, substeps, cap=1 << 20):
+    """One base step in place with `levels` symplectic levels of `substeps`
+    sub-steps (levels = 1 is `step`).  Returns (pi, pj, count, rc, counts,
+    status): the level-0 list, its count, the level-0 radii and the summed
+    list sizes found at each level."""
+    n = state["x"].size
+    rc = np.empty(n)
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    counts = np.zeros(max(int(levels), 1), dtype=np.int64)
+    st = ctypes.c_int(0)
+    cnt = _load().or_step_levels(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                                 _ptr(rc), float(G), float(m_star), float(dt), float(n1), float(n2),
+                                 int(levels), int(substeps), int(cap), _ptr(pi), _ptr(pj),
+                                 _ptr(counts), ctypes.byref(st))
+    k = min(cnt, cap)
+    return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, counts, st.value
 
 
 def kick(state, rc, G, h):

@@ -448,6 +448,223 @@ int64_t or_step(int64_t n, double *x, double *y, double *z, double *vx, double *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Symplectic levels (Sect. 6.2, higher-level changeover functions, and     */
+/* Appendix A, the recursive encounter routine).  Level 0 is the base step   */
+/* above.  With L > 1 levels, the bodies of the level-0 encounter list are   */
+/* not drifted for dt; instead, starting from their state before the drift,  */
+/* `substeps` sub-steps of dt / substeps advance them: each sub-step takes   */
+/* new critical radii with the sub-step (same eq. rcrit), kicks every pair   */
+/* of the upper level's list with the level weight for half a sub-step,     */
+/* drifts the list's bodies, and kicks again.  The pairs of that list that   */
+/* are closer than the new critical radius (at the sub-step's start) form    */
+/* the next level's list, whose bodies are in turn advanced by sub-steps of  */
+/* the sub-step instead of its drift, down to level L - 1.                   */
+/* Level weights (l >= 1): W_l = prod_{k < l} (1 - K(r; rho_k)) K(r; rho_l); */
+/* what is left, prod_{k < L} (1 - K(r; rho_k)), belongs to the direct       */
+/* solver and is not integrated here (as for L = 1).                         */
+/* Readings: a level's encounter list is taken at the start of each of its  */
+/* sub-steps (the pre-check of its first kick, as at level 0); rho_k of an   */
+/* upper level is the value of its current sub-step; no H_C term inside the  */
+/* levels (the Sun kick stays at level 0).                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z, *vx, *vy, *vz;
+    const double *m;
+    double G, m_star, n1, n2;
+    int levels, substeps;
+    double *rc;        /* [levels][n]: the current critical radii of each level */
+    int status;
+} LevelSys;
+
+/* Weight of level l for the pair (i, j) at separation r. */
+static double level_weight(const LevelSys *S, int l, int64_t i, int64_t j, double r)
+{
+    double w = 1.0;
+    for (int k = 0; k < l; ++k) w *= 1.0 - or_changeover(r, pair_rho(S->rc + k * S->n, i, j));
+    return w * or_changeover(r, pair_rho(S->rc + l * S->n, i, j));
+}
+
+/* v += h a over the pairs of the list with the level-l weight: each pair  */
+/* acts on both of its bodies; a body's terms are added in the list order, */
+/* which is its partners in ascending order.                               */
+static void level_kick(LevelSys *S, int l, const int32_t *pi, const int32_t *pj, int64_t np,
+                       double h)
+{
+    const int64_t n = S->n;
+    double *a = (double *)calloc((size_t)(3 * n), sizeof(double));
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t i = pi[p], j = pj[p];
+        const double dx = S->x[j] - S->x[i], dy = S->y[j] - S->y[i], dz = S->z[j] - S->z[i];
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 == 0.0) { S->status = OR_E_NONFINITE; continue; }
+        const double r = sqrt(r2);
+        const double w = level_weight(S, l, i, j, r);
+        const double si = S->G * S->m[j] * w / (r2 * r);
+        const double sj = S->G * S->m[i] * w / (r2 * r);
+        a[i] += si * dx; a[n + i] += si * dy; a[2 * n + i] += si * dz;
+        a[j] -= sj * dx; a[n + j] -= sj * dy; a[2 * n + j] -= sj * dz;
+    }
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t b[2] = {pi[p], pj[p]};
+        for (int q = 0; q < 2; ++q) {
+            const int64_t k = b[q];
+            if (a[k] == 0.0 && a[n + k] == 0.0 && a[2 * n + k] == 0.0) continue;
+            S->vx[k] += h * a[k];
+            S->vy[k] += h * a[n + k];
+            S->vz[k] += h * a[2 * n + k];
+            a[k] = a[n + k] = a[2 * n + k] = 0.0;   /* each body once */
+        }
+    }
+    free(a);
+}
+
+/* Bodies of a pair list, ascending. */
+static int64_t list_bodies(int64_t n, const int32_t *pi, const int32_t *pj, int64_t np,
+                           int64_t *out)
+{
+    char *f = (char *)calloc((size_t)n, 1);
+    for (int64_t p = 0; p < np; ++p) f[pi[p]] = f[pj[p]] = 1;
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (f[i]) out[k++] = i;
+    free(f);
+    return k;
+}
+
+static void drift_one(LevelSys *S, int64_t i, double dt)
+{
+    double X[3] = {S->x[i], S->y[i], S->z[i]}, V[3] = {S->vx[i], S->vy[i], S->vz[i]};
+    const int st = kepler_one(S->G * S->m_star, dt, X, V);
+    if (st != OR_OK) S->status = st;
+    S->x[i] = X[0]; S->y[i] = X[1]; S->z[i] = X[2];
+    S->vx[i] = V[0]; S->vy[i] = V[1]; S->vz[i] = V[2];
+}
+
+/* State of the listed bodies: save into / restore from buf[6 * k]. */
+static void save_bodies(const LevelSys *S, const int64_t *b, int64_t k, double *buf)
+{
+    for (int64_t q = 0; q < k; ++q) {
+        const int64_t i = b[q];
+        double *o = buf + 6 * q;
+        o[0] = S->x[i]; o[1] = S->y[i]; o[2] = S->z[i];
+        o[3] = S->vx[i]; o[4] = S->vy[i]; o[5] = S->vz[i];
+    }
+}
+
+static void restore_bodies(LevelSys *S, const int64_t *b, int64_t k, const double *buf)
+{
+    for (int64_t q = 0; q < k; ++q) {
+        const int64_t i = b[q];
+        const double *o = buf + 6 * q;
+        S->x[i] = o[0]; S->y[i] = o[1]; S->z[i] = o[2];
+        S->vx[i] = o[3]; S->vy[i] = o[4]; S->vz[i] = o[5];
+    }
+}
+
+/* Level l >= 1: advance the bodies of the list (the encounters of level   */
+/* l - 1) over substeps sub-steps of dt_l each.  counts[l] accumulates the   */
+/* sizes of the lists found at level l.                                     */
+static void level_advance(LevelSys *S, int l, double dt_l, const int32_t *pi, const int32_t *pj,
+                          int64_t np, int64_t *counts)
+{
+    const int64_t n = S->n;
+    int64_t *bod = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * np + 1));
+    const int64_t nb = list_bodies(n, pi, pj, np, bod);
+    int32_t *qi = (int32_t *)malloc(sizeof(int32_t) * (size_t)(np + 1));
+    int32_t *qj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(np + 1));
+    int64_t *sub = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * np + 1));
+    double *buf = (double *)malloc(sizeof(double) * 6 * (size_t)(2 * np + 1));
+    double *rcl = S->rc + l * n;
+    for (int s = 0; s < S->substeps; ++s) {
+        /* critical radii of this level from the sub-step's starting state */
+        for (int64_t q = 0; q < nb; ++q) {
+            const int64_t i = bod[q];
+            or_rcrit(1, S->x + i, S->y + i, S->z + i, S->vx + i, S->vy + i, S->vz + i, S->m + i,
+                     S->m_star, dt_l, S->n1, S->n2, rcl + i);
+        }
+        /* this level's encounters among the list's pairs */
+        int64_t nq = 0;
+        for (int64_t p = 0; p < np; ++p) {
+            const double rho = pair_rho(rcl, pi[p], pj[p]);
+            if (pair_r2(S->x, S->y, S->z, pi[p], pj[p]) < rho * rho) {
+                qi[nq] = pi[p];
+                qj[nq] = pj[p];
+                ++nq;
+            }
+        }
+        counts[l] += nq;
+        const int deeper = l < S->levels - 1 && nq > 0;
+        level_kick(S, l, pi, pj, np, 0.5 * dt_l);
+        int64_t ns = 0;
+        if (deeper) {
+            ns = list_bodies(n, qi, qj, nq, sub);
+            save_bodies(S, sub, ns, buf);
+        }
+        for (int64_t q = 0; q < nb; ++q) drift_one(S, bod[q], dt_l);
+        if (deeper) {
+            restore_bodies(S, sub, ns, buf);
+            level_advance(S, l + 1, dt_l / S->substeps, qi, qj, nq, counts);
+        }
+        level_kick(S, l, pi, pj, np, 0.5 * dt_l);
+    }
+    free(bod); free(qi); free(qj); free(sub); free(buf);
+}
+
+/* One base step with `levels` symplectic levels of `substeps` sub-steps    */
+/* (levels = 1: or_step exactly).  rc receives the level-0 radii; counts     */
+/* (length levels, may be null) the summed list sizes per level.  Returns   */
+/* the level-0 pair count; the level-0 list (cap entries) goes to pi, pj.   */
+int64_t or_step_levels(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                       double *vz, const double *m, double *rc, double G, double m_star,
+                       double dt, double n1, double n2, int levels, int substeps, int64_t cap,
+                       int32_t *pi, int32_t *pj, int64_t *counts, int *status)
+{
+    if (levels < 1) levels = 1;
+    if (substeps < 1) substeps = 1;
+    LevelSys S = {n, x, y, z, vx, vy, vz, m, G, m_star, n1, n2, levels, substeps, NULL, OR_OK};
+    S.rc = (double *)calloc((size_t)(levels * n + 1), sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)levels, sizeof(int64_t));
+    or_rcrit(n, x, y, z, vx, vy, vz, m, m_star, dt, n1, n2, S.rc);
+    const int64_t np = or_pairs(n, x, y, z, S.rc, 0, NULL, NULL);
+    int32_t *ei = (int32_t *)malloc(sizeof(int32_t) * (size_t)(np + 1));
+    int32_t *ej = (int32_t *)malloc(sizeof(int32_t) * (size_t)(np + 1));
+    or_pairs(n, x, y, z, S.rc, np, ei, ej);
+    cnt[0] = np;
+    int st = kick_tp(n, x, y, z, vx, vy, vz, m, S.rc, G, 0.5 * dt, n, 0);
+    if (st < S.status) S.status = st;
+    hc_n(n, n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    const int deeper = levels > 1 && np > 0;
+    int64_t *bod = NULL, nb = 0;
+    double *buf = NULL;
+    if (deeper) {
+        bod = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * np));
+        nb = list_bodies(n, ei, ej, np, bod);
+        buf = (double *)malloc(sizeof(double) * 6 * (size_t)nb);
+        save_bodies(&S, bod, nb, buf);
+    }
+    st = or_drift(n, x, y, z, vx, vy, vz, G * m_star, dt);
+    if (st < S.status) S.status = st;
+    if (deeper) {
+        restore_bodies(&S, bod, nb, buf);
+        level_advance(&S, 1, dt / substeps, ei, ej, np, cnt);
+    }
+    hc_n(n, n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    st = kick_tp(n, x, y, z, vx, vy, vz, m, S.rc, G, 0.5 * dt, n, 0);
+    if (st < S.status) S.status = st;
+    for (int64_t i = 0; i < n; ++i) rc[i] = S.rc[i];
+    for (int64_t p = 0; p < np && p < cap; ++p) {
+        pi[p] = ei[p];
+        pj[p] = ej[p];
+    }
+    if (counts)
+        for (int l = 0; l < levels; ++l) counts[l] = cnt[l];
+    if (status) *status = S.status;
+    free(S.rc); free(cnt); free(ei); free(ej); free(bod); free(buf);
+    return np;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Total energy in democratic coordinates (eqs. H, Ha, Hb, Hc):              */
 /* E = sum m v^2 / 2 + |sum m v|^2 / (2 m_star) - sum G m_star m / r_i        */
 /*     - sum_{i<j} G m_i m_j / r_ij  (the K-weighted parts add up to 1/r).   */

@@ -46,11 +46,15 @@ struct KickCfg {
     // single system in a test-particle mode (tp = 1 or 2): rows [0, nm) are
     // the massive bodies (gx_m row blocks, s_m slices of len_m over all
     // columns), rows [nm, n) the test particles (gx_t row blocks, s_t slices
-    // of len_t over the massive columns); tiles are numbered massive first
+    // of len_t over the massive columns); tiles are numbered massive first.
+    // The massive rows' partial sums form a compact block [s_m][.][mpad]
+    // ahead of the test particles' [s_t][.][npad]; slices then counts the
+    // npad-long slice rows that both need (it sizes the workspace).
     int tp = 0;
     int64_t nm = 0;
     int gx_m = 0, s_m = 0, gx_t = 0, s_t = 0;
     int64_t len_m = 0, len_t = 0;
+    int64_t mpad = 0;
 };
 
 // Byte offsets of the workspace regions.

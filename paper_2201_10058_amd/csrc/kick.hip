@@ -46,6 +46,7 @@ struct KickDev {
     int64_t nm;           // test-particle modes: bodies [0, nm) are massive
     int gx_m, s_m, gx_t;  // test-particle modes: massive / test-particle tiling
     int64_t len_m, len_t;
+    int64_t mpad;         // test-particle modes: row stride of the massive rows' partials
     double *part;         // [slices][3][npad] (mixed: [slices][4][npad], 4th = sum m/r^2)
     int32_t *cnt;         // [slices][npad]
     int32_t *stage;       // [nwaves][WSEG][3]
@@ -58,6 +59,22 @@ struct KickDev {
     double c53;           // 5/3
     double widen;         // mixed: squared widening of the binary32 pre-check radius
 };
+
+// Where the partial values of row i live: value c of slice s is at
+// base + (s * ps + c) * stride + i.  In the test-particle modes the massive
+// rows [0, nm) use a compact block of row stride mpad (they are few and may
+// have many slices), followed by the test particles' slices of stride npad.
+struct PartRows {
+    size_t base, stride;
+};
+
+__device__ __forceinline__ PartRows part_rows(int tp, int64_t nm, int64_t mpad, int s_m,
+                                              int64_t npad, int ps, int64_t i)
+{
+    if (!tp) return {0, (size_t)npad};
+    if (i < nm) return {0, (size_t)mpad};
+    return {(size_t)s_m * ps * mpad, (size_t)npad};
+}
 
 // Tile t: from the list, or from the implicit (row block, slice) grid.
 template <int NT, int IPT>
@@ -402,17 +419,21 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
         fold<IPT, MODE>(R);
     }
 
+    constexpr int PS = MODE == KM_MIXED ? 4 : 3;
+    // (a tile's rows are all massive or all test particles)
+    const PartRows pr = part_rows(a.tp, a.nm, a.mpad, a.s_m, a.npad, PS, td.row0);
+    const PartRows cr = part_rows(a.tp, a.nm, a.mpad, a.s_m, a.npad, 1, td.row0);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         if (R.ii[q] >= 0) {
             if (MODE != KM_PAIRS) {
-                constexpr int PS = MODE == KM_MIXED ? 4 : 3;
-                a.part[((size_t)s * PS + 0) * a.npad + R.ii[q]] = R.ax[q];
-                a.part[((size_t)s * PS + 1) * a.npad + R.ii[q]] = R.ay[q];
-                a.part[((size_t)s * PS + 2) * a.npad + R.ii[q]] = R.az[q];
-                if (MODE == KM_MIXED) a.part[((size_t)s * PS + 3) * a.npad + R.ii[q]] = R.mag[q];
+                double *p = a.part + pr.base + (size_t)s * PS * pr.stride + R.ii[q];
+                p[0] = R.ax[q];
+                p[pr.stride] = R.ay[q];
+                p[2 * pr.stride] = R.az[q];
+                if (MODE == KM_MIXED) p[3 * pr.stride] = R.mag[q];
             }
-            if (a.emit) a.cnt[(size_t)s * a.npad + R.ii[q]] = R.kc[q];
+            if (a.emit) a.cnt[cr.base + (size_t)s * cr.stride + R.ii[q]] = R.kc[q];
         }
     }
     if (a.emit && lane == 0)
@@ -452,7 +473,7 @@ __global__ __launch_bounds__(NT) void k_kick_persistent(KickDev a)
 
 // Sum the slice partials in slice order, apply v += h a, prepare pair offsets.
 struct ReduceDev {
-    const double *part;
+    double *part;
     int32_t *cnt;
     int32_t *rowloc;
     int64_t *bsum;
@@ -467,8 +488,9 @@ struct ReduceDev {
     double G, h, hfac;            // v += h a (single) or hfac * dt_s * a (batched)
     int forces, emit;
     int tp;                       // test-particle mode: rows [0, nm) use s_m slices, the rest s_t
-    int64_t nm;
+    int64_t nm, mpad;
     int s_m, s_t;
+    int m_folded;                 // massive rows' sums already folded into their slice 0
     int32_t *queue;               // batch: tile counter of the kick, reset here
     int pstride;                  // partial values per row and slice (3; mixed 4)
     double kappa2;                // mixed: square of the refinement threshold (else 0)
@@ -482,7 +504,9 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     const bool valid = i < r.n;
     if (r.queue && i == 0) *r.queue = 0;
     int nsl = r.slices;
-    if (r.tp) nsl = i < r.nm ? r.s_m : r.s_t;
+    if (r.tp) nsl = i < r.nm ? (r.m_folded ? 1 : r.s_m) : r.s_t;
+    const PartRows pr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, r.pstride, i);
+    const PartRows cr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, 1, i);
     double h = r.h;
     if (valid && r.sysid) {
         const int sy = r.sysid[i];
@@ -493,7 +517,7 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
         double a3[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            a3[c] = ordered_sum(r.part + (size_t)c * r.npad + i, (size_t)r.pstride * r.npad, nsl);
+            a3[c] = ordered_sum(r.part + pr.base + c * pr.stride + i, r.pstride * pr.stride, nsl);
         }
         bool refine = false;
         if (r.kappa2 > 0.0) {
@@ -501,7 +525,7 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
             // (sum_j m_j / r^2 > kappa |sum_j m_j d / r^3|) is evaluated
             // again in binary64 by k_kick_refine
             const double mag =
-                ordered_sum(r.part + (size_t)3 * r.npad + i, (size_t)r.pstride * r.npad, nsl);
+                ordered_sum(r.part + pr.base + 3 * pr.stride + i, r.pstride * pr.stride, nsl);
             const double a2 = a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2];
             refine = !(mag * mag <= r.kappa2 * a2);
         }
@@ -527,20 +551,21 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     if (r.emit) {
         int64_t c = 0;
         if (valid) {
+            int32_t *cp = r.cnt + cr.base + i;
             int s = 0;
             for (; s + 8 <= nsl; s += 8) {
                 int32_t t[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) t[k] = r.cnt[(size_t)(s + k) * r.npad + i];
+                for (int k = 0; k < 8; ++k) t[k] = cp[(size_t)(s + k) * cr.stride];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    r.cnt[(size_t)(s + k) * r.npad + i] = (int32_t)c;
+                    cp[(size_t)(s + k) * cr.stride] = (int32_t)c;
                     c += t[k];
                 }
             }
             for (; s < nsl; ++s) {
-                const int32_t t = r.cnt[(size_t)s * r.npad + i];
-                r.cnt[(size_t)s * r.npad + i] = (int32_t)c;
+                const int32_t t = cp[(size_t)s * cr.stride];
+                cp[(size_t)s * cr.stride] = (int32_t)c;
                 c += t;
             }
         }
@@ -548,6 +573,53 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
         const int64_t ex = block_excl_scan<RB>(c, &tot, sm);
         if (valid) r.rowloc[i] = (int32_t)ex;
         if (threadIdx.x == 0) r.bsum[blockIdx.x] = tot;
+    }
+}
+
+// Test-particle modes: one wave per massive row folds its s_m slices into
+// slice 0, so that k_kick_reduce reads one slice for these rows.  Lane l takes
+// the slices [l ch, (l + 1) ch) in order, the 64 lane sums are combined by a
+// fixed butterfly; the pair counts become per-slice offsets within the row
+// (an exclusive scan in slice order), and slice 0 then holds the row total
+// (its offset is 0, which k_kick_reduce writes back).
+__global__ __launch_bounds__(RB) void k_fold_massive(ReduceDev r)
+{
+    const int64_t i = (int64_t)blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= r.nm) return;
+    const int ns = r.s_m;
+    const int ch = (ns + 63) / 64;
+    const int s0 = min(ns, lane * ch), s1 = min(ns, s0 + ch);
+    if (r.forces) {
+        const PartRows pr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, r.pstride, i);
+        double *p = r.part + pr.base + i;
+        const size_t step = (size_t)r.pstride * pr.stride;
+        double v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = s1 > s0 ? ordered_sum(p + c * pr.stride + s0 * step, step, s1 - s0) : 0.0;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) v[c] += __shfl_xor(v[c], d, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p[c * pr.stride] = v[c];
+        }
+    }
+    if (r.emit) {
+        const PartRows cr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, 1, i);
+        int32_t *cp = r.cnt + cr.base + i;
+        int64_t mine = 0;
+        for (int s = s0; s < s1; ++s) mine += cp[(size_t)s * cr.stride];
+        const int64_t inc = wave_incl_scan(mine);
+        const int64_t total = __shfl(inc, 63, 64);
+        int64_t off = inc - mine;
+        for (int s = s0; s < s1; ++s) {
+            const int32_t t = cp[(size_t)s * cr.stride];
+            if (s > 0) cp[(size_t)s * cr.stride] = (int32_t)off;
+            off += t;
+        }
+        if (lane == 0) cp[0] = (int32_t)total;
     }
 }
 
@@ -819,7 +891,9 @@ __device__ void scatter_wave(const ScatterDev &d, int64_t wave_g)
         for (int e = lane; e < nst; e += 64) {
             const int32_t *e3 = a.stage + ((size_t)wave_g * WSEG + e) * 3;
             const int64_t i = e3[0];
-            const int64_t pos = d.boff[i / RB] + d.rowloc[i] + a.cnt[(size_t)s * a.npad + i] + e3[2];
+            const PartRows cr = part_rows(a.tp, a.nm, a.mpad, a.s_m, a.npad, 1, i);
+            const int64_t pos =
+                d.boff[i / RB] + d.rowloc[i] + a.cnt[cr.base + (size_t)s * cr.stride + i] + e3[2];
             if (pos < d.capacity) {
                 d.pi[pos] = e3[0];
                 d.pj[pos] = e3[1];
@@ -836,7 +910,8 @@ __device__ void scatter_wave(const ScatterDev &d, int64_t wave_g)
         const int64_t slot = rowbase + q * 64 + lane;
         if (slot >= rowend) continue;
         const int64_t i = slot;
-        int64_t pos = d.boff[i / RB] + d.rowloc[i] + a.cnt[(size_t)s * a.npad + i];
+        const PartRows cr = part_rows(a.tp, a.nm, a.mpad, a.s_m, a.npad, 1, i);
+        int64_t pos = d.boff[i / RB] + d.rowloc[i] + a.cnt[cr.base + (size_t)s * cr.stride + i];
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
         const double rci = a.rc[i];
         const double rc2i = rci * rci;
@@ -923,7 +998,11 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
         split(n, c.gx_m, c.s_m, c.len_m);
         split(nm, c.gx_t, c.s_t, c.len_t);
         c.ntiles = (int64_t)c.gx_m * c.s_m + (int64_t)c.gx_t * c.s_t;
-        c.slices = c.s_m > c.s_t ? c.s_m : c.s_t;
+        // the compact block of the massive rows (up to 5 values per slice, as
+        // the kick's region is sized for) in npad-long slice rows
+        const int64_t npad = ((n + RB - 1) / RB) * RB;
+        c.mpad = ((nm + 63) / 64) * 64;
+        c.slices = (int)(c.s_t + ((int64_t)c.s_m * c.mpad + npad - 1) / npad);
         if (c.slices < 1) c.slices = 1;
         c.gx = (int)c.ntiles;    // one-dimensional launch over the tile numbers
         c.gy = 1;
@@ -1030,6 +1109,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     d.gx_t = c.gx_t;
     d.len_m = c.len_m;
     d.len_t = c.len_t;
+    d.mpad = c.mpad;
     d.part = (double *)(ws + L.part);
     d.cnt = (int32_t *)(ws + L.cnt);
     d.stage = (int32_t *)(ws + L.stage);
@@ -1088,10 +1168,19 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.nm = c.nm;
     r.s_m = c.s_m;
     r.s_t = c.s_t;
+    r.mpad = c.mpad;
+    r.m_folded = 0;
     r.pstride = refine ? 4 : 3;
     r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
     r.refine_list = (int32_t *)(ws + L.rlist);
     r.refine_cnt = d.refine_cnt;
+    if ((r.forces || r.emit) && c.tp && c.nm > 0 && c.s_m > 1) {
+        const unsigned fb = (unsigned)((c.nm + RB / 64 - 1) / (RB / 64));
+        hipLaunchKernelGGL(k_fold_massive, dim3(fb), dim3(RB), 0, s, r);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        r.m_folded = 1;
+    }
     if (r.forces || r.emit) {
         hipLaunchKernelGGL(k_kick_reduce, dim3((unsigned)L.nb), dim3(RB), 0, s, r);
         e = hipGetLastError();

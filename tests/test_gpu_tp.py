@@ -69,6 +69,29 @@ def test_tp_kick_disk(dev, mode):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
+def test_tp_kick_disk65536_sampled(dev, mode):
+    # the benchmark's test-particle disk (16 massive bodies, 65,520 test
+    # particles) in the launch configuration the benchmark times: every
+    # massive row (1,024 column slices each) and two blocks of test-particle
+    # rows against the oracle, and the whole encounter list
+    d = W.make_tp_disk(65536, 16)
+    rc = oracle.rcrit(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["m"], 1.0, 6.0, 3.0, 0.4)
+    a, (pi, pj, cnt), code = _kick(d, rc, 16, mode)
+    assert code == N.OK
+    for i0, i1 in ((0, 16), (16, 2064), (63488, 65536)):
+        ax, ay, az, st = oracle.kick_acc_tp(d["x"], d["y"], d["z"], d["m"], rc, G, 16, mode,
+                                            rows=(i0, i1), precise=True)
+        assert st == 0
+        ref = np.stack([ax, ay, az])
+        err = np.linalg.norm(a[:, i0:i1] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        _say(f"tp{mode} disk65536 rows [{i0}, {i1}): max rel err {err.max():.3e}")
+        assert err.max() <= ACC_TOL
+    opi, opj, ocnt = oracle.pairs_tp(d["x"], d["y"], d["z"], rc, 16, mode)
+    _say(f"tp{mode} disk65536 pairs {cnt}")
+    assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
 def test_tp_no_massive_body(dev, mode):
     d = _cloud(500, 0, seed=77)
     a, (pi, pj, cnt), code = _kick(d, d["rc"], 0, mode)
