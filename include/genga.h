@@ -110,9 +110,25 @@ typedef struct {
                       massive.  Modes 1 and 2 run in the binary64 single-system
                       genga_kick, genga_encounter_pairs, genga_hc and genga_step;
                       elsewhere they return GENGA_E_UNSUPPORTED.              */
-    int reserved;  /* 0                                                          */
+    int slevels;   /* symplectic levels of genga_step (Sect. 6.2, higher-level
+                      changeover functions; Appendix A, recursive encounter
+                      routine).  0 or 1: the base step.  L in [2, GENGA_MAX_LEVELS]:
+                      the bodies of the level-0 encounter list are advanced,
+                      instead of their drift, by `substeps` sub-steps of dt /
+                      substeps at level 1, whose own encounters go one level
+                      deeper, down to level L - 1 (see genga_step).         */
     int64_t n_massive; /* number of massive bodies (0 <= n_massive <= n)        */
+    int substeps;  /* sub-steps per level (>= 1 when slevels > 1)               */
+    int reserved;  /* 0                                                          */
+    int64_t level_capacity; /* slevels > 1: pairs each level's list can hold;
+                               genga_workspace_bytes sizes the workspace for
+                               it.  A level-0 list longer than this sets
+                               GENGA_E_OVERFLOW: the levels then used only its
+                               first level_capacity pairs, and genga_step's
+                               `pairs` receives those and the true count.   */
 } genga_params;
+
+#define GENGA_MAX_LEVELS 8
 
 /* Close-encounter list (device memory). */
 typedef struct {
@@ -189,8 +205,33 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
  *   rc <- Rcrit(x, v); Kick(dt/2) [+ pairs]; HC(dt/2); FG(dt); HC(dt/2);
  *   Kick(dt/2) with the same rc.
  * pairs (nullable) receives the list of the first half kick.  Unless
- * GENGA_FLAG_NOSYNC, synchronises the stream and returns the status. */
+ * GENGA_FLAG_NOSYNC, synchronises the stream and returns the status.
+ *
+ * Symplectic levels (p->slevels = L > 1; Sect. 6.2 and Appendix A): the
+ * bodies of the level-0 list E_0 are not drifted for dt; from their state
+ * before the drift, level l = 1 advances them by `substeps` sub-steps of
+ * dt_l = dt_{l-1} / substeps (dt_0 = dt).  Each sub-step: critical radii
+ * rc_l of eq. (rcrit) with dt_l for the bodies of E_{l-1}; E_l = the pairs
+ * of E_{l-1} with r^2 < max(rc_l,i, rc_l,j)^2 (canonical order); a kick of
+ * dt_l / 2 over the pairs of E_{l-1} with the weight
+ *   W_l(r) = prod_{k<l} (1 - K(r; rho_k)) * K(r; rho_l),
+ * each pair acting on both bodies; the drift of E_{l-1}'s bodies for dt_l,
+ * except that, for l < L - 1, E_l's bodies are instead advanced by level
+ * l + 1 from their state before that drift; and the same kick again.  The
+ * remainder prod_{k<L} (1 - K(r; rho_k)), the direct solver's part, is not
+ * integrated (as for L = 1).  There is no H_C term inside the levels.
+ * ws must be sized with the same params (genga_workspace_bytes); every
+ * level runs in binary64 on the device, with no host synchronisation, so
+ * a step can be captured in a graph.  Not with test-particle modes
+ * (GENGA_E_UNSUPPORTED). */
 int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void *ws, void *stream);
+
+/* Sizes of the symplectic levels' lists in the last genga_step with these
+ * params (slevels > 1): out[0] = |E_0| (the true level-0 count) and, for
+ * l = 1 .. slevels - 1, the sum of |E_l| over all sub-steps of level l
+ * (E_{slevels-1} holds the pairs left to the direct solver).  out is a host
+ * array of slevels int64; synchronises the stream. */
+int genga_level_counts(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream);
 
 /* Energy bookkeeping in binary64: the Hamiltonian of the democratic
  * heliocentric splitting (Sect. 2, eqs. H, Ha, Hb, Hc), whose parts the

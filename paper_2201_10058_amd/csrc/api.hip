@@ -39,6 +39,12 @@ static int check_params(const genga_params *p)
     if (p->ipt < 0 || p->ipt > 2 || p->slices < 0) return GENGA_E_INVAL;
     if (p->block < 0 || p->tile_cols < 0 || p->grid < 0) return GENGA_E_INVAL;
     if (p->tp_mode < 0 || p->tp_mode > 2 || p->n_massive < 0) return GENGA_E_INVAL;
+    if (p->slevels < 0 || p->slevels > GENGA_MAX_LEVELS) return GENGA_E_INVAL;
+    if (p->slevels > 1) {
+        // adjacency offsets are int32 over 2 level_capacity entries
+        if (p->substeps < 1 || p->level_capacity < 1 || p->level_capacity > (1 << 30))
+            return GENGA_E_INVAL;
+    }
     return GENGA_OK;
 }
 
@@ -134,7 +140,7 @@ size_t genga_workspace_bytes(int64_t n, const genga_params *p)
 {
     if (n < 1) return 0;
     const KickCfg c = choose_kick_cfg(n, p);
-    return make_layout(n, c).total;
+    return make_level_layout(n, p, make_layout(n, c).total).total;
 }
 
 int genga_read_status(void *ws, void *stream)
@@ -303,21 +309,44 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if ((r = check_pairs(pairs))) return r;
     if (!ws) return GENGA_E_INVAL;
     if ((r = check_tp(b, p, true))) return r;
+    const bool levels = p->slevels > 1;
+    if (levels && p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const double h = 0.5 * p->dt;
     const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
+    const LevelLayout V = make_level_layout(b->n, p, L.total);
+    genga_pairs e0;
+    if (levels) e0 = level0_pairs(V, (char *)ws);
     hipError_t e = launch_rcrit(b, p, (char *)ws, s);
     if (e != hipSuccess) return hip_fail(e);
-    if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, pairs, true, ws, stream))) return r;
+    if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, levels ? &e0 : pairs, true, ws, stream)))
+        return r;
     if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s, hc_count(b, p))) != hipSuccess)
         return hip_fail(e);
+    if (levels && (e = levels_before_drift(b, V, pairs, (char *)ws, s)) != hipSuccess)
+        return hip_fail(e);
     if ((e = launch_drift(b, p->G * p->m_star, p->dt, (char *)ws, s)) != hipSuccess)
+        return hip_fail(e);
+    if (levels && (e = levels_after_drift(b, p, V, (char *)ws, s)) != hipSuccess)
         return hip_fail(e);
     if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s, hc_count(b, p))) != hipSuccess)
         return hip_fail(e);
     if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2))) return r;
     if (p->flags & GENGA_FLAG_NOSYNC) return GENGA_OK;
     return genga_read_status(ws, stream);
+}
+
+int genga_level_counts(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream)
+{
+    int r = check_params(p);
+    if (r) return r;
+    if (n < 1 || !ws || !out || p->slevels < 2) return GENGA_E_INVAL;
+    const LevelLayout V = make_level_layout(n, p, make_layout(n, choose_kick_cfg(n, p)).total);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(out, (char *)ws + V.lcount, sizeof(int64_t) * V.L,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
 }
 
 }  // extern "C"

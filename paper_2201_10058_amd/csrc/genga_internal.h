@@ -140,4 +140,37 @@ hipError_t launch_hc_b(genga_bodies *b, const BatchDev &bd, double hfac, hipStre
 hipError_t launch_drift_b(genga_bodies *b, const BatchDev &bd, double G, double hfac, char *ws,
                           hipStream_t s);
 
+// Symplectic levels (genga_step with slevels > 1): workspace regions placed
+// after the kick's Layout.  Lists l = 0 .. L-1 (E_0 from the first half kick,
+// E_l detected at level l); adjacency, body list and saved states for the
+// lists that a deeper level integrates (l = 0 .. L-2); critical radii of the
+// levels 1 .. L-1 (level 0 uses the bodies' rc).
+struct LevelLayout {
+    int L = 0;
+    int64_t cap = 0;
+    size_t lcount = 0;                  // int64 [L]   summed list sizes per level
+    size_t cnt = 0;                     // int64 [L]   current size of list l
+    size_t nbod = 0;                    // int32 [L]   bodies of list l
+    size_t bcnt = 0;                    // int64 [DB]  detection block counts / offsets
+    size_t pi[GENGA_MAX_LEVELS] = {}, pj[GENGA_MAX_LEVELS] = {};   // int32 [cap]
+    size_t start[GENGA_MAX_LEVELS] = {};   // int32 [n + 1]  adjacency offsets
+    size_t adj[GENGA_MAX_LEVELS] = {};     // int32 [2 cap]  partners, ascending per body
+    size_t deg[GENGA_MAX_LEVELS] = {};     // int32 [n]      degrees / fill counters
+    size_t bodies[GENGA_MAX_LEVELS] = {};  // int32 [n]      bodies of the list, ascending
+    size_t rc[GENGA_MAX_LEVELS] = {};      // double [n]     rc of level l (l >= 1)
+    size_t shadow[GENGA_MAX_LEVELS] = {};  // double [6][n]  state saved before a drift
+    size_t total = 0;
+};
+// base: byte offset where the level regions start (the kick Layout's total).
+LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base);
+// The level-0 list in the workspace (the first half kick writes it there).
+genga_pairs level0_pairs(const LevelLayout &V, char *ws);
+// After the first half kick and HC: record |E_0|, copy E_0 to the caller's
+// list (nullable), build its adjacency and save its bodies' state.
+hipError_t levels_before_drift(const genga_bodies *b, const LevelLayout &V, genga_pairs *out,
+                               char *ws, hipStream_t s);
+// After the drift of every body: restore E_0's bodies and run levels 1 .. L-1.
+hipError_t levels_after_drift(genga_bodies *b, const genga_params *p, const LevelLayout &V,
+                              char *ws, hipStream_t s);
+
 }  // namespace genga

@@ -576,34 +576,41 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     }
 }
 
-// Test-particle modes: one wave per massive row folds its s_m slices into
-// slice 0, so that k_kick_reduce reads one slice for these rows.  Lane l takes
-// the slices [l ch, (l + 1) ch) in order, the 64 lane sums are combined by a
-// fixed butterfly; the pair counts become per-slice offsets within the row
-// (an exclusive scan in slice order), and slice 0 then holds the row total
-// (its offset is 0, which k_kick_reduce writes back).
-__global__ __launch_bounds__(RB) void k_fold_massive(ReduceDev r)
+// Test-particle modes: one block per massive row folds its s_m slices into
+// slice 0, so that k_kick_reduce reads one slice for these rows.  Thread t
+// takes the slices [t ch, (t + 1) ch) in order, the FT thread sums are
+// combined by a fixed tree in LDS; the pair counts become per-slice offsets
+// within the row (a block exclusive scan in slice order), and slice 0 then
+// holds the row total (its offset is 0, which k_kick_reduce writes back).
+constexpr int FT = 256;
+
+__global__ __launch_bounds__(FT) void k_fold_massive(ReduceDev r)
 {
-    const int64_t i = (int64_t)blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= r.nm) return;
+    __shared__ double sh[3][FT];
+    __shared__ int64_t sc[FT / 64];
+    const int64_t i = blockIdx.x;
+    const int t = threadIdx.x;
     const int ns = r.s_m;
-    const int ch = (ns + 63) / 64;
-    const int s0 = min(ns, lane * ch), s1 = min(ns, s0 + ch);
+    const int ch = (ns + FT - 1) / FT;
+    const int s0 = min(ns, t * ch), s1 = min(ns, s0 + ch);
     if (r.forces) {
         const PartRows pr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, r.pstride, i);
         double *p = r.part + pr.base + i;
         const size_t step = (size_t)r.pstride * pr.stride;
-        double v[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            v[c] = s1 > s0 ? ordered_sum(p + c * pr.stride + s0 * step, step, s1 - s0) : 0.0;
+        for (int c = 0; c < 3; ++c)
+            sh[c][t] = s1 > s0 ? ordered_sum(p + c * pr.stride + s0 * step, step, s1 - s0) : 0.0;
+        __syncthreads();
+        for (int h = FT / 2; h > 0; h >>= 1) {
+            if (t < h) {
 #pragma unroll
-            for (int d = 32; d > 0; d >>= 1) v[c] += __shfl_xor(v[c], d, 64);
+                for (int c = 0; c < 3; ++c) sh[c][t] += sh[c][t + h];
+            }
+            __syncthreads();
         }
-        if (lane == 0) {
+        if (t == 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) p[c * pr.stride] = v[c];
+            for (int c = 0; c < 3; ++c) p[c * pr.stride] = sh[c][0];
         }
     }
     if (r.emit) {
@@ -611,15 +618,14 @@ __global__ __launch_bounds__(RB) void k_fold_massive(ReduceDev r)
         int32_t *cp = r.cnt + cr.base + i;
         int64_t mine = 0;
         for (int s = s0; s < s1; ++s) mine += cp[(size_t)s * cr.stride];
-        const int64_t inc = wave_incl_scan(mine);
-        const int64_t total = __shfl(inc, 63, 64);
-        int64_t off = inc - mine;
+        int64_t total;
+        int64_t off = block_excl_scan<FT>(mine, &total, sc);
         for (int s = s0; s < s1; ++s) {
-            const int32_t t = cp[(size_t)s * cr.stride];
+            const int32_t c = cp[(size_t)s * cr.stride];
             if (s > 0) cp[(size_t)s * cr.stride] = (int32_t)off;
-            off += t;
+            off += c;
         }
-        if (lane == 0) cp[0] = (int32_t)total;
+        if (t == 0) cp[0] = (int32_t)total;
     }
 }
 
@@ -1175,8 +1181,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.refine_list = (int32_t *)(ws + L.rlist);
     r.refine_cnt = d.refine_cnt;
     if ((r.forces || r.emit) && c.tp && c.nm > 0 && c.s_m > 1) {
-        const unsigned fb = (unsigned)((c.nm + RB / 64 - 1) / (RB / 64));
-        hipLaunchKernelGGL(k_fold_massive, dim3(fb), dim3(RB), 0, s, r);
+        hipLaunchKernelGGL(k_fold_massive, dim3((unsigned)c.nm), dim3(FT), 0, s, r);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         r.m_folded = 1;

@@ -43,7 +43,9 @@ class Params(ctypes.Structure):
                 ("flags", ctypes.c_int), ("ipt", ctypes.c_int), ("slices", ctypes.c_int),
                 ("block", ctypes.c_int), ("tile_cols", ctypes.c_int), ("grid", ctypes.c_int),
                 ("prof_events", ctypes.c_void_p * 4), ("tp_mode", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("n_massive", ctypes.c_int64)]
+                ("slevels", ctypes.c_int), ("n_massive", ctypes.c_int64),
+                ("substeps", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("level_capacity", ctypes.c_int64)]
 
 
 class BatchC(ctypes.Structure):
@@ -82,6 +84,8 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "genga_step": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
                                   ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_level_counts": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "genga_energy": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "genga_kick_vjp": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
@@ -182,6 +186,9 @@ class Config:
     events: tuple = field(default=(None, None, None, None))
     tp_mode: int = 0
     n_massive: int = 0
+    slevels: int = 0
+    substeps: int = 0
+    level_capacity: int = 0
 
     def params(self) -> Params:
         p = Params(self.G, self.m_star, self.dt, self.n1, self.n2, self.precision, self.flags,
@@ -190,6 +197,9 @@ class Config:
             p.prof_events[k] = e
         p.tp_mode = self.tp_mode
         p.n_massive = self.n_massive
+        p.slevels = self.slevels
+        p.substeps = self.substeps
+        p.level_capacity = self.level_capacity
         return p
 
 
@@ -319,6 +329,18 @@ def step(state: State, cfg: Config, ws: Workspace, pairs: PairList | None = None
     if code in (E_INVAL, E_HIP, E_UNSUPPORTED):
         raise GengaError(code, "genga_step")
     return code
+
+
+def level_counts(n: int, cfg: Config, ws: Workspace):
+    """Sizes of the symplectic levels' lists in the last step (numpy int64
+    array of cfg.slevels entries; synchronises the stream)."""
+    import numpy as np
+    out = np.zeros(max(cfg.slevels, 1), dtype=np.int64)
+    p = cfg.params()
+    _check(load().genga_level_counts(n, ctypes.byref(p), ctypes.c_void_p(ws.ptr),
+                                     out.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.c_void_p(_stream_ptr())), "genga_level_counts")
+    return out
 
 
 def energy(state: State, cfg: Config, ws: Workspace, out=None):

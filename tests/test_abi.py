@@ -83,6 +83,39 @@ def test_host_side_argument_errors():
                               None) in (native.E_INVAL, native.E_UNSUPPORTED)
 
 
+def test_level_params_on_host():
+    from paper_2201_10058_amd import native
+    lib = native.load()
+    fake = ctypes.c_void_p(256)     # never dereferenced by the host-side checks
+    b = native.Bodies()
+    b.n = 10
+    for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rc"):
+        setattr(b, k, fake)
+    for kw in (dict(slevels=9, substeps=2, level_capacity=100),
+               dict(slevels=2, substeps=0, level_capacity=100),
+               dict(slevels=2, substeps=2, level_capacity=0),
+               dict(slevels=3, substeps=2, level_capacity=(1 << 30) + 1),
+               dict(slevels=-1)):
+        p = native.Config(G=2.959e-4, **kw).params()
+        assert lib.genga_step(ctypes.byref(b), ctypes.byref(p), None, fake, None) == native.E_INVAL
+    tp = native.Config(G=2.959e-4, tp_mode=1, n_massive=4, slevels=2, substeps=2,
+                       level_capacity=64).params()
+    assert lib.genga_step(ctypes.byref(b), ctypes.byref(tp), None, fake, None) == native.E_UNSUPPORTED
+    one = native.Config(G=2.959e-4, slevels=1).params()
+    out = (ctypes.c_int64 * 4)()
+    assert lib.genga_level_counts(10, ctypes.byref(one), fake, out, None) == native.E_INVAL
+    # the workspace grows with the levels and their capacity (two lists and
+    # one adjacency of 2 int32 each per pair at L = 2); a larger L
+    # contains the layout of a smaller one
+    sizes = []
+    for L in (1, 2, 3, 4):
+        p = native.Config(G=2.959e-4, slevels=L, substeps=2, level_capacity=1 << 16).params()
+        sizes.append(lib.genga_workspace_bytes(4096, ctypes.byref(p)))
+    assert sizes == sorted(sizes) and len(set(sizes)) == 4
+    big = native.Config(G=2.959e-4, slevels=2, substeps=2, level_capacity=1 << 20).params()
+    assert lib.genga_workspace_bytes(4096, ctypes.byref(big)) >= sizes[1] + 24 * ((1 << 20) - (1 << 16))
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 2048, 65536, 4_000_000])
 def test_workspace_grows_with_n(n):
     from paper_2201_10058_amd import native

@@ -15,53 +15,15 @@ functions; Appendix A, the recursive encounter routine).
 """
 import numpy as np
 import pytest
-from scipy.integrate import solve_ivp
-
 import oracle
+from encounter_fixture import two_planets
 from paper_2201_10058_amd import workload as W
 
 G = W.GAUSS_G
 
 
 def _two_planets(a2, m=3e-6, T=300.0):
-    """Two planets on circular orbits at 1 AU and a2, at conjunction at T/2.
-    Democratic state (heliocentric x, barycentric v) and the Newtonian
-    heliocentric positions at T."""
-    ms = 1.0
-    mm = np.array([m, m])
-
-    def circ(a, th):
-        v = np.sqrt(G * ms / a)
-        return np.array([a * np.cos(th), a * np.sin(th), 0.0]), np.array(
-            [-v * np.sin(th), v * np.cos(th), 0.0])
-
-    n1, n2 = np.sqrt(G / 1.0), np.sqrt(G / a2 ** 3)
-    x1, v1 = circ(1.0, -(n1 - n2) * T / 2)
-    x2, v2 = circ(a2, 0.0)
-    xh, vh = np.array([x1, x2]), np.array([v1, v2])
-    mt = ms + mm.sum()
-    vb = vh - (mm[:, None] * vh).sum(0) / mt
-    state = {"x": xh[:, 0].copy(), "y": xh[:, 1].copy(), "z": xh[:, 2].copy(),
-             "vx": vb[:, 0].copy(), "vy": vb[:, 1].copy(), "vz": vb[:, 2].copy(), "m": mm.copy()}
-    xs = -(mm[:, None] * xh).sum(0) / mt
-    X = np.vstack([xs, xh + xs])
-    V = np.vstack([-(mm[:, None] * vb).sum(0) / ms, vb])
-    M = np.array([ms, *mm])
-
-    def f(t, u):
-        X = u[:9].reshape(3, 3)
-        A = np.zeros((3, 3))
-        for i in range(3):
-            for j in range(3):
-                if i != j:
-                    d = X[j] - X[i]
-                    A[i] += G * M[j] * d / np.linalg.norm(d) ** 3
-        return np.concatenate([u[9:], A.ravel()])
-
-    sol = solve_ivp(f, (0.0, T), np.concatenate([X.ravel(), V.ravel()]), method="DOP853",
-                    rtol=1e-13, atol=1e-16)
-    Xe = sol.y[:9, -1].reshape(3, 3)
-    return state, Xe[1:] - Xe[0]
+    return two_planets(a2, m=m, T=T)
 
 
 def _run(state, T, dt, n1, n2, levels, substeps):
