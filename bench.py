@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-tp", action="store_true",
                     help="skip the test-particle mode timings")
+    ap.add_argument("--no-levels", action="store_true",
+                    help="skip the symplectic-level timings")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 2,048-body eager vs hipGraph step timing")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -267,6 +269,45 @@ def bench_tp(N, W, torch, np, steps=20):
         out[f"tp{mode}"] = {"step_us": round(dt_s * 1e6, 2),
                             "ginter_s": round(2.0 * terms / dt_s / 1e9, 3),
                             "encounter_pairs_last_step": int(pairs.count.item())}
+    return out
+
+
+LEVEL_CANDIDATES = ((1, 1), (2, 2), (2, 4), (3, 2), (2, 10), (3, 4))
+
+
+def bench_levels(N, W, torch, np, steps=10):
+    """Symplectic levels on the 65,536-body disk: for each (levels, sub-steps)
+    choice, from the same initial state, the time per step, the list sizes of
+    its last step and the relative change of the total energy over its steps;
+    then the native tuner's choice among them (run on a fresh copy)."""
+    from paper_2201_10058_amd import autotune as AT
+    d = W.make_disk(W.DISK_65536)
+    out = {"workload": d["name"], "steps": steps, "configs": {}}
+    base = dict(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                flags=N.FLAG_NOSYNC, level_capacity=1 << 20)
+    for L, s in LEVEL_CANDIDATES:
+        st = N.State.from_numpy(d)
+        cfg = N.Config(**base, slevels=L, substeps=s)
+        ws = N.Workspace(st.n, cfg)
+        pairs = N.PairList(1 << 20)
+        e0 = float(N.energy(st, cfg, ws)[0].item())
+        N.step(st, cfg, ws, pairs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            N.step(st, cfg, ws, pairs)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / steps
+        if N.read_status(ws) != N.OK:
+            raise SystemExit(f"levels {L}x{s}: status")
+        e1 = float(N.energy(st, cfg, ws)[0].item())
+        counts = (N.level_counts(st.n, cfg, ws).tolist() if L > 1
+                  else [int(pairs.count.item())])
+        out["configs"][f"{L}x{s}"] = {"step_ms": round(dt_s * 1e3, 4),
+                                      "list_sizes_last_step": counts,
+                                      "energy_rel_change": (e1 - e0) / abs(e0)}
+    st = N.State.from_numpy(d)
+    out["tuner"] = AT.tune_levels(st, N.Config(**base), LEVEL_CANDIDATES, steps=3)
     return out
 
 
@@ -525,6 +566,9 @@ def main():
     if not args.no_tp:
         out["test_particles"] = bench_tp(N, W, torch, np)
         print(f"test particles done: {out['test_particles']}", file=sys.stderr, flush=True)
+    if not args.no_levels:
+        out["levels"] = bench_levels(N, W, torch, np)
+        print(f"levels done: {out['levels']}", file=sys.stderr, flush=True)
     if not args.no_small:
         out["small_system"] = bench_small(N, W, torch, np)
         print(f"small system done: {out['small_system']}", file=sys.stderr, flush=True)

@@ -368,6 +368,22 @@ size_t genga_autotune_workspace_bytes(int64_t n, const genga_params *p);
 int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_bytes,
                    const char *cache_path, double *ms_out, void *stream);
 
+/* Symplectic-level configuration (Sect. 6.2: each choice of levels and
+ * sub-steps runs for a number of time steps before the simulation, the
+ * fastest is kept, and the test is repeated as the system changes).
+ * Candidate c is (levels[c], substeps[c]) (host arrays of ncand); each runs
+ * one untimed and `steps` timed genga_step calls on the caller's bodies with
+ * the other fields of *p, so the state ADVANCES by ncand * (steps + 1) steps,
+ * all of them ordinary steps of the integration.  Writes p->slevels and
+ * p->substeps of the fastest; ms_out (nullable, host, ncand) receives each
+ * candidate's time per step, or -1 where the workspace (ws_bytes) was too
+ * small for it or a step reported an error (e.g. GENGA_E_OVERFLOW: raise
+ * p->level_capacity).  GENGA_E_UNSUPPORTED if no candidate ran.
+ * Synchronises the stream. */
+int genga_tune_levels(genga_bodies *b, genga_params *p, const int *levels, const int *substeps,
+                      int ncand, int steps, void *ws, size_t ws_bytes, double *ms_out,
+                      void *stream);
+
 #ifdef __cplusplus
 }
 #endif

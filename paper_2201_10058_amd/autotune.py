@@ -65,3 +65,30 @@ def tune_single(state: N.State, cfg: N.Config, use_cache: bool = True) -> dict:
                                 ctypes.c_void_p(N._stream_ptr())),
              "genga_autotune")
     return dict(ipt=p.ipt, slices=p.slices, ms=ms.value)
+
+
+def tune_levels(state: N.State, cfg: N.Config, candidates, steps: int = 10) -> dict:
+    """Pick (slevels, substeps) of the levelled step by running each candidate
+    for `steps` steps on `state` (which advances: these are steps of the
+    integration).  Returns the choice and every candidate's ms per step (-1
+    where it could not run)."""
+    lib = N.load()
+    cands = [(int(L), int(s)) for L, s in candidates]
+    most = 0
+    for L, s in cands:
+        q = N.Config(**{**cfg.__dict__, "slevels": L, "substeps": s}).params()
+        most = max(most, int(lib.genga_workspace_bytes(state.n, ctypes.byref(q))))
+    if most == 0:
+        raise N.GengaError(N.E_INVAL, "genga_workspace_bytes")
+    ws = torch.zeros(most, dtype=torch.uint8, device=state.t["x"].device)
+    lev = (ctypes.c_int * len(cands))(*[c[0] for c in cands])
+    sub = (ctypes.c_int * len(cands))(*[c[1] for c in cands])
+    ms = (ctypes.c_double * len(cands))()
+    p = cfg.params()
+    b = state.bodies()
+    N._check(lib.genga_tune_levels(ctypes.byref(b), ctypes.byref(p), lev, sub, len(cands), int(steps),
+                                   ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(most), ms,
+                                   ctypes.c_void_p(N._stream_ptr())),
+             "genga_tune_levels")
+    return dict(slevels=p.slevels, substeps=p.substeps,
+                ms={f"{L}x{s}": ms[k] for k, (L, s) in enumerate(cands)})

@@ -278,4 +278,49 @@ int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_b
     return GENGA_OK;
 }
 
+int genga_tune_levels(genga_bodies *b, genga_params *p, const int *levels, const int *substeps,
+                      int ncand, int steps, void *ws, size_t ws_bytes, double *ms_out,
+                      void *stream)
+{
+    if (!b || !p || !ws || !levels || !substeps || ncand < 1 || steps < 1) return GENGA_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return GENGA_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return GENGA_E_HIP;
+    }
+    int best = -1;
+    double best_ms = -1.0;
+    for (int c = 0; c < ncand; ++c) {
+        genga_params q = timing_params(p);
+        q.slevels = levels[c];
+        q.substeps = substeps[c];
+        q.flags |= GENGA_FLAG_NOSYNC;
+        double ms = -1.0;
+        const size_t need = genga_workspace_bytes(b->n, &q);
+        // one untimed step (first use of this layout), then `steps` timed ones
+        if (need > 0 && need <= ws_bytes && genga_step(b, &q, nullptr, ws, stream) == GENGA_OK) {
+            bool ok = hipEventRecord(e0, s) == hipSuccess;
+            for (int k = 0; ok && k < steps; ++k) ok = genga_step(b, &q, nullptr, ws, stream) == GENGA_OK;
+            ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float t = 0.0f;
+            if (ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess &&
+                genga_read_status(ws, stream) == GENGA_OK)
+                ms = (double)t / steps;
+        }
+        if (ms_out) ms_out[c] = ms;
+        if (ms >= 0.0 && (best < 0 || ms < best_ms)) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best < 0) return GENGA_E_UNSUPPORTED;
+    p->slevels = levels[best];
+    p->substeps = substeps[best];
+    return GENGA_OK;
+}
+
 }  // extern "C"

@@ -152,9 +152,12 @@ struct LevelLayout {
     size_t cnt = 0;                     // int64 [L]   current size of list l
     size_t nbod = 0;                    // int32 [L]   bodies of list l
     size_t bcnt = 0;                    // int64 [DB]  detection block counts / offsets
+    size_t tsum = 0;                    // int64 [2][n / 256] adjacency tile sums / offsets
     size_t pi[GENGA_MAX_LEVELS] = {}, pj[GENGA_MAX_LEVELS] = {};   // int32 [cap]
     size_t start[GENGA_MAX_LEVELS] = {};   // int32 [n + 1]  adjacency offsets
     size_t adj[GENGA_MAX_LEVELS] = {};     // int32 [2 cap]  partners, ascending per body
+    size_t adj_tmp[GENGA_MAX_LEVELS] = {}; // int32 [2 cap]  partners in arrival order
+    size_t owner[GENGA_MAX_LEVELS] = {};   // int32 [2 cap]  body of each arrival entry
     size_t deg[GENGA_MAX_LEVELS] = {};     // int32 [n]      degrees / fill counters
     size_t bodies[GENGA_MAX_LEVELS] = {};  // int32 [n]      bodies of the list, ascending
     size_t rc[GENGA_MAX_LEVELS] = {};      // double [n]     rc of level l (l >= 1)

@@ -28,7 +28,7 @@ namespace {
 constexpr int LT = 256;     // threads per block of the list kernels
 constexpr int LG = 1024;    // blocks of the grid-stride list kernels
 constexpr int DB = 256;     // blocks (and chunks) of the list compaction
-constexpr int ST = 1024;    // threads of the one-block adjacency scan
+constexpr int ST = 1024;    // threads of the one-block scan of the adjacency tile sums
 
 __device__ __forceinline__ int64_t list_len(const int64_t *cnt, int64_t cap)
 {
@@ -82,8 +82,9 @@ __global__ __launch_bounds__(LT) void k_zero_i32(int32_t *a, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
-// Adjacency of a list: degrees, one-block scan (offsets and the ascending
-// list of bodies), fill, and an insertion sort of each body's partners.
+// Adjacency of a list: degrees, their scan (offsets and the ascending list of
+// bodies), fill in arrival order, and placement of each entry at its rank
+// among the body's partners (so every segment is sorted ascending).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(LT) void k_adj_count(const int32_t *pi, const int32_t *pj,
                                                   const int64_t *cnt, int64_t cap, int32_t *deg)
@@ -95,28 +96,44 @@ __global__ __launch_bounds__(LT) void k_adj_count(const int32_t *pi, const int32
     }
 }
 
-__global__ __launch_bounds__(ST) void k_adj_scan(int32_t *deg, int64_t n, int32_t *start,
-                                                 int32_t *bodies, int32_t *nbod)
+// Offsets and body list in three passes over tiles of LT bodies: tile sums
+// of the degrees and of the bodies with a pair, one block scanning the tile
+// sums, and the tiles again with those offsets.
+__global__ __launch_bounds__(LT) void k_adj_tiles(const int32_t *deg, int64_t n, int64_t *tsum)
+{
+    __shared__ int64_t sm[LT / 64];
+    const int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x;
+    const int32_t d = k < n ? deg[k] : 0;
+    int64_t td, tb;
+    block_excl_scan<LT>(d, &td, sm);
+    block_excl_scan<LT>(d > 0 ? 1 : 0, &tb, sm);
+    if (threadIdx.x == 0) {
+        tsum[2 * blockIdx.x] = td;
+        tsum[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ __launch_bounds__(ST) void k_adj_top(int64_t *tsum, int64_t ntiles, int32_t *start,
+                                                int64_t n, int32_t *nbod)
 {
     __shared__ int64_t sm[ST / 64];
     const int t = threadIdx.x;
-    const int64_t ch = (n + ST - 1) / ST;
-    const int64_t k0 = min(n, t * ch), k1 = min(n, k0 + ch);
+    const int64_t ch = (ntiles + ST - 1) / ST;
+    const int64_t k0 = min(ntiles, t * ch), k1 = min(ntiles, k0 + ch);
     int64_t sd = 0, sb = 0;
     for (int64_t k = k0; k < k1; ++k) {
-        const int32_t d = deg[k];
-        sd += d;
-        sb += d > 0;
+        sd += tsum[2 * k];
+        sb += tsum[2 * k + 1];
     }
     int64_t td, tb;
     int64_t od = block_excl_scan<ST>(sd, &td, sm);
     int64_t ob = block_excl_scan<ST>(sb, &tb, sm);
     for (int64_t k = k0; k < k1; ++k) {
-        const int32_t d = deg[k];
-        start[k] = (int32_t)od;
-        od += d;
-        if (d > 0) bodies[ob++] = (int32_t)k;
-        deg[k] = 0;   // fill counter of k_adj_fill
+        const int64_t a = tsum[2 * k], b = tsum[2 * k + 1];
+        tsum[2 * k] = od;
+        tsum[2 * k + 1] = ob;
+        od += a;
+        ob += b;
     }
     if (t == 0) {
         start[n] = (int32_t)td;
@@ -124,35 +141,53 @@ __global__ __launch_bounds__(ST) void k_adj_scan(int32_t *deg, int64_t n, int32_
     }
 }
 
+__global__ __launch_bounds__(LT) void k_adj_write(int32_t *deg, int64_t n, const int64_t *tsum,
+                                                  int32_t *start, int32_t *bodies)
+{
+    __shared__ int64_t sm[LT / 64];
+    const int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x;
+    const int32_t d = k < n ? deg[k] : 0;
+    int64_t td, tb;
+    const int64_t od = block_excl_scan<LT>(d, &td, sm);
+    const int64_t ob = block_excl_scan<LT>(d > 0 ? 1 : 0, &tb, sm);
+    if (k < n) {
+        start[k] = (int32_t)(tsum[2 * blockIdx.x] + od);
+        if (d > 0) bodies[tsum[2 * blockIdx.x + 1] + ob] = (int32_t)k;
+        deg[k] = 0;   // fill counter of k_adj_fill
+    }
+}
+
+// Each pair into both bodies' segments, in arrival order (owner recorded).
 __global__ __launch_bounds__(LT) void k_adj_fill(const int32_t *pi, const int32_t *pj,
                                                  const int64_t *cnt, int64_t cap,
-                                                 const int32_t *start, int32_t *fill, int32_t *adj)
+                                                 const int32_t *start, int32_t *fill, int32_t *tmp,
+                                                 int32_t *owner)
 {
     const int64_t m = list_len(cnt, cap);
     for (int64_t p = (int64_t)blockIdx.x * LT + threadIdx.x; p < m; p += (int64_t)gridDim.x * LT) {
         const int32_t i = pi[p], j = pj[p];
-        adj[start[i] + atomicAdd(fill + i, 1)] = j;
-        adj[start[j] + atomicAdd(fill + j, 1)] = i;
+        const int32_t si = start[i] + atomicAdd(fill + i, 1);
+        tmp[si] = j;
+        owner[si] = i;
+        const int32_t sj = start[j] + atomicAdd(fill + j, 1);
+        tmp[sj] = i;
+        owner[sj] = j;
     }
 }
 
-__global__ __launch_bounds__(LT) void k_adj_sort(const int32_t *bodies, const int32_t *nbod,
-                                                 const int32_t *start, int32_t *adj)
+// Sorted placement: an entry's rank among its body's partners (all distinct)
+// is the number of smaller partners in the segment.
+__global__ __launch_bounds__(LT) void k_adj_rank(const int32_t *start, int64_t n, const int32_t *tmp,
+                                                 const int32_t *owner, int32_t *adj)
 {
-    const int64_t nb = *nbod;
-    for (int64_t q = (int64_t)blockIdx.x * LT + threadIdx.x; q < nb; q += (int64_t)gridDim.x * LT) {
-        const int32_t b = bodies[q];
-        int32_t *a = adj + start[b];
-        const int len = start[b + 1] - start[b];
-        for (int u = 1; u < len; ++u) {
-            const int32_t v = a[u];
-            int w = u - 1;
-            while (w >= 0 && a[w] > v) {
-                a[w + 1] = a[w];
-                --w;
-            }
-            a[w + 1] = v;
-        }
+    const int64_t total = start[n];
+    for (int64_t e = (int64_t)blockIdx.x * LT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * LT) {
+        const int32_t b = owner[e], v = tmp[e];
+        const int32_t s0 = start[b], s1 = start[b + 1];
+        int32_t r = 0;
+        for (int32_t q = s0; q < s1; ++q) r += tmp[q] < v;
+        adj[s0 + r] = v;
     }
 }
 
@@ -288,7 +323,12 @@ __global__ __launch_bounds__(LT) void k_state_list(BodyDev a, double *shadow, in
 }
 
 // Kick of level l over a list: v_b += h G sum_j m_j W_l(r_bj) (x_j - x_b) / r^3
-// for every body b of the list, its partners j in ascending order.
+// for every body b of the list.  A group of GL lanes takes one body: lane u
+// adds the partners u, u + GL, ... of the body's ascending partner list, and
+// the GL partial sums are combined by a fixed butterfly, so the result does
+// not depend on scheduling.
+constexpr int GL = 8;
+
 struct LevelKickDev {
     BodyDev a;
     const int32_t *start, *adj;
@@ -301,11 +341,16 @@ __global__ __launch_bounds__(LT) void k_level_kick(LevelKickDev k)
 {
     const BodyDev &a = k.a;
     const int64_t nb = *a.nbod;
-    for (int64_t q = (int64_t)blockIdx.x * LT + threadIdx.x; q < nb; q += (int64_t)gridDim.x * LT) {
+    const int u = threadIdx.x & (GL - 1);
+    const int64_t g0 = ((int64_t)blockIdx.x * LT + threadIdx.x) / GL;
+    const int64_t gstride = (int64_t)gridDim.x * (LT / GL);
+    // every lane of a group runs the same trip count (the body loop is
+    // uniform per group), so the butterfly below sees all GL lanes
+    for (int64_t q = g0; q < nb; q += gstride) {
         const int32_t b = a.bodies[q];
         const double xb = a.x[b], yb = a.y[b], zb = a.z[b];
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int32_t e = k.start[b]; e < k.start[b + 1]; ++e) {
+        for (int32_t e = k.start[b] + u; e < k.start[b + 1]; e += GL) {
             const int32_t j = k.adj[e];
             const double dx = a.x[j] - xb, dy = a.y[j] - yb, dz = a.z[j] - zb;
             const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
@@ -322,9 +367,17 @@ __global__ __launch_bounds__(LT) void k_level_kick(LevelKickDev k)
             ay += s * dy;
             az += s * dz;
         }
-        a.vx[b] += k.h * ax;
-        a.vy[b] += k.h * ay;
-        a.vz[b] += k.h * az;
+#pragma unroll
+        for (int d = GL / 2; d > 0; d >>= 1) {
+            ax += __shfl_xor(ax, d, GL);
+            ay += __shfl_xor(ay, d, GL);
+            az += __shfl_xor(az, d, GL);
+        }
+        if (u == 0) {
+            a.vx[b] += k.h * ax;
+            a.vy[b] += k.h * ay;
+            a.vz[b] += k.h * az;
+        }
     }
 }
 
@@ -361,14 +414,19 @@ static hipError_t build_adj(const LevelRun &R, int l)
     const int64_t *cnt = R.at<int64_t>(V.cnt) + l;
     int32_t *deg = R.at<int32_t>(V.deg[l]), *start = R.at<int32_t>(V.start[l]);
     int32_t *adj = R.at<int32_t>(V.adj[l]), *bod = R.at<int32_t>(V.bodies[l]);
+    int32_t *tmp = R.at<int32_t>(V.adj_tmp[l]), *owner = R.at<int32_t>(V.owner[l]);
+    int64_t *tsum = R.at<int64_t>(V.tsum);
     const int64_t n = R.b->n;
+    const unsigned nt = (unsigned)((n + LT - 1) / LT);
     hipLaunchKernelGGL(k_zero_i32, dim3(LG), dim3(LT), 0, R.s, deg, n);
     hipLaunchKernelGGL(k_adj_count, dim3(LG), dim3(LT), 0, R.s, pi, pj, cnt, V.cap, deg);
-    hipLaunchKernelGGL(k_adj_scan, dim3(1), dim3(ST), 0, R.s, deg, n, start, bod,
+    hipLaunchKernelGGL(k_adj_tiles, dim3(nt), dim3(LT), 0, R.s, deg, n, tsum);
+    hipLaunchKernelGGL(k_adj_top, dim3(1), dim3(ST), 0, R.s, tsum, (int64_t)nt, start, n,
                        R.at<int32_t>(V.nbod) + l);
-    hipLaunchKernelGGL(k_adj_fill, dim3(LG), dim3(LT), 0, R.s, pi, pj, cnt, V.cap, start, deg, adj);
-    hipLaunchKernelGGL(k_adj_sort, dim3(LG), dim3(LT), 0, R.s, bod, R.at<int32_t>(V.nbod) + l,
-                       start, adj);
+    hipLaunchKernelGGL(k_adj_write, dim3(nt), dim3(LT), 0, R.s, deg, n, tsum, start, bod);
+    hipLaunchKernelGGL(k_adj_fill, dim3(LG), dim3(LT), 0, R.s, pi, pj, cnt, V.cap, start, deg, tmp,
+                       owner);
+    hipLaunchKernelGGL(k_adj_rank, dim3(LG), dim3(LT), 0, R.s, start, n, tmp, owner, adj);
     return hipGetLastError();
 }
 
@@ -459,6 +517,7 @@ LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base)
     V.cnt = take(sizeof(int64_t) * V.L);
     V.nbod = take(sizeof(int32_t) * V.L);
     V.bcnt = take(sizeof(int64_t) * DB);
+    V.tsum = take(sizeof(int64_t) * 2 * (size_t)((n + LT - 1) / LT));
     for (int l = 0; l < V.L; ++l) {
         V.pi[l] = take(sizeof(int32_t) * (size_t)V.cap);
         V.pj[l] = take(sizeof(int32_t) * (size_t)V.cap);
@@ -466,6 +525,8 @@ LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base)
         if (l < V.L - 1) {
             V.start[l] = take(sizeof(int32_t) * (size_t)(n + 1));
             V.adj[l] = take(sizeof(int32_t) * 2 * (size_t)V.cap);
+            V.adj_tmp[l] = take(sizeof(int32_t) * 2 * (size_t)V.cap);
+            V.owner[l] = take(sizeof(int32_t) * 2 * (size_t)V.cap);
             V.deg[l] = take(sizeof(int32_t) * (size_t)n);
             V.bodies[l] = take(sizeof(int32_t) * (size_t)n);
             V.shadow[l] = take(sizeof(double) * 6 * (size_t)n);

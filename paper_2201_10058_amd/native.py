@@ -84,6 +84,10 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "genga_step": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
                                   ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_tune_levels": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     "genga_level_counts": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "genga_energy": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),

@@ -171,3 +171,21 @@ def test_levels_disk65536_one_step(dev):
     ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
     _say(f"disk65536 levels 2x2: counts {counts}, position {ep:.2e} velocity {ev:.2e}")
     assert ep < 1e-13 and ev < 1e-13
+
+
+def test_tune_levels_picks_the_fastest_that_ran(dev):
+    from paper_2201_10058_amd import autotune as AT
+    d = W.make_disk(W.DISK_2048)
+    st = N.State.from_numpy(d)
+    x0 = st.t["x"].clone()
+    cfg = N.Config(G=G, level_capacity=1 << 16)
+    cands = [(1, 1), (2, 2), (3, 2), (9, 2)]      # 9 levels: rejected, never runs
+    r = AT.tune_levels(st, cfg, cands, steps=2)
+    ms = r["ms"]
+    _say("level tuner", r)
+    assert ms["9x2"] == -1
+    ran = {k: v for k, v in ms.items() if v >= 0}
+    assert len(ran) == 3
+    best = min(ran, key=ran.get)
+    assert f"{r['slevels']}x{r['substeps']}" == best
+    assert not torch.equal(st.t["x"], x0)        # the tuning steps are steps of the run
