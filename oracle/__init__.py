@@ -58,6 +58,14 @@ def _load():
     lib.or_step_levels.restype = _i64
     lib.or_step_levels.argtypes = ([_i64] + [_p] * 8 + [_d] * 5
                                    + [ctypes.c_int, ctypes.c_int, _i64, _p, _p, _p, _p])
+    lib.or_step_direct.restype = _i64
+    lib.or_step_direct.argtypes = ([_i64] + [_p] * 8 + [_d] * 5
+                                   + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _i64]
+                                   + [_p] * 5)
+    lib.or_groups.restype = None
+    lib.or_groups.argtypes = [_i64, _p, _p, _i64, _p]
+    lib.or_direct_group.restype = None
+    lib.or_direct_group.argtypes = ([_i64] + [_p] * 8 + [ctypes.c_int, _d, _d, _p, _i64, _d, _i64])
     lib.or_kick.restype = ctypes.c_int
     lib.or_kick.argtypes = [_i64] + [_p] * 8 + [_d, _d]
     lib.or_pairs.restype = _i64
@@ -178,6 +186,45 @@ def step_levels(state, G, m_star, dt, n1, n2, levels, substeps, cap=1 << 20):
                                  _ptr(counts), ctypes.byref(st))
     k = min(cnt, cap)
     return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, counts, st.value
+
+
+def step_direct(state, G, m_star, dt, n1, n2, levels, substeps, rk_steps=2000, cap=1 << 20):
+    """One step with levels and the direct solver for the deepest level's
+    groups.  Returns (pi, pj, count, rc, counts, (groups, largest), status)."""
+    n = state["x"].size
+    rc = np.empty(n)
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    counts = np.zeros(max(int(levels), 1), dtype=np.int64)
+    gstats = np.zeros(2, dtype=np.int64)
+    st = ctypes.c_int(0)
+    cnt = _load().or_step_direct(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                                 _ptr(rc), float(G), float(m_star), float(dt), float(n1), float(n2),
+                                 int(levels), int(substeps), 1, int(rk_steps), int(cap), _ptr(pi),
+                                 _ptr(pj), _ptr(counts), _ptr(gstats), ctypes.byref(st))
+    k = min(cnt, cap)
+    return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, counts, (int(gstats[0]), int(gstats[1])), st.value
+
+
+def groups(n, pi, pj):
+    """Connected components of the pair graph: label = smallest body of the
+    group for the list's bodies, -1 elsewhere."""
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    pj = np.ascontiguousarray(pj, dtype=np.int32)
+    label = np.zeros(max(int(n), 1), dtype=np.int32)
+    _load().or_groups(int(n), _ptr(pi), _ptr(pj), int(pi.size), _ptr(label))
+    return label[:n]
+
+
+def direct_group(state, rc_levels, G, m_star, members, dt, steps=2000):
+    """Advance the members of one group in place by the direct solver's
+    flow (RK4); rc_levels: (levels used, n) radii."""
+    n = state["x"].size
+    rcl = np.ascontiguousarray(rc_levels, dtype=np.float64).reshape(-1, n)
+    mem = np.ascontiguousarray(members, dtype=np.int64)
+    _load().or_direct_group(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                            _ptr(rcl), rcl.shape[0] - 1, float(G), float(m_star), _ptr(mem),
+                            int(mem.size), float(dt), int(steps))
 
 
 def kick(state, rc, G, h):

@@ -475,6 +475,9 @@ typedef struct {
     int levels, substeps;
     double *rc;        /* [levels][n]: the current critical radii of each level */
     int status;
+    int direct;        /* integrate the deepest level's remainder (groups) */
+    int64_t rk_steps;  /* fourth-order Runge-Kutta steps per group and interval */
+    int64_t groups, group_max;   /* groups integrated, largest group */
 } LevelSys;
 
 /* Weight of level l for the pair (i, j) at separation r. */
@@ -562,6 +565,151 @@ static void restore_bodies(LevelSys *S, const int64_t *b, int64_t k, const doubl
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Close-encounter groups (Sect. 2; Appendix A "grouping"): the bodies of a */
+/* pair list joined by its pairs, i.e. the connected components of the pair  */
+/* graph.  label[b] = the smallest body of b's group for the list's bodies,  */
+/* -1 for every other body.  Breadth-first search from each unlabelled body  */
+/* in ascending order.                                                       */
+/* ------------------------------------------------------------------------ */
+void or_groups(int64_t n, const int32_t *pi, const int32_t *pj, int64_t np, int32_t *label)
+{
+    int64_t *deg = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *nbr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * np + 1));
+    int64_t *fill = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    for (int64_t p = 0; p < np; ++p) {
+        ++deg[pi[p] + 1];
+        ++deg[pj[p] + 1];
+    }
+    for (int64_t i = 0; i < n; ++i) deg[i + 1] += deg[i];
+    for (int64_t p = 0; p < np; ++p) {
+        nbr[deg[pi[p]] + fill[pi[p]]++] = pj[p];
+        nbr[deg[pj[p]] + fill[pj[p]]++] = pi[p];
+    }
+    for (int64_t i = 0; i < n; ++i) label[i] = -1;
+    for (int64_t s0 = 0; s0 < n; ++s0) {
+        if (label[s0] >= 0 || deg[s0 + 1] == deg[s0]) continue;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s0;
+        label[s0] = (int32_t)s0;
+        while (head < tail) {
+            const int64_t b = queue[head++];
+            for (int64_t e = deg[b]; e < deg[b + 1]; ++e) {
+                const int64_t c = nbr[e];
+                if (label[c] < 0) {
+                    label[c] = (int32_t)s0;
+                    queue[tail++] = c;
+                }
+            }
+        }
+    }
+    free(deg); free(nbr); free(fill); free(queue);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The direct solver's share (Sect. 2, Sect. 6.1): the bodies of one group   */
+/* move under the star's Kepler force and the part of their mutual forces   */
+/* that no symplectic level took, R(r) = prod_{k <= l} (1 - K(r; rho_k)),   */
+/* with the radii of the levels as they are (rc[k n + i]):                  */
+/*   dx_i/dt = v_i,                                                         */
+/*   dv_i/dt = -G m_star x_i / |x_i|^3 + G sum_{j in group} m_j R d / r^3.   */
+/* This reference integrates that flow with the classical fourth-order      */
+/* Runge-Kutta method in rk_steps equal steps (pinned against scipy's      */
+/* DOP853 at tight tolerance).                                              */
+/* ------------------------------------------------------------------------ */
+static void direct_rhs(const double *m, const double *rc, int64_t n, int lmax, double G,
+                       double mu, const int64_t *mem, int64_t g, const double *Y, double *F)
+{
+    for (int64_t a = 0; a < g; ++a) {
+        const double *ya = Y + 6 * a;
+        double *fa = F + 6 * a;
+        fa[0] = ya[3]; fa[1] = ya[4]; fa[2] = ya[5];
+        const double r2s = ya[0] * ya[0] + ya[1] * ya[1] + ya[2] * ya[2];
+        const double rs = sqrt(r2s);
+        double ax = -mu * ya[0] / (r2s * rs), ay = -mu * ya[1] / (r2s * rs),
+               az = -mu * ya[2] / (r2s * rs);
+        for (int64_t b = 0; b < g; ++b) {
+            if (b == a) continue;
+            const double *yb = Y + 6 * b;
+            const double dx = yb[0] - ya[0], dy = yb[1] - ya[1], dz = yb[2] - ya[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double r = sqrt(r2);
+            double R = 1.0;
+            for (int k = 0; k <= lmax; ++k)
+                R *= 1.0 - or_changeover(r, pair_rho(rc + (int64_t)k * n, mem[a], mem[b]));
+            const double s = G * m[mem[b]] * R / (r2 * r);
+            ax += s * dx; ay += s * dy; az += s * dz;
+        }
+        fa[3] = ax; fa[4] = ay; fa[5] = az;
+    }
+}
+
+static void direct_rk4(const double *m, const double *rc, int64_t n, int lmax, double G,
+                       double mu, const int64_t *mem, int64_t g, double *Y, double dt,
+                       int64_t steps)
+{
+    const int64_t w = 6 * g;
+    double *k1 = (double *)malloc(sizeof(double) * (size_t)(5 * w));
+    double *k2 = k1 + w, *k3 = k2 + w, *k4 = k3 + w, *T = k4 + w;
+    const double h = dt / (double)steps;
+    for (int64_t st = 0; st < steps; ++st) {
+        direct_rhs(m, rc, n, lmax, G, mu, mem, g, Y, k1);
+        for (int64_t q = 0; q < w; ++q) T[q] = Y[q] + 0.5 * h * k1[q];
+        direct_rhs(m, rc, n, lmax, G, mu, mem, g, T, k2);
+        for (int64_t q = 0; q < w; ++q) T[q] = Y[q] + 0.5 * h * k2[q];
+        direct_rhs(m, rc, n, lmax, G, mu, mem, g, T, k3);
+        for (int64_t q = 0; q < w; ++q) T[q] = Y[q] + h * k3[q];
+        direct_rhs(m, rc, n, lmax, G, mu, mem, g, T, k4);
+        for (int64_t q = 0; q < w; ++q)
+            Y[q] += h / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+    }
+    free(k1);
+}
+
+/* One group alone (for the pins): state arrays of n bodies, members mem[g], */
+/* radii rc[(lmax + 1) n]; the members' state is advanced by dt in place.   */
+void or_direct_group(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                     double *vz, const double *m, const double *rc, int lmax, double G,
+                     double m_star, const int64_t *mem, int64_t g, double dt, int64_t steps)
+{
+    double *Y = (double *)malloc(sizeof(double) * (size_t)(6 * g + 1));
+    for (int64_t a = 0; a < g; ++a) {
+        const int64_t i = mem[a];
+        double *ya = Y + 6 * a;
+        ya[0] = x[i]; ya[1] = y[i]; ya[2] = z[i]; ya[3] = vx[i]; ya[4] = vy[i]; ya[5] = vz[i];
+    }
+    direct_rk4(m, rc, n, lmax, G, G * m_star, mem, g, Y, dt, steps);
+    for (int64_t a = 0; a < g; ++a) {
+        const int64_t i = mem[a];
+        const double *ya = Y + 6 * a;
+        x[i] = ya[0]; y[i] = ya[1]; z[i] = ya[2]; vx[i] = ya[3]; vy[i] = ya[4]; vz[i] = ya[5];
+    }
+    free(Y);
+}
+
+/* The groups of the list (pairs of the deepest level l) advanced over dt   */
+/* from the state they had before the drift (restored by the caller).      */
+static void direct_groups(LevelSys *S, int l, const int32_t *pi, const int32_t *pj, int64_t np,
+                          double dt)
+{
+    const int64_t n = S->n;
+    int32_t *label = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    or_groups(n, pi, pj, np, label);
+    for (int64_t r = 0; r < n; ++r) {
+        if (label[r] != r) continue;          /* r is the smallest body of its group */
+        int64_t g = 0;
+        for (int64_t i = r; i < n; ++i)
+            if (label[i] == r) mem[g++] = i;
+        ++S->groups;
+        if (g > S->group_max) S->group_max = g;
+        or_direct_group(n, S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, S->rc, l, S->G,
+                        S->m_star, mem, g, dt, S->rk_steps);
+    }
+    free(label); free(mem);
+}
+
 /* Level l >= 1: advance the bodies of the list (the encounters of level   */
 /* l - 1) over substeps sub-steps of dt_l each.  counts[l] accumulates the   */
 /* sizes of the lists found at level l.                                     */
@@ -595,17 +743,17 @@ static void level_advance(LevelSys *S, int l, double dt_l, const int32_t *pi, co
         }
         counts[l] += nq;
         const int deeper = l < S->levels - 1 && nq > 0;
+        const int direct = S->direct && l == S->levels - 1 && nq > 0;
         level_kick(S, l, pi, pj, np, 0.5 * dt_l);
         int64_t ns = 0;
-        if (deeper) {
+        if (deeper || direct) {
             ns = list_bodies(n, qi, qj, nq, sub);
             save_bodies(S, sub, ns, buf);
         }
         for (int64_t q = 0; q < nb; ++q) drift_one(S, bod[q], dt_l);
-        if (deeper) {
-            restore_bodies(S, sub, ns, buf);
-            level_advance(S, l + 1, dt_l / S->substeps, qi, qj, nq, counts);
-        }
+        if (deeper || direct) restore_bodies(S, sub, ns, buf);
+        if (deeper) level_advance(S, l + 1, dt_l / S->substeps, qi, qj, nq, counts);
+        if (direct) direct_groups(S, l, qi, qj, nq, dt_l);
         level_kick(S, l, pi, pj, np, 0.5 * dt_l);
     }
     free(bod); free(qi); free(qj); free(sub); free(buf);
@@ -615,14 +763,21 @@ static void level_advance(LevelSys *S, int l, double dt_l, const int32_t *pi, co
 /* (levels = 1: or_step exactly).  rc receives the level-0 radii; counts     */
 /* (length levels, may be null) the summed list sizes per level.  Returns   */
 /* the level-0 pair count; the level-0 list (cap entries) goes to pi, pj.   */
-int64_t or_step_levels(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+/* With direct != 0 the deepest level's remainder is integrated as well:    */
+/* the groups of the deepest list (level-0 list for levels = 1) advance,     */
+/* instead of their drift, under the direct solver's flow (rk_steps RK4     */
+/* steps per group and interval); gstats (nullable) receives the number of  */
+/* groups integrated and the largest group size.                            */
+int64_t or_step_direct(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
                        double *vz, const double *m, double *rc, double G, double m_star,
-                       double dt, double n1, double n2, int levels, int substeps, int64_t cap,
-                       int32_t *pi, int32_t *pj, int64_t *counts, int *status)
+                       double dt, double n1, double n2, int levels, int substeps, int direct,
+                       int64_t rk_steps, int64_t cap, int32_t *pi, int32_t *pj, int64_t *counts,
+                       int64_t *gstats, int *status)
 {
     if (levels < 1) levels = 1;
     if (substeps < 1) substeps = 1;
-    LevelSys S = {n, x, y, z, vx, vy, vz, m, G, m_star, n1, n2, levels, substeps, NULL, OR_OK};
+    LevelSys S = {n, x, y, z, vx, vy, vz, m, G, m_star, n1, n2, levels, substeps, NULL, OR_OK,
+                  direct, rk_steps > 0 ? rk_steps : 1, 0, 0};
     S.rc = (double *)calloc((size_t)(levels * n + 1), sizeof(double));
     int64_t *cnt = (int64_t *)calloc((size_t)levels, sizeof(int64_t));
     or_rcrit(n, x, y, z, vx, vy, vz, m, m_star, dt, n1, n2, S.rc);
@@ -634,7 +789,7 @@ int64_t or_step_levels(int64_t n, double *x, double *y, double *z, double *vx, d
     int st = kick_tp(n, x, y, z, vx, vy, vz, m, S.rc, G, 0.5 * dt, n, 0);
     if (st < S.status) S.status = st;
     hc_n(n, n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
-    const int deeper = levels > 1 && np > 0;
+    const int deeper = (levels > 1 || direct) && np > 0;
     int64_t *bod = NULL, nb = 0;
     double *buf = NULL;
     if (deeper) {
@@ -647,7 +802,8 @@ int64_t or_step_levels(int64_t n, double *x, double *y, double *z, double *vx, d
     if (st < S.status) S.status = st;
     if (deeper) {
         restore_bodies(&S, bod, nb, buf);
-        level_advance(&S, 1, dt / substeps, ei, ej, np, cnt);
+        if (levels > 1) level_advance(&S, 1, dt / substeps, ei, ej, np, cnt);
+        else direct_groups(&S, 0, ei, ej, np, dt);
     }
     hc_n(n, n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
     st = kick_tp(n, x, y, z, vx, vy, vz, m, S.rc, G, 0.5 * dt, n, 0);
@@ -659,9 +815,22 @@ int64_t or_step_levels(int64_t n, double *x, double *y, double *z, double *vx, d
     }
     if (counts)
         for (int l = 0; l < levels; ++l) counts[l] = cnt[l];
+    if (gstats) {
+        gstats[0] = S.groups;
+        gstats[1] = S.group_max;
+    }
     if (status) *status = S.status;
     free(S.rc); free(cnt); free(ei); free(ej); free(bod); free(buf);
     return np;
+}
+
+int64_t or_step_levels(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                       double *vz, const double *m, double *rc, double G, double m_star,
+                       double dt, double n1, double n2, int levels, int substeps, int64_t cap,
+                       int32_t *pi, int32_t *pj, int64_t *counts, int *status)
+{
+    return or_step_direct(n, x, y, z, vx, vy, vz, m, rc, G, m_star, dt, n1, n2, levels, substeps,
+                          0, 1, cap, pi, pj, counts, NULL, status);
 }
 
 /* ------------------------------------------------------------------------ */
