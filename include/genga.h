@@ -59,8 +59,10 @@ extern "C" {
 #define GENGA_E_NONFINITE   (-3) /* two distinct bodies coincide, or a NaN/inf result  */
 #define GENGA_E_HIP         (-4) /* a HIP runtime call failed (genga_last_hip_error)   */
 #define GENGA_E_UNSUPPORTED (-5) /* option not available on this device               */
-#define GENGA_E_NOCONV      (-6) /* Kepler solver did not converge                     */
+#define GENGA_E_NOCONV      (-6) /* Kepler solver or Bulirsch-Stoer did not converge    */
 #define GENGA_E_RCRIT       (-7) /* a critical radius is negative or NaN               */
+#define GENGA_E_GROUP       (-8) /* a close-encounter group exceeds the direct solver's
+                                    GENGA_GROUP_MAX bodies (its bodies kept their drift) */
 
 /* genga_params.precision */
 #define GENGA_FP64  0 /* all pair arithmetic in binary64                              */
@@ -119,16 +121,23 @@ typedef struct {
                       deeper, down to level L - 1 (see genga_step).         */
     int64_t n_massive; /* number of massive bodies (0 <= n_massive <= n)        */
     int substeps;  /* sub-steps per level (>= 1 when slevels > 1)               */
-    int reserved;  /* 0                                                          */
-    int64_t level_capacity; /* slevels > 1: pairs each level's list can hold;
-                               genga_workspace_bytes sizes the workspace for
-                               it.  A level-0 list longer than this sets
-                               GENGA_E_OVERFLOW: the levels then used only its
-                               first level_capacity pairs, and genga_step's
-                               `pairs` receives those and the true count.   */
+    int direct;    /* 1: genga_step also integrates the deepest level's
+                      remainder with the direct solver (close-encounter
+                      groups + Bulirsch-Stoer, Sect. 2 and Sect. 6.1; see
+                      genga_step).  0: that remainder is left out.          */
+    int64_t level_capacity; /* slevels > 1 or direct: pairs each level's list
+                               can hold; genga_workspace_bytes sizes the
+                               workspace for it.  A level-0 list longer than
+                               this sets GENGA_E_OVERFLOW: the levels then used
+                               only its first level_capacity pairs, and
+                               genga_step's `pairs` receives those and the true
+                               count.                                        */
+    double bs_eps; /* direct solver: relative tolerance of the Bulirsch-Stoer
+                      extrapolation; 0 = 1e-12                               */
 } genga_params;
 
 #define GENGA_MAX_LEVELS 8
+#define GENGA_GROUP_MAX 256 /* bodies of the largest group the direct solver takes */
 
 /* Close-encounter list (device memory). */
 typedef struct {
@@ -219,7 +228,22 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
  * except that, for l < L - 1, E_l's bodies are instead advanced by level
  * l + 1 from their state before that drift; and the same kick again.  The
  * remainder prod_{k<L} (1 - K(r; rho_k)), the direct solver's part, is not
- * integrated (as for L = 1).  There is no H_C term inside the levels.
+ * integrated (as for L = 1) unless p->direct.  There is no H_C term inside
+ * the levels.
+ *
+ * Direct solver (p->direct = 1; Sect. 2 and Sect. 6.1; Appendix A "grouping"
+ * and "Bulirsch-Stoer"): the deepest list D (E_0 for L = 1, else the list
+ * E_{L-1} of each sub-step of level L - 1) is split into close-encounter
+ * groups, the connected components of its pair graph; the bodies of each
+ * group move, instead of their drift over that level's interval, under
+ *   dx_i/dt = v_i,
+ *   dv_i/dt = -G m_star x_i/|x_i|^3 + G sum_{j in group} m_j R(r_ij) d/r^3,
+ * R = prod_{k<L} (1 - K(r; rho_k)) with the levels' current radii, from
+ * their state before the drift, integrated by Bulirsch-Stoer extrapolation of
+ * the modified midpoint rule (step sequence 2, 4, ..., 16; each step accepted
+ * when the last two extrapolations agree within p->bs_eps relative to the
+ * state's magnitude, else halved).  One workgroup per group; a group of more
+ * than GENGA_GROUP_MAX bodies sets GENGA_E_GROUP and keeps its drift.
  * ws must be sized with the same params (genga_workspace_bytes); every
  * level runs in binary64 on the device, with no host synchronisation, so
  * a step can be captured in a graph.  Not with test-particle modes
@@ -232,6 +256,12 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
  * (E_{slevels-1} holds the pairs left to the direct solver).  out is a host
  * array of slevels int64; synchronises the stream. */
 int genga_level_counts(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream);
+
+/* Direct solver statistics of the last genga_step with these params (direct
+ * = 1): out[0] = groups integrated (summed over the deepest level's
+ * sub-steps), out[1] = the largest group's size.  out is a host array of 2
+ * int64; synchronises the stream. */
+int genga_group_stats(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream);
 
 /* Energy bookkeeping in binary64: the Hamiltonian of the democratic
  * heliocentric splitting (Sect. 2, eqs. H, Ha, Hb, Hc), whose parts the

@@ -40,10 +40,12 @@ static int check_params(const genga_params *p)
     if (p->block < 0 || p->tile_cols < 0 || p->grid < 0) return GENGA_E_INVAL;
     if (p->tp_mode < 0 || p->tp_mode > 2 || p->n_massive < 0) return GENGA_E_INVAL;
     if (p->slevels < 0 || p->slevels > GENGA_MAX_LEVELS) return GENGA_E_INVAL;
-    if (p->slevels > 1) {
+    if (p->direct != 0 && p->direct != 1) return GENGA_E_INVAL;
+    if (!is_fin(p->bs_eps) || p->bs_eps < 0.0) return GENGA_E_INVAL;
+    if (p->slevels > 1 || p->direct) {
         // adjacency offsets are int32 over 2 level_capacity entries
-        if (p->substeps < 1 || p->level_capacity < 1 || p->level_capacity > (1 << 30))
-            return GENGA_E_INVAL;
+        if (p->level_capacity < 1 || p->level_capacity > (1 << 30)) return GENGA_E_INVAL;
+        if (p->slevels > 1 && p->substeps < 1) return GENGA_E_INVAL;
     }
     return GENGA_OK;
 }
@@ -78,6 +80,7 @@ static int status_to_code(int32_t st)
     if (st & ST_RCRIT) return GENGA_E_RCRIT;
     if (st & ST_NONFINITE) return GENGA_E_NONFINITE;
     if (st & ST_NOCONV) return GENGA_E_NOCONV;
+    if (st & ST_GROUP) return GENGA_E_GROUP;
     if (st & ST_OVERFLOW) return GENGA_E_OVERFLOW;
     return GENGA_OK;
 }
@@ -128,8 +131,9 @@ const char *genga_strerror(int code)
     case GENGA_E_NONFINITE: return "coincident bodies or non-finite result";
     case GENGA_E_HIP: return "HIP runtime error";
     case GENGA_E_UNSUPPORTED: return "unsupported option";
-    case GENGA_E_NOCONV: return "Kepler solver did not converge";
+    case GENGA_E_NOCONV: return "Kepler solver or Bulirsch-Stoer did not converge";
     case GENGA_E_RCRIT: return "negative or non-finite critical radius";
+    case GENGA_E_GROUP: return "close-encounter group larger than the direct solver's limit";
     default: return "unknown error";
     }
 }
@@ -309,7 +313,7 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if ((r = check_pairs(pairs))) return r;
     if (!ws) return GENGA_E_INVAL;
     if ((r = check_tp(b, p, true))) return r;
-    const bool levels = p->slevels > 1;
+    const bool levels = p->slevels > 1 || p->direct;
     if (levels && p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const double h = 0.5 * p->dt;
@@ -336,11 +340,24 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     return genga_read_status(ws, stream);
 }
 
+int genga_group_stats(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream)
+{
+    int r = check_params(p);
+    if (r) return r;
+    if (n < 1 || !ws || !out || !p->direct) return GENGA_E_INVAL;
+    const LevelLayout V = make_level_layout(n, p, make_layout(n, choose_kick_cfg(n, p)).total);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(out, (char *)ws + V.gstats, 2 * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
 int genga_level_counts(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream)
 {
     int r = check_params(p);
     if (r) return r;
-    if (n < 1 || !ws || !out || p->slevels < 2) return GENGA_E_INVAL;
+    if (n < 1 || !ws || !out || (p->slevels < 2 && !p->direct)) return GENGA_E_INVAL;
     const LevelLayout V = make_level_layout(n, p, make_layout(n, choose_kick_cfg(n, p)).total);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(out, (char *)ws + V.lcount, sizeof(int64_t) * V.L,

@@ -14,7 +14,8 @@ enum : int32_t {
     ST_OVERFLOW = 1,   // encounter list longer than its capacity
     ST_NONFINITE = 2,  // coincident distinct bodies or a non-finite result
     ST_RCRIT = 4,      // negative or NaN critical radius
-    ST_NOCONV = 8,     // Kepler solve did not converge
+    ST_NOCONV = 8,     // Kepler solve or Bulirsch-Stoer did not converge
+    ST_GROUP = 16,     // a close-encounter group larger than GENGA_GROUP_MAX
 };
 
 constexpr int KB = 256;      // threads per kick block (4 waves of 64)
@@ -162,6 +163,19 @@ struct LevelLayout {
     size_t bodies[GENGA_MAX_LEVELS] = {};  // int32 [n]      bodies of the list, ascending
     size_t rc[GENGA_MAX_LEVELS] = {};      // double [n]     rc of level l (l >= 1)
     size_t shadow[GENGA_MAX_LEVELS] = {};  // double [6][n]  state saved before a drift
+    // direct solver (groups of the deepest list L - 1)
+    int direct = 0;
+    size_t glab = 0;       // int32 [n]  parent in the union-find, then the group's root
+    size_t gflag = 0;      // int32 [n]  body in the deepest list
+    size_t gsize = 0;      // int32 [n]  members per root
+    size_t gfill = 0;      // int32 [n]  fill counters per root
+    size_t gstart = 0;     // int32 [n]  first member slot per root
+    size_t groot = 0;      // int32 [n]  roots in ascending order (one per group)
+    size_t gtmp = 0;       // int32 [n]  members in arrival order
+    size_t gmem = 0;       // int32 [n]  members, ascending within each group
+    size_t gcount = 0;     // int32 [2]  groups, members
+    size_t gstats = 0;     // int64 [2]  groups integrated, largest group (per step)
+    size_t gtsum = 0;      // int64 [2][n / 256] tile sums of the group scan
     size_t total = 0;
 };
 // base: byte offset where the level regions start (the kick Layout's total).
@@ -172,7 +186,9 @@ genga_pairs level0_pairs(const LevelLayout &V, char *ws);
 // list (nullable), build its adjacency and save its bodies' state.
 hipError_t levels_before_drift(const genga_bodies *b, const LevelLayout &V, genga_pairs *out,
                                char *ws, hipStream_t s);
-// After the drift of every body: restore E_0's bodies and run levels 1 .. L-1.
+// After the drift of every body: restore E_0's bodies and run levels 1 .. L-1
+// (with the direct solver: for L = 1 the groups of E_0, else those of each
+// sub-step of level L - 1).
 hipError_t levels_after_drift(genga_bodies *b, const genga_params *p, const LevelLayout &V,
                               char *ws, hipStream_t s);
 

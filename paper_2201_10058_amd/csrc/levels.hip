@@ -49,10 +49,12 @@ __device__ __forceinline__ double sep2(const double *x, const double *y, const d
     return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
 }
 
-__global__ __launch_bounds__(64) void k_level_begin(int64_t *lcount, int L, const int64_t *cnt0)
+__global__ __launch_bounds__(64) void k_level_begin(int64_t *lcount, int L, const int64_t *cnt0,
+                                                    int64_t *gstats)
 {
     const int t = threadIdx.x;
     if (t < L) lcount[t] = t == 0 ? *cnt0 : 0;
+    if (gstats && t < 2) gstats[t] = 0;
 }
 
 // E_0 to the caller's list: min(count, capacities) entries and the true count.
@@ -382,6 +384,374 @@ __global__ __launch_bounds__(LT) void k_level_kick(LevelKickDev k)
 }
 
 // ---------------------------------------------------------------------------
+// Close-encounter groups of a list: connected components of its pair graph
+// by a lock-free union-find (a root is hooked under the smaller root, so each
+// group's root is its smallest body, whatever the order of the unions), then
+// per-root sizes, a scan over the roots in ascending order, and the members
+// of each group placed in ascending order (rank among the group's members).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t uf_load(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t uf_find(const int32_t *parent, int32_t x)
+{
+    for (;;) {
+        const int32_t p = uf_load(parent + x);
+        if (p == x) return x;
+        x = p;     // parents only point to smaller bodies: the walk ends
+    }
+}
+
+__global__ __launch_bounds__(LT) void k_group_init(int32_t *parent, int32_t *flag, int32_t *gsize,
+                                                   int32_t *gfill, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x; k < n; k += (int64_t)gridDim.x * LT) {
+        parent[k] = (int32_t)k;
+        flag[k] = 0;
+        gsize[k] = 0;
+        gfill[k] = 0;
+    }
+}
+
+__global__ __launch_bounds__(LT) void k_group_union(const int32_t *pi, const int32_t *pj,
+                                                    const int64_t *cnt, int64_t cap,
+                                                    int32_t *parent, int32_t *flag)
+{
+    const int64_t m = list_len(cnt, cap);
+    for (int64_t p = (int64_t)blockIdx.x * LT + threadIdx.x; p < m; p += (int64_t)gridDim.x * LT) {
+        const int32_t i = pi[p], j = pj[p];
+        flag[i] = 1;
+        flag[j] = 1;
+        for (;;) {
+            int32_t ra = uf_find(parent, i), rb = uf_find(parent, j);
+            if (ra == rb) break;
+            if (ra < rb) {
+                const int32_t t = ra;
+                ra = rb;
+                rb = t;
+            }
+            // hook the larger root under the smaller; a failed exchange means
+            // ra stopped being a root meanwhile: look again
+            if (atomicCAS(parent + ra, ra, rb) == ra) break;
+        }
+    }
+}
+
+// Root of every listed body (into lab), members counted per root.
+__global__ __launch_bounds__(LT) void k_group_root(const int32_t *parent, const int32_t *flag,
+                                                   int32_t *lab, int32_t *gsize, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x; k < n; k += (int64_t)gridDim.x * LT) {
+        if (!flag[k]) continue;
+        const int32_t r = uf_find(parent, (int32_t)k);
+        lab[k] = r;
+        atomicAdd(gsize + r, 1);
+    }
+}
+
+// Tile sums of (members of the groups whose root is in the tile, roots).
+__global__ __launch_bounds__(LT) void k_group_tiles(const int32_t *flag, const int32_t *lab,
+                                                    const int32_t *gsize, int64_t n, int64_t *tsum)
+{
+    __shared__ int64_t sm[LT / 64];
+    const int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x;
+    const bool root = k < n && flag[k] && lab[k] == k;
+    int64_t tm, tr;
+    block_excl_scan<LT>(root ? gsize[k] : 0, &tm, sm);
+    block_excl_scan<LT>(root ? 1 : 0, &tr, sm);
+    if (threadIdx.x == 0) {
+        tsum[2 * blockIdx.x] = tm;
+        tsum[2 * blockIdx.x + 1] = tr;
+    }
+}
+
+__global__ __launch_bounds__(ST) void k_group_top(int64_t *tsum, int64_t ntiles, int32_t *gcount)
+{
+    __shared__ int64_t sm[ST / 64];
+    const int t = threadIdx.x;
+    const int64_t ch = (ntiles + ST - 1) / ST;
+    const int64_t k0 = min(ntiles, t * ch), k1 = min(ntiles, k0 + ch);
+    int64_t sa = 0, sb = 0;
+    for (int64_t k = k0; k < k1; ++k) {
+        sa += tsum[2 * k];
+        sb += tsum[2 * k + 1];
+    }
+    int64_t ta, tb;
+    int64_t oa = block_excl_scan<ST>(sa, &ta, sm);
+    int64_t ob = block_excl_scan<ST>(sb, &tb, sm);
+    for (int64_t k = k0; k < k1; ++k) {
+        const int64_t a = tsum[2 * k], b = tsum[2 * k + 1];
+        tsum[2 * k] = oa;
+        tsum[2 * k + 1] = ob;
+        oa += a;
+        ob += b;
+    }
+    if (t == 0) {
+        gcount[0] = (int32_t)tb;   // groups
+        gcount[1] = (int32_t)ta;   // members
+    }
+}
+
+__global__ __launch_bounds__(LT) void k_group_write(const int32_t *flag, const int32_t *lab,
+                                                    const int32_t *gsize, int64_t n,
+                                                    const int64_t *tsum, int32_t *gstart,
+                                                    int32_t *groot)
+{
+    __shared__ int64_t sm[LT / 64];
+    const int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x;
+    const bool root = k < n && flag[k] && lab[k] == k;
+    int64_t tm, tr;
+    const int64_t om = block_excl_scan<LT>(root ? gsize[k] : 0, &tm, sm);
+    const int64_t orr = block_excl_scan<LT>(root ? 1 : 0, &tr, sm);
+    if (root) {
+        gstart[k] = (int32_t)(tsum[2 * blockIdx.x] + om);
+        groot[tsum[2 * blockIdx.x + 1] + orr] = (int32_t)k;
+    }
+}
+
+__global__ __launch_bounds__(LT) void k_group_fill(const int32_t *flag, const int32_t *lab,
+                                                   const int32_t *gstart, int32_t *gfill,
+                                                   int32_t *gtmp, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x; k < n; k += (int64_t)gridDim.x * LT) {
+        if (!flag[k]) continue;
+        const int32_t r = lab[k];
+        gtmp[gstart[r] + atomicAdd(gfill + r, 1)] = (int32_t)k;
+    }
+}
+
+__global__ __launch_bounds__(LT) void k_group_rank(const int32_t *lab, const int32_t *gstart,
+                                                   const int32_t *gsize, const int32_t *gtmp,
+                                                   const int32_t *gcount, int32_t *gmem)
+{
+    const int64_t total = gcount[1];
+    for (int64_t e = (int64_t)blockIdx.x * LT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * LT) {
+        const int32_t k = gtmp[e], r = lab[k];
+        const int32_t s0 = gstart[r], g = gsize[r];
+        int32_t rank = 0;
+        for (int32_t q = s0; q < s0 + g; ++q) rank += gtmp[q] < k;
+        gmem[s0 + rank] = k;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct solver: one workgroup per group, one thread per member.  The
+// group's flow (Kepler force of the star plus the remainder R of the mutual
+// forces) is integrated over H by Bulirsch-Stoer steps: the modified
+// midpoint rule with n = 2, 4, ..., 2 KM sub-steps, polynomial extrapolation
+// in (h/n)^2 (Neville), a step accepted when the last two extrapolations
+// agree within eps (relative to each member's position and velocity
+// magnitudes), else retried with half the step; after a step that converged
+// early the next one doubles (never beyond what is left of H).
+// ---------------------------------------------------------------------------
+constexpr int KM = 8;
+constexpr int BS_TRIES = 4096;
+
+struct BsDev {
+    const int32_t *groot, *gstart, *gsize, *gmem, *gcount;
+    const double *shadow;               // [6][n] state before the drift
+    int64_t n;
+    double *x, *y, *z, *vx, *vy, *vz;
+    const double *m;
+    const double *rc[GENGA_MAX_LEVELS]; // levels 0 .. nlev - 1 weigh R
+    int nlev;
+    double G, mu, H, eps;
+    int32_t *status;
+    unsigned long long *gstats;         // groups, largest group
+};
+
+template <int BT>
+struct BsSmem {
+    double px[BT], py[BT], pz[BT], m[BT];
+    double rc[GENGA_MAX_LEVELS][BT];
+    double red[BT / 64];
+};
+
+// Acceleration of member t at its position (o) from the positions in LDS.
+template <int BT>
+__device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, int t, int g,
+                                         const double o[3], double acc[3])
+{
+    const double r2s = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+    const double ks = -a.mu / (r2s * __builtin_sqrt(r2s));
+    acc[0] = ks * o[0];
+    acc[1] = ks * o[1];
+    acc[2] = ks * o[2];
+    for (int q = 0; q < g; ++q) {
+        if (q == t) continue;
+        const double dx = sm.px[q] - o[0], dy = sm.py[q] - o[1], dz = sm.pz[q] - o[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r = __builtin_sqrt(r2);
+        double R = 1.0;
+        for (int l = 0; l < a.nlev; ++l) {
+            const double rho = sm.rc[l][t] > sm.rc[l][q] ? sm.rc[l][t] : sm.rc[l][q];
+            R *= 1.0 - changeover_k(r, rho);
+        }
+        const double s = a.G * sm.m[q] * R / (r2 * r);
+        acc[0] += s * dx;
+        acc[1] += s * dy;
+        acc[2] += s * dz;
+    }
+}
+
+// Publish positions, then every member's derivative at them.
+template <int BT>
+__device__ __forceinline__ void bs_deriv(const BsDev &a, BsSmem<BT> &sm, int t, int g,
+                                         const double z[6], double f[6])
+{
+    __syncthreads();   // the previous evaluation has finished reading
+    if (t < g) {
+        sm.px[t] = z[0];
+        sm.py[t] = z[1];
+        sm.pz[t] = z[2];
+    }
+    __syncthreads();
+    f[0] = z[3];
+    f[1] = z[4];
+    f[2] = z[5];
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (t < g) bs_accel<BT>(a, sm, t, g, z, acc);
+    f[3] = acc[0];
+    f[4] = acc[1];
+    f[5] = acc[2];
+}
+
+template <int BT>
+__device__ __forceinline__ double bs_block_max(BsSmem<BT> &sm, double v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const double o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sm.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sm.red[0];
+#pragma unroll
+    for (int w = 1; w < BT / 64; ++w) r = sm.red[w] > r ? sm.red[w] : r;
+    return r;
+}
+
+// Groups of lo < size <= hi (the last class also reports the oversized).
+template <int BT>
+__global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
+{
+    __shared__ BsSmem<BT> sm;
+    const int t = threadIdx.x;
+    const int ng = a.gcount[0];
+    for (int gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+        const int32_t root = a.groot[gi];
+        const int g = a.gsize[root];
+        if (g <= lo) continue;                       // another class's group
+        if (g > BT) {
+            if (BT == GENGA_GROUP_MAX && t == 0) atomicOr(a.status, ST_GROUP);
+            continue;
+        }
+        if (t == 0) {
+            atomicAdd(a.gstats, 1ull);
+            atomicMax(a.gstats + 1, (unsigned long long)g);
+        }
+        const int32_t b = t < g ? a.gmem[a.gstart[root] + t] : 0;
+        double y[6] = {0, 0, 0, 0, 0, 0};
+        if (t < g) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
+            sm.m[t] = a.m[b];
+            for (int l = 0; l < a.nlev; ++l) sm.rc[l][t] = a.rc[l][b];
+        }
+        double tt = 0.0, h = a.H;
+        int tries = 0;
+        bool failed = false;
+        while (tt < a.H) {      // uniform: every thread holds the same tt, h
+            const bool last = h >= a.H - tt;
+            if (last) h = a.H - tt;
+            double f0[6];
+            bs_deriv<BT>(a, sm, t, g, y, f0);
+            const double sx = __builtin_sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) +
+                              h * __builtin_sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
+            const double sv = __builtin_sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]) +
+                              h * __builtin_sqrt(f0[3] * f0[3] + f0[4] * f0[4] + f0[5] * f0[5]);
+            double prev[KM][6], cur[KM][6];
+            int kdone = -1;
+            for (int k = 0; k < KM; ++k) {
+                const int nk = 2 * (k + 1);
+                const double hh = h / nk;
+                double z0[6], z1[6], fz[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    z0[c] = y[c];
+                    z1[c] = y[c] + hh * f0[c];
+                }
+                for (int q = 1; q < nk; ++q) {
+                    bs_deriv<BT>(a, sm, t, g, z1, fz);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        const double z2 = z0[c] + 2.0 * hh * fz[c];
+                        z0[c] = z1[c];
+                        z1[c] = z2;
+                    }
+                }
+                bs_deriv<BT>(a, sm, t, g, z1, fz);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) cur[0][c] = 0.5 * (z0[c] + z1[c] + hh * fz[c]);
+                for (int j = 1; j <= k; ++j) {
+                    const double ratio = (double)nk / (double)(nk - 2 * j);
+                    const double den = ratio * ratio - 1.0;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        cur[j][c] = cur[j - 1][c] + (cur[j - 1][c] - prev[j - 1][c]) / den;
+                }
+                double err = 0.0;
+                if (k > 0 && t < g) {
+                    double ex = 0.0, ev = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        const double dxc = fabs(cur[k][c] - cur[k - 1][c]);
+                        const double dvc = fabs(cur[k][c + 3] - cur[k - 1][c + 3]);
+                        ex = dxc > ex ? dxc : ex;
+                        ev = dvc > ev ? dvc : ev;
+                    }
+                    const double e1 = ex / (sx + 1e-300), e2 = ev / (sv + 1e-300);
+                    err = e1 > e2 ? e1 : e2;
+                }
+                if (k > 0) err = bs_block_max<BT>(sm, err);
+                for (int j = 0; j <= k; ++j)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) prev[j][c] = cur[j][c];
+                if (k > 0 && err <= a.eps) {
+                    kdone = k;
+                    break;
+                }
+            }
+            if (kdone >= 0) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) y[c] = prev[kdone][c];
+                tt = last ? a.H : tt + h;
+                if (kdone < KM / 2) h *= 2.0;
+            } else {
+                h *= 0.5;
+            }
+            if (++tries > BS_TRIES || h < a.H * 1e-12) {
+                failed = true;
+                break;
+            }
+        }
+        if (failed && t == 0) atomicOr(a.status, ST_NOCONV);
+        if (t < g) {
+            a.x[b] = y[0];
+            a.y[b] = y[1];
+            a.z[b] = y[2];
+            a.vx[b] = y[3];
+            a.vy[b] = y[4];
+            a.vz[b] = y[5];
+        }
+        __syncthreads();   // LDS reuse by the next group
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host sequencing
 // ---------------------------------------------------------------------------
 struct LevelRun {
@@ -447,6 +817,69 @@ static hipError_t level_kick(const LevelRun &R, int l, double h)
     return hipGetLastError();
 }
 
+// Groups of list l and their members' state saved into shadow[l].
+static hipError_t group_and_save(const LevelRun &R, int l)
+{
+    const LevelLayout &V = *R.V;
+    const int64_t n = R.b->n;
+    const unsigned nt = (unsigned)((n + LT - 1) / LT);
+    int32_t *lab = R.at<int32_t>(V.glab), *flag = R.at<int32_t>(V.gflag);
+    int32_t *gsize = R.at<int32_t>(V.gsize), *gfill = R.at<int32_t>(V.gfill);
+    int32_t *gstart = R.at<int32_t>(V.gstart), *groot = R.at<int32_t>(V.groot);
+    int32_t *gtmp = R.at<int32_t>(V.gtmp), *gmem = R.at<int32_t>(V.gmem);
+    int32_t *gcount = R.at<int32_t>(V.gcount);
+    int64_t *tsum = R.at<int64_t>(V.gtsum);
+    const int32_t *pi = R.at<int32_t>(V.pi[l]), *pj = R.at<int32_t>(V.pj[l]);
+    const int64_t *cnt = R.at<int64_t>(V.cnt) + l;
+    // the union-find's parents live in gtmp until the roots are known
+    hipLaunchKernelGGL(k_group_init, dim3(LG), dim3(LT), 0, R.s, gtmp, flag, gsize, gfill, n);
+    hipLaunchKernelGGL(k_group_union, dim3(LG), dim3(LT), 0, R.s, pi, pj, cnt, V.cap, gtmp, flag);
+    hipLaunchKernelGGL(k_group_root, dim3(LG), dim3(LT), 0, R.s, gtmp, flag, lab, gsize, n);
+    hipLaunchKernelGGL(k_group_tiles, dim3(nt), dim3(LT), 0, R.s, flag, lab, gsize, n, tsum);
+    hipLaunchKernelGGL(k_group_top, dim3(1), dim3(ST), 0, R.s, tsum, (int64_t)nt, gcount);
+    hipLaunchKernelGGL(k_group_write, dim3(nt), dim3(LT), 0, R.s, flag, lab, gsize, n, tsum, gstart,
+                       groot);
+    hipLaunchKernelGGL(k_group_fill, dim3(LG), dim3(LT), 0, R.s, flag, lab, gstart, gfill, gtmp, n);
+    hipLaunchKernelGGL(k_group_rank, dim3(LG), dim3(LT), 0, R.s, lab, gstart, gsize, gtmp, gcount,
+                       gmem);
+    BodyDev mem = R.bodies_of(0);
+    mem.bodies = gmem;
+    mem.nbod = gcount + 1;
+    hipLaunchKernelGGL(k_state_list, dim3(LG), dim3(LT), 0, R.s, mem, R.at<double>(V.shadow[l]), n,
+                       1);
+    return hipGetLastError();
+}
+
+// The groups of list l over dt_l from the saved state, weights of levels 0..l.
+static hipError_t direct_solve(const LevelRun &R, int l, double dt_l)
+{
+    const LevelLayout &V = *R.V;
+    BsDev a;
+    a.groot = R.at<int32_t>(V.groot);
+    a.gstart = R.at<int32_t>(V.gstart);
+    a.gsize = R.at<int32_t>(V.gsize);
+    a.gmem = R.at<int32_t>(V.gmem);
+    a.gcount = R.at<int32_t>(V.gcount);
+    a.shadow = R.at<double>(V.shadow[l]);
+    a.n = R.b->n;
+    a.x = R.b->x; a.y = R.b->y; a.z = R.b->z;
+    a.vx = R.b->vx; a.vy = R.b->vy; a.vz = R.b->vz;
+    a.m = R.b->m;
+    for (int q = 0; q < GENGA_MAX_LEVELS; ++q) a.rc[q] = nullptr;
+    a.rc[0] = R.b->rc;
+    for (int q = 1; q <= l; ++q) a.rc[q] = R.at<double>(V.rc[q]);
+    a.nlev = l + 1;
+    a.G = R.p->G;
+    a.mu = R.p->G * R.p->m_star;
+    a.H = dt_l;
+    a.eps = R.p->bs_eps > 0.0 ? R.p->bs_eps : 1e-12;
+    a.status = R.status();
+    a.gstats = R.at<unsigned long long>(V.gstats);
+    hipLaunchKernelGGL(k_bs<64>, dim3(LG), dim3(64), 0, R.s, a, 0);
+    hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG), dim3(GENGA_GROUP_MAX), 0, R.s, a, 64);
+    return hipGetLastError();
+}
+
 // Level l >= 1 over list l - 1, sub-steps of dt_l.
 static hipError_t advance(const LevelRun &R, int l, double dt_l)
 {
@@ -454,6 +887,7 @@ static hipError_t advance(const LevelRun &R, int l, double dt_l)
     const genga_params *p = R.p;
     const int64_t n = R.b->n;
     const bool deeper = l < V.L - 1;
+    const bool direct = V.direct && l == V.L - 1;
     hipError_t e;
     for (int sub = 0; sub < p->substeps; ++sub) {
         BodyDev up = R.bodies_of(l - 1);
@@ -481,6 +915,7 @@ static hipError_t advance(const LevelRun &R, int l, double dt_l)
             hipLaunchKernelGGL(k_state_list, dim3(LG), dim3(LT), 0, R.s, R.bodies_of(l),
                                R.at<double>(V.shadow[l]), n, 1);
         }
+        if (direct && (e = group_and_save(R, l)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_drift_list, dim3(LG), dim3(LT), 0, R.s, up, p->G * p->m_star, dt_l);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (deeper) {
@@ -489,6 +924,7 @@ static hipError_t advance(const LevelRun &R, int l, double dt_l)
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = advance(R, l + 1, dt_l / p->substeps)) != hipSuccess) return e;
         }
+        if (direct && (e = direct_solve(R, l, dt_l)) != hipSuccess) return e;
         if ((e = level_kick(R, l, 0.5 * dt_l)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -501,11 +937,12 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base)
 {
     LevelLayout V;
-    if (!p || p->slevels < 2) {
+    if (!p || (p->slevels < 2 && !p->direct)) {
         V.total = base;
         return V;
     }
-    V.L = p->slevels;
+    V.L = p->slevels > 1 ? p->slevels : 1;
+    V.direct = p->direct ? 1 : 0;
     V.cap = p->level_capacity;
     size_t off = align_up(base);
     auto take = [&](size_t bytes) {
@@ -532,6 +969,20 @@ LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base)
             V.shadow[l] = take(sizeof(double) * 6 * (size_t)n);
         }
     }
+    if (V.direct) {
+        V.shadow[V.L - 1] = take(sizeof(double) * 6 * (size_t)n);
+        V.glab = take(sizeof(int32_t) * (size_t)n);
+        V.gflag = take(sizeof(int32_t) * (size_t)n);
+        V.gsize = take(sizeof(int32_t) * (size_t)n);
+        V.gfill = take(sizeof(int32_t) * (size_t)n);
+        V.gstart = take(sizeof(int32_t) * (size_t)n);
+        V.groot = take(sizeof(int32_t) * (size_t)n);
+        V.gtmp = take(sizeof(int32_t) * (size_t)n);
+        V.gmem = take(sizeof(int32_t) * (size_t)n);
+        V.gcount = take(sizeof(int32_t) * 2);
+        V.gstats = take(sizeof(int64_t) * 2);
+        V.gtsum = take(sizeof(int64_t) * 2 * (size_t)((n + LT - 1) / LT));
+    }
     V.total = off;
     return V;
 }
@@ -551,7 +1002,8 @@ hipError_t levels_before_drift(const genga_bodies *b, const LevelLayout &V, geng
 {
     LevelRun R{const_cast<genga_bodies *>(b), nullptr, &V, ws, s};
     const int64_t *cnt0 = R.at<int64_t>(V.cnt);
-    hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(64), 0, s, R.at<int64_t>(V.lcount), V.L, cnt0);
+    hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(64), 0, s, R.at<int64_t>(V.lcount), V.L, cnt0,
+                       V.direct ? R.at<int64_t>(V.gstats) : nullptr);
     if (out) {
         hipLaunchKernelGGL(k_copy_pairs, dim3(LG), dim3(LT), 0, s, R.at<int32_t>(V.pi[0]),
                            R.at<int32_t>(V.pj[0]), cnt0, V.cap, out->i, out->j, out->capacity,
@@ -559,6 +1011,7 @@ hipError_t levels_before_drift(const genga_bodies *b, const LevelLayout &V, geng
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (V.L == 1) return group_and_save(R, 0);   // direct solver on E_0
     if ((e = build_adj(R, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_state_list, dim3(LG), dim3(LT), 0, s, R.bodies_of(0),
                        R.at<double>(V.shadow[0]), b->n, 1);
@@ -569,6 +1022,7 @@ hipError_t levels_after_drift(genga_bodies *b, const genga_params *p, const Leve
                               char *ws, hipStream_t s)
 {
     LevelRun R{b, p, &V, ws, s};
+    if (V.L == 1) return direct_solve(R, 0, p->dt);
     hipLaunchKernelGGL(k_state_list, dim3(LG), dim3(LT), 0, s, R.bodies_of(0),
                        R.at<double>(V.shadow[0]), b->n, 0);
     hipError_t e = hipGetLastError();

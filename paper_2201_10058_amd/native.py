@@ -24,6 +24,7 @@ E_HIP = -4
 E_UNSUPPORTED = -5
 E_NOCONV = -6
 E_RCRIT = -7
+E_GROUP = -8
 
 FP64 = 0
 MIXED = 1
@@ -44,8 +45,8 @@ class Params(ctypes.Structure):
                 ("block", ctypes.c_int), ("tile_cols", ctypes.c_int), ("grid", ctypes.c_int),
                 ("prof_events", ctypes.c_void_p * 4), ("tp_mode", ctypes.c_int),
                 ("slevels", ctypes.c_int), ("n_massive", ctypes.c_int64),
-                ("substeps", ctypes.c_int), ("reserved", ctypes.c_int),
-                ("level_capacity", ctypes.c_int64)]
+                ("substeps", ctypes.c_int), ("direct", ctypes.c_int),
+                ("level_capacity", ctypes.c_int64), ("bs_eps", ctypes.c_double)]
 
 
 class BatchC(ctypes.Structure):
@@ -88,6 +89,8 @@ SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "genga_group_stats": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "genga_level_counts": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "genga_energy": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
@@ -193,6 +196,8 @@ class Config:
     slevels: int = 0
     substeps: int = 0
     level_capacity: int = 0
+    direct: int = 0
+    bs_eps: float = 0.0
 
     def params(self) -> Params:
         p = Params(self.G, self.m_star, self.dt, self.n1, self.n2, self.precision, self.flags,
@@ -204,6 +209,8 @@ class Config:
         p.slevels = self.slevels
         p.substeps = self.substeps
         p.level_capacity = self.level_capacity
+        p.direct = self.direct
+        p.bs_eps = self.bs_eps
         return p
 
 
@@ -345,6 +352,17 @@ def level_counts(n: int, cfg: Config, ws: Workspace):
                                      out.ctypes.data_as(ctypes.c_void_p),
                                      ctypes.c_void_p(_stream_ptr())), "genga_level_counts")
     return out
+
+
+def group_stats(n: int, cfg: Config, ws: Workspace):
+    """(groups integrated, largest group) of the last step's direct solver."""
+    import numpy as np
+    out = np.zeros(2, dtype=np.int64)
+    p = cfg.params()
+    _check(load().genga_group_stats(n, ctypes.byref(p), ctypes.c_void_p(ws.ptr),
+                                    out.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.c_void_p(_stream_ptr())), "genga_group_stats")
+    return int(out[0]), int(out[1])
 
 
 def energy(state: State, cfg: Config, ws: Workspace, out=None):

@@ -86,6 +86,7 @@ def test_host_side_argument_errors():
 def test_level_params_on_host():
     from paper_2201_10058_amd import native
     lib = native.load()
+    out = (ctypes.c_int64 * 4)()
     fake = ctypes.c_void_p(256)     # never dereferenced by the host-side checks
     b = native.Bodies()
     b.n = 10
@@ -98,11 +99,18 @@ def test_level_params_on_host():
                dict(slevels=-1)):
         p = native.Config(G=2.959e-4, **kw).params()
         assert lib.genga_step(ctypes.byref(b), ctypes.byref(p), None, fake, None) == native.E_INVAL
+    for kw in (dict(direct=2, level_capacity=64), dict(direct=1, level_capacity=0),
+               dict(direct=1, level_capacity=64, bs_eps=-1.0),
+               dict(direct=1, level_capacity=64, bs_eps=float("nan"))):
+        p = native.Config(G=2.959e-4, **kw).params()
+        assert lib.genga_step(ctypes.byref(b), ctypes.byref(p), None, fake, None) == native.E_INVAL
+    assert lib.genga_strerror(native.E_GROUP).decode().startswith("close-encounter group")
+    no_direct = native.Config(G=2.959e-4, slevels=2, substeps=2, level_capacity=64).params()
+    assert lib.genga_group_stats(10, ctypes.byref(no_direct), fake, out, None) == native.E_INVAL
     tp = native.Config(G=2.959e-4, tp_mode=1, n_massive=4, slevels=2, substeps=2,
                        level_capacity=64).params()
     assert lib.genga_step(ctypes.byref(b), ctypes.byref(tp), None, fake, None) == native.E_UNSUPPORTED
     one = native.Config(G=2.959e-4, slevels=1).params()
-    out = (ctypes.c_int64 * 4)()
     assert lib.genga_level_counts(10, ctypes.byref(one), fake, out, None) == native.E_INVAL
     # the workspace grows with the levels and their capacity (two lists and
     # one adjacency of 2 int32 each per pair at L = 2); a larger L

@@ -1,0 +1,134 @@
+"""Direct solver of genga_step (close-encounter groups + Bulirsch-Stoer;
+Sect. 2, Sect. 6.1, Appendix A) against the oracle's grouping and RK4 group
+flow (pinned in test_oracle_direct.py) and the Newtonian three-body problem."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from encounter_fixture import two_planets
+from paper_2201_10058_amd import native as N
+from paper_2201_10058_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+G = W.GAUSS_G
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _cfg(L, s, **kw):
+    return N.Config(G=G, slevels=L, substeps=s, level_capacity=1 << 16, direct=1, **kw)
+
+
+def _rel(out, ref, keys):
+    g = np.stack([out[k] for k in keys])
+    r = np.stack([ref[k] for k in keys])
+    return np.max(np.abs(g - r)) / np.max(np.abs(r))
+
+
+@pytest.mark.parametrize("L,s", [(3, 4), (2, 10), (4, 2)])
+def test_direct_step_matches_oracle(dev, L, s):
+    # 5 steps of the 2,048-body disk with the deepest level's groups
+    # integrated: groups, largest group, level list sizes and the state
+    # against the oracle (its RK4 flow in fine steps)
+    d = W.make_disk(W.DISK_2048)
+    st = N.State.from_numpy(d)
+    cfg = _cfg(L, s)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(d)
+    for k in range(5):
+        assert N.step(st, cfg, ws) == N.OK
+        counts = N.level_counts(st.n, cfg, ws)
+        gs = N.group_stats(st.n, cfg, ws)
+        r = oracle.step_direct(ref, G, 1.0, 6.0, 3.0, 0.4, L, s, rk_steps=400)
+        assert r[6] == 0
+        assert np.array_equal(counts, r[4]), (k, counts, r[4])
+        assert gs == r[5], (k, gs, r[5])
+    out = st.numpy()
+    ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
+    _say(f"direct {L}x{s}: groups {gs}, position {ep:.2e} velocity {ev:.2e}")
+    assert gs[0] > 0
+    assert ep < 1e-11 and ev < 1e-11
+
+
+@pytest.mark.parametrize("L,s", [(1, 1), (2, 10)])
+def test_direct_follows_a_close_encounter(dev, L, s):
+    # closest approach at a third of the Hill radius (the oracle pin's case)
+    state, newton = two_planets(1.004)
+    st = N.State.from_numpy(state)
+    cfg = N.Config(G=G, slevels=L, substeps=s, level_capacity=64, direct=1, n1=0.5, n2=0.4)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(state)
+    groups = 0
+    for _ in range(50):
+        assert N.step(st, cfg, ws) == N.OK
+        groups += N.group_stats(st.n, cfg, ws)[0]
+        oracle.step_direct(ref, G, 1.0, 6.0, 0.5, 0.4, L, s, rk_steps=4000)
+    out = st.numpy()
+    pos = np.stack([out["x"], out["y"], out["z"]], 1)
+    rpos = np.stack([ref["x"], ref["y"], ref["z"]], 1)
+    e_or, e_nw = np.abs(pos - rpos).max(), np.abs(pos - newton).max()
+    _say(f"direct encounter {L}x{s}: groups {groups}, vs oracle {e_or:.2e} AU, vs Newton {e_nw:.2e} AU")
+    assert groups > 0
+    assert e_nw < 1e-4
+    assert e_or < 1e-8
+
+
+def test_oversized_group_is_reported(dev):
+    # without levels the 2,048-body disk's level-0 list joins far more than
+    # 256 bodies in one group
+    d = W.make_disk(W.DISK_2048)
+    st = N.State.from_numpy(d)
+    cfg = _cfg(1, 1)
+    ws = N.Workspace(st.n, cfg)
+    assert N.step(st, cfg, ws) == N.E_GROUP
+
+
+def test_direct_graph_replay_bitwise(dev):
+    d = W.make_disk(W.DISK_2048)
+    cfg = _cfg(3, 4, flags=N.FLAG_NOSYNC)
+    st_g, st_e = N.State.from_numpy(d), N.State.from_numpy(d)
+    ws_g, ws_e = N.Workspace(st_g.n, cfg), N.Workspace(st_e.n, cfg)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tmp = N.State.from_numpy(d)
+        N.step(tmp, cfg, N.Workspace(tmp.n, cfg))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        N.step(st_g, cfg, ws_g)
+    torch.cuda.synchronize()
+    for k in st_g.t:
+        st_g.t[k].copy_(st_e.t[k])
+    for rep in range(3):
+        g.replay()
+        N.step(st_e, cfg, ws_e)
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert N.read_status(ws_g) == N.OK and N.read_status(ws_e) == N.OK
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            assert torch.equal(st_g.t[k], st_e.t[k]), (rep, k)
+        assert N.group_stats(st_g.n, cfg, ws_g) == N.group_stats(st_e.n, cfg, ws_e)
+        del junk
+
+
+def test_direct_cuts_the_energy_error(dev):
+    d = W.make_disk(W.DISK_2048)
+    err = {}
+    for direct in (0, 1):
+        st = N.State.from_numpy(d)
+        cfg = N.Config(G=G, slevels=3, substeps=4, level_capacity=1 << 16, direct=direct)
+        ws = N.Workspace(st.n, cfg)
+        E0 = float(N.energy(st, cfg, ws)[0].item())
+        e = 0.0
+        for _ in range(40):
+            assert N.step(st, cfg, ws) == N.OK
+            e = max(e, abs(float(N.energy(st, cfg, ws)[0].item()) - E0) / abs(E0))
+        err[direct] = e
+    _say("energy error over 40 steps, 3 x 4 levels: without / with the direct solver", err)
+    assert err[1] < 0.1 * err[0]
