@@ -273,21 +273,24 @@ def bench_tp(N, W, torch, np, steps=20):
 
 
 LEVEL_CANDIDATES = ((1, 1), (2, 2), (2, 4), (3, 2), (2, 10), (3, 4))
+DIRECT_CANDIDATES = ((3, 4), (2, 10), (4, 4))
 
 
 def bench_levels(N, W, torch, np, steps=10):
     """Symplectic levels on the 65,536-body disk: for each (levels, sub-steps)
-    choice, from the same initial state, the time per step, the list sizes of
-    its last step and the relative change of the total energy over its steps;
-    then the native tuner's choice among them (run on a fresh copy)."""
+    choice, with and without the direct solver for the deepest level's groups,
+    from the same initial state, the time per step, the list sizes of its last
+    step and the relative change of the total energy over its steps; then the
+    native tuner's choice among the level choices (run on a fresh copy)."""
     from paper_2201_10058_amd import autotune as AT
     d = W.make_disk(W.DISK_65536)
     out = {"workload": d["name"], "steps": steps, "configs": {}}
     base = dict(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
                 flags=N.FLAG_NOSYNC, level_capacity=1 << 20)
-    for L, s in LEVEL_CANDIDATES:
+    runs = [(L, s, 0) for L, s in LEVEL_CANDIDATES] + [(L, s, 1) for L, s in DIRECT_CANDIDATES]
+    for L, s, direct in runs:
         st = N.State.from_numpy(d)
-        cfg = N.Config(**base, slevels=L, substeps=s)
+        cfg = N.Config(**base, slevels=L, substeps=s, direct=direct)
         ws = N.Workspace(st.n, cfg)
         pairs = N.PairList(1 << 20)
         e0 = float(N.energy(st, cfg, ws)[0].item())
@@ -298,14 +301,19 @@ def bench_levels(N, W, torch, np, steps=10):
             N.step(st, cfg, ws, pairs)
         torch.cuda.synchronize()
         dt_s = (time.perf_counter() - t0) / steps
-        if N.read_status(ws) != N.OK:
-            raise SystemExit(f"levels {L}x{s}: status")
+        code = N.read_status(ws)
+        if code != N.OK and not (direct and code == N.E_GROUP):
+            raise SystemExit(f"levels {L}x{s}: status {code}")
         e1 = float(N.energy(st, cfg, ws)[0].item())
-        counts = (N.level_counts(st.n, cfg, ws).tolist() if L > 1
+        counts = (N.level_counts(st.n, cfg, ws).tolist() if L > 1 or direct
                   else [int(pairs.count.item())])
-        out["configs"][f"{L}x{s}"] = {"step_ms": round(dt_s * 1e3, 4),
-                                      "list_sizes_last_step": counts,
-                                      "energy_rel_change": (e1 - e0) / abs(e0)}
+        rec = {"step_ms": round(dt_s * 1e3, 4), "list_sizes_last_step": counts,
+               "energy_rel_change": (e1 - e0) / abs(e0)}
+        if direct:
+            g, gmax = N.group_stats(st.n, cfg, ws)
+            rec.update({"groups_last_step": g, "largest_group": gmax,
+                        "status": "ok" if code == N.OK else "group over 256 bodies"})
+        out["configs"][f"{L}x{s}" + ("+direct" if direct else "")] = rec
     st = N.State.from_numpy(d)
     out["tuner"] = AT.tune_levels(st, N.Config(**base), LEVEL_CANDIDATES, steps=3)
     return out
