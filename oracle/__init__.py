@@ -66,6 +66,10 @@ def _load():
     lib.or_groups.argtypes = [_i64, _p, _p, _i64, _p]
     lib.or_direct_group.restype = None
     lib.or_direct_group.argtypes = ([_i64] + [_p] * 8 + [ctypes.c_int, _d, _d, _p, _i64, _d, _i64])
+    lib.or_gr_kick.restype = None
+    lib.or_gr_kick.argtypes = [_i64] + [_p] * 7 + [_d] * 4
+    lib.or_step_gr.restype = _i64
+    lib.or_step_gr.argtypes = [_i64] + [_p] * 8 + [_d] * 6 + [_i64, _p, _p, _p]
     lib.or_kick.restype = ctypes.c_int
     lib.or_kick.argtypes = [_i64] + [_p] * 8 + [_d, _d]
     lib.or_pairs.restype = _i64
@@ -225,6 +229,27 @@ def direct_group(state, rc_levels, G, m_star, members, dt, steps=2000):
     _load().or_direct_group(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
                             _ptr(rcl), rcl.shape[0] - 1, float(G), float(m_star), _ptr(mem),
                             int(mem.size), float(dt), int(steps))
+
+
+def gr_kick(state, G, m_star, c, h):
+    """In-place post-Newtonian velocity update over h (implicit midpoint)."""
+    n = state["x"].size
+    _load().or_gr_kick(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                       float(G), float(m_star), float(c), float(h))
+
+
+def step_gr(state, G, m_star, dt, n1, n2, c, cap=1 << 20):
+    """One base step with the post-Newtonian term; (pi, pj, count, rc, status)."""
+    n = state["x"].size
+    rc = np.empty(n)
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    st = ctypes.c_int(0)
+    cnt = _load().or_step_gr(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                             _ptr(rc), float(G), float(m_star), float(dt), float(n1), float(n2),
+                             float(c), int(cap), _ptr(pi), _ptr(pj), ctypes.byref(st))
+    k = min(cnt, cap)
+    return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, st.value
 
 
 def kick(state, rc, G, h):

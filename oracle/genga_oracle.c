@@ -834,6 +834,109 @@ int64_t or_step_levels(int64_t n, double *x, double *y, double *z, double *vx, d
 }
 
 /* ------------------------------------------------------------------------ */
+/* General relativity (Sect. 3): the post-Newtonian acceleration of body i  */
+/* about the star (eq. apn) with mu = G (m_star + m_i),                      */
+/* eta = m_star m_i / (m_star + m_i)^2, position x_i (heliocentric) and       */
+/* heliocentric velocity u_i,                                                */
+/*   a = -mu / (r^2 c^2) [ -2 (2 - eta) rdot u                               */
+/*        + ((1 + 3 eta) u.u - 3/2 eta rdot^2 - 2 (2 + eta) mu / r) x / r ],  */
+/* rdot = u.x / r, applied over h by the implicit midpoint rule (eq.         */
+/* implicit): u' = u + h a(x, (u + u') / 2), iterated from the explicit       */
+/* guess until the change is below 1e-16 |u'| (at most 50 times).            */
+/* Readings: u_i = v_i + P / m_star with P = sum_j m_j v_j (the star moves   */
+/* at -P / m_star); afterwards the barycentric velocities are recovered with */
+/* the momentum kept at zero: v'_i = u'_i - P' / m_star,                     */
+/* P' = sum_j m_j u'_j / (1 + M / m_star), M = sum_j m_j.                    */
+/* ------------------------------------------------------------------------ */
+static void apn(double mu, double eta, double c2, const double X[3], const double U[3], double A[3])
+{
+    const double r = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    const double nx = X[0] / r, ny = X[1] / r, nz = X[2] / r;
+    const double rdot = nx * U[0] + ny * U[1] + nz * U[2];
+    const double u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    const double coef = -mu / (r * r * c2);
+    const double cu = -2.0 * (2.0 - eta) * rdot;
+    const double cn = (1.0 + 3.0 * eta) * u2 - 1.5 * eta * rdot * rdot - 2.0 * (2.0 + eta) * mu / r;
+    A[0] = coef * (cu * U[0] + cn * nx);
+    A[1] = coef * (cu * U[1] + cn * ny);
+    A[2] = coef * (cu * U[2] + cn * nz);
+}
+
+void or_gr_kick(int64_t n, const double *x, const double *y, const double *z, double *vx,
+                double *vy, double *vz, const double *m, double G, double m_star, double c,
+                double h)
+{
+    double P[3] = {0.0, 0.0, 0.0}, M = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        P[0] += m[i] * vx[i];
+        P[1] += m[i] * vy[i];
+        P[2] += m[i] * vz[i];
+        M += m[i];
+    }
+    const double c2 = c * c;
+    double *un = (double *)malloc(sizeof(double) * (size_t)(3 * n + 1));
+    for (int64_t i = 0; i < n; ++i) {
+        const double mu = G * (m_star + m[i]);
+        const double eta = m_star * m[i] / ((m_star + m[i]) * (m_star + m[i]));
+        const double X[3] = {x[i], y[i], z[i]};
+        const double U[3] = {vx[i] + P[0] / m_star, vy[i] + P[1] / m_star, vz[i] + P[2] / m_star};
+        double A[3], W[3], N[3];
+        apn(mu, eta, c2, X, U, A);
+        for (int k = 0; k < 3; ++k) N[k] = U[k] + h * A[k];
+        for (int it = 0; it < 50; ++it) {
+            for (int k = 0; k < 3; ++k) W[k] = 0.5 * (U[k] + N[k]);
+            apn(mu, eta, c2, X, W, A);
+            double d = 0.0, s2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double nk = U[k] + h * A[k];
+                d += (nk - N[k]) * (nk - N[k]);
+                s2 += nk * nk;
+                N[k] = nk;
+            }
+            if (d <= 1e-32 * s2) break;
+        }
+        for (int k = 0; k < 3; ++k) un[3 * i + k] = N[k];
+    }
+    double Q[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) Q[k] += m[i] * un[3 * i + k];
+    for (int k = 0; k < 3; ++k) Q[k] /= 1.0 + M / m_star;
+    for (int64_t i = 0; i < n; ++i) {
+        vx[i] = un[3 * i + 0] - Q[0] / m_star;
+        vy[i] = un[3 * i + 1] - Q[1] / m_star;
+        vz[i] = un[3 * i + 2] - Q[2] / m_star;
+    }
+    free(un);
+}
+
+/* The base step with the post-Newtonian term (c > 0): its velocity update  */
+/* joins each half kick, after the first and before the second, so that the */
+/* step stays symmetric:                                                    */
+/*   Rcrit; Kick(dt/2); GR(dt/2); HC(dt/2); FG(dt); HC(dt/2); GR(dt/2);      */
+/*   Kick(dt/2).                                                            */
+int64_t or_step_gr(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                   double *vz, const double *m, double *rc, double G, double m_star, double dt,
+                   double n1, double n2, double c, int64_t cap, int32_t *pi, int32_t *pj,
+                   int *status)
+{
+    int st = OR_OK, s2;
+    or_rcrit(n, x, y, z, vx, vy, vz, m, m_star, dt, n1, n2, rc);
+    int64_t np = or_pairs(n, x, y, z, rc, cap, pi, pj);
+    s2 = kick_tp(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt, n, 0);
+    if (s2 < st) st = s2;
+    or_gr_kick(n, x, y, z, vx, vy, vz, m, G, m_star, c, 0.5 * dt);
+    hc_n(n, n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    s2 = or_drift(n, x, y, z, vx, vy, vz, G * m_star, dt);
+    if (s2 < st) st = s2;
+    hc_n(n, n, x, y, z, vx, vy, vz, m, m_star, 0.5 * dt);
+    or_gr_kick(n, x, y, z, vx, vy, vz, m, G, m_star, c, 0.5 * dt);
+    s2 = kick_tp(n, x, y, z, vx, vy, vz, m, rc, G, 0.5 * dt, n, 0);
+    if (s2 < st) st = s2;
+    if (status) *status = st;
+    return np;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Total energy in democratic coordinates (eqs. H, Ha, Hb, Hc):              */
 /* E = sum m v^2 / 2 + |sum m v|^2 / (2 m_star) - sum G m_star m / r_i        */
 /*     - sum_{i<j} G m_i m_j / r_ij  (the K-weighted parts add up to 1/r).   */
