@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-tp", action="store_true",
                     help="skip the test-particle mode timings")
     ap.add_argument("--no-levels", action="store_true",
-                    help="skip the symplectic-level timings")
+                    help="skip the symplectic-level, direct-solver and GR timings")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 2,048-body eager vs hipGraph step timing")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -319,6 +319,34 @@ def bench_levels(N, W, torch, np, steps=10):
     return out
 
 
+def bench_gr(N, W, torch, np, steps=10):
+    """Post-Newtonian term on the 65,536-body disk: step time with and without
+    it (the same initial state), and the GR update alone."""
+    d = W.make_disk(W.DISK_65536)
+    out = {"workload": d["name"], "c_light_au_per_day": 173.1446326846693}
+    for label, c in (("without", 0.0), ("with", 173.1446326846693)):
+        st = N.State.from_numpy(d)
+        cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                       flags=N.FLAG_NOSYNC, c_light=c)
+        ws = N.Workspace(st.n, cfg)
+        N.step(st, cfg, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            N.step(st, cfg, ws)
+        torch.cuda.synchronize()
+        out[f"step_ms_{label}"] = round((time.perf_counter() - t0) / steps * 1e3, 4)
+        if c > 0:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                N.gr_kick(st, cfg, ws, 0.5 * d["dt"])
+            torch.cuda.synchronize()
+            out["gr_update_us"] = round((time.perf_counter() - t0) / steps * 1e6, 2)
+        if N.read_status(ws) != N.OK:
+            raise SystemExit("gr status")
+    return out
+
+
 def pair_list_sha256(pairs) -> str:
     """SHA-256 of the canonical list (int32 i then int32 j, little endian)."""
     import hashlib
@@ -577,6 +605,9 @@ def main():
     if not args.no_levels:
         out["levels"] = bench_levels(N, W, torch, np)
         print(f"levels done: {out['levels']}", file=sys.stderr, flush=True)
+    if not args.no_levels:
+        out["gr"] = bench_gr(N, W, torch, np)
+        print(f"gr done: {out['gr']}", file=sys.stderr, flush=True)
     if not args.no_small:
         out["small_system"] = bench_small(N, W, torch, np)
         print(f"small system done: {out['small_system']}", file=sys.stderr, flush=True)

@@ -134,6 +134,9 @@ typedef struct {
                                count.                                        */
     double bs_eps; /* direct solver: relative tolerance of the Bulirsch-Stoer
                       extrapolation; 0 = 1e-12                               */
+    double c_light; /* speed of light in the caller's units: > 0 adds the
+                       post-Newtonian term to genga_step (genga_gr_kick);
+                       0 = off                                               */
 } genga_params;
 
 #define GENGA_MAX_LEVELS 8
@@ -262,6 +265,24 @@ int genga_level_counts(int64_t n, const genga_params *p, void *ws, int64_t *out,
  * sub-steps), out[1] = the largest group's size.  out is a host array of 2
  * int64; synchronises the stream. */
 int genga_group_stats(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream);
+
+/* General relativity (Sect. 3): the post-Newtonian acceleration of every
+ * body about the star (eq. apn),
+ *   a_i = -mu_i / (r_i^2 c^2) [ -2 (2 - eta_i) rdot_i u_i
+ *          + ((1 + 3 eta_i) u_i.u_i - 3/2 eta_i rdot_i^2 - 2 (2 + eta_i) mu_i / r_i) x_i / r_i ],
+ * mu_i = G (m_star + m_i), eta_i = m_star m_i / (m_star + m_i)^2, rdot_i =
+ * u_i.x_i / r_i, in heliocentric velocities u_i = v_i + P / m_star
+ * (P = sum_j m_j v_j), applied over h by the implicit midpoint rule (eq.
+ * implicit: u' = u + h a(x, (u + u') / 2), iterated from the explicit guess
+ * until the change is below 1e-16 |u'|, at most 50 times); the barycentric
+ * velocities are then v'_i = u'_i - P' / m_star with
+ * P' = sum_j m_j u'_j / (1 + M / m_star), M = sum_j m_j (total momentum
+ * stays zero).  c = p->c_light (> 0).  Momentum sums run in a fixed order.
+ * genga_step with c_light > 0 applies it after its first half kick and
+ * before its second (a symmetric step); only for the single-system base step
+ * (GENGA_E_UNSUPPORTED with levels, the direct solver, test-particle modes,
+ * batches). */
+int genga_gr_kick(genga_bodies *b, const genga_params *p, double h, void *ws, void *stream);
 
 /* Energy bookkeeping in binary64: the Hamiltonian of the democratic
  * heliocentric splitting (Sect. 2, eqs. H, Ha, Hb, Hc), whose parts the

@@ -32,6 +32,10 @@ def _state(X, V, m, rc) -> N.State:
 
 class _Runner:
     def __init__(self, n, cfg: N.Config, device):
+        if cfg.c_light or cfg.slevels > 1 or cfg.direct or cfg.tp_mode:
+            # the adjoint covers the base step's operators only
+            raise N.GengaError(N.E_UNSUPPORTED, "adjoint of a step with GR, levels, the direct "
+                               "solver or test particles")
         self.cfg = N.Config(**{**cfg.__dict__, "flags": N.FLAG_NOSYNC, "events": (None,) * 4})
         self.ws = N.Workspace(n, self.cfg, device=device)
         self.h = 0.5 * cfg.dt

@@ -40,6 +40,7 @@ static int check_params(const genga_params *p)
     if (p->block < 0 || p->tile_cols < 0 || p->grid < 0) return GENGA_E_INVAL;
     if (p->tp_mode < 0 || p->tp_mode > 2 || p->n_massive < 0) return GENGA_E_INVAL;
     if (p->slevels < 0 || p->slevels > GENGA_MAX_LEVELS) return GENGA_E_INVAL;
+    if (!is_fin(p->c_light) || p->c_light < 0.0) return GENGA_E_INVAL;
     if (p->direct != 0 && p->direct != 1) return GENGA_E_INVAL;
     if (!is_fin(p->bs_eps) || p->bs_eps < 0.0) return GENGA_E_INVAL;
     if (p->slevels > 1 || p->direct) {
@@ -314,7 +315,9 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if (!ws) return GENGA_E_INVAL;
     if ((r = check_tp(b, p, true))) return r;
     const bool levels = p->slevels > 1 || p->direct;
+    const bool gr = p->c_light > 0.0;
     if (levels && p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
+    if (gr && (levels || p->tp_mode != 0)) return GENGA_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const double h = 0.5 * p->dt;
     const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
@@ -325,6 +328,7 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if (e != hipSuccess) return hip_fail(e);
     if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, levels ? &e0 : pairs, true, ws, stream)))
         return r;
+    if (gr && (e = launch_gr(b, p, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
     if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s, hc_count(b, p))) != hipSuccess)
         return hip_fail(e);
     if (levels && (e = levels_before_drift(b, V, pairs, (char *)ws, s)) != hipSuccess)
@@ -335,9 +339,22 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
         return hip_fail(e);
     if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s, hc_count(b, p))) != hipSuccess)
         return hip_fail(e);
+    if (gr && (e = launch_gr(b, p, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
     if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2))) return r;
     if (p->flags & GENGA_FLAG_NOSYNC) return GENGA_OK;
     return genga_read_status(ws, stream);
+}
+
+int genga_gr_kick(genga_bodies *b, const genga_params *p, double h, void *ws, void *stream)
+{
+    int r = check_bodies(b, true, false);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (!ws || !is_fin(h) || !(p->c_light > 0.0)) return GENGA_E_INVAL;
+    if (p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
+    const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
+    hipError_t e = launch_gr(b, p, h, L, (char *)ws, (hipStream_t)stream);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
 }
 
 int genga_group_stats(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream)

@@ -236,6 +236,8 @@ int genga_kick_batched(const genga_bodies *b, const genga_batch *bt, const genga
     if (pairs && (!pairs->count || pairs->capacity < 0 || (pairs->capacity > 0 && (!pairs->i || !pairs->j))))
         return GENGA_E_INVAL;
     if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
+    if (p->c_light != 0.0 || p->slevels > 1 || p->direct || p->tp_mode != 0)
+        return GENGA_E_UNSUPPORTED;
     return kick_batched(b, bt, p, hfac, ax, ay, az, pairs, true, ws, stream, 0);
 }
 
@@ -248,6 +250,8 @@ int genga_step_batched(genga_bodies *b, const genga_batch *bt, const genga_param
     if (pairs && (!pairs->count || pairs->capacity < 0 || (pairs->capacity > 0 && (!pairs->i || !pairs->j))))
         return GENGA_E_INVAL;
     if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
+    if (p->c_light != 0.0 || p->slevels > 1 || p->direct || p->tp_mode != 0)
+        return GENGA_E_UNSUPPORTED;
     BatchShape sh;
     int r = batch_shape(bt, p, sh);
     if (r) return r;

@@ -239,6 +239,124 @@ hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Post-Newtonian term (Sect. 3, eq. apn) by the implicit midpoint rule (eq.
+// implicit) in heliocentric velocities u = v + P / m_star.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void apn(double mu, double eta, double c2, const double X[3],
+                                    const double U[3], double A[3])
+{
+    const double r = __builtin_sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    const double nx = X[0] / r, ny = X[1] / r, nz = X[2] / r;
+    const double rdot = nx * U[0] + ny * U[1] + nz * U[2];
+    const double u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    const double coef = -mu / (r * r * c2);
+    const double cu = -2.0 * (2.0 - eta) * rdot;
+    const double cn = (1.0 + 3.0 * eta) * u2 - 1.5 * eta * rdot * rdot - 2.0 * (2.0 + eta) * mu / r;
+    A[0] = coef * (cu * U[0] + cn * nx);
+    A[1] = coef * (cu * U[1] + cn * ny);
+    A[2] = coef * (cu * U[2] + cn * nz);
+}
+
+// Sum of the per-block partials (stride w, component c) in a fixed tree order.
+__device__ __forceinline__ double block_sum_partials(const double *part, int64_t nb, int w, int c,
+                                                     double *sm)
+{
+    const int t = threadIdx.x;
+    double v = 0.0;
+    for (int64_t b = t; b < nb; b += RB) v += part[b * w + c];
+    __syncthreads();
+    sm[t] = v;
+    __syncthreads();
+    for (int hh = RB / 2; hh > 0; hh >>= 1) {
+        if (t < hh) sm[t] += sm[t + hh];
+        __syncthreads();
+    }
+    return sm[0];
+}
+
+// u' of every body (into gru) and per-block partials of m u' and m.
+__global__ __launch_bounds__(RB) void k_gr_update(const double *x, const double *y, const double *z,
+                                                  const double *vx, const double *vy,
+                                                  const double *vz, const double *m, int64_t n,
+                                                  int64_t npad, const double *hc, int64_t nb,
+                                                  double G, double m_star, double c2, double h,
+                                                  double *gru, double *grp, int32_t *status)
+{
+    __shared__ double sm[RB];
+    __shared__ double red[4][RB];
+    double P[3];
+    for (int c = 0; c < 3; ++c) P[c] = block_sum_partials(hc, nb, 3, c, sm);
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * RB + t;
+    double U1[3] = {0.0, 0.0, 0.0}, mi = 0.0;
+    if (i < n) {
+        mi = m[i];
+        const double mu = G * (m_star + mi);
+        const double eta = m_star * mi / ((m_star + mi) * (m_star + mi));
+        const double X[3] = {x[i], y[i], z[i]};
+        const double U[3] = {vx[i] + P[0] / m_star, vy[i] + P[1] / m_star, vz[i] + P[2] / m_star};
+        double A[3], W[3];
+        apn(mu, eta, c2, X, U, A);
+        for (int k = 0; k < 3; ++k) U1[k] = U[k] + h * A[k];
+        for (int it = 0; it < 50; ++it) {
+            for (int k = 0; k < 3; ++k) W[k] = 0.5 * (U[k] + U1[k]);
+            apn(mu, eta, c2, X, W, A);
+            double d = 0.0, s2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double nk = U[k] + h * A[k];
+                d += (nk - U1[k]) * (nk - U1[k]);
+                s2 += nk * nk;
+                U1[k] = nk;
+            }
+            if (d <= 1e-32 * s2) break;
+        }
+        if (!(isfinite(U1[0]) && isfinite(U1[1]) && isfinite(U1[2]))) atomicOr(status, ST_NONFINITE);
+        for (int k = 0; k < 3; ++k) gru[(size_t)k * npad + i] = U1[k];
+    }
+    for (int k = 0; k < 3; ++k) red[k][t] = mi * U1[k];
+    red[3][t] = mi;
+    __syncthreads();
+    for (int hh = RB / 2; hh > 0; hh >>= 1) {
+        if (t < hh)
+            for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + hh];
+        __syncthreads();
+    }
+    if (t < 4) grp[(size_t)blockIdx.x * 4 + t] = red[t][0];
+}
+
+// v_i = u'_i - P' / m_star, P' = sum m u' / (1 + M / m_star).
+__global__ __launch_bounds__(RB) void k_gr_apply(double *vx, double *vy, double *vz, int64_t n,
+                                                 int64_t npad, const double *gru,
+                                                 const double *grp, int64_t nb, double m_star)
+{
+    __shared__ double sm[RB];
+    double Q[3];
+    for (int c = 0; c < 3; ++c) Q[c] = block_sum_partials(grp, nb, 4, c, sm);
+    const double M = block_sum_partials(grp, nb, 4, 3, sm);
+    for (int c = 0; c < 3; ++c) Q[c] /= 1.0 + M / m_star;
+    const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+    if (i >= n) return;
+    vx[i] = gru[i] - Q[0] / m_star;
+    vy[i] = gru[npad + i] - Q[1] / m_star;
+    vz[i] = gru[2 * npad + i] - Q[2] / m_star;
+}
+
+hipError_t launch_gr(genga_bodies *b, const genga_params *p, double h, const Layout &L, char *ws,
+                     hipStream_t s)
+{
+    double *hc = (double *)(ws + L.hc);
+    double *gru = (double *)(ws + L.gru), *grp = (double *)(ws + L.grp);
+    hipLaunchKernelGGL(k_momentum_partial, dim3((unsigned)L.nb), dim3(RB), 0, s, b->vx, b->vy,
+                       b->vz, b->m, b->n, hc);
+    hipLaunchKernelGGL(k_gr_update, dim3((unsigned)L.nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx,
+                       b->vy, b->vz, b->m, b->n, L.npad, hc, L.nb, p->G, p->m_star,
+                       p->c_light * p->c_light, h, gru, grp, (int32_t *)ws);
+    hipLaunchKernelGGL(k_gr_apply, dim3((unsigned)L.nb), dim3(RB), 0, s, b->vx, b->vy, b->vz, b->n,
+                       L.npad, gru, grp, L.nb, p->m_star);
+    return hipGetLastError();
+}
+
 hipError_t launch_drift(genga_bodies *b, double mu, double dt, char *ws, hipStream_t s)
 {
     const unsigned nb = (unsigned)((b->n + RB - 1) / RB);

@@ -69,6 +69,8 @@ struct Layout {
     size_t wcount = 0;     // int32  [nwaves]           staged pairs per wave
     size_t hc = 0;         // double [nb][3]            momentum partials
     size_t rlist = 0;      // int32  [npad]             mixed: rows to evaluate in binary64
+    size_t gru = 0;        // double [3][npad]          post-Newtonian: new heliocentric velocities
+    size_t grp = 0;        // double [nb][4]            post-Newtonian: partial sums of m u', m
     size_t P = 0;          // batch: double [S][3]      momentum per system
     size_t tiles = 0;      // batch: TileDesc [ntiles]
     size_t sysid = 0;      // batch: int32 [npad]
@@ -112,6 +114,8 @@ hipError_t launch_rcrit(const genga_bodies *b, const genga_params *p, char *ws, 
 hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, char *ws,
                      hipStream_t s, int64_t nsum);
 hipError_t launch_drift(genga_bodies *b, double mu, double dt, char *ws, hipStream_t s);
+hipError_t launch_gr(genga_bodies *b, const genga_params *p, double h, const Layout &L, char *ws,
+                     hipStream_t s);
 hipError_t launch_clear_status(char *ws, hipStream_t s);
 hipError_t launch_energy(const genga_bodies *b, const genga_params *p, double *out,
                          const KickCfg &c, const Layout &L, char *ws, hipStream_t s);

@@ -1043,6 +1043,10 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
     L.rlist = off;
     off = align256(off + sizeof(int32_t) * (size_t)L.npad);
+    L.gru = off;
+    off = align256(off + sizeof(double) * 3 * (size_t)L.npad);
+    L.grp = off;
+    off = align256(off + sizeof(double) * 4 * (size_t)L.nb);
     if (S > 0) {
         L.P = off;
         off = align256(off + sizeof(double) * 3 * (size_t)S);

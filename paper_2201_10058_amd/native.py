@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
                 ("prof_events", ctypes.c_void_p * 4), ("tp_mode", ctypes.c_int),
                 ("slevels", ctypes.c_int), ("n_massive", ctypes.c_int64),
                 ("substeps", ctypes.c_int), ("direct", ctypes.c_int),
-                ("level_capacity", ctypes.c_int64), ("bs_eps", ctypes.c_double)]
+                ("level_capacity", ctypes.c_int64), ("bs_eps", ctypes.c_double),
+                ("c_light", ctypes.c_double)]
 
 
 class BatchC(ctypes.Structure):
@@ -89,6 +90,8 @@ SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "genga_gr_kick": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
     "genga_group_stats": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "genga_level_counts": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
@@ -198,6 +201,7 @@ class Config:
     level_capacity: int = 0
     direct: int = 0
     bs_eps: float = 0.0
+    c_light: float = 0.0
 
     def params(self) -> Params:
         p = Params(self.G, self.m_star, self.dt, self.n1, self.n2, self.precision, self.flags,
@@ -211,6 +215,7 @@ class Config:
         p.level_capacity = self.level_capacity
         p.direct = self.direct
         p.bs_eps = self.bs_eps
+        p.c_light = self.c_light
         return p
 
 
@@ -352,6 +357,14 @@ def level_counts(n: int, cfg: Config, ws: Workspace):
                                      out.ctypes.data_as(ctypes.c_void_p),
                                      ctypes.c_void_p(_stream_ptr())), "genga_level_counts")
     return out
+
+
+def gr_kick(state: State, cfg: Config, ws: Workspace, h: float) -> None:
+    """Post-Newtonian velocity update over h (asynchronous)."""
+    b, p = state.bodies(), cfg.params()
+    _check(load().genga_gr_kick(ctypes.byref(b), ctypes.byref(p), ctypes.c_double(h),
+                                ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
+           "genga_gr_kick")
 
 
 def group_stats(n: int, cfg: Config, ws: Workspace):

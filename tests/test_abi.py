@@ -105,6 +105,10 @@ def test_level_params_on_host():
         p = native.Config(G=2.959e-4, **kw).params()
         assert lib.genga_step(ctypes.byref(b), ctypes.byref(p), None, fake, None) == native.E_INVAL
     assert lib.genga_strerror(native.E_GROUP).decode().startswith("close-encounter group")
+    neg_c = native.Config(G=2.959e-4, c_light=-1.0).params()
+    assert lib.genga_step(ctypes.byref(b), ctypes.byref(neg_c), None, fake, None) == native.E_INVAL
+    no_c = native.Config(G=2.959e-4).params()
+    assert lib.genga_gr_kick(ctypes.byref(b), ctypes.byref(no_c), 1.0, fake, None) == native.E_INVAL
     no_direct = native.Config(G=2.959e-4, slevels=2, substeps=2, level_capacity=64).params()
     assert lib.genga_group_stats(10, ctypes.byref(no_direct), fake, out, None) == native.E_INVAL
     tp = native.Config(G=2.959e-4, tp_mode=1, n_massive=4, slevels=2, substeps=2,
