@@ -82,6 +82,10 @@ def _load():
     lib.or_step.argtypes = [_i64] + [_p] * 8 + [_d] * 5 + [_i64, _p, _p, _p]
     lib.or_energy.restype = _d
     lib.or_energy.argtypes = [_i64] + [_p] * 7 + [_d, _d]
+    lib.or_changeover_integral.restype = _d
+    lib.or_changeover_integral.argtypes = [_d, _d]
+    lib.or_energy_k.restype = _d
+    lib.or_energy_k.argtypes = [_i64] + [_p] * 8 + [_d, _d]
     lib.or_num_threads.restype = ctypes.c_int
     lib.or_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -309,6 +313,18 @@ def energy(state, G, m_star):
     n = state["x"].size
     return _load().or_energy(n, *(_ptr(_f64(state[k])) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
                              float(G), float(m_star))
+
+
+def changeover_integral(r: float, rho: float) -> float:
+    """int_{max(r, 0.1 rho)}^{rho} K(s)/s^2 ds (0 for r >= rho)."""
+    return _load().or_changeover_integral(float(r), float(rho))
+
+
+def energy_k(state, rc, G, m_star):
+    """E with the changeover potential for the pairs inside rho_ij."""
+    n = state["x"].size
+    return _load().or_energy_k(n, *(_ptr(_f64(state[k])) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
+                               _ptr(_f64(rc)), float(G), float(m_star))
 
 
 def num_threads() -> int:

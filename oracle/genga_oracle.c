@@ -972,6 +972,56 @@ double or_energy(int64_t n, const double *x, const double *y, const double *z,
     return (double)(T + Hc + U + W);
 }
 
+/* ------------------------------------------------------------------------ */
+/* The changeover potential (the potential whose force is the K-weighted    */
+/* Newtonian force of the kick, Sect. 2 eq. Hb with the force reading):     */
+/*   Phi_K(r) = -G m_i m_j / r                          for r >= rho,        */
+/*   Phi_K(r) = -G m_i m_j [1/rho + int_r^rho K(s)/s^2 ds]   for r < rho,    */
+/* (K = 0 below 0.1 rho, so the integral starts at max(r, 0.1 rho)).        */
+/* The integral by composite Simpson's rule on 4000 intervals.              */
+/* ------------------------------------------------------------------------ */
+static double k_over_s2(double s, double rho)
+{
+    return or_changeover(s, rho) / (s * s);
+}
+
+double or_changeover_integral(double r, double rho)
+{
+    if (!(r < rho)) return 0.0;
+    const double a = r > 0.1 * rho ? r : 0.1 * rho;
+    const int m = 4000;
+    const double h = (rho - a) / m;
+    double acc = k_over_s2(a, rho) + k_over_s2(rho, rho);
+    for (int k = 1; k < m; ++k) acc += (k & 1 ? 4.0 : 2.0) * k_over_s2(a + k * h, rho);
+    return acc * h / 3.0;
+}
+
+/* E_K: the energy with the changeover potential in place of the Newtonian  */
+/* pair potential for the pairs inside rho_ij (the quantity that the step   */
+/* map without the direct solver conserves for fixed critical radii):       */
+/*   E_K = E + sum_{i<j, r_ij < rho_ij} [Phi_K(r_ij) + G m_i m_j / r_ij].     */
+/* All pairs are examined; long double sums.                                */
+double or_energy_k(int64_t n, const double *x, const double *y, const double *z,
+                   const double *vx, const double *vy, const double *vz, const double *m,
+                   const double *rc, double G, double m_star)
+{
+    const double E = or_energy(n, x, y, z, vx, vy, vz, m, G, m_star);
+    long double corr = 0.0L;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : corr)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            const double rho = pair_rho(rc, i, j);
+            const double r2 = pair_r2(x, y, z, i, j);
+            if (!(r2 < rho * rho)) continue;
+            const double r = sqrt(r2);
+            const long double gmm = (long double)G * m[i] * m[j];
+            /* Phi_K + G m m / r = G m m [1/r - 1/rho - integral] */
+            corr += gmm * (1.0L / r - 1.0L / rho - (long double)or_changeover_integral(r, rho));
+        }
+    }
+    return (double)((long double)E + corr);
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -86,9 +86,11 @@ static int status_to_code(int32_t st)
     return GENGA_OK;
 }
 
+// fuse_hc: also apply the Sun kick x += h P / m_star after the velocities,
+// with P from the momentum partials in L.hc2 (genga_step's second half).
 static int do_kick(const genga_bodies *b, const genga_params *p, double h, double *ax, double *ay,
                    double *az, genga_pairs *pairs, bool forces, void *ws, void *stream,
-                   int ev_slot = 0)
+                   int ev_slot = 0, bool fuse_hc = false)
 {
     const KickCfg c = choose_kick_cfg(b->n, p);
     const Layout L = make_layout(b->n, c);
@@ -110,6 +112,13 @@ static int do_kick(const genga_bodies *b, const genga_params *p, double h, doubl
     k.sys_slices = nullptr;
     k.sys_dt = nullptr;
     k.sys_off = nullptr;
+    if (fuse_hc) {
+        k.px = b->x; k.py = b->y; k.pz = b->z;
+        k.hc_part = (const double *)((char *)ws + L.hc2);
+        k.hc_nb = L.nb;
+        k.hc_h = h;
+        k.hc_m_star = p->m_star;
+    }
     hipError_t e = launch_kick(k, c, L, (char *)ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return GENGA_OK;
@@ -328,6 +337,20 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if (e != hipSuccess) return hip_fail(e);
     if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, levels ? &e0 : pairs, true, ws, stream)))
         return r;
+    if (!levels && !gr && p->precision == GENGA_FP64) {
+        // the plain binary64 step in fewer launches: HC + FG + the next HC's
+        // momentum sum in one kernel, the second HC fused into the second
+        // kick's reduction (the kick sees only position differences)
+        const int64_t nsum = hc_count(b, p);
+        if ((e = launch_momentum(b, L, (char *)ws, s, nsum)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_hc_drift(b, p->m_star, h, p->G * p->m_star, p->dt, L, (char *)ws, s,
+                                 nsum)) != hipSuccess)
+            return hip_fail(e);
+        if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, nullptr, true, ws, stream, 2, true)))
+            return r;
+        if (p->flags & GENGA_FLAG_NOSYNC) return GENGA_OK;
+        return genga_read_status(ws, stream);
+    }
     if (gr && (e = launch_gr(b, p, h, L, (char *)ws, s)) != hipSuccess) return hip_fail(e);
     if ((e = launch_hc(b, p->m_star, h, L, (char *)ws, s, hc_count(b, p))) != hipSuccess)
         return hip_fail(e);

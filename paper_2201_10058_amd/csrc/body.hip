@@ -239,6 +239,87 @@ hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, 
     return hipGetLastError();
 }
 
+// HC(h) with the partials hc_in (the fixed order of k_hc_apply), then the
+// Kepler drift, then the block partial of m v of the drifted bodies
+// [0, nsum) into hc_out: the Sun kick, the drift and the next Sun kick's
+// momentum sum in one pass over the bodies.
+__global__ __launch_bounds__(RB) void k_hc_drift(double *x, double *y, double *z, double *vx,
+                                                 double *vy, double *vz, const double *m, int64_t n,
+                                                 int64_t nsum, const double *hc_in, int64_t nb,
+                                                 double h, double m_star, double mu, double dt,
+                                                 double *hc_out, int32_t *status)
+{
+    __shared__ double sm[3][RB];
+    const int t = threadIdx.x;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    for (int64_t b = t; b < nb; b += RB) {
+        p0 += hc_in[b * 3 + 0];
+        p1 += hc_in[b * 3 + 1];
+        p2 += hc_in[b * 3 + 2];
+    }
+    sm[0][t] = p0;
+    sm[1][t] = p1;
+    sm[2][t] = p2;
+    __syncthreads();
+    for (int hh = RB / 2; hh > 0; hh >>= 1) {
+        if (t < hh) {
+            sm[0][t] += sm[0][t + hh];
+            sm[1][t] += sm[1][t + hh];
+            sm[2][t] += sm[2][t + hh];
+        }
+        __syncthreads();
+    }
+    const double P0 = sm[0][0], P1 = sm[1][0], P2 = sm[2][0];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * RB + t;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    if (i < n) {
+        double X = x[i] + (h * P0) / m_star, Y = y[i] + (h * P1) / m_star,
+               Z = z[i] + (h * P2) / m_star;
+        double VX = vx[i], VY = vy[i], VZ = vz[i];
+        const int st = kepler_uv(mu, dt, X, Y, Z, VX, VY, VZ);
+        if (st) atomicOr(status, st);
+        x[i] = X; y[i] = Y; z[i] = Z;
+        vx[i] = VX; vy[i] = VY; vz[i] = VZ;
+        if (i < nsum) {
+            const double mi = m[i];
+            q0 = mi * VX;
+            q1 = mi * VY;
+            q2 = mi * VZ;
+        }
+    }
+    sm[0][t] = q0;
+    sm[1][t] = q1;
+    sm[2][t] = q2;
+    __syncthreads();
+    for (int hh = RB / 2; hh > 0; hh >>= 1) {
+        if (t < hh) {
+            sm[0][t] += sm[0][t + hh];
+            sm[1][t] += sm[1][t + hh];
+            sm[2][t] += sm[2][t + hh];
+        }
+        __syncthreads();
+    }
+    if (t < 3) hc_out[(size_t)blockIdx.x * 3 + t] = sm[t][0];
+}
+
+hipError_t launch_momentum(const genga_bodies *b, const Layout &L, char *ws, hipStream_t s,
+                           int64_t nsum)
+{
+    hipLaunchKernelGGL(k_momentum_partial, dim3((unsigned)L.nb), dim3(RB), 0, s, b->vx, b->vy,
+                       b->vz, b->m, nsum, (double *)(ws + L.hc));
+    return hipGetLastError();
+}
+
+hipError_t launch_hc_drift(genga_bodies *b, double m_star, double h, double mu, double dt,
+                           const Layout &L, char *ws, hipStream_t s, int64_t nsum)
+{
+    hipLaunchKernelGGL(k_hc_drift, dim3((unsigned)L.nb), dim3(RB), 0, s, b->x, b->y, b->z, b->vx,
+                       b->vy, b->vz, b->m, b->n, nsum, (const double *)(ws + L.hc), L.nb, h,
+                       m_star, mu, dt, (double *)(ws + L.hc2), (int32_t *)ws);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Post-Newtonian term (Sect. 3, eq. apn) by the implicit midpoint rule (eq.
 // implicit) in heliocentric velocities u = v + P / m_star.

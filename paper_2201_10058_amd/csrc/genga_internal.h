@@ -68,6 +68,7 @@ struct Layout {
     size_t stage = 0;      // int32  [nwaves][WSEG][3]  staged (i, j, rank)
     size_t wcount = 0;     // int32  [nwaves]           staged pairs per wave
     size_t hc = 0;         // double [nb][3]            momentum partials
+    size_t hc2 = 0;        // double [nb][3]            momentum partials (second buffer)
     size_t rlist = 0;      // int32  [npad]             mixed: rows to evaluate in binary64
     size_t gru = 0;        // double [3][npad]          post-Newtonian: new heliocentric velocities
     size_t grp = 0;        // double [nb][4]            post-Newtonian: partial sums of m u', m
@@ -105,6 +106,14 @@ struct KickLaunch {
     const int32_t *sys_slices; // batch: column slices per system
     const double *sys_dt;      // batch: time step per system
     const int64_t *sys_off;    // batch: device offsets of the systems
+    // optional: after the velocities, x += hc_h P / hc_m_star for every body,
+    // P the fixed-order sum of the hc_nb momentum partials hc_part (the Sun
+    // kick H_C fused into the reduction; the kick itself only sees
+    // differences of positions, which a common shift leaves unchanged)
+    double *px = nullptr, *py = nullptr, *pz = nullptr;
+    const double *hc_part = nullptr;
+    int64_t hc_nb = 0;
+    double hc_h = 0.0, hc_m_star = 1.0;
 };
 hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, char *ws,
                        hipStream_t s);
@@ -114,6 +123,13 @@ hipError_t launch_rcrit(const genga_bodies *b, const genga_params *p, char *ws, 
 hipError_t launch_hc(genga_bodies *b, double m_star, double h, const Layout &L, char *ws,
                      hipStream_t s, int64_t nsum);
 hipError_t launch_drift(genga_bodies *b, double mu, double dt, char *ws, hipStream_t s);
+// Momentum partials of bodies [0, nsum) into L.hc.
+hipError_t launch_momentum(const genga_bodies *b, const Layout &L, char *ws, hipStream_t s,
+                           int64_t nsum);
+// HC(h) with the partials in L.hc, the drift FG(dt), and the momentum
+// partials of the drifted velocities (bodies [0, nsum)) into L.hc2: one kernel.
+hipError_t launch_hc_drift(genga_bodies *b, double m_star, double h, double mu, double dt,
+                           const Layout &L, char *ws, hipStream_t s, int64_t nsum);
 hipError_t launch_gr(genga_bodies *b, const genga_params *p, double h, const Layout &L, char *ws,
                      hipStream_t s);
 hipError_t launch_clear_status(char *ws, hipStream_t s);

@@ -492,6 +492,10 @@ struct ReduceDev {
     int s_m, s_t;
     int m_folded;                 // massive rows' sums already folded into their slice 0
     int32_t *queue;               // batch: tile counter of the kick, reset here
+    double *px, *py, *pz;         // Sun kick fused after the velocities (hc_part non-null)
+    const double *hc_part;
+    int64_t hc_nb;
+    double hc_h, hc_m_star;
     int pstride;                  // partial values per row and slice (3; mixed 4)
     double kappa2;                // mixed: square of the refinement threshold (else 0)
     int32_t *refine_list, *refine_cnt;
@@ -500,8 +504,35 @@ struct ReduceDev {
 __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
 {
     __shared__ int64_t sm[RB / 64];
+    __shared__ double hcs[3][RB];
     const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
     const bool valid = i < r.n;
+    double hcP[3] = {0.0, 0.0, 0.0};
+    if (r.hc_part) {
+        // P in the fixed order of k_hc_apply (every block the same)
+        const int t = threadIdx.x;
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+        for (int64_t b = t; b < r.hc_nb; b += RB) {
+            p0 += r.hc_part[b * 3 + 0];
+            p1 += r.hc_part[b * 3 + 1];
+            p2 += r.hc_part[b * 3 + 2];
+        }
+        hcs[0][t] = p0;
+        hcs[1][t] = p1;
+        hcs[2][t] = p2;
+        __syncthreads();
+        for (int hh = RB / 2; hh > 0; hh >>= 1) {
+            if (t < hh) {
+                hcs[0][t] += hcs[0][t + hh];
+                hcs[1][t] += hcs[1][t + hh];
+                hcs[2][t] += hcs[2][t + hh];
+            }
+            __syncthreads();
+        }
+        hcP[0] = hcs[0][0];
+        hcP[1] = hcs[1][0];
+        hcP[2] = hcs[2][0];
+    }
     if (r.queue && i == 0) *r.queue = 0;
     int nsl = r.slices;
     if (r.tp) nsl = i < r.nm ? (r.m_folded ? 1 : r.s_m) : r.s_t;
@@ -547,6 +578,11 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
                 r.az[i] = a3[2];
             }
         }
+    }
+    if (r.hc_part && valid) {
+        r.px[i] += (r.hc_h * hcP[0]) / r.hc_m_star;
+        r.py[i] += (r.hc_h * hcP[1]) / r.hc_m_star;
+        r.pz[i] += (r.hc_h * hcP[2]) / r.hc_m_star;
     }
     if (r.emit) {
         int64_t c = 0;
@@ -1041,6 +1077,8 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     off = align256(off + sizeof(int32_t) * (size_t)c.nwaves);
     L.hc = off;
     off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
+    L.hc2 = off;
+    off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
     L.rlist = off;
     off = align256(off + sizeof(int32_t) * (size_t)L.npad);
     L.gru = off;
@@ -1180,6 +1218,11 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.s_t = c.s_t;
     r.mpad = c.mpad;
     r.m_folded = 0;
+    r.px = k.px; r.py = k.py; r.pz = k.pz;
+    r.hc_part = k.hc_part;
+    r.hc_nb = k.hc_nb;
+    r.hc_h = k.hc_h;
+    r.hc_m_star = k.hc_m_star;
     r.pstride = refine ? 4 : 3;
     r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
     r.refine_list = (int32_t *)(ws + L.rlist);
