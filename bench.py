@@ -184,28 +184,35 @@ def mixed_accuracy(N, W, torch, np, checkpoints=(0, 10, 100, 1000)):
 
 
 def energy_drift(N, W, torch, np, steps=10_000, every=1000):
-    """Relative energy drift (E(t) - E(0)) / |E(0)| of the FP64 and mixed steps
-    on the 16,384-body disk over `steps` steps, energies in binary64."""
+    """Relative drift (E(t) - E(0)) / |E(0)| of the FP64 and mixed steps on
+    the 16,384-body disk over `steps` steps, energies in binary64, for E and
+    for E_K (the changeover-potential energy, with the critical radii of the
+    last step)."""
     d = W.make_disk(W.DISK_MIXED[16384])
-    drift = {}
+    drift, drift_k = {}, {}
     for name, prec in (("fp64", N.FP64), ("mixed", N.MIXED)):
         st = N.State.from_numpy(d)
         cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
                        precision=prec, flags=N.FLAG_NOSYNC)
         ws = N.Workspace(st.n, cfg)
-        Es = [N.energy(st, cfg, ws).clone()]
+        pl = N.PairList(1 << 18)
+        N.rcrit(st, cfg, ws)
+        Es = [N.energy_k(st, cfg, ws, pl).clone()]
         for k in range(steps):
             N.step(st, cfg, ws)
             if (k + 1) % every == 0:
-                Es.append(N.energy(st, cfg, ws).clone())
+                Es.append(N.energy_k(st, cfg, ws, pl).clone())
         if N.read_status(ws) != N.OK:
             raise SystemExit("energy drift status")
-        E = torch.stack(Es).cpu().numpy()[:, 0]
-        drift[name] = (E - E[0]) / abs(E[0])
+        E = torch.stack(Es).cpu().numpy()
+        drift[name] = (E[:, 0] - E[0, 0]) / abs(E[0, 0])
+        drift_k[name] = (E[:, 5] - E[0, 5]) / abs(E[0, 5])
     return {"steps": steps, "n": int(d["n"]),
             "fp64_max_abs_drift": float(np.max(np.abs(drift["fp64"]))),
             "mixed_max_abs_drift": float(np.max(np.abs(drift["mixed"]))),
-            "max_abs_mixed_minus_fp64": float(np.max(np.abs(drift["mixed"] - drift["fp64"])))}
+            "max_abs_mixed_minus_fp64": float(np.max(np.abs(drift["mixed"] - drift["fp64"]))),
+            "fp64_max_abs_drift_e_k": float(np.max(np.abs(drift_k["fp64"]))),
+            "mixed_max_abs_drift_e_k": float(np.max(np.abs(drift_k["mixed"])))}
 
 
 def bench_small(N, W, torch, np, steps=100):

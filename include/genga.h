@@ -297,6 +297,19 @@ int genga_gr_kick(genga_bodies *b, const genga_params *p, double h, void *ws, vo
 int genga_energy(const genga_bodies *b, const genga_params *p, double *out, void *ws,
                  void *stream);
 
+/* E_K (the force reading of eq. Hb, Sect. 2): the energy whose pair potential
+ * is the changeover potential, the one the step without the direct solver
+ * conserves for fixed critical radii,
+ *   E_K = E + sum_{i<j, r_ij < rho_ij} G m_i m_j [1/r - 1/rho - int_{max(r, 0.1 rho)}^{rho} K(s)/s^2 ds],
+ * with rho_ij = max(rc_i, rc_j) from b->rc.  Computes the encounter list of
+ * the current positions into `pairs` (as genga_encounter_pairs; device
+ * memory, capacity for all of them, else GENGA_E_OVERFLOW in the status and
+ * only the first `capacity` pairs count), the integral by the 32-point
+ * Gauss-Legendre rule.  Writes out[0..4] as genga_energy and out[5] = E_K
+ * (out: device array of 6 doubles).  Asynchronous. */
+int genga_energy_k(const genga_bodies *b, const genga_params *p, genga_pairs *pairs, double *out,
+                   void *ws, void *stream);
+
 /* ------------------------------------------------------------------------
  * Adjoint (vector-Jacobian products) of the operators above, for gradients of
  * final states with respect to initial conditions and masses.  Each call

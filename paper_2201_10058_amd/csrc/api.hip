@@ -252,6 +252,25 @@ int genga_energy(const genga_bodies *b, const genga_params *p, double *out, void
     return e == hipSuccess ? GENGA_OK : hip_fail(e);
 }
 
+int genga_energy_k(const genga_bodies *b, const genga_params *p, genga_pairs *pairs, double *out,
+                   void *ws, void *stream)
+{
+    int r = check_bodies(b, true, true);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if (p->tp_mode != 0) return GENGA_E_UNSUPPORTED;
+    if (!ws || !out || !pairs) return GENGA_E_INVAL;
+    if ((r = check_pairs(pairs))) return r;
+    const KickCfg c = choose_kick_cfg(b->n, p);
+    const Layout L = make_layout(b->n, c);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_energy(b, p, out, c, L, (char *)ws, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((r = do_kick(b, p, 0.0, nullptr, nullptr, nullptr, pairs, false, ws, stream))) return r;
+    e = launch_energy_k_pairs(b, p, pairs, out, L, (char *)ws, s);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
 static int check_adj(const genga_adjoint *adj, bool pos, bool vel, bool m, bool rc)
 {
     if (!adj) return GENGA_E_INVAL;

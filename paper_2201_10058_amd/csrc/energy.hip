@@ -8,6 +8,8 @@
 // with the rows x column-slices tiling of the kick (columns staged in LDS).
 // Every sum after the pair loop runs in a fixed order, so the result does not
 // depend on scheduling.
+#include <math.h>
+
 #include "device_common.h"
 #include "genga_internal.h"
 
@@ -136,7 +138,116 @@ __global__ __launch_bounds__(RB) void k_energy_final(const double *bpart, int64_
     }
 }
 
+// Gauss-Legendre rule of 32 points on [-1, 1].
+struct GL32 {
+    double x[32], w[32];
+};
+
+constexpr int EP = 256;     // threads per block of the pair correction
+constexpr int EPG = 512;    // blocks of the pair correction (fixed grid)
+
+// E_K - E over the listed pairs inside rho_ij:
+//   G m_i m_j (1/r - 1/rho - int_{max(r, 0.1 rho)}^{rho} K(s)/s^2 ds),
+// the integral by the 32-point Gauss-Legendre rule (K is smooth between the
+// band edges, the only points where its second derivative jumps).  Block
+// partials in a fixed order (fixed grid).
+__global__ __launch_bounds__(EP) void k_energy_pairs(const int32_t *pi, const int32_t *pj,
+                                                     const int64_t *cnt, int64_t cap,
+                                                     const double *x, const double *y,
+                                                     const double *z, const double *m,
+                                                     const double *rc, double G, GL32 gl,
+                                                     double *part)
+{
+    __shared__ double sm[EP];
+    const int t = threadIdx.x;
+    const int64_t c = *cnt;
+    const int64_t np = c < cap ? c : cap;
+    double acc = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * EP + t; q < np; q += (int64_t)gridDim.x * EP) {
+        const int64_t i = pi[q], j = pj[q];
+        const double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        const double rho = rc[i] > rc[j] ? rc[i] : rc[j];
+        if (!(r2 < rho * rho) || r2 == 0.0) continue;
+        const double r = __builtin_sqrt(r2);
+        const double a = r > 0.1 * rho ? r : 0.1 * rho;
+        const double half = 0.5 * (rho - a), mid = 0.5 * (rho + a);
+        double I = 0.0;
+        for (int k = 0; k < 32; ++k) {
+            const double sk = mid + half * gl.x[k];
+            I += gl.w[k] * changeover_k(sk, rho) / (sk * sk);
+        }
+        I *= half;
+        acc += G * m[i] * m[j] * (1.0 / r - 1.0 / rho - I);
+    }
+    sm[t] = acc;
+    __syncthreads();
+    for (int h = EP / 2; h > 0; h >>= 1) {
+        if (t < h) sm[t] += sm[t + h];
+        __syncthreads();
+    }
+    if (t == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(EP) void k_energy_k_final(const double *part, double *out)
+{
+    __shared__ double sm[EP];
+    const int t = threadIdx.x;
+    double v = 0.0;
+    for (int b = t; b < EPG; b += EP) v += part[b];
+    sm[t] = v;
+    __syncthreads();
+    for (int h = EP / 2; h > 0; h >>= 1) {
+        if (t < h) sm[t] += sm[t + h];
+        __syncthreads();
+    }
+    if (t == 0) out[5] = out[0] + sm[0];
+}
+
+// Nodes by Newton's method on the Legendre polynomial P_32 from the usual
+// cosine guesses; weights 2 / ((1 - x^2) P_32'(x)^2).
+GL32 make_gl32()
+{
+    GL32 g;
+    const int n = 32;
+    for (int k = 0; k < n / 2; ++k) {
+        double xk = cos(M_PI * (k + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = xk;
+            for (int l = 2; l <= n; ++l) {
+                const double p2 = ((2.0 * l - 1.0) * xk * p1 - (l - 1.0) * p0) / l;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (xk * p1 - p0) / (xk * xk - 1.0);
+            const double dx = p1 / dp;
+            xk -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        const double w = 2.0 / ((1.0 - xk * xk) * dp * dp);
+        g.x[k] = -xk;
+        g.w[k] = w;
+        g.x[n - 1 - k] = xk;
+        g.w[n - 1 - k] = w;
+    }
+    return g;
+}
+
 }  // namespace
+
+hipError_t launch_energy_k_pairs(const genga_bodies *b, const genga_params *p, genga_pairs *pairs,
+                                 double *out, const Layout &L, char *ws, hipStream_t s)
+{
+    static const GL32 gl = make_gl32();
+    double *part = (double *)(ws + L.part);
+    hipLaunchKernelGGL(k_energy_pairs, dim3(EPG), dim3(EP), 0, s, pairs->i, pairs->j, pairs->count,
+                       pairs->capacity, b->x, b->y, b->z, b->m, b->rc, p->G, gl, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_energy_k_final, dim3(1), dim3(EP), 0, s, part, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_energy(const genga_bodies *b, const genga_params *p, double *out,
                          const KickCfg &c, const Layout &L, char *ws, hipStream_t s)

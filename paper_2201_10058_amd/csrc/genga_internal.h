@@ -135,6 +135,9 @@ hipError_t launch_gr(genga_bodies *b, const genga_params *p, double h, const Lay
 hipError_t launch_clear_status(char *ws, hipStream_t s);
 hipError_t launch_energy(const genga_bodies *b, const genga_params *p, double *out,
                          const KickCfg &c, const Layout &L, char *ws, hipStream_t s);
+// out[5] = out[0] + the changeover-potential correction over the listed pairs.
+hipError_t launch_energy_k_pairs(const genga_bodies *b, const genga_params *p, genga_pairs *pairs,
+                                 double *out, const Layout &L, char *ws, hipStream_t s);
 
 // Device view of a planned batch (pointers into the caller's arrays and the
 // workspace).

@@ -90,6 +90,9 @@ SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "genga_energy_k": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
+                                      ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
     "genga_gr_kick": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "genga_group_stats": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
@@ -356,6 +359,18 @@ def level_counts(n: int, cfg: Config, ws: Workspace):
     _check(load().genga_level_counts(n, ctypes.byref(p), ctypes.c_void_p(ws.ptr),
                                      out.ctypes.data_as(ctypes.c_void_p),
                                      ctypes.c_void_p(_stream_ptr())), "genga_level_counts")
+    return out
+
+
+def energy_k(state: State, cfg: Config, ws: Workspace, pairs: PairList, out=None):
+    """Energy parts and E_K: float64 device tensor (E, T, U_*, U, C, E_K);
+    `pairs` receives the encounter list of the current positions."""
+    if out is None:
+        out = torch.empty(6, dtype=torch.float64, device=state.t["x"].device)
+    b, p, ps = state.bodies(), cfg.params(), pairs.struct()
+    _check(load().genga_energy_k(ctypes.byref(b), ctypes.byref(p), ctypes.byref(ps),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr),
+                                 ctypes.c_void_p(_stream_ptr())), "genga_energy_k")
     return out
 
 

@@ -108,3 +108,48 @@ def test_energy_drift_mixed_vs_fp64_disk16384(dev):
     _say("max |drift_mixed - drift_fp64|", diff, "max |drift_fp64|", np.max(np.abs(drift[N.FP64])))
     assert np.all(np.isfinite(drift[N.MIXED]))
     assert diff <= 1e-9
+
+
+def test_energy_k_matches_oracle(dev):
+    # E_K of the 2,048-body disk after five steps, with the radii of the last
+    # step, against the oracle's (Simpson) changeover potential
+    d = W.make_disk(W.DISK_2048)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=G)
+    ws = N.Workspace(st.n, cfg)
+    for _ in range(5):
+        assert N.step(st, cfg, ws) == N.OK
+    pl = N.PairList(1 << 16)
+    out = N.energy_k(st, cfg, ws, pl).cpu().numpy()
+    assert N.read_status(ws) == N.OK
+    s = st.numpy()
+    ek = oracle.energy_k(s, s["rc"], G, 1.0)
+    e = oracle.energy(s, G, 1.0)
+    _say("E_K", out[5], ek, "E_K - E", out[5] - out[0], ek - e, "pairs", int(pl.count.item()))
+    assert abs(out[5] - ek) <= 1e-13 * abs(ek)
+    assert abs((out[5] - out[0]) - (ek - e)) <= 1e-9 * abs(ek - e)
+    assert ek - e != 0.0
+
+
+def test_fixed_rc_map_conserves_e_k_on_gpu(dev):
+    # the oracle pin's close pass on the GPU operators with rc held fixed
+    from encounter_fixture import two_planets
+    state, _ = two_planets(1.01)
+    st = N.State.from_numpy(state, rc=np.array([0.04, 0.04]))
+    cfg = N.Config(G=G)
+    ws = N.Workspace(st.n, cfg)
+    pl = N.PairList(16)
+    e0 = N.energy_k(st, cfg, ws, pl).cpu().numpy()
+    de = dk = 0.0
+    for _ in range(50):
+        N.kick(st, cfg, ws, 3.0)
+        N.hc(st, cfg, ws, 3.0)
+        N.drift(st, cfg, ws, 6.0)
+        N.hc(st, cfg, ws, 3.0)
+        N.kick(st, cfg, ws, 3.0)
+        e = N.energy_k(st, cfg, ws, pl).cpu().numpy()
+        de = max(de, abs(e[0] - e0[0]) / abs(e0[0]))
+        dk = max(dk, abs(e[5] - e0[5]) / abs(e0[5]))
+    assert N.read_status(ws) == N.OK
+    _say("fixed-rc close pass: max |dE|/E", de, "max |dE_K|/E_K", dk)
+    assert dk < 0.01 * de
