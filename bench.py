@@ -143,10 +143,31 @@ def cpu_baseline(d, rc, G, target_s):
             break
     inter = reps * rows * (n - 1)
     what = (f"rows 0..{rows - 1}" if rows < n else f"{reps} full kick(s)")
-    return {"value": inter / t_used / 1e9, "unit": "Ginter/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same loop on one core, on a sample of about a tenth of the time
+    oracle.set_num_threads(1)
+    rows1 = max(64, int(rows * reps * 0.1 / max(cores, 1)))
+    rows1 = min(rows1, n)
+    t0 = time.perf_counter()
+    oracle.kick_acc(d["x"], d["y"], d["z"], d["m"], rc, G, rows=(0, rows1), precise=False)
+    t1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": inter / t_used / 1e9, "unit": "Ginter/s", "cores": cores,
             "kind": "oracle",
             "sample": f"plain FP64 kick (oracle), {what} of the {n}-body disk: "
-                      f"{inter:.3e} interactions in {t_used:.1f} s"}
+                      f"{inter:.3e} interactions in {t_used:.1f} s",
+            "one_core_value": rows1 * (n - 1) / t1 / 1e9,
+            "one_core_sample": f"rows 0..{rows1 - 1}: {rows1 * (n - 1):.3e} interactions in {t1:.1f} s",
+            "cpu_model": model}
 
 
 def mixed_accuracy(N, W, torch, np, checkpoints=(0, 10, 100, 1000)):
@@ -235,7 +256,10 @@ def bench_small(N, W, torch, np, steps=100):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    N.rcrit(st, cfg, ws)
+    e_start = N.energy_k(st, cfg, ws, N.PairList(1 << 16)).cpu().numpy()
     eager = timed(lambda: N.step(st, cfg, ws, pairs))
+    e_end = N.energy_k(st, cfg, ws, N.PairList(1 << 16)).cpu().numpy()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         N.step(st, cfg, ws, pairs)
@@ -246,7 +270,9 @@ def bench_small(N, W, torch, np, steps=100):
     return {"workload": W.DISK_2048.name, "n": st.n, "steps": steps,
             "eager_step_us": round(eager * 1e6, 2), "graph_step_us": round(graph * 1e6, 2),
             "eager_ginter_s": round(inter / eager / 1e9, 3),
-            "graph_ginter_s": round(inter / graph / 1e9, 3)}
+            "graph_ginter_s": round(inter / graph / 1e9, 3),
+            "energy_rel_change_eager_steps": float((e_end[0] - e_start[0]) / abs(e_start[0])),
+            "energy_k_rel_change_eager_steps": float((e_end[5] - e_start[5]) / abs(e_start[5]))}
 
 
 def bench_tp(N, W, torch, np, steps=20):
