@@ -538,7 +538,8 @@ __global__ __launch_bounds__(LT) void k_group_rank(const int32_t *lab, const int
 }
 
 // ---------------------------------------------------------------------------
-// Direct solver: one workgroup per group, one thread per member.  The
+// Direct solver: one thread per member; groups of up to 8 bodies take 8 lanes
+// of a wave each, larger ones a workgroup of 64 or 256 threads.  The
 // group's flow (Kepler force of the star plus the remainder R of the mutual
 // forces) is integrated over H by Bulirsch-Stoer steps: the modified
 // midpoint rule with n = 2, 4, ..., 2 KM sub-steps, polynomial extrapolation
@@ -635,7 +636,203 @@ __device__ __forceinline__ double bs_block_max(BsSmem<BT> &sm, double v)
     return r;
 }
 
-// Groups of lo < size <= hi (the last class also reports the oversized).
+// How the members of a group see each other: a workgroup with the positions
+// in LDS (BlockPol), or GS lanes of one wave exchanging them by shuffles
+// (LanePol, several small groups per wave and no barriers).
+template <int BT>
+struct BlockPol {
+    BsSmem<BT> &sm;
+    int t, g;
+    __device__ void deriv(const BsDev &a, const double z[6], double f[6])
+    {
+        bs_deriv<BT>(a, sm, t, g, z, f);
+    }
+    __device__ double gmax(double v) { return bs_block_max<BT>(sm, v); }
+    __device__ bool member() const { return t < g; }
+};
+
+template <int GS>
+struct LanePol {
+    int u, g;
+    double m;
+    double rc[GENGA_MAX_LEVELS];
+    // every lane of the group runs the same partner loop (the shuffles need
+    // all GS lanes); only members add terms
+    __device__ void deriv(const BsDev &a, const double z[6], double f[6])
+    {
+        f[0] = z[3];
+        f[1] = z[4];
+        f[2] = z[5];
+        double acc[3] = {0.0, 0.0, 0.0};
+        const bool mem = u < g;
+        if (mem) {
+            const double r2s = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+            const double ks = -a.mu / (r2s * __builtin_sqrt(r2s));
+            acc[0] = ks * z[0];
+            acc[1] = ks * z[1];
+            acc[2] = ks * z[2];
+        }
+        for (int q = 0; q < g; ++q) {
+            const double xq = __shfl(z[0], q, GS), yq = __shfl(z[1], q, GS),
+                         zq = __shfl(z[2], q, GS), mq = __shfl(m, q, GS);
+            double R = 1.0;
+            double rcq[GENGA_MAX_LEVELS];
+            for (int l = 0; l < a.nlev; ++l) rcq[l] = __shfl(rc[l], q, GS);
+            if (!mem || q == u) continue;
+            const double dx = xq - z[0], dy = yq - z[1], dz = zq - z[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double r = __builtin_sqrt(r2);
+            for (int l = 0; l < a.nlev; ++l) {
+                const double rho = rc[l] > rcq[l] ? rc[l] : rcq[l];
+                R *= 1.0 - changeover_k(r, rho);
+            }
+            const double s = a.G * mq * R / (r2 * r);
+            acc[0] += s * dx;
+            acc[1] += s * dy;
+            acc[2] += s * dz;
+        }
+        f[3] = acc[0];
+        f[4] = acc[1];
+        f[5] = acc[2];
+    }
+    __device__ double gmax(double v)
+    {
+        for (int d = GS / 2; d > 0; d >>= 1) {
+            const double o = __shfl_xor(v, d, GS);
+            v = o > v ? o : v;
+        }
+        return v;
+    }
+    __device__ bool member() const { return u < g; }
+};
+
+// One group's flow over H from y (in place); returns true if it failed.
+template <class Pol>
+__device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
+{
+    double tt = 0.0, h = a.H;
+    int tries = 0;
+    while (tt < a.H) {      // uniform over the group: every member holds the same tt, h
+        const bool last = h >= a.H - tt;
+        if (last) h = a.H - tt;
+        double f0[6];
+        P.deriv(a, y, f0);
+        const double sx = __builtin_sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) +
+                          h * __builtin_sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
+        const double sv = __builtin_sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]) +
+                          h * __builtin_sqrt(f0[3] * f0[3] + f0[4] * f0[4] + f0[5] * f0[5]);
+        double prev[KM][6], cur[KM][6];
+        int kdone = -1;
+        for (int k = 0; k < KM; ++k) {
+            const int nk = 2 * (k + 1);
+            const double hh = h / nk;
+            double z0[6], z1[6], fz[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                z0[c] = y[c];
+                z1[c] = y[c] + hh * f0[c];
+            }
+            for (int q = 1; q < nk; ++q) {
+                P.deriv(a, z1, fz);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double z2 = z0[c] + 2.0 * hh * fz[c];
+                    z0[c] = z1[c];
+                    z1[c] = z2;
+                }
+            }
+            P.deriv(a, z1, fz);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) cur[0][c] = 0.5 * (z0[c] + z1[c] + hh * fz[c]);
+            for (int j = 1; j <= k; ++j) {
+                const double ratio = (double)nk / (double)(nk - 2 * j);
+                const double den = ratio * ratio - 1.0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    cur[j][c] = cur[j - 1][c] + (cur[j - 1][c] - prev[j - 1][c]) / den;
+            }
+            double err = 0.0;
+            if (k > 0 && P.member()) {
+                double ex = 0.0, ev = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double dxc = fabs(cur[k][c] - cur[k - 1][c]);
+                    const double dvc = fabs(cur[k][c + 3] - cur[k - 1][c + 3]);
+                    ex = dxc > ex ? dxc : ex;
+                    ev = dvc > ev ? dvc : ev;
+                }
+                const double e1 = ex / (sx + 1e-300), e2 = ev / (sv + 1e-300);
+                err = e1 > e2 ? e1 : e2;
+            }
+            if (k > 0) err = P.gmax(err);
+            for (int j = 0; j <= k; ++j)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) prev[j][c] = cur[j][c];
+            if (k > 0 && err <= a.eps) {
+                kdone = k;
+                break;
+            }
+        }
+        if (kdone >= 0) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) y[c] = prev[kdone][c];
+            tt = last ? a.H : tt + h;
+            if (kdone < KM / 2) h *= 2.0;
+        } else {
+            h *= 0.5;
+        }
+        if (++tries > BS_TRIES || h < a.H * 1e-12) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ void bs_store(const BsDev &a, int32_t b, const double y[6])
+{
+    a.x[b] = y[0];
+    a.y[b] = y[1];
+    a.z[b] = y[2];
+    a.vx[b] = y[3];
+    a.vy[b] = y[4];
+    a.vz[b] = y[5];
+}
+
+// Groups of at most GS bodies, GS lanes each (the many small groups).
+constexpr int BS_GS = 8;
+
+template <int GS>
+__global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
+{
+    const int u = threadIdx.x % GS;
+    const int64_t ng = a.gcount[0];
+    const int64_t stride = (int64_t)gridDim.x * (LT / GS);
+    for (int64_t gi = ((int64_t)blockIdx.x * LT + threadIdx.x) / GS; gi < ng; gi += stride) {
+        const int32_t root = a.groot[gi];
+        const int g = a.gsize[root];
+        if (g > GS) continue;                        // a workgroup class's group
+        if (u == 0) {
+            atomicAdd(a.gstats, 1ull);
+            atomicMax(a.gstats + 1, (unsigned long long)g);
+        }
+        LanePol<GS> P;
+        P.u = u;
+        P.g = g;
+        P.m = 0.0;
+        for (int l = 0; l < GENGA_MAX_LEVELS; ++l) P.rc[l] = 0.0;
+        const int32_t b = u < g ? a.gmem[a.gstart[root] + u] : 0;
+        double y[6] = {0, 0, 0, 0, 0, 0};
+        if (u < g) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
+            P.m = a.m[b];
+            for (int l = 0; l < a.nlev; ++l) P.rc[l] = a.rc[l][b];
+        }
+        const bool failed = bs_run(a, P, y);
+        if (failed && u == 0) atomicOr(a.status, ST_NOCONV);
+        if (u < g) bs_store(a, b, y);
+    }
+}
+
+// Groups of lo < size <= BT, one workgroup each (the last class also reports
+// the oversized ones).
 template <int BT>
 __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
 {
@@ -662,91 +859,10 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
             sm.m[t] = a.m[b];
             for (int l = 0; l < a.nlev; ++l) sm.rc[l][t] = a.rc[l][b];
         }
-        double tt = 0.0, h = a.H;
-        int tries = 0;
-        bool failed = false;
-        while (tt < a.H) {      // uniform: every thread holds the same tt, h
-            const bool last = h >= a.H - tt;
-            if (last) h = a.H - tt;
-            double f0[6];
-            bs_deriv<BT>(a, sm, t, g, y, f0);
-            const double sx = __builtin_sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) +
-                              h * __builtin_sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
-            const double sv = __builtin_sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]) +
-                              h * __builtin_sqrt(f0[3] * f0[3] + f0[4] * f0[4] + f0[5] * f0[5]);
-            double prev[KM][6], cur[KM][6];
-            int kdone = -1;
-            for (int k = 0; k < KM; ++k) {
-                const int nk = 2 * (k + 1);
-                const double hh = h / nk;
-                double z0[6], z1[6], fz[6];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    z0[c] = y[c];
-                    z1[c] = y[c] + hh * f0[c];
-                }
-                for (int q = 1; q < nk; ++q) {
-                    bs_deriv<BT>(a, sm, t, g, z1, fz);
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) {
-                        const double z2 = z0[c] + 2.0 * hh * fz[c];
-                        z0[c] = z1[c];
-                        z1[c] = z2;
-                    }
-                }
-                bs_deriv<BT>(a, sm, t, g, z1, fz);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) cur[0][c] = 0.5 * (z0[c] + z1[c] + hh * fz[c]);
-                for (int j = 1; j <= k; ++j) {
-                    const double ratio = (double)nk / (double)(nk - 2 * j);
-                    const double den = ratio * ratio - 1.0;
-#pragma unroll
-                    for (int c = 0; c < 6; ++c)
-                        cur[j][c] = cur[j - 1][c] + (cur[j - 1][c] - prev[j - 1][c]) / den;
-                }
-                double err = 0.0;
-                if (k > 0 && t < g) {
-                    double ex = 0.0, ev = 0.0;
-                    for (int c = 0; c < 3; ++c) {
-                        const double dxc = fabs(cur[k][c] - cur[k - 1][c]);
-                        const double dvc = fabs(cur[k][c + 3] - cur[k - 1][c + 3]);
-                        ex = dxc > ex ? dxc : ex;
-                        ev = dvc > ev ? dvc : ev;
-                    }
-                    const double e1 = ex / (sx + 1e-300), e2 = ev / (sv + 1e-300);
-                    err = e1 > e2 ? e1 : e2;
-                }
-                if (k > 0) err = bs_block_max<BT>(sm, err);
-                for (int j = 0; j <= k; ++j)
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) prev[j][c] = cur[j][c];
-                if (k > 0 && err <= a.eps) {
-                    kdone = k;
-                    break;
-                }
-            }
-            if (kdone >= 0) {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) y[c] = prev[kdone][c];
-                tt = last ? a.H : tt + h;
-                if (kdone < KM / 2) h *= 2.0;
-            } else {
-                h *= 0.5;
-            }
-            if (++tries > BS_TRIES || h < a.H * 1e-12) {
-                failed = true;
-                break;
-            }
-        }
+        BlockPol<BT> P{sm, t, g};
+        const bool failed = bs_run(a, P, y);
         if (failed && t == 0) atomicOr(a.status, ST_NOCONV);
-        if (t < g) {
-            a.x[b] = y[0];
-            a.y[b] = y[1];
-            a.z[b] = y[2];
-            a.vx[b] = y[3];
-            a.vy[b] = y[4];
-            a.vz[b] = y[5];
-        }
+        if (t < g) bs_store(a, b, y);
         __syncthreads();   // LDS reuse by the next group
     }
 }
@@ -875,7 +991,8 @@ static hipError_t direct_solve(const LevelRun &R, int l, double dt_l)
     a.eps = R.p->bs_eps > 0.0 ? R.p->bs_eps : 1e-12;
     a.status = R.status();
     a.gstats = R.at<unsigned long long>(V.gstats);
-    hipLaunchKernelGGL(k_bs<64>, dim3(LG), dim3(64), 0, R.s, a, 0);
+    hipLaunchKernelGGL(k_bs_lanes<BS_GS>, dim3(LG), dim3(LT), 0, R.s, a);
+    hipLaunchKernelGGL(k_bs<64>, dim3(LG), dim3(64), 0, R.s, a, BS_GS);
     hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG), dim3(GENGA_GROUP_MAX), 0, R.s, a, 64);
     return hipGetLastError();
 }
