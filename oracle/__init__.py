@@ -86,6 +86,8 @@ def _load():
     lib.or_changeover_integral.argtypes = [_d, _d]
     lib.or_energy_k.restype = _d
     lib.or_energy_k.argtypes = [_i64] + [_p] * 8 + [_d, _d]
+    lib.or_level_weight.restype = _d
+    lib.or_level_weight.argtypes = [_d, _p, ctypes.c_int, ctypes.c_int]
     lib.or_num_threads.restype = ctypes.c_int
     lib.or_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -313,6 +315,13 @@ def energy(state, G, m_star):
     n = state["x"].size
     return _load().or_energy(n, *(_ptr(_f64(state[k])) for k in ("x", "y", "z", "vx", "vy", "vz", "m")),
                              float(G), float(m_star))
+
+
+def level_weight(r: float, rho, l: int) -> float:
+    """W_l(r) for the level radii rho (l < len(rho)); l = len(rho): the
+    remainder no level takes."""
+    rr = np.ascontiguousarray(rho, dtype=np.float64)
+    return _load().or_level_weight(float(r), _ptr(rr), int(rr.size), int(l))
 
 
 def changeover_integral(r: float, rho: float) -> float:

@@ -488,6 +488,16 @@ static double level_weight(const LevelSys *S, int l, int64_t i, int64_t j, doubl
     return w * or_changeover(r, pair_rho(S->rc + l * S->n, i, j));
 }
 
+/* The weight of level l (0 <= l <= L) for a pair at separation r with the  */
+/* pair radii rho[0..L-1] of the levels: W_l for l < L, and for l = L the   */
+/* remainder prod_{k<L} (1 - K(r; rho_k)) that no level takes.              */
+double or_level_weight(double r, const double *rho, int L, int l)
+{
+    double w = 1.0;
+    for (int k = 0; k < l && k < L; ++k) w *= 1.0 - or_changeover(r, rho[k]);
+    return l < L ? w * or_changeover(r, rho[l]) : w;
+}
+
 /* v += h a over the pairs of the list with the level-l weight: each pair  */
 /* acts on both of its bodies; a body's terms are added in the list order, */
 /* which is its partners in ascending order.                               */

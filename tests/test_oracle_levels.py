@@ -113,3 +113,28 @@ def test_level_lists_shrink(levels, substeps):
     assert counts[0] == r[2] > 0
     for l in range(1, levels):
         assert 0 < counts[l] <= counts[l - 1] * substeps
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5])
+def test_level_weights_telescope(L):
+    # sum_l W_l + remainder = 1 at every separation (Sect. 6.2: the levels
+    # and the direct solver split each pair force without gap or overlap)
+    rng = np.random.default_rng(L)
+    for _ in range(200):
+        rho = np.sort(rng.uniform(0.001, 0.05, L))[::-1]
+        r = rng.uniform(0.0, 0.06)
+        parts = [oracle.level_weight(r, rho, l) for l in range(L + 1)]
+        assert all(p >= 0.0 for p in parts)
+        assert abs(sum(parts) - 1.0) < 1e-15
+
+
+def test_ten_substeps_keep_two_levels_active():
+    # with the velocity term dominating, a level of dt / 10 has rho_1 =
+    # rho_0 / 10, so K(r; rho_1) = 1 wherever 0 < K(r; rho_0) < 1: no more than
+    # two levels act on a pair at once
+    rho0 = 0.04
+    rho1 = rho0 / 10
+    for r in np.linspace(0.1 * rho0 * (1 + 1e-3), rho0 * (1 - 1e-3), 101):
+        assert 0.0 < oracle.changeover(r, rho0) < 1.0
+        assert oracle.changeover(r, rho1) == 1.0
+        assert oracle.level_weight(r, [rho0, rho1], 2) == 0.0
