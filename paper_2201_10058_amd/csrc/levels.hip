@@ -564,6 +564,38 @@ struct BsDev {
     unsigned long long *gstats;         // groups, largest group
 };
 
+// 1/sqrt(x) and 1/x from the hardware estimates (v_rsq_f64, v_rcp_f64) and two
+// Newton steps each: the serial chain of the group derivative is dominated
+// by latency, and these are several times shorter than the IEEE square root
+// and division; two steps take the estimates' 2^-24-level error below the
+// binary64 rounding level, far inside the Bulirsch-Stoer tolerance.
+__device__ __forceinline__ double rsq2(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = __builtin_fma(-x, y * y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-x, y * y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+}
+
+__device__ __forceinline__ double rcp2(double x)
+{
+    double t = __builtin_amdgcn_rcp(x);
+    t = __builtin_fma(t, __builtin_fma(-x, t, 1.0), t);
+    return __builtin_fma(t, __builtin_fma(-x, t, 1.0), t);
+}
+
+// R = prod_l (1 - K(r; rho_l)) with y_l = r / (0.9 rho_l) - 1/9.
+__device__ __forceinline__ double bs_remainder(double r, const double *rho, int nlev)
+{
+    double R = 1.0;
+    for (int l = 0; l < nlev; ++l) {
+        const double yv = __builtin_fma(r * rcp2(rho[l]), 10.0 / 9.0, -1.0 / 9.0);
+        R *= 1.0 - changeover_of_y(yv);
+    }
+    return R;
+}
+
 template <int BT>
 struct BsSmem {
     double px[BT], py[BT], pz[BT], m[BT];
@@ -577,7 +609,8 @@ __device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, i
                                          const double o[3], double acc[3])
 {
     const double r2s = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
-    const double ks = -a.mu / (r2s * __builtin_sqrt(r2s));
+    const double irs = rsq2(r2s);
+    const double ks = -a.mu * (irs * irs * irs);
     acc[0] = ks * o[0];
     acc[1] = ks * o[1];
     acc[2] = ks * o[2];
@@ -585,13 +618,12 @@ __device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, i
         if (q == t) continue;
         const double dx = sm.px[q] - o[0], dy = sm.py[q] - o[1], dz = sm.pz[q] - o[2];
         const double r2 = dx * dx + dy * dy + dz * dz;
-        const double r = __builtin_sqrt(r2);
-        double R = 1.0;
-        for (int l = 0; l < a.nlev; ++l) {
-            const double rho = sm.rc[l][t] > sm.rc[l][q] ? sm.rc[l][t] : sm.rc[l][q];
-            R *= 1.0 - changeover_k(r, rho);
-        }
-        const double s = a.G * sm.m[q] * R / (r2 * r);
+        const double ir = rsq2(r2);
+        double rho[GENGA_MAX_LEVELS];
+        for (int l = 0; l < a.nlev; ++l)
+            rho[l] = sm.rc[l][t] > sm.rc[l][q] ? sm.rc[l][t] : sm.rc[l][q];
+        const double R = bs_remainder(r2 * ir, rho, a.nlev);
+        const double s = a.G * sm.m[q] * R * (ir * ir * ir);
         acc[0] += s * dx;
         acc[1] += s * dy;
         acc[2] += s * dz;
@@ -667,7 +699,8 @@ struct LanePol {
         const bool mem = u < g;
         if (mem) {
             const double r2s = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
-            const double ks = -a.mu / (r2s * __builtin_sqrt(r2s));
+            const double irs = rsq2(r2s);
+            const double ks = -a.mu * (irs * irs * irs);
             acc[0] = ks * z[0];
             acc[1] = ks * z[1];
             acc[2] = ks * z[2];
@@ -675,18 +708,17 @@ struct LanePol {
         for (int q = 0; q < g; ++q) {
             const double xq = __shfl(z[0], q, GS), yq = __shfl(z[1], q, GS),
                          zq = __shfl(z[2], q, GS), mq = __shfl(m, q, GS);
-            double R = 1.0;
-            double rcq[GENGA_MAX_LEVELS];
-            for (int l = 0; l < a.nlev; ++l) rcq[l] = __shfl(rc[l], q, GS);
+            double rho[GENGA_MAX_LEVELS];
+            for (int l = 0; l < a.nlev; ++l) {
+                const double rq = __shfl(rc[l], q, GS);
+                rho[l] = rc[l] > rq ? rc[l] : rq;
+            }
             if (!mem || q == u) continue;
             const double dx = xq - z[0], dy = yq - z[1], dz = zq - z[2];
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double r = __builtin_sqrt(r2);
-            for (int l = 0; l < a.nlev; ++l) {
-                const double rho = rc[l] > rcq[l] ? rc[l] : rcq[l];
-                R *= 1.0 - changeover_k(r, rho);
-            }
-            const double s = a.G * mq * R / (r2 * r);
+            const double ir = rsq2(r2);
+            const double R = bs_remainder(r2 * ir, rho, a.nlev);
+            const double s = a.G * mq * R * (ir * ir * ir);
             acc[0] += s * dx;
             acc[1] += s * dy;
             acc[2] += s * dz;
@@ -707,6 +739,9 @@ struct LanePol {
 };
 
 // One group's flow over H from y (in place); returns true if it failed.
+// The extrapolation tableau is kept row by row in T (Neville's update in
+// place), and the loop over the sequence is unrolled so that T stays in
+// registers.
 template <class Pol>
 __device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
 {
@@ -721,8 +756,9 @@ __device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
                           h * __builtin_sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
         const double sv = __builtin_sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]) +
                           h * __builtin_sqrt(f0[3] * f0[3] + f0[4] * f0[4] + f0[5] * f0[5]);
-        double prev[KM][6], cur[KM][6];
+        double T[KM][6];
         int kdone = -1;
+#pragma unroll
         for (int k = 0; k < KM; ++k) {
             const int nk = 2 * (k + 1);
             const double hh = h / nk;
@@ -732,6 +768,7 @@ __device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
                 z0[c] = y[c];
                 z1[c] = y[c] + hh * f0[c];
             }
+#pragma unroll 1
             for (int q = 1; q < nk; ++q) {
                 P.deriv(a, z1, fz);
 #pragma unroll
@@ -742,39 +779,45 @@ __device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
                 }
             }
             P.deriv(a, z1, fz);
+            // row k of the tableau: T[0] = the midpoint result, T[j] from
+            // T[j - 1] (this row) and the previous row's T[j - 1]
 #pragma unroll
-            for (int c = 0; c < 6; ++c) cur[0][c] = 0.5 * (z0[c] + z1[c] + hh * fz[c]);
-            for (int j = 1; j <= k; ++j) {
-                const double ratio = (double)nk / (double)(nk - 2 * j);
-                const double den = ratio * ratio - 1.0;
+            for (int c = 0; c < 6; ++c) {
+                double old = T[0][c];
+                T[0][c] = 0.5 * (z0[c] + z1[c] + hh * fz[c]);
 #pragma unroll
-                for (int c = 0; c < 6; ++c)
-                    cur[j][c] = cur[j - 1][c] + (cur[j - 1][c] - prev[j - 1][c]) / den;
-            }
-            double err = 0.0;
-            if (k > 0 && P.member()) {
-                double ex = 0.0, ev = 0.0;
-                for (int c = 0; c < 3; ++c) {
-                    const double dxc = fabs(cur[k][c] - cur[k - 1][c]);
-                    const double dvc = fabs(cur[k][c + 3] - cur[k - 1][c + 3]);
-                    ex = dxc > ex ? dxc : ex;
-                    ev = dvc > ev ? dvc : ev;
+                for (int j = 1; j <= k; ++j) {
+                    const double ratio = (double)nk / (double)(nk - 2 * j);
+                    const double den = ratio * ratio - 1.0;
+                    const double oj = T[j][c];
+                    T[j][c] = T[j - 1][c] + (T[j - 1][c] - old) / den;
+                    old = oj;
                 }
-                const double e1 = ex / (sx + 1e-300), e2 = ev / (sv + 1e-300);
-                err = e1 > e2 ? e1 : e2;
             }
-            if (k > 0) err = P.gmax(err);
-            for (int j = 0; j <= k; ++j)
+            if (k > 0) {
+                double err = 0.0;
+                if (P.member()) {
+                    double ex = 0.0, ev = 0.0;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) prev[j][c] = cur[j][c];
-            if (k > 0 && err <= a.eps) {
-                kdone = k;
-                break;
+                    for (int c = 0; c < 3; ++c) {
+                        const double dxc = fabs(T[k][c] - T[k - 1][c]);
+                        const double dvc = fabs(T[k][c + 3] - T[k - 1][c + 3]);
+                        ex = dxc > ex ? dxc : ex;
+                        ev = dvc > ev ? dvc : ev;
+                    }
+                    const double e1 = ex / (sx + 1e-300), e2 = ev / (sv + 1e-300);
+                    err = e1 > e2 ? e1 : e2;
+                }
+                err = P.gmax(err);
+                if (err <= a.eps) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) y[c] = T[k][c];
+                    kdone = k;
+                    break;
+                }
             }
         }
         if (kdone >= 0) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) y[c] = prev[kdone][c];
             tt = last ? a.H : tt + h;
             if (kdone < KM / 2) h *= 2.0;
         } else {
