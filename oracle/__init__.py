@@ -62,6 +62,10 @@ def _load():
     lib.or_step_direct.argtypes = ([_i64] + [_p] * 8 + [_d] * 5
                                    + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _i64]
                                    + [_p] * 5)
+    lib.or_step_coll.restype = _i64
+    lib.or_step_coll.argtypes = ([_i64] + [_p] * 9 + [_d] * 5
+                                 + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _d, _i64]
+                                 + [_p] * 4 + [_i64] + [_p] * 5)
     lib.or_groups.restype = None
     lib.or_groups.argtypes = [_i64, _p, _p, _i64, _p]
     lib.or_direct_group.restype = None
@@ -214,6 +218,32 @@ def step_direct(state, G, m_star, dt, n1, n2, levels, substeps, rk_steps=2000, c
                                  _ptr(pj), _ptr(counts), _ptr(gstats), ctypes.byref(st))
     k = min(cnt, cap)
     return pi[:k].copy(), pj[:k].copy(), int(cnt), rc, counts, (int(gstats[0]), int(gstats[1])), st.value
+
+
+def step_coll(state, G, m_star, dt, n1, n2, levels, substeps, rk_steps=2000, coll_tol=1e-6,
+              capcoll=1024, cap=1 << 20):
+    """One step with levels, the direct solver and collisions (state["R"]:
+    radii; m and R are updated by mergers).  Returns (pairs count, counts,
+    (groups, largest), [(survivor, absorbed, lost energy), ...], status)."""
+    n = state["x"].size
+    rc = np.empty(n)
+    pi = np.zeros(max(cap, 1), dtype=np.int32)
+    pj = np.zeros(max(cap, 1), dtype=np.int32)
+    counts = np.zeros(max(int(levels), 1), dtype=np.int64)
+    gstats = np.zeros(2, dtype=np.int64)
+    ci = np.zeros(max(capcoll, 1), dtype=np.int32)
+    cj = np.zeros(max(capcoll, 1), dtype=np.int32)
+    cdu = np.zeros(max(capcoll, 1), dtype=np.float64)
+    nc = np.zeros(1, dtype=np.int64)
+    st = ctypes.c_int(0)
+    cnt = _load().or_step_coll(n, *(_ptr(state[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "R")),
+                               _ptr(rc), float(G), float(m_star), float(dt), float(n1), float(n2),
+                               int(levels), int(substeps), 1, int(rk_steps), float(coll_tol),
+                               int(capcoll), _ptr(ci), _ptr(cj), _ptr(cdu), _ptr(nc), int(cap),
+                               _ptr(pi), _ptr(pj), _ptr(counts), _ptr(gstats), ctypes.byref(st))
+    k = int(min(nc[0], capcoll))
+    coll = [(int(ci[q]), int(cj[q]), float(cdu[q])) for q in range(k)]
+    return int(cnt), counts, (int(gstats[0]), int(gstats[1])), coll, st.value
 
 
 def groups(n, pi, pj):

@@ -478,6 +478,14 @@ typedef struct {
     int direct;        /* integrate the deepest level's remainder (groups) */
     int64_t rk_steps;  /* fourth-order Runge-Kutta steps per group and interval */
     int64_t groups, group_max;   /* groups integrated, largest group */
+    /* collisions (direct solver, R non-null): radii, contact tolerance as a */
+    /* fraction of R_i + R_j, records (survivor, absorbed, lost energy)      */
+    double *R;
+    double *mw;        /* the masses, writable (mergers) */
+    double coll_tol;
+    int64_t ncoll, capcoll;
+    int32_t *ci, *cj;
+    double *cdU;
 } LevelSys;
 
 /* Weight of level l for the pair (i, j) at separation r. */
@@ -677,6 +685,152 @@ static void direct_rk4(const double *m, const double *rc, int64_t n, int lmax, d
     free(k1);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Collisions inside the direct solver (Sect. 7, collision handling): two   */
+/* members whose distance falls below R_a + R_b merge into one body.  The   */
+/* fixed steps of the flow are checked after each step; the first pair found */
+/* (member order) is traced back to its contact time by bisection of that   */
+/* step's length, until the overlap is below coll_tol of R_a + R_b (the      */
+/* paper's collision precision), and merged there:                          */
+/*   x = (m_a x_a + m_b x_b)/(m_a + m_b), v likewise, m = m_a + m_b,          */
+/*   R = (R_a^3 + R_b^3)^(1/3), lost energy                                  */
+/*   dU = 1/2 m_a m_b/(m_a + m_b) |v_a - v_b|^2 - G m_a m_b / r_ab.            */
+/* The survivor is the more massive body, or the lower index for equal      */
+/* masses.  Readings: the absorbed body stays in the arrays as a massless,   */
+/* sizeless ghost parked at x = (1e6 + index, 0, 0) AU at rest, far from    */
+/* every other body (the caller may compact the arrays); spin is not        */
+/* tracked.                                                                  */
+/* ------------------------------------------------------------------------ */
+static void rk4_step(const double *m, const double *rc, int64_t n, int lmax, double G, double mu,
+                     const int64_t *mem, int64_t g, double *Y, double h, double *wk)
+{
+    const int64_t w = 6 * g;
+    double *k1 = wk, *k2 = k1 + w, *k3 = k2 + w, *k4 = k3 + w, *T = k4 + w;
+    direct_rhs(m, rc, n, lmax, G, mu, mem, g, Y, k1);
+    for (int64_t q = 0; q < w; ++q) T[q] = Y[q] + 0.5 * h * k1[q];
+    direct_rhs(m, rc, n, lmax, G, mu, mem, g, T, k2);
+    for (int64_t q = 0; q < w; ++q) T[q] = Y[q] + 0.5 * h * k2[q];
+    direct_rhs(m, rc, n, lmax, G, mu, mem, g, T, k3);
+    for (int64_t q = 0; q < w; ++q) T[q] = Y[q] + h * k3[q];
+    direct_rhs(m, rc, n, lmax, G, mu, mem, g, T, k4);
+    for (int64_t q = 0; q < w; ++q) Y[q] += h / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+}
+
+static double sep(const double *Y, int64_t a, int64_t b)
+{
+    const double dx = Y[6 * b] - Y[6 * a], dy = Y[6 * b + 1] - Y[6 * a + 1],
+                 dz = Y[6 * b + 2] - Y[6 * a + 2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* First overlapping pair (a < b in member order) of the group, or 0. */
+static int find_overlap(const double *R, const int64_t *mem, int64_t g, const double *Y,
+                        int64_t *pa, int64_t *pb)
+{
+    for (int64_t a = 0; a < g; ++a)
+        for (int64_t b = a + 1; b < g; ++b) {
+            const double rs = R[mem[a]] + R[mem[b]];
+            if (rs > 0.0 && sep(Y, a, b) < rs) {
+                *pa = a;
+                *pb = b;
+                return 1;
+            }
+        }
+    return 0;
+}
+
+static void merge_members(LevelSys *S, const int64_t *mem, double *Y, int64_t a, int64_t b)
+{
+    const int64_t ia = mem[a], ib = mem[b];
+    const double ma = S->mw[ia], mb = S->mw[ib];
+    /* the survivor: the more massive body, the lower index for equal masses */
+    int64_t ks = a, ka = b;
+    if (mb > ma || (mb == ma && ib < ia)) {
+        ks = b;
+        ka = a;
+    }
+    const int64_t is = mem[ks], iab = mem[ka];
+    double *ys = Y + 6 * ks, *yk = Y + 6 * ka;
+    const double M = ma + mb;
+    const double *ya = Y + 6 * a, *yb = Y + 6 * b;
+    double dv2 = 0.0;
+    for (int c = 3; c < 6; ++c) dv2 += (ya[c] - yb[c]) * (ya[c] - yb[c]);
+    const double dU = 0.5 * ma * mb / M * dv2 - S->G * ma * mb / sep(Y, a, b);
+    double merged[6];
+    for (int c = 0; c < 6; ++c) merged[c] = (ma * ya[c] + mb * yb[c]) / M;
+    for (int c = 0; c < 6; ++c) ys[c] = merged[c];
+    yk[0] = 1e6 + (double)iab;
+    yk[1] = yk[2] = yk[3] = yk[4] = yk[5] = 0.0;
+    const double Rs = S->R[ia], Rb = S->R[ib];
+    S->R[is] = cbrt(Rs * Rs * Rs + Rb * Rb * Rb);
+    S->R[iab] = 0.0;
+    S->mw[is] = M;
+    S->mw[iab] = 0.0;
+    if (S->ncoll < S->capcoll) {
+        S->ci[S->ncoll] = (int32_t)is;
+        S->cj[S->ncoll] = (int32_t)iab;
+        S->cdU[S->ncoll] = dU;
+    }
+    ++S->ncoll;
+}
+
+/* The group's flow over dt in rk_steps equal steps, with collisions. */
+static void direct_group_coll(LevelSys *S, int l, const int64_t *mem, int64_t g, double dt)
+{
+    const int64_t n = S->n;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)(6 * g + 1));
+    double *Y0 = (double *)malloc(sizeof(double) * (size_t)(6 * g + 1));
+    double *Yt = (double *)malloc(sizeof(double) * (size_t)(6 * g + 1));
+    double *wk = (double *)malloc(sizeof(double) * (size_t)(30 * g + 1));
+    for (int64_t a = 0; a < g; ++a) {
+        const int64_t i = mem[a];
+        double *ya = Y + 6 * a;
+        ya[0] = S->x[i]; ya[1] = S->y[i]; ya[2] = S->z[i];
+        ya[3] = S->vx[i]; ya[4] = S->vy[i]; ya[5] = S->vz[i];
+    }
+    const double mu = S->G * S->m_star;
+    const double h = dt / (double)S->rk_steps;
+    double t = 0.0;
+    for (int64_t st = 0; st < S->rk_steps; ++st) {
+        const double hs = st == S->rk_steps - 1 ? dt - t : h;
+        memcpy(Y0, Y, sizeof(double) * (size_t)(6 * g));
+        rk4_step(S->mw, S->rc, n, l, S->G, mu, mem, g, Y, hs, wk);
+        int64_t a, b;
+        if (S->R && find_overlap(S->R, mem, g, Y, &a, &b)) {
+            /* contact time in (0, hs]: bisection on the step length */
+            double lo = 0.0, hi = hs;
+            memcpy(Yt, Y, sizeof(double) * (size_t)(6 * g));
+            for (int it = 0; it < 80; ++it) {
+                const double rs = S->R[mem[a]] + S->R[mem[b]];
+                if ((rs - sep(Yt, a, b)) / rs < S->coll_tol) break;
+                const double mid = 0.5 * (lo + hi);
+                double *Yc = (double *)malloc(sizeof(double) * (size_t)(6 * g));
+                memcpy(Yc, Y0, sizeof(double) * (size_t)(6 * g));
+                rk4_step(S->mw, S->rc, n, l, S->G, mu, mem, g, Yc, mid, wk);
+                if (sep(Yc, a, b) < rs) {
+                    hi = mid;
+                    memcpy(Yt, Yc, sizeof(double) * (size_t)(6 * g));
+                } else {
+                    lo = mid;
+                }
+                free(Yc);
+            }
+            memcpy(Y, Yt, sizeof(double) * (size_t)(6 * g));
+            merge_members(S, mem, Y, a, b);
+            /* the rest of this step from the contact time */
+            rk4_step(S->mw, S->rc, n, l, S->G, mu, mem, g, Y, hs - hi, wk);
+        }
+        t += hs;
+    }
+    for (int64_t a = 0; a < g; ++a) {
+        const int64_t i = mem[a];
+        const double *ya = Y + 6 * a;
+        S->x[i] = ya[0]; S->y[i] = ya[1]; S->z[i] = ya[2];
+        S->vx[i] = ya[3]; S->vy[i] = ya[4]; S->vz[i] = ya[5];
+    }
+    free(Y); free(Y0); free(Yt); free(wk);
+}
+
 /* One group alone (for the pins): state arrays of n bodies, members mem[g], */
 /* radii rc[(lmax + 1) n]; the members' state is advanced by dt in place.   */
 void or_direct_group(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
@@ -714,8 +868,11 @@ static void direct_groups(LevelSys *S, int l, const int32_t *pi, const int32_t *
             if (label[i] == r) mem[g++] = i;
         ++S->groups;
         if (g > S->group_max) S->group_max = g;
-        or_direct_group(n, S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, S->rc, l, S->G,
-                        S->m_star, mem, g, dt, S->rk_steps);
+        if (S->R)
+            direct_group_coll(S, l, mem, g, dt);
+        else
+            or_direct_group(n, S->x, S->y, S->z, S->vx, S->vy, S->vz, S->m, S->rc, l, S->G,
+                            S->m_star, mem, g, dt, S->rk_steps);
     }
     free(label); free(mem);
 }
@@ -778,16 +935,39 @@ static void level_advance(LevelSys *S, int l, double dt_l, const int32_t *pi, co
 /* instead of their drift, under the direct solver's flow (rk_steps RK4     */
 /* steps per group and interval); gstats (nullable) receives the number of  */
 /* groups integrated and the largest group size.                            */
+/* With R non-null (radii, writable; m then writable too) the direct solver */
+/* merges colliding members (see above): coll receives up to capcoll        */
+/* records (survivor, absorbed, lost energy), *ncoll their true number.     */
+int64_t or_step_coll(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                     double *vz, double *m, double *R, double *rc, double G, double m_star,
+                     double dt, double n1, double n2, int levels, int substeps, int direct,
+                     int64_t rk_steps, double coll_tol, int64_t capcoll, int32_t *ci, int32_t *cj,
+                     double *cdU, int64_t *ncoll, int64_t cap, int32_t *pi, int32_t *pj,
+                     int64_t *counts, int64_t *gstats, int *status);
+
 int64_t or_step_direct(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
                        double *vz, const double *m, double *rc, double G, double m_star,
                        double dt, double n1, double n2, int levels, int substeps, int direct,
                        int64_t rk_steps, int64_t cap, int32_t *pi, int32_t *pj, int64_t *counts,
                        int64_t *gstats, int *status)
 {
+    return or_step_coll(n, x, y, z, vx, vy, vz, (double *)m, NULL, rc, G, m_star, dt, n1, n2,
+                        levels, substeps, direct, rk_steps, 0.0, 0, NULL, NULL, NULL, NULL, cap,
+                        pi, pj, counts, gstats, status);
+}
+
+int64_t or_step_coll(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                     double *vz, double *m, double *R, double *rc, double G, double m_star,
+                     double dt, double n1, double n2, int levels, int substeps, int direct,
+                     int64_t rk_steps, double coll_tol, int64_t capcoll, int32_t *ci, int32_t *cj,
+                     double *cdU, int64_t *ncoll, int64_t cap, int32_t *pi, int32_t *pj,
+                     int64_t *counts, int64_t *gstats, int *status)
+{
     if (levels < 1) levels = 1;
     if (substeps < 1) substeps = 1;
     LevelSys S = {n, x, y, z, vx, vy, vz, m, G, m_star, n1, n2, levels, substeps, NULL, OR_OK,
-                  direct, rk_steps > 0 ? rk_steps : 1, 0, 0};
+                  direct, rk_steps > 0 ? rk_steps : 1, 0, 0,
+                  R, m, coll_tol, 0, capcoll, ci, cj, cdU};
     S.rc = (double *)calloc((size_t)(levels * n + 1), sizeof(double));
     int64_t *cnt = (int64_t *)calloc((size_t)levels, sizeof(int64_t));
     or_rcrit(n, x, y, z, vx, vy, vz, m, m_star, dt, n1, n2, S.rc);
@@ -829,6 +1009,7 @@ int64_t or_step_direct(int64_t n, double *x, double *y, double *z, double *vx, d
         gstats[0] = S.groups;
         gstats[1] = S.group_max;
     }
+    if (ncoll) *ncoll = S.ncoll;
     if (status) *status = S.status;
     free(S.rc); free(cnt); free(ei); free(ej); free(bod); free(buf);
     return np;
