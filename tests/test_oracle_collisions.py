@@ -32,7 +32,7 @@ def test_merger_against_event_located_reference(kw, survivor):
     for k in ("vx", "vy", "vz"):
         assert abs(o[k][s] - ref[k][s]) < 1e-14
     assert o["m"][s] == ref["m"][s] and o["m"][g] == 0.0
-    assert o["R"][s] == ref["R"][s] and o["R"][g] == 0.0
+    assert abs(o["R"][s] - ref["R"][s]) <= 1e-15 * ref["R"][s] and o["R"][g] == 0.0
     assert abs(o["x"][g] - (1e6 + g)) < 1e-3          # the ghost is parked
 
 
