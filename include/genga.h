@@ -80,6 +80,9 @@ typedef struct {
     double *vx, *vy, *vz; /* barycentric velocities [AU/day]                    */
     double *m;            /* masses [solar masses]; the star is not an element  */
     double *rc;           /* critical radii [AU], >= 0                          */
+    double *R;            /* physical radii [AU] (nullable): with the direct
+                             solver, members closer than R_i + R_j merge (see
+                             genga_step); mergers update m and R            */
 } genga_bodies;
 
 /* Scalars of the method.  Units are the caller's; G must match them. */
@@ -137,6 +140,9 @@ typedef struct {
     double c_light; /* speed of light in the caller's units: > 0 adds the
                        post-Newtonian term to genga_step (genga_gr_kick);
                        0 = off                                               */
+    double coll_tol; /* collisions: contact located to an overlap below this
+                        fraction of R_i + R_j (the paper's collision
+                        precision); 0 = 1e-6                                 */
 } genga_params;
 
 #define GENGA_MAX_LEVELS 8
@@ -247,6 +253,17 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
  * when the last two extrapolations agree within p->bs_eps relative to the
  * state's magnitude, else halved).  One workgroup per group; a group of more
  * than GENGA_GROUP_MAX bodies sets GENGA_E_GROUP and keeps its drift.
+ *
+ * Collisions (Sect. 7; b->R non-null, direct = 1): after each accepted
+ * Bulirsch-Stoer step the group's first pair (member order) with
+ * r < R_i + R_j is traced back to its contact by bisection of that step's
+ * length, until the overlap is below p->coll_tol of R_i + R_j, and merged
+ * there: the more massive body (the lower index for equal masses) takes
+ * x = (m_i x_i + m_j x_j)/(m_i + m_j), v likewise, m_i + m_j and
+ * R = (R_i^3 + R_j^3)^(1/3); the other becomes a massless, sizeless ghost at
+ * rest at (1e6 + index, 0, 0) (far from every body; the caller may compact
+ * the arrays); the lost energy 1/2 m_i m_j/(m_i + m_j)|v_i - v_j|^2
+ * - G m_i m_j / r_ij is recorded (genga_collisions).  Spin is not tracked.
  * ws must be sized with the same params (genga_workspace_bytes); every
  * level runs in binary64 on the device, with no host synchronisation, so
  * a step can be captured in a graph.  Not with test-particle modes
@@ -259,6 +276,14 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
  * (E_{slevels-1} holds the pairs left to the direct solver).  out is a host
  * array of slevels int64; synchronises the stream. */
 int genga_level_counts(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream);
+
+/* Collisions of the last genga_step with these params (direct = 1, radii
+ * given): *count receives their number; up to `cap` records go to the host
+ * arrays i (survivor), j (absorbed body) and du (lost energy), sorted by
+ * (i, j).  At most 4096 records are kept per step (*count may be larger).
+ * Synchronises the stream. */
+int genga_collisions(int64_t n, const genga_params *p, void *ws, int64_t *count, int32_t *i,
+                     int32_t *j, double *du, int64_t cap, void *stream);
 
 /* Direct solver statistics of the last genga_step with these params (direct
  * = 1): out[0] = groups integrated (summed over the deepest level's

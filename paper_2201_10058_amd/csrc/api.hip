@@ -3,6 +3,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "genga_internal.h"
 
 namespace genga {
@@ -41,6 +44,7 @@ static int check_params(const genga_params *p)
     if (p->tp_mode < 0 || p->tp_mode > 2 || p->n_massive < 0) return GENGA_E_INVAL;
     if (p->slevels < 0 || p->slevels > GENGA_MAX_LEVELS) return GENGA_E_INVAL;
     if (!is_fin(p->c_light) || p->c_light < 0.0) return GENGA_E_INVAL;
+    if (!is_fin(p->coll_tol) || p->coll_tol < 0.0 || p->coll_tol >= 1.0) return GENGA_E_INVAL;
     if (p->direct != 0 && p->direct != 1) return GENGA_E_INVAL;
     if (!is_fin(p->bs_eps) || p->bs_eps < 0.0) return GENGA_E_INVAL;
     if (p->slevels > 1 || p->direct) {
@@ -397,6 +401,46 @@ int genga_gr_kick(genga_bodies *b, const genga_params *p, double h, void *ws, vo
     const Layout L = make_layout(b->n, choose_kick_cfg(b->n, p));
     hipError_t e = launch_gr(b, p, h, L, (char *)ws, (hipStream_t)stream);
     return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_collisions(int64_t n, const genga_params *p, void *ws, int64_t *count, int32_t *i,
+                     int32_t *j, double *du, int64_t cap, void *stream)
+{
+    int r = check_params(p);
+    if (r) return r;
+    if (n < 1 || !ws || !count || !p->direct || cap < 0) return GENGA_E_INVAL;
+    if (cap > 0 && (!i || !j || !du)) return GENGA_E_INVAL;
+    const LevelLayout V = make_level_layout(n, p, make_layout(n, choose_kick_cfg(n, p)).total);
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t c = 0;
+    hipError_t e = hipMemcpyAsync(&c, (char *)ws + V.coll_count, sizeof(c), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    *count = (int64_t)c;
+    const int64_t k = std::min<int64_t>(std::min<int64_t>((int64_t)c, LEVEL_COLL_CAP), cap);
+    if (k <= 0) return GENGA_OK;
+    std::vector<int32_t> ci(k), cj(k);
+    std::vector<double> cd(k);
+    e = hipMemcpyAsync(ci.data(), (char *)ws + V.coll_i, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cj.data(), (char *)ws + V.coll_j, sizeof(int32_t) * k,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cd.data(), (char *)ws + V.coll_du, sizeof(double) * k,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    std::vector<int64_t> ord(k);
+    for (int64_t q = 0; q < k; ++q) ord[q] = q;
+    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+        return ci[a] != ci[b] ? ci[a] < ci[b] : cj[a] < cj[b];
+    });
+    for (int64_t q = 0; q < k; ++q) {
+        i[q] = ci[ord[q]];
+        j[q] = cj[ord[q]];
+        du[q] = cd[ord[q]];
+    }
+    return GENGA_OK;
 }
 
 int genga_group_stats(int64_t n, const genga_params *p, void *ws, int64_t *out, void *stream)

@@ -199,8 +199,13 @@ struct LevelLayout {
     size_t gcount = 0;     // int32 [2]  groups, members
     size_t gstats = 0;     // int64 [2]  groups integrated, largest group (per step)
     size_t gtsum = 0;      // int64 [2][n / 256] tile sums of the group scan
+    size_t coll_count = 0; // uint64     collisions of the step
+    size_t coll_i = 0, coll_j = 0;   // int32 [LEVEL_COLL_CAP] survivor, absorbed
+    size_t coll_du = 0;    // double [LEVEL_COLL_CAP] lost energy
     size_t total = 0;
 };
+
+constexpr int64_t LEVEL_COLL_CAP = 4096;   // collision records kept per step
 // base: byte offset where the level regions start (the kick Layout's total).
 LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base);
 // The level-0 list in the workspace (the first half kick writes it there).

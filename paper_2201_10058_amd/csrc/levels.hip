@@ -17,6 +17,8 @@
 // writes).  For the kicks every list gets an adjacency structure whose
 // partners are sorted ascending per body, so each body adds its pair terms in
 // a fixed order and no floating-point atomics are used.
+#include <climits>
+
 #include "device_common.h"
 #include "genga_internal.h"
 #include "kepler.h"
@@ -50,11 +52,12 @@ __device__ __forceinline__ double sep2(const double *x, const double *y, const d
 }
 
 __global__ __launch_bounds__(64) void k_level_begin(int64_t *lcount, int L, const int64_t *cnt0,
-                                                    int64_t *gstats)
+                                                    int64_t *gstats, int64_t *coll_count)
 {
     const int t = threadIdx.x;
     if (t < L) lcount[t] = t == 0 ? *cnt0 : 0;
     if (gstats && t < 2) gstats[t] = 0;
+    if (coll_count && t == 0) *coll_count = 0;
 }
 
 // E_0 to the caller's list: min(count, capacities) entries and the true count.
@@ -556,12 +559,20 @@ struct BsDev {
     const double *shadow;               // [6][n] state before the drift
     int64_t n;
     double *x, *y, *z, *vx, *vy, *vz;
-    const double *m;
+    double *m;                          // written by mergers
     const double *rc[GENGA_MAX_LEVELS]; // levels 0 .. nlev - 1 weigh R
     int nlev;
     double G, mu, H, eps;
     int32_t *status;
     unsigned long long *gstats;         // groups, largest group
+    // collisions (radius non-null): radii (written by mergers), contact
+    // tolerance, records (survivor, absorbed, lost energy)
+    double *radius;
+    double coll_tol;
+    int32_t *coll_i, *coll_j;
+    double *coll_du;
+    unsigned long long *coll_count;
+    int64_t coll_cap;
 };
 
 // 1/sqrt(x) and 1/x from the hardware estimates (v_rsq_f64, v_rcp_f64) and two
@@ -599,8 +610,11 @@ __device__ __forceinline__ double bs_remainder(double r, const double *rho, int 
 template <int BT>
 struct BsSmem {
     double px[BT], py[BT], pz[BT], m[BT];
+    double pv[3][BT], R[BT];
+    int32_t idx[BT];
     double rc[GENGA_MAX_LEVELS][BT];
     double red[BT / 64];
+    int ired[BT / 64];
 };
 
 // Acceleration of member t at its position (o) from the positions in LDS.
@@ -671,6 +685,10 @@ __device__ __forceinline__ double bs_block_max(BsSmem<BT> &sm, double v)
 // How the members of a group see each other: a workgroup with the positions
 // in LDS (BlockPol), or GS lanes of one wave exchanging them by shuffles
 // (LanePol, several small groups per wave and no barriers).
+// Both policies also expose, for the collision search and the merger: the
+// whole state of member q after publish(), its mass, radius and body index,
+// a group-wide minimum of an integer key, and updates of the own member's
+// mass and radius.
 template <int BT>
 struct BlockPol {
     BsSmem<BT> &sm;
@@ -681,13 +699,92 @@ struct BlockPol {
     }
     __device__ double gmax(double v) { return bs_block_max<BT>(sm, v); }
     __device__ bool member() const { return t < g; }
+    __device__ int self() const { return t; }
+    __device__ void publish(const double z[6])
+    {
+        __syncthreads();
+        if (t < g) {
+            sm.px[t] = z[0];
+            sm.py[t] = z[1];
+            sm.pz[t] = z[2];
+            sm.pv[0][t] = z[3];
+            sm.pv[1][t] = z[4];
+            sm.pv[2][t] = z[5];
+        }
+        __syncthreads();
+    }
+    __device__ void get(int q, double o[6]) const
+    {
+        o[0] = sm.px[q];
+        o[1] = sm.py[q];
+        o[2] = sm.pz[q];
+        o[3] = sm.pv[0][q];
+        o[4] = sm.pv[1][q];
+        o[5] = sm.pv[2][q];
+    }
+    __device__ double mass(int q) const { return sm.m[q]; }
+    __device__ double rad(int q) const { return sm.R[q]; }
+    __device__ int idx(int q) const { return sm.idx[q]; }
+    __device__ void set_own(double m, double R)
+    {
+        if (t < g) {
+            sm.m[t] = m;
+            sm.R[t] = R;
+        }
+    }
+    __device__ int gmin(int v)
+    {
+        for (int d = 32; d > 0; d >>= 1) {
+            const int o = __shfl_xor(v, d, 64);
+            v = o < v ? o : v;
+        }
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sm.ired[threadIdx.x >> 6] = v;
+        __syncthreads();
+        int r = sm.ired[0];
+#pragma unroll
+        for (int w = 1; w < BT / 64; ++w) r = sm.ired[w] < r ? sm.ired[w] : r;
+        return r;
+    }
 };
 
 template <int GS>
 struct LanePol {
     int u, g;
-    double m;
+    double m, R;
+    int32_t bidx;
+    double zc[6];
     double rc[GENGA_MAX_LEVELS];
+    __device__ bool member() const { return u < g; }
+    __device__ int self() const { return u; }
+    __device__ void publish(const double z[6])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) zc[c] = z[c];
+    }
+    __device__ void get(int q, double o[6]) const
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = __shfl(zc[c], q, GS);
+    }
+    __device__ double mass(int q) const { return __shfl(m, q, GS); }
+    __device__ double rad(int q) const { return __shfl(R, q, GS); }
+    __device__ int idx(int q) const { return __shfl(bidx, q, GS); }
+    __device__ void set_own(double mm, double RR)
+    {
+        if (u < g) {
+            m = mm;
+            R = RR;
+        }
+    }
+    __device__ int gmin(int v)
+    {
+        for (int d = GS / 2; d > 0; d >>= 1) {
+            const int o = __shfl_xor(v, d, GS);
+            v = o < v ? o : v;
+        }
+        return v;
+    }
     // every lane of the group runs the same partner loop (the shuffles need
     // all GS lanes); only members add terms
     __device__ void deriv(const BsDev &a, const double z[6], double f[6])
@@ -735,13 +832,171 @@ struct LanePol {
         }
         return v;
     }
-    __device__ bool member() const { return u < g; }
 };
 
+// One Bulirsch-Stoer step of length h from y: the modified midpoint rule
+// with n = 2, 4, ..., 2 KM sub-steps and Neville's extrapolation (the tableau
+// updated in place, the loop over the sequence unrolled so that it stays in
+// registers).  Returns the number of extrapolations that met the tolerance
+// (-1 if none did; yout then holds the last one).
+template <class Pol>
+__device__ int bs_step(const BsDev &a, Pol &P, const double y[6], double h, double yout[6])
+{
+    double f0[6];
+    P.deriv(a, y, f0);
+    const double sx = __builtin_sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) +
+                      h * __builtin_sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
+    const double sv = __builtin_sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]) +
+                      h * __builtin_sqrt(f0[3] * f0[3] + f0[4] * f0[4] + f0[5] * f0[5]);
+    double T[KM][6];
+    int kdone = -1;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int nk = 2 * (k + 1);
+        const double hh = h / nk;
+        double z0[6], z1[6], fz[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            z0[c] = y[c];
+            z1[c] = y[c] + hh * f0[c];
+        }
+#pragma unroll 1
+        for (int q = 1; q < nk; ++q) {
+            P.deriv(a, z1, fz);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double z2 = z0[c] + 2.0 * hh * fz[c];
+                z0[c] = z1[c];
+                z1[c] = z2;
+            }
+        }
+        P.deriv(a, z1, fz);
+        // row k of the tableau: T[0] = the midpoint result, T[j] from T[j - 1]
+        // (this row) and the previous row's T[j - 1]
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            double old = T[0][c];
+            T[0][c] = 0.5 * (z0[c] + z1[c] + hh * fz[c]);
+#pragma unroll
+            for (int j = 1; j <= k; ++j) {
+                const double ratio = (double)nk / (double)(nk - 2 * j);
+                const double den = ratio * ratio - 1.0;
+                const double oj = T[j][c];
+                T[j][c] = T[j - 1][c] + (T[j - 1][c] - old) / den;
+                old = oj;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) yout[c] = T[k][c];
+        if (k > 0) {
+            double err = 0.0;
+            if (P.member()) {
+                double ex = 0.0, ev = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double dxc = fabs(T[k][c] - T[k - 1][c]);
+                    const double dvc = fabs(T[k][c + 3] - T[k - 1][c + 3]);
+                    // (written so that a NaN propagates into the error)
+                    ex = (dxc > ex || dxc != dxc) ? dxc : ex;
+                    ev = (dvc > ev || dvc != dvc) ? dvc : ev;
+                }
+                const double e1 = ex / (sx + 1e-300), e2 = ev / (sv + 1e-300);
+                err = e1 > e2 ? e1 : e2;
+                // a step through a singularity (two members passing through
+                // each other) yields NaN: count it as not converged, so that
+                // every member takes the same decision
+                if (!(err <= INFINITY)) err = INFINITY;
+            }
+            err = P.gmax(err);
+            if (err <= a.eps) {
+                kdone = k;
+                break;
+            }
+        }
+    }
+    return kdone;
+}
+
+// The first overlapping pair of the group at state z (a < b, encoded as
+// a * 1024 + b), or INT_MAX.  Uniform over the group.
+template <class Pol>
+__device__ int bs_overlap(const BsDev &a, Pol &P, const double z[6])
+{
+    P.publish(z);
+    int key = INT_MAX;
+    const int u = P.self();
+    const double ru = P.rad(u);
+    for (int q = 0; q < P.g; ++q) {
+        double o[6];
+        P.get(q, o);
+        const double rq = P.rad(q);
+        if (!P.member() || q <= u) continue;
+        const double rs = ru + rq;
+        const double dx = o[0] - z[0], dy = o[1] - z[1], dz = o[2] - z[2];
+        if (rs > 0.0 && dx * dx + dy * dy + dz * dz < rs * rs && key == INT_MAX) key = u * 1024 + q;
+    }
+    return P.gmin(key);
+}
+
+// Distance of members ma, mb at state z (uniform).
+template <class Pol>
+__device__ double bs_sep(Pol &P, const double z[6], int ma, int mb)
+{
+    P.publish(z);
+    double oa[6], ob[6];
+    P.get(ma, oa);
+    P.get(mb, ob);
+    const double dx = ob[0] - oa[0], dy = ob[1] - oa[1], dz = ob[2] - oa[2];
+    return __builtin_sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// Perfect merger of members ma, mb at state z (in place): the survivor (the
+// more massive, the lower body index for equal masses) takes the mass-weighted
+// position and velocity, the summed mass and the radius (R_a^3 + R_b^3)^(1/3);
+// the absorbed body becomes a massless, sizeless ghost at rest at
+// (1e6 + index, 0, 0); one record (survivor, absorbed, lost energy
+// 1/2 m_a m_b / (m_a + m_b) |v_a - v_b|^2 - G m_a m_b / r).
+template <class Pol>
+__device__ void bs_merge(const BsDev &a, Pol &P, double z[6], int ma, int mb)
+{
+    P.publish(z);
+    double ya[6], yb[6];
+    P.get(ma, ya);
+    P.get(mb, yb);
+    const double m1 = P.mass(ma), m2 = P.mass(mb), R1 = P.rad(ma), R2 = P.rad(mb);
+    const int i1 = P.idx(ma), i2 = P.idx(mb);
+    const bool first = m1 > m2 || (m1 == m2 && i1 < i2);
+    const int ms = first ? ma : mb, mg = first ? mb : ma;
+    const double M = m1 + m2;
+    const int u = P.self();
+    if (u == ms) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) z[c] = (m1 * ya[c] + m2 * yb[c]) / M;
+        P.set_own(M, cbrt(R1 * R1 * R1 + R2 * R2 * R2));
+        double dv2 = 0.0, dx2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            dx2 += (ya[c] - yb[c]) * (ya[c] - yb[c]);
+            dv2 += (ya[c + 3] - yb[c + 3]) * (ya[c + 3] - yb[c + 3]);
+        }
+        const double du = 0.5 * m1 * m2 / M * dv2 - a.G * m1 * m2 / __builtin_sqrt(dx2);
+        const unsigned long long slot = atomicAdd(a.coll_count, 1ull);
+        if ((int64_t)slot < a.coll_cap) {
+            a.coll_i[slot] = first ? i1 : i2;
+            a.coll_j[slot] = first ? i2 : i1;
+            a.coll_du[slot] = du;
+        }
+    } else if (u == mg) {
+        z[0] = 1e6 + (double)(first ? i2 : i1);
+        z[1] = z[2] = z[3] = z[4] = z[5] = 0.0;
+        P.set_own(0.0, 0.0);
+    }
+}
+
 // One group's flow over H from y (in place); returns true if it failed.
-// The extrapolation tableau is kept row by row in T (Neville's update in
-// place), and the loop over the sequence is unrolled so that T stays in
-// registers.
+// With radii, each accepted step is searched for an overlapping pair; the
+// contact is bisected on the step length until the overlap is below
+// coll_tol of R_a + R_b, the pair merges there, and the flow continues from
+// that time.
 template <class Pol>
 __device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
 {
@@ -750,76 +1005,40 @@ __device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
     while (tt < a.H) {      // uniform over the group: every member holds the same tt, h
         const bool last = h >= a.H - tt;
         if (last) h = a.H - tt;
-        double f0[6];
-        P.deriv(a, y, f0);
-        const double sx = __builtin_sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) +
-                          h * __builtin_sqrt(f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2]);
-        const double sv = __builtin_sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]) +
-                          h * __builtin_sqrt(f0[3] * f0[3] + f0[4] * f0[4] + f0[5] * f0[5]);
-        double T[KM][6];
-        int kdone = -1;
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int nk = 2 * (k + 1);
-            const double hh = h / nk;
-            double z0[6], z1[6], fz[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                z0[c] = y[c];
-                z1[c] = y[c] + hh * f0[c];
-            }
-#pragma unroll 1
-            for (int q = 1; q < nk; ++q) {
-                P.deriv(a, z1, fz);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    const double z2 = z0[c] + 2.0 * hh * fz[c];
-                    z0[c] = z1[c];
-                    z1[c] = z2;
-                }
-            }
-            P.deriv(a, z1, fz);
-            // row k of the tableau: T[0] = the midpoint result, T[j] from
-            // T[j - 1] (this row) and the previous row's T[j - 1]
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                double old = T[0][c];
-                T[0][c] = 0.5 * (z0[c] + z1[c] + hh * fz[c]);
-#pragma unroll
-                for (int j = 1; j <= k; ++j) {
-                    const double ratio = (double)nk / (double)(nk - 2 * j);
-                    const double den = ratio * ratio - 1.0;
-                    const double oj = T[j][c];
-                    T[j][c] = T[j - 1][c] + (T[j - 1][c] - old) / den;
-                    old = oj;
-                }
-            }
-            if (k > 0) {
-                double err = 0.0;
-                if (P.member()) {
-                    double ex = 0.0, ev = 0.0;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double dxc = fabs(T[k][c] - T[k - 1][c]);
-                        const double dvc = fabs(T[k][c + 3] - T[k - 1][c + 3]);
-                        ex = dxc > ex ? dxc : ex;
-                        ev = dvc > ev ? dvc : ev;
-                    }
-                    const double e1 = ex / (sx + 1e-300), e2 = ev / (sv + 1e-300);
-                    err = e1 > e2 ? e1 : e2;
-                }
-                err = P.gmax(err);
-                if (err <= a.eps) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) y[c] = T[k][c];
-                    kdone = k;
-                    break;
-                }
-            }
-        }
+        double yn[6];
+        const int kdone = bs_step(a, P, y, h, yn);
         if (kdone >= 0) {
-            tt = last ? a.H : tt + h;
-            if (kdone < KM / 2) h *= 2.0;
+            const int key = a.radius ? bs_overlap(a, P, yn) : INT_MAX;
+            if (key != INT_MAX) {
+                const int ma = key / 1024, mb = key % 1024;
+                const double rs = P.rad(ma) + P.rad(mb);
+                double lo = 0.0, hi = h;
+                double yh[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) yh[c] = yn[c];
+                for (int it = 0; it < 60; ++it) {
+                    if ((rs - bs_sep(P, yh, ma, mb)) / rs < a.coll_tol) break;
+                    const double mid = 0.5 * (lo + hi);
+                    double ym[6];
+                    bs_step(a, P, y, mid, ym);
+                    if (bs_sep(P, ym, ma, mb) < rs) {
+                        hi = mid;
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) yh[c] = ym[c];
+                    } else {
+                        lo = mid;
+                    }
+                }
+                bs_merge(a, P, yh, ma, mb);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) y[c] = yh[c];
+                tt = (last && hi == h) ? a.H : tt + hi;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) y[c] = yn[c];
+                tt = last ? a.H : tt + h;
+                if (kdone < KM / 2) h *= 2.0;
+            }
         } else {
             h *= 0.5;
         }
@@ -859,18 +1078,28 @@ __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
         P.u = u;
         P.g = g;
         P.m = 0.0;
+        P.R = 0.0;
+        for (int c = 0; c < 6; ++c) P.zc[c] = 0.0;
         for (int l = 0; l < GENGA_MAX_LEVELS; ++l) P.rc[l] = 0.0;
         const int32_t b = u < g ? a.gmem[a.gstart[root] + u] : 0;
+        P.bidx = b;
         double y[6] = {0, 0, 0, 0, 0, 0};
         if (u < g) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
             P.m = a.m[b];
+            P.R = a.radius ? a.radius[b] : 0.0;
             for (int l = 0; l < a.nlev; ++l) P.rc[l] = a.rc[l][b];
         }
         const bool failed = bs_run(a, P, y);
         if (failed && u == 0) atomicOr(a.status, ST_NOCONV);
-        if (u < g) bs_store(a, b, y);
+        if (u < g) {
+            bs_store(a, b, y);
+            if (a.radius) {
+                a.m[b] = P.m;
+                a.radius[b] = P.R;
+            }
+        }
     }
 }
 
@@ -900,12 +1129,20 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
 #pragma unroll
             for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
             sm.m[t] = a.m[b];
+            sm.R[t] = a.radius ? a.radius[b] : 0.0;
+            sm.idx[t] = b;
             for (int l = 0; l < a.nlev; ++l) sm.rc[l][t] = a.rc[l][b];
         }
         BlockPol<BT> P{sm, t, g};
         const bool failed = bs_run(a, P, y);
         if (failed && t == 0) atomicOr(a.status, ST_NOCONV);
-        if (t < g) bs_store(a, b, y);
+        if (t < g) {
+            bs_store(a, b, y);
+            if (a.radius) {
+                a.m[b] = sm.m[t];
+                a.radius[b] = sm.R[t];
+            }
+        }
         __syncthreads();   // LDS reuse by the next group
     }
 }
@@ -1034,6 +1271,13 @@ static hipError_t direct_solve(const LevelRun &R, int l, double dt_l)
     a.eps = R.p->bs_eps > 0.0 ? R.p->bs_eps : 1e-12;
     a.status = R.status();
     a.gstats = R.at<unsigned long long>(V.gstats);
+    a.radius = R.b->R;
+    a.coll_tol = R.p->coll_tol > 0.0 ? R.p->coll_tol : 1e-6;
+    a.coll_i = R.at<int32_t>(V.coll_i);
+    a.coll_j = R.at<int32_t>(V.coll_j);
+    a.coll_du = R.at<double>(V.coll_du);
+    a.coll_count = R.at<unsigned long long>(V.coll_count);
+    a.coll_cap = LEVEL_COLL_CAP;
     hipLaunchKernelGGL(k_bs_lanes<BS_GS>, dim3(LG), dim3(LT), 0, R.s, a);
     hipLaunchKernelGGL(k_bs<64>, dim3(LG), dim3(64), 0, R.s, a, BS_GS);
     hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG), dim3(GENGA_GROUP_MAX), 0, R.s, a, 64);
@@ -1141,6 +1385,10 @@ LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base)
         V.gmem = take(sizeof(int32_t) * (size_t)n);
         V.gcount = take(sizeof(int32_t) * 2);
         V.gstats = take(sizeof(int64_t) * 2);
+        V.coll_count = take(sizeof(int64_t));
+        V.coll_i = take(sizeof(int32_t) * LEVEL_COLL_CAP);
+        V.coll_j = take(sizeof(int32_t) * LEVEL_COLL_CAP);
+        V.coll_du = take(sizeof(double) * LEVEL_COLL_CAP);
         V.gtsum = take(sizeof(int64_t) * 2 * (size_t)((n + LT - 1) / LT));
     }
     V.total = off;
@@ -1163,7 +1411,8 @@ hipError_t levels_before_drift(const genga_bodies *b, const LevelLayout &V, geng
     LevelRun R{const_cast<genga_bodies *>(b), nullptr, &V, ws, s};
     const int64_t *cnt0 = R.at<int64_t>(V.cnt);
     hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(64), 0, s, R.at<int64_t>(V.lcount), V.L, cnt0,
-                       V.direct ? R.at<int64_t>(V.gstats) : nullptr);
+                       V.direct ? R.at<int64_t>(V.gstats) : nullptr,
+                       V.direct ? R.at<int64_t>(V.coll_count) : nullptr);
     if (out) {
         hipLaunchKernelGGL(k_copy_pairs, dim3(LG), dim3(LT), 0, s, R.at<int32_t>(V.pi[0]),
                            R.at<int32_t>(V.pj[0]), cnt0, V.cap, out->i, out->j, out->capacity,

@@ -35,7 +35,7 @@ _c_double_p = ctypes.c_void_p
 
 class Bodies(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in
-                                           ("x", "y", "z", "vx", "vy", "vz", "m", "rc")]
+                                           ("x", "y", "z", "vx", "vy", "vz", "m", "rc", "R")]
 
 
 class Params(ctypes.Structure):
@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
                 ("slevels", ctypes.c_int), ("n_massive", ctypes.c_int64),
                 ("substeps", ctypes.c_int), ("direct", ctypes.c_int),
                 ("level_capacity", ctypes.c_int64), ("bs_eps", ctypes.c_double),
-                ("c_light", ctypes.c_double)]
+                ("c_light", ctypes.c_double), ("coll_tol", ctypes.c_double)]
 
 
 class BatchC(ctypes.Structure):
@@ -95,6 +95,9 @@ SIGNATURES = {
                                       ctypes.c_void_p]),
     "genga_gr_kick": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_collisions": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "genga_group_stats": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "genga_level_counts": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(Params), ctypes.c_void_p,
@@ -205,6 +208,7 @@ class Config:
     direct: int = 0
     bs_eps: float = 0.0
     c_light: float = 0.0
+    coll_tol: float = 0.0
 
     def params(self) -> Params:
         p = Params(self.G, self.m_star, self.dt, self.n1, self.n2, self.precision, self.flags,
@@ -219,6 +223,7 @@ class Config:
         p.direct = self.direct
         p.bs_eps = self.bs_eps
         p.c_light = self.c_light
+        p.coll_tol = self.coll_tol
         return p
 
 
@@ -236,7 +241,8 @@ class State:
                 raise ValueError(f"{k} has {tensors[k].numel()} elements, expected {self.n}")
 
     @classmethod
-    def from_numpy(cls, d: dict, device="cuda:0", rc=None):
+    def from_numpy(cls, d: dict, device="cuda:0", rc=None, radius=None):
+        """radius: physical radii (enables collisions in the direct solver)."""
         t = {}
         for k in ("x", "y", "z", "vx", "vy", "vz", "m"):
             t[k] = torch.as_tensor(d[k], dtype=torch.float64).to(device).contiguous()
@@ -245,6 +251,8 @@ class State:
             t["rc"] = torch.zeros_like(t["x"])
         else:
             t["rc"] = torch.as_tensor(src, dtype=torch.float64).to(device).contiguous()
+        if radius is not None:
+            t["R"] = torch.as_tensor(radius, dtype=torch.float64).to(device).contiguous()
         return cls(t)
 
     def bodies(self) -> Bodies:
@@ -252,6 +260,7 @@ class State:
         b.n = self.n
         for k in self.KEYS:
             setattr(b, k, self.t[k].data_ptr())
+        b.R = self.t["R"].data_ptr() if "R" in self.t else None
         return b
 
     def numpy(self) -> dict:
@@ -380,6 +389,23 @@ def gr_kick(state: State, cfg: Config, ws: Workspace, h: float) -> None:
     _check(load().genga_gr_kick(ctypes.byref(b), ctypes.byref(p), ctypes.c_double(h),
                                 ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr())),
            "genga_gr_kick")
+
+
+def collisions(n: int, cfg: Config, ws: Workspace, cap: int = 4096):
+    """Mergers of the last step: (count, [(survivor, absorbed, lost energy), ...])
+    sorted by (survivor, absorbed)."""
+    import numpy as np
+    c = np.zeros(1, dtype=np.int64)
+    i = np.zeros(max(cap, 1), dtype=np.int32)
+    j = np.zeros(max(cap, 1), dtype=np.int32)
+    du = np.zeros(max(cap, 1), dtype=np.float64)
+    p = cfg.params()
+    _check(load().genga_collisions(n, ctypes.byref(p), ctypes.c_void_p(ws.ptr),
+                                   c.ctypes.data_as(ctypes.c_void_p), i.ctypes.data_as(ctypes.c_void_p),
+                                   j.ctypes.data_as(ctypes.c_void_p), du.ctypes.data_as(ctypes.c_void_p),
+                                   int(cap), ctypes.c_void_p(_stream_ptr())), "genga_collisions")
+    k = int(min(c[0], cap, 4096))
+    return int(c[0]), [(int(i[q]), int(j[q]), float(du[q])) for q in range(k)]
 
 
 def group_stats(n: int, cfg: Config, ws: Workspace):

@@ -15,9 +15,10 @@ from paper_2201_10058_amd import workload as W
 G = W.GAUSS_G
 
 
-def two_bodies(m0=1e-9, m1=1e-9, R=1e-5, gap=1e-4, dv=1e-4):
+def two_bodies(m0=1e-9, m1=1e-9, R=1e-5, gap=1e-4, dv=1e-4, offset=0.0):
+    """offset: radial offset of body 1 (an impact parameter)."""
     v = np.sqrt(G / 1.0)
-    st = {"x": np.array([1.0, 1.0]), "y": np.array([0.0, -gap]), "z": np.array([0.0, 0.0]),
+    st = {"x": np.array([1.0, 1.0 + offset]), "y": np.array([0.0, -gap]), "z": np.array([0.0, 0.0]),
           "vx": np.array([0.0, 0.0]), "vy": np.array([v, v + dv]), "vz": np.array([0.0, 0.0]),
           "m": np.array([m0, m1]), "R": np.array([R, R])}
     return st

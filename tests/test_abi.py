@@ -105,6 +105,12 @@ def test_level_params_on_host():
         p = native.Config(G=2.959e-4, **kw).params()
         assert lib.genga_step(ctypes.byref(b), ctypes.byref(p), None, fake, None) == native.E_INVAL
     assert lib.genga_strerror(native.E_GROUP).decode().startswith("close-encounter group")
+    bad_tol = native.Config(G=2.959e-4, coll_tol=1.5).params()
+    assert lib.genga_step(ctypes.byref(b), ctypes.byref(bad_tol), None, fake, None) == native.E_INVAL
+    cnt = (ctypes.c_int64 * 1)()
+    plain = native.Config(G=2.959e-4, slevels=2, substeps=2, level_capacity=64).params()
+    assert lib.genga_collisions(10, ctypes.byref(plain), fake, cnt, None, None, None, 0,
+                                None) == native.E_INVAL
     neg_c = native.Config(G=2.959e-4, c_light=-1.0).params()
     assert lib.genga_step(ctypes.byref(b), ctypes.byref(neg_c), None, fake, None) == native.E_INVAL
     no_c = native.Config(G=2.959e-4).params()
