@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--n", type=int, default=65536, help="bodies (default: the 65,536-body disk)")
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--slices", type=int, default=0)
+    ap.add_argument("--kick-form", choices=("auto", "symmetric", "one-sided"), default="auto",
+                    help="binary64 kick form (auto: symmetric from 16,384 bodies)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target duration of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -59,7 +61,7 @@ def parse():
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KICK_SOURCES = ("kick.hip", "device_common.h", "genga_internal.h")
+KICK_SOURCES = ("kick.hip", "kick_sym.hip", "device_common.h", "genga_internal.h")
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_kick_fp64_disk65536_traffic.txt")
 
 
@@ -542,11 +544,15 @@ def main():
     G = d["G"]
     hip = HipEvents()
 
-    def run(precision):
+    form_flags = {"auto": 0, "symmetric": N.FLAG_SYMMETRIC, "one-sided": N.FLAG_DIRECTED}
+    sym = args.kick_form == "symmetric" or (args.kick_form == "auto" and n >= 16384)
+
+    def run(precision, form=None):
         """Warm up, then time `steps` base steps; returns the measurements."""
         st = N.State.from_numpy(d)
+        flags = N.FLAG_NOSYNC | form_flags[form or args.kick_form]
         cfg = N.Config(G=G, m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
-                       precision=precision, flags=N.FLAG_NOSYNC, ipt=args.ipt, slices=args.slices)
+                       precision=precision, flags=flags, ipt=args.ipt, slices=args.slices)
         ws = N.Workspace(n, cfg)
         pairs = N.PairList(max(1 << 20, 8 * n))
         for _ in range(args.warmup):
@@ -581,6 +587,12 @@ def main():
     r64 = run(N.FP64)
     print(f"fp64 step done: {r64['elapsed'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
+    r1s = None
+    if sym:
+        # the one-sided binary64 kick on the same workload, for comparison
+        r1s = run(N.FP64, "one-sided")
+        print(f"one-sided fp64 step done: {r1s['elapsed'] / args.steps * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
     r32 = None
     if not args.no_mixed:
         r32 = run(N.MIXED)
@@ -613,11 +625,22 @@ def main():
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic(),
-                     "kernel": "k_kick<256,1,KM_F64>", "kernel_ms": round(r64["kick_s"] * 1e3, 4),
+                     "kernel": "k_kick_sym" if sym else "k_kick<256,1,KM_F64>",
+                     "kernel_ms": round(r64["kick_s"] * 1e3, 4),
                      "kernel_ms_median": round(r64["kick_ms_median"], 4),
                      "kernel_ms_min": round(r64["kick_ms_min"], 4),
                      "flop_per_interaction": FLOP_PER_INTERACTION},
     }
+    out["config"]["kick_form"] = "symmetric" if sym else "one-sided"
+    if r1s:
+        a1s = FLOP_PER_INTERACTION * n * (n - 1) / r1s["kick_s"] / 1e12
+        out["one_sided"] = {"value": round(inter_step * args.steps / r1s["elapsed"] / 1e9, 3),
+                            "unit": "Ginter/s",
+                            "ms_per_step": round(r1s["elapsed"] / args.steps * 1e3, 4),
+                            "kernel": "k_kick<256,1,KM_F64>",
+                            "kernel_ms": round(r1s["kick_s"] * 1e3, 4),
+                            "frac": round(a1s / FP64_VECTOR_PEAK_TFLOPS, 4),
+                            "same_pairs": r1s["pairs_sha256"] == r64["pairs_sha256"]}
     if r32:
         out["mixed"] = {"value": round(value32, 3), "unit": "Ginter/s",
                         "ms_per_step": round(r32["elapsed"] / args.steps * 1e3, 4),

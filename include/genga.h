@@ -71,6 +71,18 @@ extern "C" {
 
 /* genga_params.flags */
 #define GENGA_FLAG_NOSYNC 1 /* genga_step: do not synchronise nor read the status     */
+/* Form of the binary64 single-system kick (Newton's third law, Sect. 2: the
+ * pair force and its changeover weight K(r_ij; max(rc_i, rc_j)) are symmetric
+ * in i and j).  The symmetric form evaluates each unordered pair once and
+ * applies it to both bodies; the one-sided form evaluates every ordered pair
+ * for its first body.  Both give the same encounter list (bit for bit) and
+ * accelerations that differ by summation order only.  By default the
+ * symmetric form runs from n >= 16384 bodies in the binary64 all-massive
+ * kick (genga_kick, genga_step and the levels' base kick); the flags force
+ * one form at any n (both set: GENGA_E_INVAL).  Test-particle modes, the
+ * mixed precision, the batch and genga_encounter_pairs are one-sided. */
+#define GENGA_FLAG_DIRECTED  2
+#define GENGA_FLAG_SYMMETRIC 4
 
 /* Bodies of one system, democratic coordinates, device SoA of length n.
  * rc holds the critical radii r_crit,i (eq. rcrit); genga_rcrit writes it.    */

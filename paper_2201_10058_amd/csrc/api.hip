@@ -40,6 +40,7 @@ static int check_params(const genga_params *p)
     if (p->n1 < 0.0 || p->n2 < 0.0) return GENGA_E_INVAL;
     if (p->precision != GENGA_FP64 && p->precision != GENGA_MIXED) return GENGA_E_INVAL;
     if (p->ipt < 0 || p->ipt > 2 || p->slices < 0) return GENGA_E_INVAL;
+    if ((p->flags & GENGA_FLAG_DIRECTED) && (p->flags & GENGA_FLAG_SYMMETRIC)) return GENGA_E_INVAL;
     if (p->block < 0 || p->tile_cols < 0 || p->grid < 0) return GENGA_E_INVAL;
     if (p->tp_mode < 0 || p->tp_mode > 2 || p->n_massive < 0) return GENGA_E_INVAL;
     if (p->slevels < 0 || p->slevels > GENGA_MAX_LEVELS) return GENGA_E_INVAL;

@@ -33,6 +33,48 @@ struct TileDesc {
     int32_t sys;
 };
 
+// Symmetric binary64 kick of one system (each unordered pair evaluated once,
+// its force applied to both bodies).  Rows are cut into groups of SYM_RG (one
+// block of SYM_NW waves, SYM_IPT rows per lane); group g works on the columns
+// [g SYM_RG, n) in slices of W columns (W divides SYM_RG, d = SYM_RG / W of
+// them cover the group's own rows).  A tile is (group g, slice s), stored as
+// sid = tb(g) + s; launched as the d..ns(g)-1 slices of every group first,
+// then the d diagonal slices of every group.
+constexpr int SYM_NW = 8;
+constexpr int SYM_IPT = 2;
+constexpr int SYM_NT = SYM_NW * 64;
+constexpr int SYM_RG = SYM_NT * SYM_IPT;
+
+struct SymShape {
+    int64_t n = 0;
+    int64_t G = 0;       // row groups
+    int64_t S0 = 0;      // slices of group 0 (ceil(n / W))
+    int W = 0, d = 0;    // columns per slice, slices over a group's own rows
+    int64_t T = 0;       // tiles
+    int64_t tfull = 0;   // tiles off the diagonal (launched first)
+    // slices of group g, first storage tile of group g
+    __host__ __device__ int64_t ns(int64_t g) const { return S0 - g * d; }
+    __host__ __device__ int64_t tb(int64_t g) const { return g * S0 - d * ((g * (g - 1)) / 2); }
+    // column sums of group g: 3 rows of collen(g) doubles from 3 coloff(g)
+    __host__ __device__ int64_t collen(int64_t g) const { return n - g * SYM_RG; }
+    __host__ __device__ int64_t coloff(int64_t g) const
+    {
+        return g * n - (int64_t)SYM_RG * ((g * (g - 1)) / 2);
+    }
+    // tiles off the diagonal before group g
+    __host__ __device__ int64_t bf(int64_t g) const { return g * S0 - d * ((g * (g + 1)) / 2); }
+};
+SymShape sym_shape(int64_t n, int W);
+constexpr int64_t SYM_MIN_N = 16384;   // default: symmetric kick from this many bodies
+hipError_t launch_kick_sym(const SymShape &h, const double *x, const double *y, const double *z,
+                           const double *m, const double *rc, double *rowpart, double *colpart,
+                           int32_t *cnt, int32_t *stage, int32_t *wcount, int32_t *status,
+                           bool emit, hipStream_t s);
+hipError_t launch_scatter_sym(const SymShape &h, const double *x, const double *y,
+                              const double *z, const double *rc, const int32_t *cnt,
+                              const int32_t *stage, const int32_t *wcount, const int32_t *rowloc,
+                              const int64_t *boff, genga_pairs *pairs, hipStream_t s);
+
 // Launch shape of the kick.
 struct KickCfg {
     int nt = KB;              // threads per block (64 or 256)
@@ -56,6 +98,10 @@ struct KickCfg {
     int gx_m = 0, s_m = 0, gx_t = 0, s_t = 0;
     int64_t len_m = 0, len_t = 0;
     int64_t mpad = 0;
+    // binary64 forces of one system: the symmetric kick (sym.T > 0) instead
+    // of the one-sided tiles above
+    bool use_sym = false;
+    SymShape sym;
 };
 
 // Byte offsets of the workspace regions.

@@ -497,6 +497,9 @@ struct ReduceDev {
     int64_t hc_nb;
     double hc_h, hc_m_star;
     int pstride;                  // partial values per row and slice (3; mixed 4)
+    int sym;                      // symmetric kick: row sums per tile, then column sums
+    SymShape sh;
+    const double *colpart;
     double kappa2;                // mixed: square of the refinement threshold (else 0)
     int32_t *refine_list, *refine_cnt;
 };
@@ -536,8 +539,16 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     if (r.queue && i == 0) *r.queue = 0;
     int nsl = r.slices;
     if (r.tp) nsl = i < r.nm ? (r.m_folded ? 1 : r.s_m) : r.s_t;
-    const PartRows pr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, r.pstride, i);
-    const PartRows cr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, 1, i);
+    PartRows pr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, r.pstride, i);
+    PartRows cr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, 1, i);
+    const int64_t grp = i / SYM_RG;
+    if (r.sym) {
+        // the tiles of row i's group, slice by slice: [tile][3][SYM_RG]
+        nsl = (int)r.sh.ns(grp);
+        const size_t t0 = (size_t)r.sh.tb(grp);
+        pr = {t0 * 3 * SYM_RG - (size_t)grp * SYM_RG, (size_t)SYM_RG};
+        cr = {t0 * SYM_RG - (size_t)grp * SYM_RG, (size_t)SYM_RG};
+    }
     double h = r.h;
     if (valid && r.sysid) {
         const int sy = r.sysid[i];
@@ -549,6 +560,15 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             a3[c] = ordered_sum(r.part + pr.base + c * pr.stride + i, r.pstride * pr.stride, nsl);
+        }
+        if (r.sym) {
+            // then the column sums of the groups up to row i's, in group order
+            for (int64_t gg = 0; gg <= grp; ++gg) {
+                const double *cp = r.colpart + 3 * r.sh.coloff(gg) + (i - gg * SYM_RG);
+                const int64_t L = r.sh.collen(gg);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a3[c] += cp[c * L];
+            }
         }
         bool refine = false;
         if (r.kappa2 > 0.0) {
@@ -989,6 +1009,16 @@ __global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Symmetric kick: columns per slice, the widest (up to SYM_RG) that still
+// gives about 4096 tiles, so that row sums cost little HBM traffic while the
+// chip holds several rounds of tiles (measured at 65,536 bodies: 512).
+static int sym_width(int64_t n)
+{
+    int W = SYM_RG;
+    while (W > 64 && sym_shape(n, W).T < 4096) W /= 2;
+    return W;
+}
+
 KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
 {
     KickCfg c;
@@ -1050,6 +1080,16 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
         c.gy = 1;
     }
     c.nwaves = c.ntiles * (c.nt / 64);
+    // binary64 forces of one all-massive system: the symmetric kick from
+    // SYM_MIN_N bodies (or as the flags ask)
+    const int flags = p ? p->flags : 0;
+    const bool fp64 = !p || p->precision == GENGA_FP64;
+    const bool plain = !p || p->tp_mode == 0 || p->n_massive >= n;
+    if (fp64 && plain && !(flags & GENGA_FLAG_DIRECTED) &&
+        (n >= SYM_MIN_N || (flags & GENGA_FLAG_SYMMETRIC))) {
+        c.use_sym = true;
+        c.sym = sym_shape(n, sym_width(n));
+    }
     return c;
 }
 
@@ -1063,18 +1103,23 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     size_t off = 0;
     L.status = off;
     off += 256;
+    // the symmetric kick's row sums [T][3][SYM_RG] and column sums share the
+    // partial-sum region; its per-tile pair counts the count region
+    const size_t sym_part = c.use_sym ? 3 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G)) : 0;
+    const size_t sym_cnt = c.use_sym ? (size_t)c.sym.T * SYM_RG : 0;
+    const size_t nw = std::max<size_t>((size_t)c.nwaves, c.use_sym ? (size_t)c.sym.T * SYM_NW : 0);
     L.part = off;   // 3 values per row and slice for the kick, 5 for its adjoint
-    off = align256(off + sizeof(double) * 5 * (size_t)c.slices * L.npad);
+    off = align256(off + sizeof(double) * std::max(5 * (size_t)c.slices * L.npad, sym_part));
     L.cnt = off;
-    off = align256(off + sizeof(int32_t) * (size_t)c.slices * L.npad);
+    off = align256(off + sizeof(int32_t) * std::max((size_t)c.slices * L.npad, sym_cnt));
     L.rowloc = off;
     off = align256(off + sizeof(int32_t) * (size_t)L.npad);
     L.bsum = off;
     off = align256(off + sizeof(int64_t) * (size_t)(L.nb + 1));
     L.stage = off;
-    off = align256(off + sizeof(int32_t) * 3 * (size_t)WSEG * c.nwaves);
+    off = align256(off + sizeof(int32_t) * 3 * (size_t)WSEG * nw);
     L.wcount = off;
-    off = align256(off + sizeof(int32_t) * (size_t)c.nwaves);
+    off = align256(off + sizeof(int32_t) * nw);
     L.hc = off;
     off = align256(off + sizeof(double) * 3 * (size_t)L.nb);
     L.hc2 = off;
@@ -1177,11 +1222,17 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
 
     const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
     const bool refine = mode == KM_MIXED;
+    const bool sym = c.use_sym && mode == KM_F64 && !k.tiles && c.tp == 0;
     if (k.ev0) {
         hipError_t e0 = hipEventRecord((hipEvent_t)k.ev0, s);
         if (e0 != hipSuccess) return e0;
     }
-    if (c.ntiles == 0) {
+    if (sym) {
+        hipError_t es = launch_kick_sym(c.sym, k.x, k.y, k.z, k.m, k.rc, d.part,
+                                        d.part + (size_t)3 * c.sym.T * SYM_RG, d.cnt, d.stage,
+                                        d.wcount, d.status, d.emit, s);
+        if (es != hipSuccess) return es;
+    } else if (c.ntiles == 0) {
         // (test-particle mode without massive bodies: nothing acts on anything)
     } else if (c.nt == 64) {
         if (c.ipt == 2) launch_mode<64, 2>(d, c, mode, s);
@@ -1224,6 +1275,9 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.hc_h = k.hc_h;
     r.hc_m_star = k.hc_m_star;
     r.pstride = refine ? 4 : 3;
+    r.sym = sym ? 1 : 0;
+    r.sh = c.sym;
+    r.colpart = d.part + (size_t)3 * c.sym.T * SYM_RG;
     r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
     r.refine_list = (int32_t *)(ws + L.rlist);
     r.refine_cnt = d.refine_cnt;
@@ -1282,6 +1336,9 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
+    if (sym)
+        return launch_scatter_sym(c.sym, k.x, k.y, k.z, k.rc, d.cnt, d.stage, d.wcount, r.rowloc,
+                                  r.bsum, k.pairs, s);
     ScatterDev sd;
     sd.k = d;
     sd.rowloc = r.rowloc;

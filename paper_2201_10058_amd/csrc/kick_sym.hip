@@ -1,0 +1,549 @@
+// Symmetric changeover-weighted kick (binary64, one system, every body massive):
+// each unordered pair is evaluated once and its force applied to both bodies.
+//
+// Paper: GENGA II Sect. 2 (interaction part H_B of the democratic-heliocentric
+// splitting, eq. Hb, whose pair terms G m_i m_j K / r_ij are symmetric in i and
+// j when the pair's critical radius is max(rc_i, rc_j), eq. rcrit), Sect. 6.2
+// (changeover band 0.1 < r/r_crit < 1 with the form of Chambers 1999 eq. 10),
+// Appendix A (kick with the close-encounter pre-check), Appendix B (fixed
+// order of the encounter list).
+//
+// Design for gfx950 (wave64, 256 CUs, FP64 vector ALU bound):
+//  * Rows are cut into groups of SYM_RG = 1024: one block of 8 waves with 2
+//    rows per lane.  Group g works on the columns [g SYM_RG, n) -- its own rows
+//    and every row after them -- in slices of W columns; a tile is one slice.
+//  * A tile's columns are staged in LDS in chunks of 64, each stored twice in
+//    a row so that lane l reads entry l + k at step k without a wrap.  At step
+//    k (0..63) lane l takes column (l + k) mod 64: the 64 lanes of a wave meet
+//    64 different columns, and each lane carries the running sum of the
+//    column it is on.  After every step the three column sums move one lane
+//    down (v_mov_b32_dpp wave_rol:1, lane l receives lane l + 1), which hands
+//    each lane the sum of its next column; after 64 steps every sum is back
+//    in the lane of its column.  Per step and lane: 2 pairs of 21 FP64
+//    instructions and 6 moves cover 4 directed interactions (the one-sided
+//    kick spends 4 x 18).
+//  * Chunks over the group's own rows: a chunk after the lane's row chunk is
+//    done symmetrically, the row's own chunk one-sided (each lane sums all 64
+//    columns into its row only, self pair excluded), a chunk before it not at
+//    all: those pairs are transposes of pairs done symmetrically.
+//  * The 8 waves' column sums of a chunk are added in LDS in wave order and
+//    written once per (group, column); row sums once per (tile, row).
+//    k_kick_reduce adds a row's tile sums in slice order, then its column
+//    sums in group order: no atomics, the same bits on every run.
+//  * Pairs inside the critical radius take a divergent rare path (K, the
+//    self pair, coincident bodies, encounter recording) as in the one-sided
+//    kick.  A lane meets its columns in rotated order, so a staged pair
+//    carries no rank; k_pairs_scatter_sym ranks it among the pairs of its row
+//    in the wave's staging segment, which hold all of that row's pairs of
+//    the tile, and the list comes out in canonical order (i, then j).
+#include "genga_internal.h"
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace genga {
+
+SymShape sym_shape(int64_t n, int W)
+{
+    SymShape h;
+    h.n = n;
+    h.W = W;
+    h.d = SYM_RG / W;
+    h.G = (n + SYM_RG - 1) / SYM_RG;
+    h.S0 = (n + W - 1) / W;
+    h.T = h.tb(h.G);
+    h.tfull = h.bf(h.G - 1);
+    return h;
+}
+
+struct SymDev {
+    const double *x, *y, *z, *m, *rc;
+    SymShape sh;
+    double *rowpart;   // [T][3][SYM_RG]
+    double *colpart;   // group g: [3][collen(g)] from 3 coloff(g)
+    int32_t *cnt;      // [T][SYM_RG]
+    int32_t *stage;    // [T SYM_NW][WSEG][3]  (i, j, unused)
+    int32_t *wcount;   // [T SYM_NW]
+    int32_t *status;
+    int emit;
+    double c53;        // 5/3
+};
+
+// Padding rows and columns sit far away, on opposite sides (no two padding
+// bodies coincide), with mass 0 and critical radius 0: r^2 stays finite (below
+// 1.3e201), every weight they give or take is 0 and they never reach the rare
+// path.
+constexpr double SYM_FAR_ROW = 1e100, SYM_FAR_COL = -1e100;
+
+// One chunk of 64 columns, stored twice (entries e and e + 64 are column e).
+struct SymCols {
+    double2 xy[128];
+    double2 zm[128];   // (z, 3/2 m)
+    double rc2[128];
+    double m[128];
+};
+
+struct SymSmem {
+    SymCols col[2];
+    double acc[2][3][SYM_NW][64];   // column sums of a chunk, per wave
+    int wcnt[SYM_NW];
+};
+
+struct SymRows {
+    double xi[SYM_IPT], yi[SYM_IPT], zi[SYM_IPT], rc2i[SYM_IPT];
+    double mpi[SYM_IPT];   // 3/2 m_i
+    double ax[SYM_IPT], ay[SYM_IPT], az[SYM_IPT];
+    int ii[SYM_IPT];       // row index, -1 for padding (n < 2^31)
+    int kc[SYM_IPT];
+};
+
+// Lane l receives lane (l + 1) mod 64's value.
+__device__ __forceinline__ double rotate_down(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x134, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Tile of launch index t: group g and slice s (s = -1: an empty diagonal slot
+// of the last group).
+__device__ __forceinline__ void sym_tile(const SymShape &h, int64_t t, int64_t &g, int64_t &s)
+{
+    if (t < h.tfull) {
+        // largest g with bf(g) <= t: root of d/2 g^2 - (S0 - d/2) g + t = 0
+        const double b = (double)h.S0 - 0.5 * h.d;
+        double r = b * b - 2.0 * h.d * (double)t;
+        r = r > 0.0 ? r : 0.0;
+        int64_t gg = (int64_t)((b - __builtin_sqrt(r)) / h.d);
+        gg = gg < 0 ? 0 : (gg > h.G - 2 ? h.G - 2 : gg);
+        while (gg > 0 && h.bf(gg) > t) --gg;
+        while (gg < h.G - 2 && h.bf(gg + 1) <= t) ++gg;
+        g = gg;
+        s = h.d + (t - h.bf(gg));
+        return;
+    }
+    const int64_t u = t - h.tfull;
+    g = u / h.d;
+    s = u % h.d;
+    if (s >= h.ns(g)) s = -1;
+}
+
+// Group of storage tile sid: largest g with tb(g) <= sid.
+__device__ __forceinline__ int64_t sym_group_of(const SymShape &h, int64_t sid)
+{
+    const double b = (double)h.S0 + 0.5 * h.d;
+    double r = b * b - 2.0 * h.d * (double)sid;
+    r = r > 0.0 ? r : 0.0;
+    int64_t g = (int64_t)((b - __builtin_sqrt(r)) / h.d);
+    g = g < 0 ? 0 : (g > h.G - 1 ? h.G - 1 : g);
+    while (g > 0 && h.tb(g) > sid) --g;
+    while (g < h.G - 1 && h.tb(g + 1) <= sid) ++g;
+    return g;
+}
+
+// Rare path of one pair (r^2 <= max(rc_i^2, rc_j^2)): the self pair, coincident
+// bodies, the changeover band and encounter recording.  si, sj hold the fast
+// weights (m_j and m_i times r^-3) and are replaced by K-weighted ones inside
+// rho_ij; a pair exactly at rho_ij keeps them (K = 1).  1/r and 1/rho from
+// v_rsq_f64 with one Newton correction (relative error below 5e-15), so the
+// band variable is y = (r/rho) / 0.9 - 1/9; m_i = (2/3) (3/2 m_i) to 2 ulp.
+// Whether a pair is inside rho_ij, and so in the encounter list, is decided by
+// r^2 < max(rc_i^2, rc_j^2) alone.
+__device__ __forceinline__ double rsq_nr(double v)
+{
+    const double y = __builtin_amdgcn_rsq(v);
+    const double e = __builtin_fma(-v, y * y, 1.0);
+    return __builtin_fma(y * e, 0.5, y);
+}
+
+__device__ __forceinline__ void sym_slow(const SymDev &a, SymRows &R, int q, int jg, double r2,
+                                         double rc2c, double mc, double &si, double &sj,
+                                         int64_t wave_g, int *wcnt)
+{
+    bool emit = false;
+    if (jg == R.ii[q]) {
+        si = 0.0;
+        sj = 0.0;
+    } else if (r2 == 0.0) {
+        atomicOr(a.status, ST_NONFINITE);
+        si = 0.0;
+        sj = 0.0;
+    } else {
+        const double rho2 = R.rc2i[q] > rc2c ? R.rc2i[q] : rc2c;
+        const bool inside = r2 < rho2;
+        emit = inside && jg > R.ii[q];
+        if (inside) {
+            const double yc = rsq_nr(r2);
+            const double irho = rsq_nr(rho2);
+            const double K = changeover_of_y(__builtin_fma((r2 * yc) * irho, 1.0 / 0.9, -1.0 / 9.0));
+            const double kr = K * (yc * yc * yc);
+            si = mc * kr;
+            sj = (R.mpi[q] * (2.0 / 3.0)) * kr;
+        }
+    }
+    if (a.emit) {
+        const uint64_t mask = __ballot(emit);
+        if (mask != 0ull) {
+            const int base = __hip_atomic_load(wcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            if (emit) {
+                const int pos = base + __popcll(mask & lanemask_lt());
+                if (pos < WSEG) {
+                    int32_t *e3 = a.stage + ((size_t)wave_g * WSEG + pos) * 3;
+                    e3[0] = R.ii[q];
+                    e3[1] = jg;
+                    e3[2] = 0;
+                }
+                R.kc[q] += 1;
+            }
+            const uint64_t act = __ballot(1);
+            if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1)
+                __hip_atomic_store(wcnt, base + __popcll(mask), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+    }
+}
+
+// One chunk of 64 columns against the lane's rows.  GEN = false: every row
+// pairs symmetrically.  GEN = true (chunks over the group's own rows): mode[q]
+// is 2 (symmetric), 1 (one-sided: the row's own chunk) or 0 (skip), uniform
+// over the wave.  m r^-3 as in the one-sided kick: v_rsq_f64 (relative error
+// below 2^-24) with its first-order correction, (3/2 m) y^3 (5/3 - r^2 y^2).
+template <bool GEN>
+__device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows &R, const SymCols &C,
+                                          int colbase, const int *mode, double &cx,
+                                          double &cy, double &cz, double c53, int64_t wave_g,
+                                          int *wcnt, int lane)
+{
+    for (int k0 = 0; k0 < 64; k0 += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = lane + k0 + u;
+            const double2 p = C.xy[e];
+            const double2 zm = C.zm[e];
+            const double rc2c = C.rc2[e];
+#pragma unroll
+            for (int q = 0; q < SYM_IPT; ++q) {
+                if (GEN && mode[q] == 0) continue;
+                const double dx = p.x - R.xi[q];
+                const double dy = p.y - R.yi[q];
+                const double dz = zm.x - R.zi[q];
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                const bool cand = r2 <= vmax_f64(R.rc2i[q], rc2c);
+                const double yv = __builtin_amdgcn_rsq(r2);
+                const double y2 = yv * yv;
+                const double pp = __builtin_fma(-r2, y2, c53);
+                const double t = (y2 * yv) * pp;
+                double si = t * zm.y;
+                double sj = t * R.mpi[q];
+                if (cand) {
+                    // the column index only here: an empty volatile asm keeps the
+                    // compiler from computing it on the fast path
+                    int ee = lane;
+                    asm volatile("" : "+v"(ee));
+                    ee += k0 + u;
+                    sym_slow(a, R, q, colbase + (ee & 63), r2, rc2c, C.m[ee], si, sj, wave_g,
+                             wcnt);
+                }
+                R.ax[q] = __builtin_fma(dx, si, R.ax[q]);
+                R.ay[q] = __builtin_fma(dy, si, R.ay[q]);
+                R.az[q] = __builtin_fma(dz, si, R.az[q]);
+                if (!GEN || mode[q] == 2) {
+                    cx = __builtin_fma(-dx, sj, cx);
+                    cy = __builtin_fma(-dy, sj, cy);
+                    cz = __builtin_fma(-dz, sj, cz);
+                }
+            }
+            cx = rotate_down(cx);
+            cy = rotate_down(cy);
+            cz = rotate_down(cz);
+        }
+    }
+}
+
+// Column jg (or padding) into entries t and t + 64 of an LDS chunk.
+__device__ __forceinline__ void sym_put(SymCols &C, int t, bool real, double x, double y,
+                                        double z, double m, double rc)
+{
+    if (!real) {
+        x = y = z = SYM_FAR_COL;
+        m = 0.0;
+        rc = 0.0;
+    }
+    const double2 xy = make_double2(x, y), zm = make_double2(z, 1.5 * m);
+    const double rc2 = rc * rc;
+    C.xy[t] = xy;
+    C.xy[t + 64] = xy;
+    C.zm[t] = zm;
+    C.zm[t + 64] = zm;
+    C.rc2[t] = rc2;
+    C.rc2[t + 64] = rc2;
+    C.m[t] = m;
+    C.m[t + 64] = m;
+}
+
+// At most 128 VGPRs (4 waves per SIMD, 2 blocks per CU); the few values this
+// moves to scratch are reloaded once per chunk, not per step.
+__global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_kick_sym(
+    SymDev a)
+{
+    __shared__ SymSmem sm;
+    const SymShape &h = a.sh;
+    int64_t g, s;
+    sym_tile(h, blockIdx.x, g, s);
+    if (s < 0) return;   // (uniform over the block)
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int64_t n = h.n;
+    const int64_t row0 = g * SYM_RG;
+    const int64_t rowend = row0 + SYM_RG < n ? row0 + SYM_RG : n;
+    const int64_t col0 = row0 + s * h.W;
+    const int64_t col1 = col0 + h.W < n ? col0 + h.W : n;
+    const int nch = (int)((col1 - col0 + 63) / 64);
+    const int64_t sid = h.tb(g) + s;
+    const int64_t wave_g = sid * SYM_NW + w;
+    const bool diag = s < h.d;
+    const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+    const double c53 = a.c53 + (double)vzero;
+
+    SymRows R;
+    int64_t rch[SYM_IPT];   // global 64-row chunk of each row slot
+#pragma unroll
+    for (int q = 0; q < SYM_IPT; ++q) {
+        const int cq = q * SYM_NW + w;
+        const int64_t i = row0 + (int64_t)cq * 64 + lane;
+        rch[q] = (row0 >> 6) + cq;
+        R.ii[q] = i < rowend ? (int)i : -1;
+        double mi = 0.0;
+        if (i < rowend) {
+            R.xi[q] = a.x[i];
+            R.yi[q] = a.y[i];
+            R.zi[q] = a.z[i];
+            const double r = a.rc[i];
+            R.rc2i[q] = r * r;
+            mi = a.m[i];
+        } else {
+            R.xi[q] = R.yi[q] = R.zi[q] = SYM_FAR_ROW;
+            R.rc2i[q] = 0.0;
+        }
+        R.mpi[q] = 1.5 * mi;
+        R.ax[q] = R.ay[q] = R.az[q] = 0.0;
+        R.kc[q] = 0;
+    }
+    int *wcnt = &sm.wcnt[w];
+    if (lane == 0) __hip_atomic_store(wcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+
+    // chunk 0 by wave 0
+    if (w == 0) {
+        const int64_t jg = col0 + lane;
+        const bool real = jg < col1;
+        double x = 0, y = 0, z = 0, m = 0, rc = 0;
+        if (real) {
+            x = a.x[jg]; y = a.y[jg]; z = a.z[jg]; m = a.m[jg]; rc = a.rc[jg];
+            if (!(rc >= 0.0 && rc < INFINITY)) atomicOr(a.status, ST_RCRIT);
+        }
+        sym_put(sm.col[0], lane, real, x, y, z, m, rc);
+    }
+    __syncthreads();
+
+    const int64_t cc0 = col0 >> 6;
+    for (int kc = 0; kc < nch; ++kc) {
+        const int b = kc & 1;
+        const int64_t cc = cc0 + kc;
+        // column sums of the previous chunk, in wave order
+        if (kc > 0 && w == (kc - 1) % SYM_NW) {
+            const int64_t j = (cc - 1) * 64 + lane;
+            if (j < n) {
+                double *cp = a.colpart + 3 * h.coloff(g) + (j - row0);
+                const int64_t L = h.collen(g);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double t = sm.acc[b ^ 1][c][0][lane];
+#pragma unroll
+                    for (int v = 1; v < SYM_NW; ++v) t += sm.acc[b ^ 1][c][v][lane];
+                    cp[c * L] = t;
+                }
+            }
+        }
+        // next chunk into registers (loader wave)
+        const bool loader = kc + 1 < nch && w == (kc + 1) % SYM_NW;
+        double px = 0, py = 0, pz = 0, pm = 0, prc = 0;
+        bool preal = false;
+        if (loader) {
+            const int64_t jg = (cc + 1) * 64 + lane;
+            preal = jg < col1;
+            if (preal) {
+                px = a.x[jg]; py = a.y[jg]; pz = a.z[jg]; pm = a.m[jg]; prc = a.rc[jg];
+            }
+        }
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+        const SymCols &C = sm.col[b];
+        const int colbase = (int)(cc * 64);
+        bool full = !diag;
+        int mode[SYM_IPT] = {};
+        if (diag) {
+            full = true;
+#pragma unroll
+            for (int q = 0; q < SYM_IPT; ++q) {
+                mode[q] = cc > rch[q] ? 2 : (cc == rch[q] ? 1 : 0);
+                full = full && mode[q] == 2;
+            }
+        }
+        if (full)
+            sym_chunk<false>(a, R, C, colbase, mode, cx, cy, cz, c53, wave_g, wcnt, lane);
+        else
+            sym_chunk<true>(a, R, C, colbase, mode, cx, cy, cz, c53, wave_g, wcnt, lane);
+        sm.acc[b][0][w][lane] = cx;
+        sm.acc[b][1][w][lane] = cy;
+        sm.acc[b][2][w][lane] = cz;
+        if (loader) {
+            if (preal && !(prc >= 0.0 && prc < INFINITY)) atomicOr(a.status, ST_RCRIT);
+            sym_put(sm.col[b ^ 1], lane, preal, px, py, pz, pm, prc);
+        }
+        __syncthreads();
+    }
+    if (w == (nch - 1) % SYM_NW) {
+        const int64_t j = (cc0 + nch - 1) * 64 + lane;
+        if (j < n) {
+            double *cp = a.colpart + 3 * h.coloff(g) + (j - row0);
+            const int64_t L = h.collen(g);
+            const int b = (nch - 1) & 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double t = sm.acc[b][c][0][lane];
+#pragma unroll
+                for (int v = 1; v < SYM_NW; ++v) t += sm.acc[b][c][v][lane];
+                cp[c * L] = t;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < SYM_IPT; ++q) {
+        if (R.ii[q] < 0) continue;
+        const int64_t off = R.ii[q] - row0;
+        double *p = a.rowpart + (size_t)sid * 3 * SYM_RG + off;
+        p[0] = R.ax[q];
+        p[SYM_RG] = R.ay[q];
+        p[2 * SYM_RG] = R.az[q];
+        if (a.emit) a.cnt[(size_t)sid * SYM_RG + off] = R.kc[q];
+    }
+    if (a.emit && lane == 0)
+        a.wcount[wave_g] = __hip_atomic_load(wcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Place the staged pairs of the symmetric kick (one wave of 64 threads per
+// kick wave).  Rank of a pair inside its (row, tile): the number of pairs of
+// the same row with a smaller j in the wave's segment.  A wave whose segment
+// overflowed is recomputed over its rows and the tile's columns, j ascending.
+struct SymScatterDev {
+    SymShape sh;
+    const double *x, *y, *z, *rc;
+    const int32_t *cnt, *stage, *wcount;
+    const int32_t *rowloc;
+    const int64_t *boff;
+    int32_t *pi, *pj;
+    int64_t capacity;
+};
+
+__global__ __launch_bounds__(64) void k_pairs_scatter_sym(SymScatterDev d)
+{
+    __shared__ int32_t si_[WSEG], sj_[WSEG];
+    const int lane = threadIdx.x;
+    const SymShape &h = d.sh;
+    const int64_t wave_g = blockIdx.x;
+    const int64_t sid = wave_g / SYM_NW;
+    const int w = (int)(wave_g % SYM_NW);
+    const int64_t g = sym_group_of(h, sid);
+    const int64_t s = sid - h.tb(g);
+    const int64_t row0 = g * SYM_RG;
+    const int nst = d.wcount[wave_g];
+    if (nst <= WSEG) {
+        for (int e = lane; e < nst; e += 64) {
+            const int32_t *e3 = d.stage + ((size_t)wave_g * WSEG + e) * 3;
+            si_[e] = e3[0];
+            sj_[e] = e3[1];
+        }
+        __syncthreads();
+        for (int e = lane; e < nst; e += 64) {
+            const int32_t i = si_[e], j = sj_[e];
+            int rank = 0;
+            for (int f = 0; f < nst; ++f) rank += (si_[f] == i && sj_[f] < j) ? 1 : 0;
+            const int64_t pos = d.boff[i / RB] + d.rowloc[i] +
+                                d.cnt[(size_t)sid * SYM_RG + (i - row0)] + rank;
+            if (pos < d.capacity) {
+                d.pi[pos] = i;
+                d.pj[pos] = j;
+            }
+        }
+        return;
+    }
+    const int64_t n = h.n;
+    const int64_t rowend = row0 + SYM_RG < n ? row0 + SYM_RG : n;
+    const int64_t col0 = row0 + s * h.W;
+    const int64_t col1 = col0 + h.W < n ? col0 + h.W : n;
+    for (int q = 0; q < SYM_IPT; ++q) {
+        const int64_t i = row0 + (int64_t)(q * SYM_NW + w) * 64 + lane;
+        if (i >= rowend) continue;
+        int64_t pos = d.boff[i / RB] + d.rowloc[i] + d.cnt[(size_t)sid * SYM_RG + (i - row0)];
+        const double xi = d.x[i], yi = d.y[i], zi = d.z[i];
+        const double rci = d.rc[i];
+        const double rc2i = rci * rci;
+        for (int64_t j = (col0 > i + 1 ? col0 : i + 1); j < col1; ++j) {
+            const double dx = d.x[j] - xi, dy = d.y[j] - yi, dz = d.z[j] - zi;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double rcj = d.rc[j];
+            const double rc2j = rcj * rcj;
+            const double rho2 = rc2i > rc2j ? rc2i : rc2j;
+            if (r2 < rho2) {
+                if (pos < d.capacity) {
+                    d.pi[pos] = (int32_t)i;
+                    d.pj[pos] = (int32_t)j;
+                }
+                ++pos;
+            }
+        }
+    }
+}
+
+hipError_t launch_kick_sym(const SymShape &h, const double *x, const double *y, const double *z,
+                           const double *m, const double *rc, double *rowpart, double *colpart,
+                           int32_t *cnt, int32_t *stage, int32_t *wcount, int32_t *status,
+                           bool emit, hipStream_t s)
+{
+    SymDev a;
+    a.x = x; a.y = y; a.z = z; a.m = m; a.rc = rc;
+    a.sh = h;
+    a.rowpart = rowpart;
+    a.colpart = colpart;
+    a.cnt = cnt;
+    a.stage = stage;
+    a.wcount = wcount;
+    a.status = status;
+    a.emit = emit ? 1 : 0;
+    a.c53 = 5.0 / 3.0;
+    const int64_t blocks = h.tfull + h.G * h.d;
+    hipLaunchKernelGGL(k_kick_sym, dim3((unsigned)blocks), dim3(SYM_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_sym(const SymShape &h, const double *x, const double *y,
+                              const double *z, const double *rc, const int32_t *cnt,
+                              const int32_t *stage, const int32_t *wcount, const int32_t *rowloc,
+                              const int64_t *boff, genga_pairs *pairs, hipStream_t s)
+{
+    SymScatterDev d;
+    d.sh = h;
+    d.x = x; d.y = y; d.z = z; d.rc = rc;
+    d.cnt = cnt;
+    d.stage = stage;
+    d.wcount = wcount;
+    d.rowloc = rowloc;
+    d.boff = boff;
+    d.pi = pairs->i;
+    d.pj = pairs->j;
+    d.capacity = pairs->capacity;
+    hipLaunchKernelGGL(k_pairs_scatter_sym, dim3((unsigned)(h.T * SYM_NW)), dim3(64), 0, s, d);
+    return hipGetLastError();
+}
+
+}  // namespace genga

@@ -29,6 +29,8 @@ E_GROUP = -8
 FP64 = 0
 MIXED = 1
 FLAG_NOSYNC = 1
+FLAG_DIRECTED = 2     # binary64 kick: one-sided form at any n
+FLAG_SYMMETRIC = 4    # binary64 kick: symmetric form at any n
 
 _c_double_p = ctypes.c_void_p
 

@@ -278,12 +278,13 @@ def test_step_matches_oracle_and_pairs_per_step(dev):
 # ---------------------------------------------------------------------------
 # Full size (65,536 bodies): sampled rows against the oracle, full pair list
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("ipt", [1, 2])
-def test_kick_disk65536_sampled(dev, ipt):
+@pytest.mark.parametrize("ipt,flags", [(1, N.FLAG_DIRECTED), (2, N.FLAG_DIRECTED), (0, 0)])
+def test_kick_disk65536_sampled(dev, ipt, flags):
+    # one-sided form with 1 and 2 rows per lane, and the default (symmetric)
     d = W.make_disk(W.DISK_65536)
     rc = _disk_rc(d)
-    _say("kick disk65536 ipt", ipt)
-    a, (pi, pj, cnt), code, _ = _run_kick(d, rc, N.Config(G=G, ipt=ipt))
+    _say("kick disk65536 ipt", ipt, "flags", flags)
+    a, (pi, pj, cnt), code, _ = _run_kick(d, rc, N.Config(G=G, ipt=ipt, flags=flags))
     assert code == N.OK
     rng = np.random.default_rng(7)
     rows = np.sort(rng.choice(d["n"], 384, replace=False))
