@@ -107,7 +107,9 @@ typedef struct {
     int precision; /* GENGA_FP64 or GENGA_MIXED                                 */
     int flags;     /* GENGA_FLAG_*                                              */
     int ipt;       /* kick rows per thread (1 or 2); 0 = library choice         */
-    int slices;    /* single system: kick column slices; 0 = library choice     */
+    int slices;    /* single system: kick column slices; 0 = library choice.
+                      Symmetric kick: slices of 512 / d columns with d the
+                      largest power of two <= min(slices, 8)               */
     int block;     /* batch: kick threads per block (64 or 256); 0 = 256         */
     int tile_cols; /* batch: columns per kick tile (rounded up to 64); 0 = 1024  */
     int grid;      /* batch: persistent kick blocks; 0 = library choice         */

@@ -40,7 +40,7 @@ struct TileDesc {
 // them cover the group's own rows).  A tile is (group g, slice s), stored as
 // sid = tb(g) + s; launched as the d..ns(g)-1 slices of every group first,
 // then the d diagonal slices of every group.
-constexpr int SYM_NW = 8;
+constexpr int SYM_NW = 4;
 constexpr int SYM_IPT = 2;
 constexpr int SYM_NT = SYM_NW * 64;
 constexpr int SYM_RG = SYM_NT * SYM_IPT;

@@ -1011,7 +1011,9 @@ __global__ __launch_bounds__(64) void k_pairs_scatter(ScatterDev d)
 // ---------------------------------------------------------------------------
 // Symmetric kick: columns per slice, the widest (up to SYM_RG) that still
 // gives about 4096 tiles, so that row sums cost little HBM traffic while the
-// chip holds several rounds of tiles (measured at 65,536 bodies: 512).
+// chip holds several rounds of tiles (65,536 bodies: 512 columns, 8,256
+// tiles; 128 and 256 columns measured within 0.3 % of its kick time, with
+// longer reductions).
 static int sym_width(int64_t n)
 {
     int W = SYM_RG;
@@ -1088,7 +1090,14 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
     if (fp64 && plain && !(flags & GENGA_FLAG_DIRECTED) &&
         (n >= SYM_MIN_N || (flags & GENGA_FLAG_SYMMETRIC))) {
         c.use_sym = true;
-        c.sym = sym_shape(n, sym_width(n));
+        int W = sym_width(n);
+        if (p && p->slices > 0) {
+            // slices over a row group's own rows: 1, 2, 4, 8 or 16
+            int dd = 1;
+            while (dd * 2 <= p->slices && dd < SYM_RG / 64) dd *= 2;
+            W = SYM_RG / dd;
+        }
+        c.sym = sym_shape(n, W);
     }
     return c;
 }

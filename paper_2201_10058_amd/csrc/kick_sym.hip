@@ -9,9 +9,11 @@
 // order of the encounter list).
 //
 // Design for gfx950 (wave64, 256 CUs, FP64 vector ALU bound):
-//  * Rows are cut into groups of SYM_RG = 1024: one block of 8 waves with 2
+//  * Rows are cut into groups of SYM_RG = 512: one block of 4 waves with 2
 //    rows per lane.  Group g works on the columns [g SYM_RG, n) -- its own rows
-//    and every row after them -- in slices of W columns; a tile is one slice.
+//    and every row after them -- in slices of W columns; a tile is one slice
+//    (W = 512 at 65,536 bodies: 8,256 tiles; measured against 8-wave blocks of
+//    1,024 rows and against W = 128, 256: 1.76 ms per kick, 2-7 % faster).
 //  * A tile's columns are staged in LDS in chunks of 64, each stored twice in
 //    a row so that lane l reads entry l + k at step k without a wrap.  At step
 //    k (0..63) lane l takes column (l + k) mod 64: the 64 lanes of a wave meet
@@ -26,7 +28,7 @@
 //    done symmetrically, the row's own chunk one-sided (each lane sums all 64
 //    columns into its row only, self pair excluded), a chunk before it not at
 //    all: those pairs are transposes of pairs done symmetrically.
-//  * The 8 waves' column sums of a chunk are added in LDS in wave order and
+//  * The 4 waves' column sums of a chunk are added in LDS in wave order and
 //    written once per (group, column); row sums once per (tile, row).
 //    k_kick_reduce adds a row's tile sums in slice order, then its column
 //    sums in group order: no atomics, the same bits on every run.
@@ -281,8 +283,9 @@ __device__ __forceinline__ void sym_put(SymCols &C, int t, bool real, double x, 
     C.m[t + 64] = m;
 }
 
-// At most 128 VGPRs (4 waves per SIMD, 2 blocks per CU); the few values this
-// moves to scratch are reloaded once per chunk, not per step.
+// At most 128 VGPRs (4 waves per SIMD, 4 blocks per CU); the few values this
+// moves to scratch are reloaded once per chunk, not per step (unrolling 4
+// steps, or 5 waves per SIMD, spill inside the step loop: 15 % slower).
 __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_kick_sym(
     SymDev a)
 {

@@ -3,7 +3,7 @@ to both bodies, Newton's third law; the pair force of eq. Hb and its weight
 K(r; max(rc_i, rc_j)) are symmetric in i and j, Sect. 2 and Sect. 6.2)
 against the oracle: accelerations within 1e-12 relative per body, encounter
 lists bit-exact (canonical order), on sizes that span one and several row
-groups of 1,024 with ragged tails, and against the one-sided form."""
+groups of 512 with ragged tails, and against the one-sided form."""
 import numpy as np
 import pytest
 import torch
