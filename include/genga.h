@@ -71,16 +71,16 @@ extern "C" {
 
 /* genga_params.flags */
 #define GENGA_FLAG_NOSYNC 1 /* genga_step: do not synchronise nor read the status     */
-/* Form of the binary64 single-system kick (Newton's third law, Sect. 2: the
- * pair force and its changeover weight K(r_ij; max(rc_i, rc_j)) are symmetric
- * in i and j).  The symmetric form evaluates each unordered pair once and
- * applies it to both bodies; the one-sided form evaluates every ordered pair
- * for its first body.  Both give the same encounter list (bit for bit) and
+/* Form of the single-system kick (Newton's third law, Sect. 2: the pair
+ * force and its changeover weight K(r_ij; max(rc_i, rc_j)) are symmetric in i
+ * and j).  The symmetric form evaluates each unordered pair once and applies
+ * it to both bodies; the one-sided form evaluates every ordered pair for its
+ * first body.  Both give the same encounter list (bit for bit) and
  * accelerations that differ by summation order only.  By default the
- * symmetric form runs from n >= 16384 bodies in the binary64 all-massive
- * kick (genga_kick, genga_step and the levels' base kick); the flags force
- * one form at any n (both set: GENGA_E_INVAL).  Test-particle modes, the
- * mixed precision, the batch and genga_encounter_pairs are one-sided. */
+ * symmetric form runs from n >= 16384 bodies in the all-massive kick, binary64
+ * and mixed (genga_kick, genga_step and the levels' base kick); the flags
+ * force one form at any n (both set: GENGA_E_INVAL).  Test-particle modes,
+ * the batch and genga_encounter_pairs are one-sided. */
 #define GENGA_FLAG_DIRECTED  2
 #define GENGA_FLAG_SYMMETRIC 4
 
@@ -206,8 +206,9 @@ int genga_rcrit(const genga_bodies *b, const genga_params *p, void *ws, void *st
  * If the count exceeds capacity, the first `capacity` pairs are written, the
  * true count is stored and the status records GENGA_E_OVERFLOW.
  * precision GENGA_MIXED: differences d in binary64 rounded to binary32,
- * binary32 distance, weight and partial sums over 64 columns, folded into
- * binary64 accumulators; every pair closer than 3 rho_ij (selected by a
+ * binary32 distance, weight and partial sums over 64 columns (the symmetric
+ * form's column side: over the 128 rows of a wave), folded into binary64
+ * accumulators; every pair closer than 3 rho_ij (selected by a
  * conservative binary32 test) is evaluated entirely in binary64, and the
  * encounter test stays in binary64, so the list is identical to GENGA_FP64.
  * A row whose binary32 terms add up in magnitude (sum m_j / r_ij^2) to more

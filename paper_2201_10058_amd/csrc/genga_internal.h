@@ -66,10 +66,11 @@ struct SymShape {
 };
 SymShape sym_shape(int64_t n, int W);
 constexpr int64_t SYM_MIN_N = 16384;   // default: symmetric kick from this many bodies
-hipError_t launch_kick_sym(const SymShape &h, const double *x, const double *y, const double *z,
-                           const double *m, const double *rc, double *rowpart, double *colpart,
-                           int32_t *cnt, int32_t *stage, int32_t *wcount, int32_t *status,
-                           bool emit, hipStream_t s);
+hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const double *x,
+                           const double *y, const double *z, const double *m, const double *rc,
+                           double *rowpart, double *colpart, int32_t *cnt, int32_t *stage,
+                           int32_t *wcount, int32_t *status, int32_t *refine_cnt, bool emit,
+                           hipStream_t s);
 hipError_t launch_scatter_sym(const SymShape &h, const double *x, const double *y,
                               const double *z, const double *rc, const int32_t *cnt,
                               const int32_t *stage, const int32_t *wcount, const int32_t *rowloc,

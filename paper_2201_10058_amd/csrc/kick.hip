@@ -546,7 +546,7 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
         // the tiles of row i's group, slice by slice: [tile][3][SYM_RG]
         nsl = (int)r.sh.ns(grp);
         const size_t t0 = (size_t)r.sh.tb(grp);
-        pr = {t0 * 3 * SYM_RG - (size_t)grp * SYM_RG, (size_t)SYM_RG};
+        pr = {t0 * r.pstride * SYM_RG - (size_t)grp * SYM_RG, (size_t)SYM_RG};
         cr = {t0 * SYM_RG - (size_t)grp * SYM_RG, (size_t)SYM_RG};
     }
     double h = r.h;
@@ -561,13 +561,15 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
         for (int c = 0; c < 3; ++c) {
             a3[c] = ordered_sum(r.part + pr.base + c * pr.stride + i, r.pstride * pr.stride, nsl);
         }
+        double cmag = 0.0;
         if (r.sym) {
             // then the column sums of the groups up to row i's, in group order
             for (int64_t gg = 0; gg <= grp; ++gg) {
-                const double *cp = r.colpart + 3 * r.sh.coloff(gg) + (i - gg * SYM_RG);
+                const double *cp = r.colpart + (size_t)r.pstride * r.sh.coloff(gg) + (i - gg * SYM_RG);
                 const int64_t L = r.sh.collen(gg);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) a3[c] += cp[c * L];
+                if (r.pstride == 4) cmag += cp[3 * L];
             }
         }
         bool refine = false;
@@ -576,7 +578,8 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
             // (sum_j m_j / r^2 > kappa |sum_j m_j d / r^3|) is evaluated
             // again in binary64 by k_kick_refine
             const double mag =
-                ordered_sum(r.part + pr.base + 3 * pr.stride + i, r.pstride * pr.stride, nsl);
+                ordered_sum(r.part + pr.base + 3 * pr.stride + i, r.pstride * pr.stride, nsl) +
+                cmag;
             const double a2 = a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2];
             refine = !(mag * mag <= r.kappa2 * a2);
         }
@@ -1082,12 +1085,11 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
         c.gy = 1;
     }
     c.nwaves = c.ntiles * (c.nt / 64);
-    // binary64 forces of one all-massive system: the symmetric kick from
-    // SYM_MIN_N bodies (or as the flags ask)
+    // forces of one all-massive system (binary64 or mixed): the symmetric
+    // kick from SYM_MIN_N bodies (or as the flags ask)
     const int flags = p ? p->flags : 0;
-    const bool fp64 = !p || p->precision == GENGA_FP64;
     const bool plain = !p || p->tp_mode == 0 || p->n_massive >= n;
-    if (fp64 && plain && !(flags & GENGA_FLAG_DIRECTED) &&
+    if (plain && !(flags & GENGA_FLAG_DIRECTED) &&
         (n >= SYM_MIN_N || (flags & GENGA_FLAG_SYMMETRIC))) {
         c.use_sym = true;
         int W = sym_width(n);
@@ -1114,7 +1116,7 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     off += 256;
     // the symmetric kick's row sums [T][3][SYM_RG] and column sums share the
     // partial-sum region; its per-tile pair counts the count region
-    const size_t sym_part = c.use_sym ? 3 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G)) : 0;
+    const size_t sym_part = c.use_sym ? 4 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G)) : 0;
     const size_t sym_cnt = c.use_sym ? (size_t)c.sym.T * SYM_RG : 0;
     const size_t nw = std::max<size_t>((size_t)c.nwaves, c.use_sym ? (size_t)c.sym.T * SYM_NW : 0);
     L.part = off;   // 3 values per row and slice for the kick, 5 for its adjoint
@@ -1231,15 +1233,17 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
 
     const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
     const bool refine = mode == KM_MIXED;
-    const bool sym = c.use_sym && mode == KM_F64 && !k.tiles && c.tp == 0;
+    const bool sym = c.use_sym && (mode == KM_F64 || mode == KM_MIXED) && !k.tiles && c.tp == 0;
+    const int sym_ps = mode == KM_MIXED ? 4 : 3;
     if (k.ev0) {
         hipError_t e0 = hipEventRecord((hipEvent_t)k.ev0, s);
         if (e0 != hipSuccess) return e0;
     }
     if (sym) {
-        hipError_t es = launch_kick_sym(c.sym, k.x, k.y, k.z, k.m, k.rc, d.part,
-                                        d.part + (size_t)3 * c.sym.T * SYM_RG, d.cnt, d.stage,
-                                        d.wcount, d.status, d.emit, s);
+        hipError_t es = launch_kick_sym(c.sym, mode == KM_MIXED, d.widen, k.x, k.y, k.z, k.m,
+                                        k.rc, d.part, d.part + (size_t)sym_ps * c.sym.T * SYM_RG,
+                                        d.cnt, d.stage, d.wcount, d.status, d.refine_cnt,
+                                        d.emit, s);
         if (es != hipSuccess) return es;
     } else if (c.ntiles == 0) {
         // (test-particle mode without massive bodies: nothing acts on anything)
@@ -1286,7 +1290,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.pstride = refine ? 4 : 3;
     r.sym = sym ? 1 : 0;
     r.sh = c.sym;
-    r.colpart = d.part + (size_t)3 * c.sym.T * SYM_RG;
+    r.colpart = d.part + (size_t)sym_ps * c.sym.T * SYM_RG;
     r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
     r.refine_list = (int32_t *)(ws + L.rlist);
     r.refine_cnt = d.refine_cnt;

@@ -61,42 +61,64 @@ SymShape sym_shape(int64_t n, int W)
 struct SymDev {
     const double *x, *y, *z, *m, *rc;
     SymShape sh;
-    double *rowpart;   // [T][3][SYM_RG]
-    double *colpart;   // group g: [3][collen(g)] from 3 coloff(g)
+    double *rowpart;   // [T][ps][SYM_RG]
+    double *colpart;   // group g: [ps][collen(g)] from ps coloff(g)
     int32_t *cnt;      // [T][SYM_RG]
     int32_t *stage;    // [T SYM_NW][WSEG][3]  (i, j, unused)
     int32_t *wcount;   // [T SYM_NW]
     int32_t *status;
+    int32_t *refine_cnt;   // mixed: rows listed for binary64 evaluation (reset here)
     int emit;
+    int ps;            // partial values per row: 3 (a), mixed 4 (a, sum of m / r^2)
     double c53;        // 5/3
+    double c15, c1875; // 3/2, 15/8
+    double widen;      // mixed: squared widening of the binary32 near test
 };
 
 // Padding rows and columns sit far away, on opposite sides (no two padding
 // bodies coincide), with mass 0 and critical radius 0: r^2 stays finite (below
-// 1.3e201), every weight they give or take is 0 and they never reach the rare
-// path.
-constexpr double SYM_FAR_ROW = 1e100, SYM_FAR_COL = -1e100;
+// 1.3e37, also in binary32), every weight they give or take is 0 and they
+// never reach the rare path.
+constexpr double SYM_FAR_ROW = 1e18, SYM_FAR_COL = -1e18;
 
 // One chunk of 64 columns, stored twice (entries e and e + 64 are column e).
-struct SymCols {
+template <bool MIXED>
+struct SymCols;
+template <>
+struct SymCols<false> {
     double2 xy[128];
     double2 zm[128];   // (z, 3/2 m)
     double rc2[128];
     double m[128];
 };
+template <>
+struct SymCols<true> {
+    double2 xy[128];
+    double z[128];
+    float2 fw[128];    // (m, widened rc^2) in binary32
+    double rc2[128];
+    double m[128];
+};
 
+template <bool MIXED>
 struct SymSmem {
-    SymCols col[2];
-    double acc[2][3][SYM_NW][64];   // column sums of a chunk, per wave
+    SymCols<MIXED> col[2];
+    double acc[2][MIXED ? 4 : 3][SYM_NW][64];   // column sums of a chunk, per wave
+    double nacc[MIXED ? SYM_NW : 1][3][64];      // mixed: binary64 column sums of near pairs
     int wcnt[SYM_NW];
 };
 
+template <bool MIXED>
 struct SymRows {
     double xi[SYM_IPT], yi[SYM_IPT], zi[SYM_IPT], rc2i[SYM_IPT];
-    double mpi[SYM_IPT];   // 3/2 m_i
+    double mw[SYM_IPT];    // 3/2 m_i (mixed: m_i)
     double ax[SYM_IPT], ay[SYM_IPT], az[SYM_IPT];
     int ii[SYM_IPT];       // row index, -1 for padding (n < 2^31)
     int kc[SYM_IPT];
+    // mixed
+    double mag[SYM_IPT];                  // binary64 sum of the binary32 m_j / r^2
+    float rc2fi[SYM_IPT], mif[SYM_IPT];
+    float axf[SYM_IPT], ayf[SYM_IPT], azf[SYM_IPT], magf[SYM_IPT];
 };
 
 // Lane l receives lane (l + 1) mod 64's value.
@@ -105,6 +127,11 @@ __device__ __forceinline__ double rotate_down(double v)
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x134, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x134, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float rotate_down(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
 }
 
 // Tile of launch index t: group g and slice s (s = -1: an empty diagonal slot
@@ -148,9 +175,9 @@ __device__ __forceinline__ int64_t sym_group_of(const SymShape &h, int64_t sid)
 // weights (m_j and m_i times r^-3) and are replaced by K-weighted ones inside
 // rho_ij; a pair exactly at rho_ij keeps them (K = 1).  1/r and 1/rho from
 // v_rsq_f64 with one Newton correction (relative error below 5e-15), so the
-// band variable is y = (r/rho) / 0.9 - 1/9; m_i = (2/3) (3/2 m_i) to 2 ulp.
-// Whether a pair is inside rho_ij, and so in the encounter list, is decided by
-// r^2 < max(rc_i^2, rc_j^2) alone.
+// band variable is y = (r/rho) / 0.9 - 1/9; in the binary64 kick m_i is
+// (2/3) (3/2 m_i), to 2 ulp.  Whether a pair is inside rho_ij, and so in the
+// encounter list, is decided by r^2 < max(rc_i^2, rc_j^2) alone.
 __device__ __forceinline__ double rsq_nr(double v)
 {
     const double y = __builtin_amdgcn_rsq(v);
@@ -158,9 +185,10 @@ __device__ __forceinline__ double rsq_nr(double v)
     return __builtin_fma(y * e, 0.5, y);
 }
 
-__device__ __forceinline__ void sym_slow(const SymDev &a, SymRows &R, int q, int jg, double r2,
-                                         double rc2c, double mc, double &si, double &sj,
-                                         int64_t wave_g, int *wcnt)
+template <bool MIXED>
+__device__ __forceinline__ void sym_slow(const SymDev &a, SymRows<MIXED> &R, int q, int jg,
+                                         double r2, double rc2c, double mc, double &si,
+                                         double &sj, int64_t wave_g, int *wcnt)
 {
     bool emit = false;
     if (jg == R.ii[q]) {
@@ -180,7 +208,7 @@ __device__ __forceinline__ void sym_slow(const SymDev &a, SymRows &R, int q, int
             const double K = changeover_of_y(__builtin_fma((r2 * yc) * irho, 1.0 / 0.9, -1.0 / 9.0));
             const double kr = K * (yc * yc * yc);
             si = mc * kr;
-            sj = (R.mpi[q] * (2.0 / 3.0)) * kr;
+            sj = (MIXED ? R.mw[q] : R.mw[q] * (2.0 / 3.0)) * kr;
         }
     }
     if (a.emit) {
@@ -205,16 +233,17 @@ __device__ __forceinline__ void sym_slow(const SymDev &a, SymRows &R, int q, int
     }
 }
 
-// One chunk of 64 columns against the lane's rows.  GEN = false: every row
-// pairs symmetrically.  GEN = true (chunks over the group's own rows): mode[q]
-// is 2 (symmetric), 1 (one-sided: the row's own chunk) or 0 (skip), uniform
-// over the wave.  m r^-3 as in the one-sided kick: v_rsq_f64 (relative error
-// below 2^-24) with its first-order correction, (3/2 m) y^3 (5/3 - r^2 y^2).
+// One chunk of 64 columns against the lane's rows (binary64).  GEN = false:
+// every row pairs symmetrically.  GEN = true (chunks over the group's own
+// rows): mode[q] is 2 (symmetric), 1 (one-sided: the row's own chunk) or 0
+// (skip), uniform over the wave.  m r^-3 as in the one-sided kick: v_rsq_f64
+// (relative error below 2^-24) with its first-order correction,
+// (3/2 m) y^3 (5/3 - r^2 y^2).
 template <bool GEN>
-__device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows &R, const SymCols &C,
-                                          int colbase, const int *mode, double &cx,
-                                          double &cy, double &cz, double c53, int64_t wave_g,
-                                          int *wcnt, int lane)
+__device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows<false> &R,
+                                          const SymCols<false> &C, int colbase, const int *mode,
+                                          double &cx, double &cy, double &cz, double c53,
+                                          int64_t wave_g, int *wcnt, int lane)
 {
     for (int k0 = 0; k0 < 64; k0 += 2) {
 #pragma unroll
@@ -236,15 +265,15 @@ __device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows &R, const Sym
                 const double pp = __builtin_fma(-r2, y2, c53);
                 const double t = (y2 * yv) * pp;
                 double si = t * zm.y;
-                double sj = t * R.mpi[q];
+                double sj = t * R.mw[q];
                 if (cand) {
                     // the column index only here: an empty volatile asm keeps the
                     // compiler from computing it on the fast path
                     int ee = lane;
                     asm volatile("" : "+v"(ee));
                     ee += k0 + u;
-                    sym_slow(a, R, q, colbase + (ee & 63), r2, rc2c, C.m[ee], si, sj, wave_g,
-                             wcnt);
+                    sym_slow<false>(a, R, q, colbase + (ee & 63), r2, rc2c, C.m[ee], si, sj,
+                                    wave_g, wcnt);
                 }
                 R.ax[q] = __builtin_fma(dx, si, R.ax[q]);
                 R.ay[q] = __builtin_fma(dy, si, R.ay[q]);
@@ -262,35 +291,152 @@ __device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows &R, const Sym
     }
 }
 
+// The same in mixed precision: binary32 pair arithmetic on the binary64
+// differences (as the one-sided mixed kick).  A pair closer than 3 rho_ij in
+// the conservative binary32 test is evaluated in binary64 (second-order
+// corrected v_rsq_f64, the rare path inside rho_ij); its row term goes to the
+// binary64 row sum and its column term to this wave's binary64 column sums
+// nacc in LDS (at a given step the lanes hold distinct columns, and only this
+// wave touches nacc, so the updates need no atomics).  The binary32 sums,
+// including the sums of m / r^2 that decide the binary64 refinement of
+// cancelling rows, rotate like the binary64 ones.
+template <bool GEN>
+__device__ __forceinline__ void sym_chunk_mixed(const SymDev &a, SymRows<true> &R,
+                                                const SymCols<true> &C, double (*nacc)[64],
+                                                int colbase, const int *mode, float &cx,
+                                                float &cy, float &cz, float &cm, double c15,
+                                                double c1875, int64_t wave_g, int *wcnt, int lane)
+{
+    for (int k0 = 0; k0 < 64; k0 += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = lane + k0 + u;
+            const double2 p = C.xy[e];
+            const double zc = C.z[e];
+            const float2 fw = C.fw[e];
+#pragma unroll
+            for (int q = 0; q < SYM_IPT; ++q) {
+                if (GEN && mode[q] == 0) continue;
+                const bool col = !GEN || mode[q] == 2;
+                const double dx = p.x - R.xi[q];
+                const double dy = p.y - R.yi[q];
+                const double dz = zc - R.zi[q];
+                const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
+                const float r2f = __builtin_fmaf(dzf, dzf, __builtin_fmaf(dyf, dyf, dxf * dxf));
+                const bool near = r2f <= vmax_f32(R.rc2fi[q], fw.y);
+                const float yv = __builtin_amdgcn_rsqf(r2f);
+                const float y2 = yv * yv;
+                float mti = fw.x * y2, mtj = R.mif[q] * y2;
+                float si = mti * yv, sj = mtj * yv;
+                if (near) {
+                    si = sj = mti = mtj = 0.0f;
+                    int ee = lane;
+                    asm volatile("" : "+v"(ee));
+                    ee += k0 + u;
+                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                    const double mc = C.m[ee], rc2c = C.rc2[ee];
+                    const double y = __builtin_amdgcn_rsq(r2);
+                    const double yy = y * y;
+                    const double e1 = __builtin_fma(-r2, yy, 1.0);
+                    const double pp = __builtin_fma(e1, c1875, c15);
+                    const double t3 = yy * y;
+                    const double r3 = __builtin_fma(t3 * e1, pp, t3);
+                    double wi = mc * r3, wj = R.mw[q] * r3;
+                    if (r2 <= vmax_f64(R.rc2i[q], rc2c))
+                        sym_slow<true>(a, R, q, colbase + (ee & 63), r2, rc2c, mc, wi, wj, wave_g,
+                                       wcnt);
+                    R.ax[q] = __builtin_fma(dx, wi, R.ax[q]);
+                    R.ay[q] = __builtin_fma(dy, wi, R.ay[q]);
+                    R.az[q] = __builtin_fma(dz, wi, R.az[q]);
+                    if (col) {
+                        const int c = ee & 63;
+                        nacc[0][c] = __builtin_fma(-dx, wj, nacc[0][c]);
+                        nacc[1][c] = __builtin_fma(-dy, wj, nacc[1][c]);
+                        nacc[2][c] = __builtin_fma(-dz, wj, nacc[2][c]);
+                    }
+                }
+                R.axf[q] = __builtin_fmaf(dxf, si, R.axf[q]);
+                R.ayf[q] = __builtin_fmaf(dyf, si, R.ayf[q]);
+                R.azf[q] = __builtin_fmaf(dzf, si, R.azf[q]);
+                R.magf[q] += mti;
+                if (col) {
+                    cx = __builtin_fmaf(-dxf, sj, cx);
+                    cy = __builtin_fmaf(-dyf, sj, cy);
+                    cz = __builtin_fmaf(-dzf, sj, cz);
+                    cm += mtj;
+                }
+            }
+            cx = rotate_down(cx);
+            cy = rotate_down(cy);
+            cz = rotate_down(cz);
+            cm = rotate_down(cm);
+        }
+    }
+}
+
 // Column jg (or padding) into entries t and t + 64 of an LDS chunk.
-__device__ __forceinline__ void sym_put(SymCols &C, int t, bool real, double x, double y,
-                                        double z, double m, double rc)
+template <bool MIXED>
+__device__ __forceinline__ void sym_put(SymCols<MIXED> &C, int t, bool real, double x, double y,
+                                        double z, double m, double rc, double widen)
 {
     if (!real) {
         x = y = z = SYM_FAR_COL;
         m = 0.0;
         rc = 0.0;
     }
-    const double2 xy = make_double2(x, y), zm = make_double2(z, 1.5 * m);
+    const double2 xy = make_double2(x, y);
     const double rc2 = rc * rc;
     C.xy[t] = xy;
     C.xy[t + 64] = xy;
-    C.zm[t] = zm;
-    C.zm[t + 64] = zm;
+    if constexpr (MIXED) {
+        const float2 fw = make_float2((float)m, (float)(rc2 * widen));
+        C.z[t] = z;
+        C.z[t + 64] = z;
+        C.fw[t] = fw;
+        C.fw[t + 64] = fw;
+    } else {
+        const double2 zm = make_double2(z, 1.5 * m);
+        C.zm[t] = zm;
+        C.zm[t + 64] = zm;
+    }
     C.rc2[t] = rc2;
     C.rc2[t + 64] = rc2;
     C.m[t] = m;
     C.m[t + 64] = m;
 }
 
+// Column sums of chunk cc (columns cc*64 + lane) of group g: the waves' sums
+// in wave order.
+template <bool MIXED>
+__device__ __forceinline__ void sym_colsum(const SymDev &a, const SymSmem<MIXED> &sm, int b,
+                                           int64_t cc, int64_t g, int lane)
+{
+    constexpr int NC = MIXED ? 4 : 3;
+    const SymShape &h = a.sh;
+    const int64_t j = cc * 64 + lane;
+    if (j >= h.n) return;
+    const int64_t row0 = g * SYM_RG;
+    double *cp = a.colpart + (size_t)NC * h.coloff(g) + (j - row0);
+    const int64_t L = h.collen(g);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double t = sm.acc[b][c][0][lane];
+#pragma unroll
+        for (int v = 1; v < SYM_NW; ++v) t += sm.acc[b][c][v][lane];
+        cp[c * L] = t;
+    }
+}
+
 // At most 128 VGPRs (4 waves per SIMD, 4 blocks per CU); the few values this
 // moves to scratch are reloaded once per chunk, not per step (unrolling 4
 // steps, or 5 waves per SIMD, spill inside the step loop: 15 % slower).
+template <bool MIXED>
 __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_kick_sym(
     SymDev a)
 {
-    __shared__ SymSmem sm;
+    __shared__ SymSmem<MIXED> sm;
     const SymShape &h = a.sh;
+    if (MIXED && blockIdx.x == 0 && threadIdx.x == 0) *a.refine_cnt = 0;
     int64_t g, s;
     sym_tile(h, blockIdx.x, g, s);
     if (s < 0) return;   // (uniform over the block)
@@ -308,8 +454,9 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     const bool diag = s < h.d;
     const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
     const double c53 = a.c53 + (double)vzero;
+    const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
 
-    SymRows R;
+    SymRows<MIXED> R;
     int64_t rch[SYM_IPT];   // global 64-row chunk of each row slot
 #pragma unroll
     for (int q = 0; q < SYM_IPT; ++q) {
@@ -329,12 +476,23 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             R.xi[q] = R.yi[q] = R.zi[q] = SYM_FAR_ROW;
             R.rc2i[q] = 0.0;
         }
-        R.mpi[q] = 1.5 * mi;
+        R.mw[q] = MIXED ? mi : 1.5 * mi;
         R.ax[q] = R.ay[q] = R.az[q] = 0.0;
         R.kc[q] = 0;
+        if constexpr (MIXED) {
+            R.mag[q] = 0.0;
+            R.rc2fi[q] = (float)(R.rc2i[q] * a.widen);
+            R.mif[q] = (float)mi;
+            R.axf[q] = R.ayf[q] = R.azf[q] = R.magf[q] = 0.0f;
+        }
     }
     int *wcnt = &sm.wcnt[w];
     if (lane == 0) __hip_atomic_store(wcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if constexpr (MIXED) {
+        sm.nacc[w][0][lane] = 0.0;
+        sm.nacc[w][1][lane] = 0.0;
+        sm.nacc[w][2][lane] = 0.0;
+    }
 
     // chunk 0 by wave 0
     if (w == 0) {
@@ -345,7 +503,7 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             x = a.x[jg]; y = a.y[jg]; z = a.z[jg]; m = a.m[jg]; rc = a.rc[jg];
             if (!(rc >= 0.0 && rc < INFINITY)) atomicOr(a.status, ST_RCRIT);
         }
-        sym_put(sm.col[0], lane, real, x, y, z, m, rc);
+        sym_put<MIXED>(sm.col[0], lane, real, x, y, z, m, rc, a.widen);
     }
     __syncthreads();
 
@@ -353,21 +511,8 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     for (int kc = 0; kc < nch; ++kc) {
         const int b = kc & 1;
         const int64_t cc = cc0 + kc;
-        // column sums of the previous chunk, in wave order
-        if (kc > 0 && w == (kc - 1) % SYM_NW) {
-            const int64_t j = (cc - 1) * 64 + lane;
-            if (j < n) {
-                double *cp = a.colpart + 3 * h.coloff(g) + (j - row0);
-                const int64_t L = h.collen(g);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double t = sm.acc[b ^ 1][c][0][lane];
-#pragma unroll
-                    for (int v = 1; v < SYM_NW; ++v) t += sm.acc[b ^ 1][c][v][lane];
-                    cp[c * L] = t;
-                }
-            }
-        }
+        // column sums of the previous chunk
+        if (kc > 0 && w == (kc - 1) % SYM_NW) sym_colsum<MIXED>(a, sm, b ^ 1, cc - 1, g, lane);
         // next chunk into registers (loader wave)
         const bool loader = kc + 1 < nch && w == (kc + 1) % SYM_NW;
         double px = 0, py = 0, pz = 0, pm = 0, prc = 0;
@@ -379,8 +524,6 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 px = a.x[jg]; py = a.y[jg]; pz = a.z[jg]; pm = a.m[jg]; prc = a.rc[jg];
             }
         }
-        double cx = 0.0, cy = 0.0, cz = 0.0;
-        const SymCols &C = sm.col[b];
         const int colbase = (int)(cc * 64);
         bool full = !diag;
         int mode[SYM_IPT] = {};
@@ -392,42 +535,59 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 full = full && mode[q] == 2;
             }
         }
-        if (full)
-            sym_chunk<false>(a, R, C, colbase, mode, cx, cy, cz, c53, wave_g, wcnt, lane);
-        else
-            sym_chunk<true>(a, R, C, colbase, mode, cx, cy, cz, c53, wave_g, wcnt, lane);
-        sm.acc[b][0][w][lane] = cx;
-        sm.acc[b][1][w][lane] = cy;
-        sm.acc[b][2][w][lane] = cz;
+        if constexpr (MIXED) {
+            float cx = 0.0f, cy = 0.0f, cz = 0.0f, cm = 0.0f;
+            if (full)
+                sym_chunk_mixed<false>(a, R, sm.col[b], sm.nacc[w], colbase, mode, cx, cy, cz, cm,
+                                       c15, c1875, wave_g, wcnt, lane);
+            else
+                sym_chunk_mixed<true>(a, R, sm.col[b], sm.nacc[w], colbase, mode, cx, cy, cz, cm,
+                                      c15, c1875, wave_g, wcnt, lane);
+            // binary32 row sums of the chunk into binary64
+#pragma unroll
+            for (int q = 0; q < SYM_IPT; ++q) {
+                R.ax[q] += (double)R.axf[q];
+                R.ay[q] += (double)R.ayf[q];
+                R.az[q] += (double)R.azf[q];
+                R.mag[q] += (double)R.magf[q];
+                R.axf[q] = R.ayf[q] = R.azf[q] = R.magf[q] = 0.0f;
+            }
+            sm.acc[b][0][w][lane] = (double)cx + sm.nacc[w][0][lane];
+            sm.acc[b][1][w][lane] = (double)cy + sm.nacc[w][1][lane];
+            sm.acc[b][2][w][lane] = (double)cz + sm.nacc[w][2][lane];
+            sm.acc[b][3][w][lane] = (double)cm;
+            sm.nacc[w][0][lane] = 0.0;
+            sm.nacc[w][1][lane] = 0.0;
+            sm.nacc[w][2][lane] = 0.0;
+        } else {
+            double cx = 0.0, cy = 0.0, cz = 0.0;
+            if (full)
+                sym_chunk<false>(a, R, sm.col[b], colbase, mode, cx, cy, cz, c53, wave_g, wcnt,
+                                 lane);
+            else
+                sym_chunk<true>(a, R, sm.col[b], colbase, mode, cx, cy, cz, c53, wave_g, wcnt,
+                                lane);
+            sm.acc[b][0][w][lane] = cx;
+            sm.acc[b][1][w][lane] = cy;
+            sm.acc[b][2][w][lane] = cz;
+        }
         if (loader) {
             if (preal && !(prc >= 0.0 && prc < INFINITY)) atomicOr(a.status, ST_RCRIT);
-            sym_put(sm.col[b ^ 1], lane, preal, px, py, pz, pm, prc);
+            sym_put<MIXED>(sm.col[b ^ 1], lane, preal, px, py, pz, pm, prc, a.widen);
         }
         __syncthreads();
     }
-    if (w == (nch - 1) % SYM_NW) {
-        const int64_t j = (cc0 + nch - 1) * 64 + lane;
-        if (j < n) {
-            double *cp = a.colpart + 3 * h.coloff(g) + (j - row0);
-            const int64_t L = h.collen(g);
-            const int b = (nch - 1) & 1;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double t = sm.acc[b][c][0][lane];
-#pragma unroll
-                for (int v = 1; v < SYM_NW; ++v) t += sm.acc[b][c][v][lane];
-                cp[c * L] = t;
-            }
-        }
-    }
+    if (w == (nch - 1) % SYM_NW) sym_colsum<MIXED>(a, sm, (nch - 1) & 1, cc0 + nch - 1, g, lane);
+    constexpr int NC = MIXED ? 4 : 3;
 #pragma unroll
     for (int q = 0; q < SYM_IPT; ++q) {
         if (R.ii[q] < 0) continue;
         const int64_t off = R.ii[q] - row0;
-        double *p = a.rowpart + (size_t)sid * 3 * SYM_RG + off;
+        double *p = a.rowpart + (size_t)sid * NC * SYM_RG + off;
         p[0] = R.ax[q];
         p[SYM_RG] = R.ay[q];
         p[2 * SYM_RG] = R.az[q];
+        if constexpr (MIXED) p[3 * SYM_RG] = R.mag[q];
         if (a.emit) a.cnt[(size_t)sid * SYM_RG + off] = R.kc[q];
     }
     if (a.emit && lane == 0)
@@ -508,10 +668,11 @@ __global__ __launch_bounds__(64) void k_pairs_scatter_sym(SymScatterDev d)
     }
 }
 
-hipError_t launch_kick_sym(const SymShape &h, const double *x, const double *y, const double *z,
-                           const double *m, const double *rc, double *rowpart, double *colpart,
-                           int32_t *cnt, int32_t *stage, int32_t *wcount, int32_t *status,
-                           bool emit, hipStream_t s)
+hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const double *x,
+                           const double *y, const double *z, const double *m, const double *rc,
+                           double *rowpart, double *colpart, int32_t *cnt, int32_t *stage,
+                           int32_t *wcount, int32_t *status, int32_t *refine_cnt, bool emit,
+                           hipStream_t s)
 {
     SymDev a;
     a.x = x; a.y = y; a.z = z; a.m = m; a.rc = rc;
@@ -522,10 +683,18 @@ hipError_t launch_kick_sym(const SymShape &h, const double *x, const double *y, 
     a.stage = stage;
     a.wcount = wcount;
     a.status = status;
+    a.refine_cnt = refine_cnt;
     a.emit = emit ? 1 : 0;
+    a.ps = mixed ? 4 : 3;
     a.c53 = 5.0 / 3.0;
+    a.c15 = 1.5;
+    a.c1875 = 1.875;
+    a.widen = widen;
     const int64_t blocks = h.tfull + h.G * h.d;
-    hipLaunchKernelGGL(k_kick_sym, dim3((unsigned)blocks), dim3(SYM_NT), 0, s, a);
+    if (mixed)
+        hipLaunchKernelGGL(k_kick_sym<true>, dim3((unsigned)blocks), dim3(SYM_NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_kick_sym<false>, dim3((unsigned)blocks), dim3(SYM_NT), 0, s, a);
     return hipGetLastError();
 }
 

@@ -22,9 +22,9 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _kick(d, rc, precision, ipt=0, cap=None, h=0.0):
+def _kick(d, rc, precision, ipt=0, cap=None, h=0.0, flags=0):
     st = N.State.from_numpy(d, rc=rc)
-    cfg = N.Config(G=G, precision=precision, ipt=ipt)
+    cfg = N.Config(G=G, precision=precision, ipt=ipt, flags=flags)
     ws = N.Workspace(st.n, cfg)
     if cap is None:
         cap = max(16, oracle.pairs(d["x"], d["y"], d["z"], rc, cap=0)[2])
@@ -42,25 +42,28 @@ def _rc(d):
     return oracle.rcrit(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["m"], 1.0, 6.0, 3.0, 0.4)
 
 
-@pytest.mark.parametrize("ipt", [1, 2])
-def test_mixed_disk2048(dev, ipt):
+@pytest.mark.parametrize("ipt,flags", [(1, 0), (2, 0), (0, N.FLAG_SYMMETRIC)])
+def test_mixed_disk2048(dev, ipt, flags):
+    # one-sided (the default at this size) and symmetric mixed kick
     d = W.make_disk(W.DISK_2048)
     rc = _rc(d)
-    a, (pi, pj, cnt), code, _ = _kick(d, rc, N.MIXED, ipt)
+    a, (pi, pj, cnt), code, _ = _kick(d, rc, N.MIXED, ipt, flags=flags)
     assert code == N.OK
     ax, ay, az, _ = oracle.kick_acc(d["x"], d["y"], d["z"], d["m"], rc, G, precise=True)
     err = _rel(a, np.stack([ax, ay, az]))
-    _say("mixed 2048 ipt", ipt, "max", err.max(), "p99", np.quantile(err, 0.99))
+    _say("mixed 2048 ipt", ipt, "flags", flags, "max", err.max(), "p99", np.quantile(err, 0.99))
     assert err.max() <= MIXED_TOL
     opi, opj, ocnt = oracle.pairs(d["x"], d["y"], d["z"], rc)
     assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(12))
 def test_mixed_random_small(dev, seed):
-    n = [1, 5, 64, 65, 257, 600][seed]
+    # seeds 0-5 one-sided, 6-11 symmetric (one and several row groups of 512)
+    n = [1, 5, 64, 65, 257, 600, 1, 5, 65, 600, 1025, 2500][seed]
+    flags = N.FLAG_SYMMETRIC if seed >= 6 else 0
     d = W.random_cloud(n, seed=50 + seed, rc_scale=0.3)
-    a, (pi, pj, cnt), code, _ = _kick(d, d["rc"], N.MIXED, 1 + seed % 2)
+    a, (pi, pj, cnt), code, _ = _kick(d, d["rc"], N.MIXED, 1 + seed % 2, flags=flags)
     assert code == N.OK
     if n > 1:
         ax, ay, az, _ = oracle.kick_acc(d["x"], d["y"], d["z"], d["m"], d["rc"], G, precise=True)
@@ -69,14 +72,15 @@ def test_mixed_random_small(dev, seed):
     assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
 
 
-@pytest.mark.parametrize("n", [16384, 32768, 65536])
-def test_mixed_full_disk_all_bodies(dev, n):
+@pytest.mark.parametrize("n,flags", [(16384, 0), (32768, 0), (65536, 0), (16384, N.FLAG_DIRECTED)])
+def test_mixed_full_disk_all_bodies(dev, n, flags):
     # every body against the FP64 GPU kick (itself validated against the
-    # oracle to 1e-12), plus sampled rows against the oracle directly
+    # oracle to 1e-12), plus sampled rows against the oracle directly; the
+    # default (symmetric) form at these sizes, and the one-sided one
     d = W.make_disk(W.DISK_MIXED[n])
     rc = _rc(d)
     a64, p64, c64, _ = _kick(d, rc, N.FP64)
-    a32, p32, c32, _ = _kick(d, rc, N.MIXED)
+    a32, p32, c32, _ = _kick(d, rc, N.MIXED, flags=flags)
     assert c64 == N.OK and c32 == N.OK
     err = _rel(a32, a64)
     _say(f"mixed N={n}: max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e} "
@@ -112,7 +116,8 @@ def _refined_rows(ws) -> int:
     return int(ws.buf[:12].view(torch.int32)[2].item())
 
 
-def test_mixed_refines_cancelling_rows(dev):
+@pytest.mark.parametrize("flags", [0, N.FLAG_SYMMETRIC])
+def test_mixed_refines_cancelling_rows(dev, flags):
     # a body close to the centre of a ring of 4,096 equal masses: its terms
     # cancel almost completely (sum |a_ij| / |a_i| ~ 10^3), so the binary32
     # sum alone could not reach 1e-6; the kick must evaluate it in binary64
@@ -122,7 +127,7 @@ def test_mixed_refines_cancelling_rows(dev):
           ("m", 1e-9), ("rc", 1e-3))}
     n = d["x"].size
     st = N.State.from_numpy(d, rc=d["rc"])
-    cfg = N.Config(G=G, precision=N.MIXED)
+    cfg = N.Config(G=G, precision=N.MIXED, flags=flags)
     ws = N.Workspace(n, cfg)
     a = N.kick(st, cfg, ws, 0.0, acc=True).cpu().numpy()
     assert N.read_status(ws) == N.OK
