@@ -62,7 +62,7 @@ def parse():
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KICK_SOURCES = ("kick.hip", "kick_sym.hip", "device_common.h", "genga_internal.h")
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_kick_fp64_disk65536_traffic.txt")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_kick_sym_disk65536_traffic.txt")
 
 
 def kick_source_hash() -> str:
