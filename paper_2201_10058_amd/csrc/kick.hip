@@ -504,6 +504,60 @@ struct ReduceDev {
     int32_t *refine_list, *refine_cnt;
 };
 
+// Symmetric kick: total of row i (group grp) over its nsl tiles and the
+// column sums of groups 0..grp; components 0-2 into a3, component 3 (mixed:
+// sum of m / r^2) into mag.
+__device__ __forceinline__ void sym_row_total(const ReduceDev &r, const PartRows &pr, int nsl,
+                                              int64_t grp, int64_t i, double a3[3], double &mag)
+{
+    const int nc = r.pstride;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double *p = r.part + pr.base + i;
+    const size_t step = (size_t)nc * pr.stride;
+    int s = 0;
+    for (; s + 8 <= nsl; s += 8) {
+        double v[8][4];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[k][c] = c < nc ? p[(size_t)(s + k) * step + c * pr.stride] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += v[k][c];
+    }
+    for (; s < nsl; ++s)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += c < nc ? p[(size_t)s * step + c * pr.stride] : 0.0;
+    const int64_t ng = grp + 1;
+    int64_t gg = 0;
+    for (; gg + 8 <= ng; gg += 8) {
+        double v[8][4];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t g2 = gg + k;
+            const double *cp = r.colpart + (size_t)nc * r.sh.coloff(g2) + (i - g2 * SYM_RG);
+            const int64_t L = r.sh.collen(g2);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[k][c] = c < nc ? cp[c * L] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += v[k][c];
+    }
+    for (; gg < ng; ++gg) {
+        const double *cp = r.colpart + (size_t)nc * r.sh.coloff(gg) + (i - gg * SYM_RG);
+        const int64_t L = r.sh.collen(gg);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += c < nc ? cp[c * L] : 0.0;
+    }
+    a3[0] = acc[0];
+    a3[1] = acc[1];
+    a3[2] = acc[2];
+    mag = acc[3];
+}
+
 __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
 {
     __shared__ int64_t sm[RB / 64];
@@ -557,29 +611,25 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     }
     if (r.forces && valid) {
         double a3[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            a3[c] = ordered_sum(r.part + pr.base + c * pr.stride + i, r.pstride * pr.stride, nsl);
-        }
-        double cmag = 0.0;
+        double mag = 0.0;
         if (r.sym) {
-            // then the column sums of the groups up to row i's, in group order
-            for (int64_t gg = 0; gg <= grp; ++gg) {
-                const double *cp = r.colpart + (size_t)r.pstride * r.sh.coloff(gg) + (i - gg * SYM_RG);
-                const int64_t L = r.sh.collen(gg);
+            // row sums of the group's tiles in slice order, then the column
+            // sums of the groups up to row i's in group order; the loads of
+            // 8 tiles (groups) and all components are issued before their
+            // additions, whose order is unchanged
+            sym_row_total(r, pr, nsl, grp, i, a3, mag);
+        } else {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) a3[c] += cp[c * L];
-                if (r.pstride == 4) cmag += cp[3 * L];
-            }
+            for (int c = 0; c < 3; ++c)
+                a3[c] = ordered_sum(r.part + pr.base + c * pr.stride + i, r.pstride * pr.stride, nsl);
+            if (r.kappa2 > 0.0)
+                mag = ordered_sum(r.part + pr.base + 3 * pr.stride + i, r.pstride * pr.stride, nsl);
         }
         bool refine = false;
         if (r.kappa2 > 0.0) {
             // mixed: a row whose binary32 terms are large against their sum
             // (sum_j m_j / r^2 > kappa |sum_j m_j d / r^3|) is evaluated
             // again in binary64 by k_kick_refine
-            const double mag =
-                ordered_sum(r.part + pr.base + 3 * pr.stride + i, r.pstride * pr.stride, nsl) +
-                cmag;
             const double a2 = a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2];
             refine = !(mag * mag <= r.kappa2 * a2);
         }
@@ -797,7 +847,8 @@ __global__ __launch_bounds__(FB) void k_kick_refine(RefineDev a)
 // sum region of the workspace (cap doubles); each slice is a multiple of 64
 // columns.
 constexpr int RT = KB;        // listed rows per refine tile
-constexpr int RMAXS = 128;    // most column slices of the refinement
+constexpr int RMAXS = 1024;   // most column slices of the refinement (a few hundred listed rows
+                              // then fill the chip: 2 row tiles x 1024 slices of 64 columns)
 
 __device__ __forceinline__ void refine_shape(int cnt, int64_t n, int64_t cap, int &S, int64_t &len)
 {
