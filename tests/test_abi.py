@@ -81,6 +81,44 @@ def test_host_side_argument_errors():
     tp = native.Config(G=2.959e-4, tp_mode=2, n_massive=5).params()
     assert lib.genga_kick_vjp(ctypes.byref(b), ctypes.byref(tp), 1.0, fake, fake, fake, None, fake,
                               None) in (native.E_INVAL, native.E_UNSUPPORTED)
+    # the two kick forms exclude each other
+    both = native.Config(G=2.959e-4, flags=native.FLAG_SYMMETRIC | native.FLAG_DIRECTED).params()
+    assert lib.genga_kick(ctypes.byref(b), ctypes.byref(both), 0.0, None, None, None, None, fake,
+                          None) == native.E_INVAL
+
+
+@pytest.mark.parametrize("n", [1, 1000, 16383, 16384, 65536, 100003])
+def test_symmetric_kick_workspace_on_host(n):
+    # the workspace holds either form: the symmetric kick's row and column
+    # sums (4 values each in mixed precision) and its per-tile counts
+    from paper_2201_10058_amd import native
+    lib = native.load()
+    rg, tiles = 512, 0
+    w = 512
+    while w > 64:
+        G = -(-n // rg)
+        S0 = -(-n // w)
+        d = rg // w
+        tiles = G * S0 - d * (G * (G - 1) // 2)
+        if tiles >= 4096:
+            break
+        w //= 2
+    if w == 64:
+        G = -(-n // rg)
+        S0 = -(-n // w)
+        d = rg // w
+        tiles = G * S0 - d * (G * (G - 1) // 2)
+    G = -(-n // rg)
+    colsums = G * n - rg * (G * (G - 1) // 2)
+    need = 8 * 4 * (tiles * rg + colsums) + 4 * tiles * rg
+    for flags in (0, native.FLAG_SYMMETRIC, native.FLAG_DIRECTED):
+        for prec in (native.FP64, native.MIXED):
+            p = native.Config(G=2.959e-4, flags=flags, precision=prec).params()
+            ws = lib.genga_workspace_bytes(n, ctypes.byref(p))
+            sym = flags == native.FLAG_SYMMETRIC or (flags == 0 and n >= 16384)
+            if sym:
+                assert ws >= need, (n, flags, prec, ws, need)
+            assert ws > 0
 
 
 def test_level_params_on_host():
