@@ -160,7 +160,7 @@ typedef struct {
 } genga_params;
 
 #define GENGA_MAX_LEVELS 8
-#define GENGA_GROUP_MAX 256 /* bodies of the largest group the direct solver takes */
+#define GENGA_GROUP_MAX 512 /* bodies of the largest group the direct solver takes */
 
 /* Close-encounter list (device memory). */
 typedef struct {

@@ -29,6 +29,7 @@ namespace {
 
 constexpr int LT = 256;     // threads per block of the list kernels
 constexpr int LG = 1024;    // blocks of the grid-stride list kernels
+constexpr int LG_BIG = 64;  // workgroups of the Bulirsch-Stoer class of 257-512 bodies
 constexpr int DB = 256;     // blocks (and chunks) of the list compaction
 constexpr int ST = 1024;    // threads of the one-block scan of the adjacency tile sums
 
@@ -542,7 +543,9 @@ __global__ __launch_bounds__(LT) void k_group_rank(const int32_t *lab, const int
 
 // ---------------------------------------------------------------------------
 // Direct solver: one thread per member; groups of up to 8 bodies take 8 lanes
-// of a wave each, larger ones a workgroup of 64 or 256 threads.  The
+// of a wave each, larger ones a workgroup of 64, 256 or 512 threads (the
+// classes of Table 1 up to 512 bodies; 512 threads hold the extrapolation
+// tableau in registers at 2 waves per SIMD and 68 KB of LDS).  The
 // group's flow (Kepler force of the star plus the remainder R of the mutual
 // forces) is integrated over H by Bulirsch-Stoer steps: the modified
 // midpoint rule with n = 2, 4, ..., 2 KM sub-steps, polynomial extrapolation
@@ -1280,7 +1283,9 @@ static hipError_t direct_solve(const LevelRun &R, int l, double dt_l)
     a.coll_cap = LEVEL_COLL_CAP;
     hipLaunchKernelGGL(k_bs_lanes<BS_GS>, dim3(LG), dim3(LT), 0, R.s, a);
     hipLaunchKernelGGL(k_bs<64>, dim3(LG), dim3(64), 0, R.s, a, BS_GS);
-    hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG), dim3(GENGA_GROUP_MAX), 0, R.s, a, 64);
+    hipLaunchKernelGGL(k_bs<256>, dim3(LG), dim3(256), 0, R.s, a, 64);
+    // groups of 257-512 bodies are rare: a few workgroups walk them
+    hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG_BIG), dim3(GENGA_GROUP_MAX), 0, R.s, a, 256);
     return hipGetLastError();
 }
 

@@ -49,3 +49,18 @@ def two_planets(a2, m=3e-6, T=300.0):
                     rtol=1e-13, atol=1e-16)
     Xe = sol.y[:9, -1].reshape(3, 3)
     return state, Xe[1:] - Xe[0]
+
+
+def ring_chain(n, a=1.0, m=3e-6):
+    """n bodies of mass m evenly spaced on a circular orbit of radius a about
+    the star (democratic state, coplanar).  With n1 = 3, n2 = 0 and m = 3e-6
+    the critical radius 3 R_H = 0.03 a exceeds the spacing 2 pi a / n for
+    n >= 210, so every body meets its neighbours and the encounter graph is
+    one chain: a single close-encounter group of all n bodies."""
+    th = 2 * np.pi * np.arange(n) / n
+    v = np.sqrt(G * (1.0 + m) / a)
+    mm = np.full(n, m)
+    vh = np.stack([-v * np.sin(th), v * np.cos(th), np.zeros(n)], 1)
+    vb = vh - (mm[:, None] * vh).sum(0) / (1.0 + mm.sum())
+    return {"x": a * np.cos(th), "y": a * np.sin(th), "z": np.zeros(n),
+            "vx": vb[:, 0].copy(), "vy": vb[:, 1].copy(), "vz": vb[:, 2].copy(), "m": mm}

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from encounter_fixture import two_planets
+from encounter_fixture import ring_chain, two_planets
 from paper_2201_10058_amd import native as N
 from paper_2201_10058_amd import workload as W
 
@@ -77,12 +77,51 @@ def test_direct_follows_a_close_encounter(dev, L, s):
     assert e_or < 1e-8
 
 
-def test_oversized_group_is_reported(dev):
-    # without levels the 2,048-body disk's level-0 list joins far more than
-    # 256 bodies in one group
+@pytest.mark.parametrize("n", [230, 300, 500])
+def test_direct_group_of_hundreds(dev, n):
+    # one group of n bodies (a ring whose neighbours are inside each other's
+    # critical radius): the 256- and 512-thread Bulirsch-Stoer classes
+    # against the oracle's RK4 group flow
+    ring = ring_chain(n)
+    st = N.State.from_numpy(ring)
+    cfg = N.Config(G=G, slevels=1, substeps=1, level_capacity=4 * n, direct=1, n1=3.0, n2=0.0)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(ring)
+    for _ in range(2):
+        assert N.step(st, cfg, ws) == N.OK
+        gs = N.group_stats(st.n, cfg, ws)
+        r = oracle.step_direct(ref, G, 1.0, 6.0, 3.0, 0.0, 1, 1, rk_steps=200)
+        assert r[6] == 0 and gs == r[5] == (1, n), (gs, r[5])
+    out = st.numpy()
+    ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
+    _say(f"group of {n}: position {ep:.2e} velocity {ev:.2e}")
+    assert ep < 1e-11 and ev < 1e-11
+
+
+def test_direct_disk2048_one_level(dev):
+    # without levels the 2,048-body disk's level-0 list forms groups of up to
+    # 337 bodies, all within the direct solver's reach
     d = W.make_disk(W.DISK_2048)
     st = N.State.from_numpy(d)
     cfg = _cfg(1, 1)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(d)
+    assert N.step(st, cfg, ws) == N.OK
+    gs = N.group_stats(st.n, cfg, ws)
+    r = oracle.step_direct(ref, G, 1.0, 6.0, 3.0, 0.4, 1, 1, rk_steps=200)
+    assert r[6] == 0 and gs == r[5], (gs, r[5])
+    out = st.numpy()
+    ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
+    _say(f"disk2048 one level: groups {gs}, position {ep:.2e} velocity {ev:.2e}")
+    assert gs[1] > 256
+    assert ep < 1e-11 and ev < 1e-11
+
+
+def test_oversized_group_is_reported(dev):
+    # a ring of 600 neighbours in one chain: more than GENGA_GROUP_MAX = 512
+    ring = ring_chain(600)
+    st = N.State.from_numpy(ring)
+    cfg = N.Config(G=G, slevels=1, substeps=1, level_capacity=4096, direct=1, n1=3.0, n2=0.0)
     ws = N.Workspace(st.n, cfg)
     assert N.step(st, cfg, ws) == N.E_GROUP
 
