@@ -364,7 +364,8 @@ def bench_gr(N, W, torch, np, steps=10):
         cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
                        flags=N.FLAG_NOSYNC, c_light=c)
         ws = N.Workspace(st.n, cfg)
-        N.step(st, cfg, ws)
+        for _ in range(3):
+            N.step(st, cfg, ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
