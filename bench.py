@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--slices", type=int, default=0)
     ap.add_argument("--kick-form", choices=("auto", "symmetric", "one-sided"), default="auto",
-                    help="binary64 kick form (auto: symmetric from 16,384 bodies)")
+                    help="binary64 kick form (auto: symmetric from 8,192 bodies)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target duration of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -546,7 +546,7 @@ def main():
     hip = HipEvents()
 
     form_flags = {"auto": 0, "symmetric": N.FLAG_SYMMETRIC, "one-sided": N.FLAG_DIRECTED}
-    sym = args.kick_form == "symmetric" or (args.kick_form == "auto" and n >= 16384)
+    sym = args.kick_form == "symmetric" or (args.kick_form == "auto" and n >= 8192)
 
     def run(precision, form=None):
         """Warm up, then time `steps` base steps; returns the measurements."""

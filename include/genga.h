@@ -77,7 +77,7 @@ extern "C" {
  * it to both bodies; the one-sided form evaluates every ordered pair for its
  * first body.  Both give the same encounter list (bit for bit) and
  * accelerations that differ by summation order only.  By default the
- * symmetric form runs from n >= 16384 bodies in the all-massive kick, binary64
+ * symmetric form runs from n >= 8192 bodies in the all-massive kick, binary64
  * and mixed (genga_kick, genga_step and the levels' base kick); the flags
  * force one form at any n (both set: GENGA_E_INVAL).  Test-particle modes,
  * the batch and genga_encounter_pairs are one-sided. */

@@ -65,7 +65,11 @@ struct SymShape {
     __host__ __device__ int64_t bf(int64_t g) const { return g * S0 - d * ((g * (g + 1)) / 2); }
 };
 SymShape sym_shape(int64_t n, int W);
-constexpr int64_t SYM_MIN_N = 16384;   // default: symmetric kick from this many bodies
+constexpr int64_t SYM_MIN_N = 8192;    // default: symmetric kick from this many bodies
+// below this many bodies the symmetric kick's row totals are summed in
+// SYM_FOLD parts over the whole chip before the reduction (k_sym_fold)
+constexpr int64_t SYM_FOLD_BELOW = 32768;
+constexpr int SYM_FOLD = 8;
 hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const double *x,
                            const double *y, const double *z, const double *m, const double *rc,
                            double *rowpart, double *colpart, int32_t *cnt, int32_t *stage,

@@ -500,9 +500,65 @@ struct ReduceDev {
     int sym;                      // symmetric kick: row sums per tile, then column sums
     SymShape sh;
     const double *colpart;
+    const double *fold;           // symmetric kick, small n: [SYM_FOLD][pstride][npad] part sums
+                                  // (k_sym_fold), else null
     double kappa2;                // mixed: square of the refinement threshold (else 0)
     int32_t *refine_list, *refine_cnt;
 };
+
+// Symmetric kick, small n (few rows per block of the reduction): the sum of
+// row i's values -- its group's tile sums in slice order, then the column sums
+// of groups 0..g(i) in group order -- cut into SYM_FOLD contiguous parts, one
+// thread per (part, component, row), so that the whole chip shares the loads;
+// k_kick_reduce adds the parts in order (the same bits on every run).
+struct SymFoldDev {
+    const double *rowpart, *colpart;
+    double *fold;
+    SymShape sh;
+    int ps;
+    int64_t npad;
+};
+
+__global__ __launch_bounds__(RB) void k_sym_fold(SymFoldDev f)
+{
+    const int64_t idx = (int64_t)blockIdx.x * RB + threadIdx.x;
+    const int64_t per = (int64_t)f.ps * f.npad;
+    const int k = (int)(idx / per);
+    const int c = (int)((idx % per) / f.npad);
+    const int64_t i = idx % f.npad;
+    if (k >= SYM_FOLD || i >= f.sh.n) return;
+    const int64_t g = i / SYM_RG;
+    const int64_t ns = f.sh.ns(g), len = ns + g + 1;
+    const int64_t e0 = len * k / SYM_FOLD, e1 = len * (k + 1) / SYM_FOLD;
+    const double *rp = f.rowpart + ((size_t)f.sh.tb(g) * f.ps + c) * SYM_RG + (i - g * SYM_RG);
+    double acc = 0.0;
+    int64_t e = e0;
+    for (; e + 8 <= e1; e += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t q = e + u;
+            if (q < ns) {
+                v[u] = rp[(size_t)q * f.ps * SYM_RG];
+            } else {
+                const int64_t gg = q - ns;
+                v[u] = f.colpart[(size_t)f.ps * f.sh.coloff(gg) + c * f.sh.collen(gg) +
+                                 (i - gg * SYM_RG)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; e < e1; ++e) {
+        if (e < ns) {
+            acc += rp[(size_t)e * f.ps * SYM_RG];
+        } else {
+            const int64_t gg = e - ns;
+            acc += f.colpart[(size_t)f.ps * f.sh.coloff(gg) + c * f.sh.collen(gg) + (i - gg * SYM_RG)];
+        }
+    }
+    f.fold[((size_t)k * f.ps + c) * f.npad + i] = acc;
+}
 
 // Symmetric kick: total of row i (group grp) over its nsl tiles and the
 // column sums of groups 0..grp; components 0-2 into a3, component 3 (mixed:
@@ -612,7 +668,17 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     if (r.forces && valid) {
         double a3[3];
         double mag = 0.0;
-        if (r.sym) {
+        if (r.sym && r.fold) {
+            // the SYM_FOLD part sums of k_sym_fold, in part order
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < SYM_FOLD; ++k)
+                for (int c = 0; c < r.pstride; ++c)
+                    acc[c] += r.fold[((size_t)k * r.pstride + c) * r.npad + i];
+            a3[0] = acc[0];
+            a3[1] = acc[1];
+            a3[2] = acc[2];
+            mag = acc[3];
+        } else if (r.sym) {
             // row sums of the group's tiles in slice order, then the column
             // sums of the groups up to row i's in group order; the loads of
             // 8 tiles (groups) and all components are issued before their
@@ -1167,7 +1233,10 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     off += 256;
     // the symmetric kick's row sums [T][3][SYM_RG] and column sums share the
     // partial-sum region; its per-tile pair counts the count region
-    const size_t sym_part = c.use_sym ? 4 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G)) : 0;
+    const size_t sym_part =
+        c.use_sym ? 4 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G)) +
+                        (n < SYM_FOLD_BELOW ? (size_t)SYM_FOLD * 4 * L.npad : 0)
+                  : 0;
     const size_t sym_cnt = c.use_sym ? (size_t)c.sym.T * SYM_RG : 0;
     const size_t nw = std::max<size_t>((size_t)c.nwaves, c.use_sym ? (size_t)c.sym.T * SYM_NW : 0);
     L.part = off;   // 3 values per row and slice for the kick, 5 for its adjoint
@@ -1345,11 +1414,26 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
     r.refine_list = (int32_t *)(ws + L.rlist);
     r.refine_cnt = d.refine_cnt;
+    r.fold = nullptr;
     if ((r.forces || r.emit) && c.tp && c.nm > 0 && c.s_m > 1) {
         hipLaunchKernelGGL(k_fold_massive, dim3((unsigned)c.nm), dim3(FT), 0, s, r);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         r.m_folded = 1;
+    }
+    if (sym && r.forces && k.n < SYM_FOLD_BELOW) {
+        SymFoldDev f;
+        f.rowpart = d.part;
+        f.colpart = r.colpart;
+        f.fold = d.part + (size_t)4 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G));
+        f.sh = c.sym;
+        f.ps = sym_ps;
+        f.npad = L.npad;
+        const int64_t threads = (int64_t)SYM_FOLD * sym_ps * L.npad;
+        hipLaunchKernelGGL(k_sym_fold, dim3((unsigned)((threads + RB - 1) / RB)), dim3(RB), 0, s, f);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        r.fold = f.fold;
     }
     if (r.forces || r.emit) {
         hipLaunchKernelGGL(k_kick_reduce, dim3((unsigned)L.nb), dim3(RB), 0, s, r);

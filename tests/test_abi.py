@@ -115,7 +115,7 @@ def test_symmetric_kick_workspace_on_host(n):
         for prec in (native.FP64, native.MIXED):
             p = native.Config(G=2.959e-4, flags=flags, precision=prec).params()
             ws = lib.genga_workspace_bytes(n, ctypes.byref(p))
-            sym = flags == native.FLAG_SYMMETRIC or (flags == 0 and n >= 16384)
+            sym = flags == native.FLAG_SYMMETRIC or (flags == 0 and n >= 8192)
             if sym:
                 assert ws >= need, (n, flags, prec, ws, need)
             assert ws > 0

@@ -203,7 +203,7 @@ def test_sym_graph_replay_bitwise(dev):
 
 
 def test_sym_disk16384_default_form(dev):
-    # from 16,384 bodies the library picks the symmetric form by itself
+    # from 8,192 bodies the library picks the symmetric form by itself
     d = W.make_disk(W.DISK_MIXED[16384])
     rc = oracle.rcrit(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["m"], 1.0, 6.0, 3.0, 0.4)
     a, (pi, pj, cnt), code, _ = _run_kick(d, rc, 0)
