@@ -467,8 +467,13 @@ int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_p
 /* Workspace for genga_autotune: the largest any candidate needs. */
 size_t genga_autotune_workspace_bytes(int64_t n, const genga_params *p);
 
-/* Single-system kick.  Candidates: rows per thread {1, 2} x column slices
- * {library choice, 8, 16, 32, 64}.  Writes p->ipt and p->slices. */
+/* Single-system kick.  Candidates: the one-sided form with rows per thread
+ * {1, 2} x column slices {library choice, 8, 16, 32, 64}, and (without a
+ * test-particle mode) the symmetric form with slices {library choice, 1, 2, 4,
+ * 8} (see genga_params.slices).  Writes p->ipt, p->slices and the form
+ * (GENGA_FLAG_DIRECTED or GENGA_FLAG_SYMMETRIC in p->flags, the other form
+ * flag cleared).  Cache lines written before the symmetric form existed
+ * (seven fields) read as the library's form. */
 int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_bytes,
                    const char *cache_path, double *ms_out, void *stream);
 

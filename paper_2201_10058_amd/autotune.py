@@ -50,7 +50,9 @@ def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool 
 
 
 def tune_single(state: N.State, cfg: N.Config, use_cache: bool = True) -> dict:
-    """Pick (ipt, slices) for the single-system kick of this size."""
+    """Pick the kick form (one-sided or symmetric) and its (ipt, slices) for
+    the single-system kick of this size; `flags` is cfg.flags with the chosen
+    form flag."""
     lib = N.load()
     p = cfg.params()
     nbytes = lib.genga_autotune_workspace_bytes(state.n, ctypes.byref(p))
@@ -64,7 +66,8 @@ def tune_single(state: N.State, cfg: N.Config, use_cache: bool = True) -> dict:
                                 ctypes.c_size_t(int(nbytes)), path, ctypes.byref(ms),
                                 ctypes.c_void_p(N._stream_ptr())),
              "genga_autotune")
-    return dict(ipt=p.ipt, slices=p.slices, ms=ms.value)
+    form = "symmetric" if p.flags & N.FLAG_SYMMETRIC else "one-sided"
+    return dict(form=form, ipt=p.ipt, slices=p.slices, flags=p.flags, ms=ms.value)
 
 
 def tune_levels(state: N.State, cfg: N.Config, candidates, steps: int = 10) -> dict:

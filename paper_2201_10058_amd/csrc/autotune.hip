@@ -18,6 +18,7 @@ namespace {
 
 struct Shape {
     int block = 0, ipt = 0, tile_cols = 0, grid = 0, slices = 0;
+    int flags = 0;   // single system: GENGA_FLAG_DIRECTED or GENGA_FLAG_SYMMETRIC (0: library choice)
 };
 
 std::string arch_name()
@@ -76,8 +77,9 @@ bool cache_lookup(const char *path, const std::string &key, Shape &out, double &
     while (fgets(line, sizeof line, f)) {
         Shape s;
         double t = 0.0;
-        if (sscanf(line, "%383s %d %d %d %d %d %lf", k, &s.block, &s.ipt, &s.tile_cols, &s.grid,
-                   &s.slices, &t) == 7 &&
+        // (the kick-form flags are an optional eighth field)
+        if (sscanf(line, "%383s %d %d %d %d %d %lf %d", k, &s.block, &s.ipt, &s.tile_cols, &s.grid,
+                   &s.slices, &t, &s.flags) >= 7 &&
             key == k) {
             out = s;
             ms = t;
@@ -93,8 +95,8 @@ void cache_store(const char *path, const std::string &key, const Shape &s, doubl
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), s.block, s.ipt, s.tile_cols, s.grid,
-            s.slices, ms);
+    fprintf(f, "%s %d %d %d %d %d %.6f %d\n", key.c_str(), s.block, s.ipt, s.tile_cols, s.grid,
+            s.slices, ms, s.flags);
     fclose(f);
 }
 
@@ -151,7 +153,10 @@ std::vector<Shape> batch_candidates()
     return v;
 }
 
-std::vector<Shape> single_candidates()
+// One-sided form: rows per thread x column slices; symmetric form (binary64
+// or mixed, every body massive): slice widths (slices d = 1, 2, 4, 8 of a
+// 512-row group, or the library's width).
+std::vector<Shape> single_candidates(const genga_params *p)
 {
     std::vector<Shape> v;
     for (int ipt : {1, 2})
@@ -159,10 +164,20 @@ std::vector<Shape> single_candidates()
             Shape s;
             s.ipt = ipt;
             s.slices = sl;
+            s.flags = GENGA_FLAG_DIRECTED;
+            v.push_back(s);
+        }
+    if (p->tp_mode == 0)
+        for (int sl : {0, 1, 2, 4, 8}) {
+            Shape s;
+            s.slices = sl;
+            s.flags = GENGA_FLAG_SYMMETRIC;
             v.push_back(s);
         }
     return v;
 }
+
+constexpr int FORM_FLAGS = GENGA_FLAG_DIRECTED | GENGA_FLAG_SYMMETRIC;
 
 genga_params timing_params(const genga_params *p)
 {
@@ -234,9 +249,10 @@ size_t genga_autotune_workspace_bytes(int64_t n, const genga_params *p)
 {
     if (!p || n < 1) return 0;
     size_t most = 0;
-    for (const Shape &s : single_candidates()) {
+    for (const Shape &s : single_candidates(p)) {
         genga_params q = *p;
         apply(s, &q);
+        q.flags = (p->flags & ~FORM_FLAGS) | s.flags;
         most = std::max(most, genga_workspace_bytes(n, &q));
     }
     return most;
@@ -252,9 +268,10 @@ int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_b
     double best_ms = -1.0;
     if (!cache_lookup(cache_path, key, best, best_ms)) {
         best_ms = -1.0;
-        for (const Shape &c : single_candidates()) {
+        for (const Shape &c : single_candidates(p)) {
             genga_params q = timing_params(p);
             apply(c, &q);
+            q.flags = (p->flags & ~FORM_FLAGS) | c.flags;
             q.block = p->block;
             q.tile_cols = p->tile_cols;
             q.grid = p->grid;
@@ -274,6 +291,7 @@ int genga_autotune(const genga_bodies *b, genga_params *p, void *ws, size_t ws_b
     }
     p->ipt = best.ipt;
     p->slices = best.slices;
+    p->flags = (p->flags & ~FORM_FLAGS) | (best.flags & FORM_FLAGS);
     if (ms_out) *ms_out = best_ms;
     return GENGA_OK;
 }

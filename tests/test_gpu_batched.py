@@ -251,15 +251,28 @@ def test_autotune_batched_choice_is_valid(dev, tmp_path, monkeypatch):
     assert np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)) <= 1e-13
 
 
-def test_autotune_single_choice_is_valid(dev, tmp_path, monkeypatch):
+@pytest.mark.parametrize("n", [2048, 16384])
+def test_autotune_single_choice_is_valid(dev, tmp_path, monkeypatch, n):
+    # the tuner picks a form and its shape; the cached choice comes back, and
+    # the chosen shape computes the default kick's accelerations
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv(autotune.CACHE_ENV, str(cache))
-    d = W.make_disk(W.DISK_2048)
+    d = W.make_disk(W.DISK_2048 if n == 2048 else W.DISK_MIXED[n])
     st = N.State.from_numpy(d)
     cfg = N.Config(G=G)
     choice = autotune.tune_single(st, cfg)
-    _say("autotuned single shape", choice)
-    assert choice["ipt"] in (1, 2) and choice["slices"] in (0, 8, 16, 32, 64)
+    _say("autotuned single shape", n, choice)
+    if choice["form"] == "one-sided":
+        assert choice["flags"] & N.FLAG_DIRECTED
+        assert choice["ipt"] in (1, 2) and choice["slices"] in (0, 8, 16, 32, 64)
+    else:
+        assert choice["flags"] & N.FLAG_SYMMETRIC and choice["slices"] in (0, 1, 2, 4, 8)
     again = autotune.tune_single(st, cfg)
-    assert (again["ipt"], again["slices"]) == (choice["ipt"], choice["slices"])
+    assert {k: again[k] for k in ("form", "ipt", "slices")} == \
+        {k: choice[k] for k in ("form", "ipt", "slices")}
     assert cache.read_text().splitlines()[0].startswith("single:")
+    tuned = N.Config(G=G, ipt=choice["ipt"], slices=choice["slices"], flags=choice["flags"])
+    N.rcrit(st, cfg, N.Workspace(st.n, cfg))
+    a0 = N.kick(st, cfg, N.Workspace(st.n, cfg), 0.0, acc=True).cpu().numpy()
+    a1 = N.kick(st, tuned, N.Workspace(st.n, tuned), 0.0, acc=True).cpu().numpy()
+    assert np.max(np.linalg.norm(a0 - a1, axis=0) / np.linalg.norm(a0, axis=0)) <= 1e-13
