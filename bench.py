@@ -408,6 +408,7 @@ def bench_batched(args, N, W, torch, np):
     torch.cuda.synchronize()
     choice = autotune.tune_batched(st, bt, base)
     tune_ms = choice.pop("ms")
+    form = choice.pop("form")
     cfg = N.Config(**{**base.__dict__, **choice})
     ws = N.BatchWorkspace(bt, cfg)
     pairs = N.PairList(1 << 22)
@@ -432,6 +433,19 @@ def bench_batched(args, N, W, torch, np):
     code = N.read_status(ws)
     if code != N.OK:
         raise SystemExit(f"batched status: {code}")
+    # the other kick form on the same ensemble (captured step)
+    forms = N.FLAG_DIRECTED | N.FLAG_SYMMETRIC
+    other = N.FLAG_SYMMETRIC if form == "one-sided" else N.FLAG_DIRECTED
+    cfg_o = N.Config(**{**cfg.__dict__, "flags": (cfg.flags & ~forms) | other})
+    ws_o = N.BatchWorkspace(bt, cfg_o)
+    N.step_batched(st, ws_o, cfg_o, pairs)
+    torch.cuda.synchronize()
+    g_o = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_o):
+        N.step_batched(st, ws_o, cfg_o, pairs)
+    other_s = timed(g_o.replay, K)
+    if N.read_status(ws_o) != N.OK:
+        raise SystemExit("batched status (other form)")
     # per-system launches (each system its own genga_step calls)
     views, wss = [], []
     for s_ in range(d["S"]):
@@ -462,8 +476,12 @@ def bench_batched(args, N, W, torch, np):
             "per_system_graph_step_ms": round(per_sys_graph_s * 1e3, 4),
             "speedup_vs_per_system_graph": round(per_sys_graph_s / graph_s, 3),
             "speedup_vs_per_system_eager": round(per_sys_s / graph_s, 3),
-            "tile_shape": {**choice, "tiles": ws.info["tiles"], "grid": ws.info["grid"],
-                           "autotuned_kick_ms": round(tune_ms, 4)}}
+            "tile_shape": {**choice, "form": form,
+                           **({"tiles": ws.info["tiles"], "grid": ws.info["grid"]}
+                              if form == "one-sided" else {}),
+                           "autotuned_kick_ms": round(tune_ms, 4)},
+            "other_form": {"form": "symmetric" if form == "one-sided" else "one-sided",
+                           "graph_step_ms": round(other_s * 1e3, 4)}}
 
 
 def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):

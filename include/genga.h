@@ -78,9 +78,11 @@ extern "C" {
  * first body.  Both give the same encounter list (bit for bit) and
  * accelerations that differ by summation order only.  By default the
  * symmetric form runs from n >= 8192 bodies in the all-massive kick, binary64
- * and mixed (genga_kick, genga_step and the levels' base kick); the flags
- * force one form at any n (both set: GENGA_E_INVAL).  Test-particle modes,
- * the batch and genga_encounter_pairs are one-sided. */
+ * and mixed (genga_kick, genga_step and the levels' base kick), and in the
+ * binary64 batch (genga_kick_batched, genga_step_batched; every system, in
+ * 512-row groups and 512-column slices); the flags force one form at any n
+ * (both set: GENGA_E_INVAL).  Test-particle modes, the mixed batch and
+ * genga_encounter_pairs are one-sided. */
 #define GENGA_FLAG_DIRECTED  2
 #define GENGA_FLAG_SYMMETRIC 4
 
@@ -454,9 +456,11 @@ int genga_step_batched(genga_bodies *b, const genga_batch *bt, const genga_param
 /* Workspace for genga_autotune_batched: the largest any candidate needs. */
 size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga_params *p);
 
-/* Batched kick.  Candidates: block {64, 256} x rows per thread {1, 2} x
- * tile_cols {256, 512, 1024, 2048} x grid {library choice, 32 waves per CU}.
- * Writes p->block, p->ipt, p->tile_cols, p->grid (p->slices = 0).  On return
+/* Batched kick.  Candidates: the one-sided form with block {64, 256} x rows
+ * per thread {1, 2} x tile_cols {256, 512, 1024, 2048} x grid {library
+ * choice, 32 waves per CU}, and (binary64) the symmetric form.  Writes
+ * p->block, p->ipt, p->tile_cols, p->grid (p->slices = 0) and the form flag
+ * in p->flags.  On return
  * ws holds the plan of the chosen shape (as after genga_batch_plan).
  * ws_bytes >= genga_autotune_batched_workspace_bytes(bt, p), else candidates
  * that do not fit are skipped.  GENGA_E_UNSUPPORTED if no candidate ran. */

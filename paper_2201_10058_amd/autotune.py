@@ -30,8 +30,8 @@ def cache_path() -> str:
 
 
 def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool = True) -> dict:
-    """Pick (block, ipt, tile_cols, grid) for the batched kick; returns the choice
-    (with the time of one kick in "ms")."""
+    """Pick the batched kick's form and, for the one-sided form, (block, ipt,
+    tile_cols, grid); returns the choice (with the time of one kick in "ms")."""
     lib = N.load()
     bt = batch.struct()
     p = cfg.params()
@@ -46,7 +46,9 @@ def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool 
                                         ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(int(nbytes)),
                                         path, ctypes.byref(ms), ctypes.c_void_p(N._stream_ptr())),
              "genga_autotune_batched")
-    return dict(block=p.block, ipt=p.ipt, tile_cols=p.tile_cols, grid=p.grid, ms=ms.value)
+    form = "symmetric" if p.flags & N.FLAG_SYMMETRIC else "one-sided"
+    return dict(form=form, block=p.block, ipt=p.ipt, tile_cols=p.tile_cols, grid=p.grid,
+                flags=p.flags, ms=ms.value)
 
 
 def tune_single(state: N.State, cfg: N.Config, use_cache: bool = True) -> dict:

@@ -16,6 +16,7 @@
 namespace genga {
 namespace {
 
+
 struct Shape {
     int block = 0, ipt = 0, tile_cols = 0, grid = 0, slices = 0;
     int flags = 0;   // single system: GENGA_FLAG_DIRECTED or GENGA_FLAG_SYMMETRIC (0: library choice)
@@ -135,7 +136,9 @@ double time_ms(F &&call, hipStream_t s, int reps)
     return (double)t[t.size() / 2];
 }
 
-std::vector<Shape> batch_candidates()
+// One-sided tile shapes, and (binary64) the symmetric form, whose shape is
+// fixed (512-row groups, 512-column slices).
+std::vector<Shape> batch_candidates(const genga_params *p)
 {
     std::vector<Shape> v;
     const int cu = cus();
@@ -148,8 +151,14 @@ std::vector<Shape> batch_candidates()
                     s.ipt = ipt;
                     s.tile_cols = cols;
                     s.grid = g;
+                    s.flags = GENGA_FLAG_DIRECTED;
                     v.push_back(s);
                 }
+    if (p->precision == GENGA_FP64) {
+        Shape s;
+        s.flags = GENGA_FLAG_SYMMETRIC;
+        v.push_back(s);
+    }
     return v;
 }
 
@@ -197,9 +206,10 @@ size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga
 {
     if (!p) return 0;
     size_t most = 0;
-    for (const Shape &s : batch_candidates()) {
+    for (const Shape &s : batch_candidates(p)) {
         genga_params q = *p;
         apply(s, &q);
+        q.flags = (p->flags & ~FORM_FLAGS) | s.flags;
         most = std::max(most, genga_batch_workspace_bytes(bt, &q));
     }
     return most;
@@ -217,9 +227,10 @@ int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_p
     double best_ms = -1.0;
     if (!cache_lookup(cache_path, key, best, best_ms)) {
         best_ms = -1.0;
-        for (const Shape &c : batch_candidates()) {
+        for (const Shape &c : batch_candidates(p)) {
             genga_params q = timing_params(p);
             apply(c, &q);
+            q.flags = (p->flags & ~FORM_FLAGS) | c.flags;
             const size_t need = genga_batch_workspace_bytes(bt, &q);
             if (need == 0 || need > ws_bytes) continue;
             if (genga_batch_plan(bt, &q, ws, stream) != GENGA_OK) continue;
@@ -238,6 +249,7 @@ int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_p
         cache_store(cache_path, key, best, best_ms);
     }
     apply(best, p);
+    p->flags = (p->flags & ~FORM_FLAGS) | (best.flags & FORM_FLAGS);
     if (genga_batch_workspace_bytes(bt, p) > ws_bytes) return GENGA_E_INVAL;
     const int r = genga_batch_plan(bt, p, ws, stream);
     if (r != GENGA_OK) return r;

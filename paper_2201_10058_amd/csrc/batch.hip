@@ -74,7 +74,56 @@ static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape 
     int64_t grid = (p && p->grid > 0) ? p->grid : (int64_t)cu_count() * per_cu;
     if (grid > ntiles) grid = ntiles;
     c.grid = (int)grid;
+    // binary64: the symmetric kick over every system (slices of SYM_RG
+    // columns, so system s has G_s (G_s + 1) / 2 tiles)
+    if ((!p || p->precision == GENGA_FP64) && !(p && (p->flags & GENGA_FLAG_DIRECTED))) {
+        c.use_symb = true;
+        c.symb_S = bt->S;
+        c.symb_T = 0;
+        c.symb_cols = 0;
+        for (int64_t q = 0; q < bt->S; ++q) {
+            const SymShape h = sym_shape(bt->offsets[q + 1] - bt->offsets[q], SYM_RG);
+            c.symb_T += h.T;
+            c.symb_cols += h.coloff(h.G);
+        }
+    }
     return GENGA_OK;
+}
+
+// Symmetric kick of a batch: per-system shapes and offsets, tiles in storage
+// order (system by system, tb(g) + s within a system) and the launch order
+// (decreasing work: rows x columns, halved on the diagonal).
+static void build_sym_plan(const genga_batch *bt, const BatchShape &sh, std::vector<SymSys> &sys,
+                           std::vector<SymTileB> &tiles, std::vector<int32_t> &order)
+{
+    sys.assign((size_t)bt->S, SymSys{});
+    tiles.clear();
+    tiles.reserve((size_t)sh.cfg.symb_T);
+    std::vector<int64_t> cost;
+    cost.reserve((size_t)sh.cfg.symb_T);
+    int64_t tbase = 0, cbase = 0;
+    for (int64_t q = 0; q < bt->S; ++q) {
+        SymSys &ss = sys[(size_t)q];
+        ss.o = bt->offsets[q];
+        ss.sh = sym_shape(bt->offsets[q + 1] - ss.o, SYM_RG);
+        ss.tbase = tbase;
+        ss.cbase = cbase;
+        const int64_t n = ss.sh.n;
+        for (int64_t g = 0; g < ss.sh.G; ++g) {
+            const int64_t rows = std::min<int64_t>(SYM_RG, n - g * SYM_RG);
+            for (int64_t k = 0; k < ss.sh.ns(g); ++k) {
+                const int64_t cols = std::min<int64_t>(ss.sh.W, n - g * SYM_RG - k * ss.sh.W);
+                tiles.push_back(SymTileB{(int32_t)q, (int32_t)g, (int32_t)k, 0});
+                cost.push_back(k < ss.sh.d ? rows * cols / 2 : rows * cols);
+            }
+        }
+        tbase += ss.sh.T;
+        cbase += 3 * ss.sh.coloff(ss.sh.G);
+    }
+    order.resize(tiles.size());
+    for (size_t t = 0; t < order.size(); ++t) order[t] = (int32_t)t;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
 }
 
 // Tile list (sorted by decreasing work, ties by position), body -> system map
@@ -203,6 +252,21 @@ int genga_batch_plan(const genga_batch *bt, const genga_params *p, void *ws, voi
     if ((e = hipMemcpyAsync(w + L.offsets, bt->offsets, (size_t)(bt->S + 1) * sizeof(int64_t),
                             hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_err(e);
+    if (sh.cfg.use_symb) {
+        std::vector<SymSys> ssys;
+        std::vector<SymTileB> stiles;
+        std::vector<int32_t> sorder;
+        build_sym_plan(bt, sh, ssys, stiles, sorder);
+        if ((e = hipMemcpyAsync(w + L.symsys, ssys.data(), ssys.size() * sizeof(SymSys),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_err(e);
+        if ((e = hipMemcpyAsync(w + L.symtiles, stiles.data(), stiles.size() * sizeof(SymTileB),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_err(e);
+        if ((e = hipMemcpyAsync(w + L.symorder, sorder.data(), sorder.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_err(e);
+    }
     const int32_t zero2[2] = {0, 0};   // status word and tile counter
     if ((e = hipMemcpyAsync(w + L.status, zero2, sizeof(zero2), hipMemcpyHostToDevice, s)) !=
         hipSuccess)

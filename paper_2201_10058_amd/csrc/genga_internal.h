@@ -65,6 +65,25 @@ struct SymShape {
     __host__ __device__ int64_t bf(int64_t g) const { return g * S0 - d * ((g * (g + 1)) / 2); }
 };
 SymShape sym_shape(int64_t n, int W);
+
+// Batch of systems in the symmetric kick: per system its shape (n = its
+// bodies), first body o, first storage tile tbase and the offset cbase of
+// its column sums (in doubles, per component block as in one system); per
+// tile (in storage order) its system, group and slice; order[t] the storage
+// number of the t-th launched tile (decreasing work).
+struct SymSys {
+    SymShape sh;
+    int64_t o, tbase, cbase;
+};
+struct SymTileB {
+    int32_t sys, g, s, pad;
+};
+struct SymBatch {
+    const SymSys *sys;
+    const SymTileB *tiles;
+    const int32_t *order;
+    int64_t S, T;
+};
 constexpr int64_t SYM_MIN_N = 8192;    // default: symmetric kick from this many bodies
 // below this many bodies the symmetric kick's row totals are summed in
 // SYM_FOLD parts over the whole chip before the reduction (k_sym_fold)
@@ -75,10 +94,15 @@ hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const do
                            double *rowpart, double *colpart, int32_t *cnt, int32_t *stage,
                            int32_t *wcount, int32_t *status, int32_t *refine_cnt, bool emit,
                            hipStream_t s);
-hipError_t launch_scatter_sym(const SymShape &h, const double *x, const double *y,
-                              const double *z, const double *rc, const int32_t *cnt,
-                              const int32_t *stage, const int32_t *wcount, const int32_t *rowloc,
-                              const int64_t *boff, genga_pairs *pairs, hipStream_t s);
+hipError_t launch_kick_sym_b(const SymBatch &b, const double *x, const double *y,
+                             const double *z, const double *m, const double *rc, double *rowpart,
+                             double *colpart, int32_t *cnt, int32_t *stage, int32_t *wcount,
+                             int32_t *status, bool emit, hipStream_t s);
+hipError_t launch_scatter_sym(const SymShape &h, const SymBatch *b, const double *x,
+                              const double *y, const double *z, const double *rc,
+                              const int32_t *cnt, const int32_t *stage, const int32_t *wcount,
+                              const int32_t *rowloc, const int64_t *boff, genga_pairs *pairs,
+                              hipStream_t s);
 
 // Launch shape of the kick.
 struct KickCfg {
@@ -107,6 +131,10 @@ struct KickCfg {
     // of the one-sided tiles above
     bool use_sym = false;
     SymShape sym;
+    // binary64 batch in the symmetric kick: tiles and column-sum doubles (per
+    // component) of all systems
+    bool use_symb = false;
+    int64_t symb_S = 0, symb_T = 0, symb_cols = 0;
 };
 
 // Byte offsets of the workspace regions.
@@ -128,6 +156,9 @@ struct Layout {
     size_t sysid = 0;      // batch: int32 [npad]
     size_t sys_slices = 0; // batch: int32 [S]
     size_t offsets = 0;    // batch: int64 [S + 1]
+    size_t symsys = 0;     // batch, symmetric kick: SymSys [S]
+    size_t symtiles = 0;   // batch, symmetric kick: SymTileB [T]
+    size_t symorder = 0;   // batch, symmetric kick: int32 [T]
     size_t total = 0;
     int64_t npad = 0;
     int64_t nb = 0;

@@ -502,6 +502,7 @@ struct ReduceDev {
     const double *colpart;
     const double *fold;           // symmetric kick, small n: [SYM_FOLD][pstride][npad] part sums
                                   // (k_sym_fold), else null
+    const SymSys *symb_sys;       // symmetric kick of a batch: per-system shapes, else null
     double kappa2;                // mixed: square of the refinement threshold (else 0)
     int32_t *refine_list, *refine_cnt;
 };
@@ -564,7 +565,9 @@ __global__ __launch_bounds__(RB) void k_sym_fold(SymFoldDev f)
 // column sums of groups 0..grp; components 0-2 into a3, component 3 (mixed:
 // sum of m / r^2) into mag.
 __device__ __forceinline__ void sym_row_total(const ReduceDev &r, const PartRows &pr, int nsl,
-                                              int64_t grp, int64_t i, double a3[3], double &mag)
+                                              int64_t grp, int64_t i, const SymShape &sh,
+                                              const double *colpart, int64_t li, double a3[3],
+                                              double &mag)
 {
     const int nc = r.pstride;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -592,8 +595,8 @@ __device__ __forceinline__ void sym_row_total(const ReduceDev &r, const PartRows
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int64_t g2 = gg + k;
-            const double *cp = r.colpart + (size_t)nc * r.sh.coloff(g2) + (i - g2 * SYM_RG);
-            const int64_t L = r.sh.collen(g2);
+            const double *cp = colpart + (size_t)nc * sh.coloff(g2) + (li - g2 * SYM_RG);
+            const int64_t L = sh.collen(g2);
 #pragma unroll
             for (int c = 0; c < 4; ++c) v[k][c] = c < nc ? cp[c * L] : 0.0;
         }
@@ -603,8 +606,8 @@ __device__ __forceinline__ void sym_row_total(const ReduceDev &r, const PartRows
             for (int c = 0; c < 4; ++c) acc[c] += v[k][c];
     }
     for (; gg < ng; ++gg) {
-        const double *cp = r.colpart + (size_t)nc * r.sh.coloff(gg) + (i - gg * SYM_RG);
-        const int64_t L = r.sh.collen(gg);
+        const double *cp = colpart + (size_t)nc * sh.coloff(gg) + (li - gg * SYM_RG);
+        const int64_t L = sh.collen(gg);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += c < nc ? cp[c * L] : 0.0;
     }
@@ -651,19 +654,32 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
     if (r.tp) nsl = i < r.nm ? (r.m_folded ? 1 : r.s_m) : r.s_t;
     PartRows pr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, r.pstride, i);
     PartRows cr = part_rows(r.tp, r.nm, r.mpad, r.s_m, r.npad, 1, i);
-    const int64_t grp = i / SYM_RG;
-    if (r.sym) {
-        // the tiles of row i's group, slice by slice: [tile][3][SYM_RG]
-        nsl = (int)r.sh.ns(grp);
-        const size_t t0 = (size_t)r.sh.tb(grp);
-        pr = {t0 * r.pstride * SYM_RG - (size_t)grp * SYM_RG, (size_t)SYM_RG};
-        cr = {t0 * SYM_RG - (size_t)grp * SYM_RG, (size_t)SYM_RG};
-    }
     double h = r.h;
     if (valid && r.sysid) {
         const int sy = r.sysid[i];
         nsl = r.sys_slices[sy];
         h = r.hfac * r.sys_dt[sy];
+    }
+    // symmetric kick: row i of its system (local index li, group grp), whose
+    // tiles are stored from t0 on, slice by slice: [tile][pstride][SYM_RG]
+    SymShape ssh = r.sh;
+    const double *scol = r.colpart;
+    int64_t li = i, so = 0, tbase = 0;
+    if (r.sym && r.symb_sys && valid) {
+        const SymSys ss = r.symb_sys[r.sysid[i]];
+        ssh = ss.sh;
+        so = ss.o;
+        li = i - so;
+        tbase = ss.tbase;
+        scol = r.colpart + ss.cbase;
+    }
+    const int64_t grp = li / SYM_RG;
+    if (r.sym) {
+        nsl = (int)ssh.ns(grp);
+        const int64_t t0 = tbase + ssh.tb(grp);
+        // (non-negative: every system before this one has at least one tile per 512 bodies)
+        pr = {(size_t)(t0 * r.pstride * SYM_RG - grp * SYM_RG - so), (size_t)SYM_RG};
+        cr = {(size_t)(t0 * SYM_RG - grp * SYM_RG - so), (size_t)SYM_RG};
     }
     if (r.forces && valid) {
         double a3[3];
@@ -683,7 +699,7 @@ __global__ __launch_bounds__(RB) void k_kick_reduce(ReduceDev r)
             // sums of the groups up to row i's in group order; the loads of
             // 8 tiles (groups) and all components are issued before their
             // additions, whose order is unchanged
-            sym_row_total(r, pr, nsl, grp, i, a3, mag);
+            sym_row_total(r, pr, nsl, grp, i, ssh, scol, li, a3, mag);
         } else {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -1237,10 +1253,16 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
         c.use_sym ? 4 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G)) +
                         (n < SYM_FOLD_BELOW ? (size_t)SYM_FOLD * 4 * L.npad : 0)
                   : 0;
-    const size_t sym_cnt = c.use_sym ? (size_t)c.sym.T * SYM_RG : 0;
-    const size_t nw = std::max<size_t>((size_t)c.nwaves, c.use_sym ? (size_t)c.sym.T * SYM_NW : 0);
+    size_t sym_cnt = c.use_sym ? (size_t)c.sym.T * SYM_RG : 0;
+    size_t nw = std::max<size_t>((size_t)c.nwaves, c.use_sym ? (size_t)c.sym.T * SYM_NW : 0);
+    size_t symb_part = 0;
+    if (c.use_symb) {
+        symb_part = 3 * ((size_t)c.symb_T * SYM_RG + (size_t)c.symb_cols);
+        sym_cnt = std::max(sym_cnt, (size_t)c.symb_T * SYM_RG);
+        nw = std::max(nw, (size_t)c.symb_T * SYM_NW);
+    }
     L.part = off;   // 3 values per row and slice for the kick, 5 for its adjoint
-    off = align256(off + sizeof(double) * std::max(5 * (size_t)c.slices * L.npad, sym_part));
+    off = align256(off + sizeof(double) * std::max({5 * (size_t)c.slices * L.npad, sym_part, symb_part}));
     L.cnt = off;
     off = align256(off + sizeof(int32_t) * std::max((size_t)c.slices * L.npad, sym_cnt));
     L.rowloc = off;
@@ -1272,6 +1294,14 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
         off = align256(off + sizeof(int32_t) * (size_t)S);
         L.offsets = off;
         off = align256(off + sizeof(int64_t) * (size_t)(S + 1));
+        if (c.use_symb) {
+            L.symsys = off;
+            off = align256(off + sizeof(SymSys) * (size_t)S);
+            L.symtiles = off;
+            off = align256(off + sizeof(SymTileB) * (size_t)c.symb_T);
+            L.symorder = off;
+            off = align256(off + sizeof(int32_t) * (size_t)c.symb_T);
+        }
     }
     L.total = off;
     return L;
@@ -1353,13 +1383,28 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
 
     const int mode = !k.forces ? KM_PAIRS : (k.precision == GENGA_MIXED ? KM_MIXED : KM_F64);
     const bool refine = mode == KM_MIXED;
-    const bool sym = c.use_sym && (mode == KM_F64 || mode == KM_MIXED) && !k.tiles && c.tp == 0;
+    const bool symb = c.use_symb && mode == KM_F64 && k.tiles;
+    const bool sym = (c.use_sym && (mode == KM_F64 || mode == KM_MIXED) && !k.tiles && c.tp == 0) || symb;
     const int sym_ps = mode == KM_MIXED ? 4 : 3;
+    const int64_t sym_T = symb ? c.symb_T : c.sym.T;
+    SymBatch sb{nullptr, nullptr, nullptr, 0, 0};
+    if (symb) {
+        sb.sys = (const SymSys *)(ws + L.symsys);
+        sb.tiles = (const SymTileB *)(ws + L.symtiles);
+        sb.order = (const int32_t *)(ws + L.symorder);
+        sb.S = c.symb_S;
+        sb.T = c.symb_T;
+    }
     if (k.ev0) {
         hipError_t e0 = hipEventRecord((hipEvent_t)k.ev0, s);
         if (e0 != hipSuccess) return e0;
     }
-    if (sym) {
+    if (symb) {
+        hipError_t es = launch_kick_sym_b(sb, k.x, k.y, k.z, k.m, k.rc, d.part,
+                                          d.part + (size_t)3 * sym_T * SYM_RG, d.cnt, d.stage,
+                                          d.wcount, d.status, d.emit, s);
+        if (es != hipSuccess) return es;
+    } else if (sym) {
         hipError_t es = launch_kick_sym(c.sym, mode == KM_MIXED, d.widen, k.x, k.y, k.z, k.m,
                                         k.rc, d.part, d.part + (size_t)sym_ps * c.sym.T * SYM_RG,
                                         d.cnt, d.stage, d.wcount, d.status, d.refine_cnt,
@@ -1410,7 +1455,8 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     r.pstride = refine ? 4 : 3;
     r.sym = sym ? 1 : 0;
     r.sh = c.sym;
-    r.colpart = d.part + (size_t)sym_ps * c.sym.T * SYM_RG;
+    r.colpart = d.part + (size_t)sym_ps * sym_T * SYM_RG;
+    r.symb_sys = symb ? sb.sys : nullptr;
     r.kappa2 = refine ? MIXED_KAPPA * MIXED_KAPPA : 0.0;
     r.refine_list = (int32_t *)(ws + L.rlist);
     r.refine_cnt = d.refine_cnt;
@@ -1421,7 +1467,7 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
         if (e != hipSuccess) return e;
         r.m_folded = 1;
     }
-    if (sym && r.forces && k.n < SYM_FOLD_BELOW) {
+    if (sym && !symb && r.forces && k.n < SYM_FOLD_BELOW) {
         SymFoldDev f;
         f.rowpart = d.part;
         f.colpart = r.colpart;
@@ -1485,8 +1531,8 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
     if (e != hipSuccess) return e;
 
     if (sym)
-        return launch_scatter_sym(c.sym, k.x, k.y, k.z, k.rc, d.cnt, d.stage, d.wcount, r.rowloc,
-                                  r.bsum, k.pairs, s);
+        return launch_scatter_sym(c.sym, symb ? &sb : nullptr, k.x, k.y, k.z, k.rc, d.cnt, d.stage,
+                                  d.wcount, r.rowloc, r.bsum, k.pairs, s);
     ScatterDev sd;
     sd.k = d;
     sd.rowloc = r.rowloc;

@@ -68,6 +68,8 @@ struct SymDev {
     int32_t *wcount;   // [T SYM_NW]
     int32_t *status;
     int32_t *refine_cnt;   // mixed: rows listed for binary64 evaluation (reset here)
+    int64_t o;             // batch: the system's first body (x..rc and colpart are the
+                           // system's; staged pairs carry global indices); else 0
     int emit;
     int ps;            // partial values per row: 3 (a), mixed 4 (a, sum of m / r^2)
     double c53;        // 5/3
@@ -219,8 +221,8 @@ __device__ __forceinline__ void sym_slow(const SymDev &a, SymRows<MIXED> &R, int
                 const int pos = base + __popcll(mask & lanemask_lt());
                 if (pos < WSEG) {
                     int32_t *e3 = a.stage + ((size_t)wave_g * WSEG + pos) * 3;
-                    e3[0] = R.ii[q];
-                    e3[1] = jg;
+                    e3[0] = (int32_t)(R.ii[q] + a.o);
+                    e3[1] = (int32_t)(jg + a.o);
                     e3[2] = 0;
                 }
                 R.kc[q] += 1;
@@ -430,16 +432,13 @@ __device__ __forceinline__ void sym_colsum(const SymDev &a, const SymSmem<MIXED>
 // At most 128 VGPRs (4 waves per SIMD, 4 blocks per CU); the few values this
 // moves to scratch are reloaded once per chunk, not per step (unrolling 4
 // steps, or 5 waves per SIMD, spill inside the step loop: 15 % slower).
+// Tile (g, s) of the system described by a (its shape, and for a batch its
+// arrays from its first body on), stored as tile sid.
 template <bool MIXED>
-__global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_kick_sym(
-    SymDev a)
+__device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t s, int64_t sid,
+                                             SymSmem<MIXED> &sm)
 {
-    __shared__ SymSmem<MIXED> sm;
     const SymShape &h = a.sh;
-    if (MIXED && blockIdx.x == 0 && threadIdx.x == 0) *a.refine_cnt = 0;
-    int64_t g, s;
-    sym_tile(h, blockIdx.x, g, s);
-    if (s < 0) return;   // (uniform over the block)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
@@ -449,7 +448,6 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     const int64_t col0 = row0 + s * h.W;
     const int64_t col1 = col0 + h.W < n ? col0 + h.W : n;
     const int nch = (int)((col1 - col0 + 63) / 64);
-    const int64_t sid = h.tb(g) + s;
     const int64_t wave_g = sid * SYM_NW + w;
     const bool diag = s < h.d;
     const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
@@ -594,12 +592,46 @@ __global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         a.wcount[wave_g] = __hip_atomic_load(wcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+template <bool MIXED>
+__global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_kick_sym(
+    SymDev a)
+{
+    __shared__ SymSmem<MIXED> sm;
+    if (MIXED && blockIdx.x == 0 && threadIdx.x == 0) *a.refine_cnt = 0;
+    int64_t g, s;
+    sym_tile(a.sh, blockIdx.x, g, s);
+    if (s < 0) return;   // (uniform over the block)
+    sym_tile_run<MIXED>(a, g, s, a.sh.tb(g) + s, sm);
+}
+
+// Batch: one block per tile, tiles launched in decreasing order of work
+// (order[t] is the storage number of the t-th tile).  Binary64.
+__global__ __launch_bounds__(SYM_NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_kick_sym_b(
+    SymDev base, SymBatch b)
+{
+    __shared__ SymSmem<false> sm;
+    const int64_t sid = b.order[blockIdx.x];
+    const SymTileB t = b.tiles[sid];
+    const SymSys ss = b.sys[t.sys];
+    SymDev a = base;
+    a.sh = ss.sh;
+    a.o = ss.o;
+    a.x += ss.o;
+    a.y += ss.o;
+    a.z += ss.o;
+    a.m += ss.o;
+    a.rc += ss.o;
+    a.colpart += ss.cbase;
+    sym_tile_run<false>(a, t.g, t.s, sid, sm);
+}
+
 // Place the staged pairs of the symmetric kick (one wave of 64 threads per
 // kick wave).  Rank of a pair inside its (row, tile): the number of pairs of
 // the same row with a smaller j in the wave's segment.  A wave whose segment
 // overflowed is recomputed over its rows and the tile's columns, j ascending.
 struct SymScatterDev {
-    SymShape sh;
+    SymShape sh;                    // one system (b.tiles null)
+    SymBatch b;                     // batch: tile and system descriptors
     const double *x, *y, *z, *rc;
     const int32_t *cnt, *stage, *wcount;
     const int32_t *rowloc;
@@ -612,13 +644,24 @@ __global__ __launch_bounds__(64) void k_pairs_scatter_sym(SymScatterDev d)
 {
     __shared__ int32_t si_[WSEG], sj_[WSEG];
     const int lane = threadIdx.x;
-    const SymShape &h = d.sh;
     const int64_t wave_g = blockIdx.x;
     const int64_t sid = wave_g / SYM_NW;
     const int w = (int)(wave_g % SYM_NW);
-    const int64_t g = sym_group_of(h, sid);
-    const int64_t s = sid - h.tb(g);
-    const int64_t row0 = g * SYM_RG;
+    SymShape h;
+    int64_t g, s, o = 0;
+    if (d.b.tiles) {
+        const SymTileB t = d.b.tiles[sid];
+        const SymSys ss = d.b.sys[t.sys];
+        h = ss.sh;
+        o = ss.o;
+        g = t.g;
+        s = t.s;
+    } else {
+        h = d.sh;
+        g = sym_group_of(h, sid);
+        s = sid - h.tb(g);
+    }
+    const int64_t row0 = g * SYM_RG;   // (local to the system)
     const int nst = d.wcount[wave_g];
     if (nst <= WSEG) {
         for (int e = lane; e < nst; e += 64) {
@@ -632,7 +675,7 @@ __global__ __launch_bounds__(64) void k_pairs_scatter_sym(SymScatterDev d)
             int rank = 0;
             for (int f = 0; f < nst; ++f) rank += (si_[f] == i && sj_[f] < j) ? 1 : 0;
             const int64_t pos = d.boff[i / RB] + d.rowloc[i] +
-                                d.cnt[(size_t)sid * SYM_RG + (i - row0)] + rank;
+                                d.cnt[(size_t)sid * SYM_RG + (i - o - row0)] + rank;
             if (pos < d.capacity) {
                 d.pi[pos] = i;
                 d.pj[pos] = j;
@@ -645,13 +688,15 @@ __global__ __launch_bounds__(64) void k_pairs_scatter_sym(SymScatterDev d)
     const int64_t col0 = row0 + s * h.W;
     const int64_t col1 = col0 + h.W < n ? col0 + h.W : n;
     for (int q = 0; q < SYM_IPT; ++q) {
-        const int64_t i = row0 + (int64_t)(q * SYM_NW + w) * 64 + lane;
-        if (i >= rowend) continue;
-        int64_t pos = d.boff[i / RB] + d.rowloc[i] + d.cnt[(size_t)sid * SYM_RG + (i - row0)];
+        const int64_t li = row0 + (int64_t)(q * SYM_NW + w) * 64 + lane;
+        if (li >= rowend) continue;
+        const int64_t i = o + li;
+        int64_t pos = d.boff[i / RB] + d.rowloc[i] + d.cnt[(size_t)sid * SYM_RG + (li - row0)];
         const double xi = d.x[i], yi = d.y[i], zi = d.z[i];
         const double rci = d.rc[i];
         const double rc2i = rci * rci;
-        for (int64_t j = (col0 > i + 1 ? col0 : i + 1); j < col1; ++j) {
+        for (int64_t lj = (col0 > li + 1 ? col0 : li + 1); lj < col1; ++lj) {
+            const int64_t j = o + lj;
             const double dx = d.x[j] - xi, dy = d.y[j] - yi, dz = d.z[j] - zi;
             const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
             const double rcj = d.rc[j];
@@ -668,11 +713,10 @@ __global__ __launch_bounds__(64) void k_pairs_scatter_sym(SymScatterDev d)
     }
 }
 
-hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const double *x,
-                           const double *y, const double *z, const double *m, const double *rc,
-                           double *rowpart, double *colpart, int32_t *cnt, int32_t *stage,
-                           int32_t *wcount, int32_t *status, int32_t *refine_cnt, bool emit,
-                           hipStream_t s)
+static SymDev sym_dev(const SymShape &h, bool mixed, double widen, const double *x, const double *y,
+                      const double *z, const double *m, const double *rc, double *rowpart,
+                      double *colpart, int32_t *cnt, int32_t *stage, int32_t *wcount,
+                      int32_t *status, int32_t *refine_cnt, bool emit)
 {
     SymDev a;
     a.x = x; a.y = y; a.z = z; a.m = m; a.rc = rc;
@@ -684,12 +728,24 @@ hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const do
     a.wcount = wcount;
     a.status = status;
     a.refine_cnt = refine_cnt;
+    a.o = 0;
     a.emit = emit ? 1 : 0;
     a.ps = mixed ? 4 : 3;
     a.c53 = 5.0 / 3.0;
     a.c15 = 1.5;
     a.c1875 = 1.875;
     a.widen = widen;
+    return a;
+}
+
+hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const double *x,
+                           const double *y, const double *z, const double *m, const double *rc,
+                           double *rowpart, double *colpart, int32_t *cnt, int32_t *stage,
+                           int32_t *wcount, int32_t *status, int32_t *refine_cnt, bool emit,
+                           hipStream_t s)
+{
+    const SymDev a = sym_dev(h, mixed, widen, x, y, z, m, rc, rowpart, colpart, cnt, stage,
+                             wcount, status, refine_cnt, emit);
     const int64_t blocks = h.tfull + h.G * h.d;
     if (mixed)
         hipLaunchKernelGGL(k_kick_sym<true>, dim3((unsigned)blocks), dim3(SYM_NT), 0, s, a);
@@ -698,13 +754,27 @@ hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const do
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_sym(const SymShape &h, const double *x, const double *y,
-                              const double *z, const double *rc, const int32_t *cnt,
-                              const int32_t *stage, const int32_t *wcount, const int32_t *rowloc,
-                              const int64_t *boff, genga_pairs *pairs, hipStream_t s)
+hipError_t launch_kick_sym_b(const SymBatch &b, const double *x, const double *y,
+                             const double *z, const double *m, const double *rc, double *rowpart,
+                             double *colpart, int32_t *cnt, int32_t *stage, int32_t *wcount,
+                             int32_t *status, bool emit, hipStream_t s)
+{
+    const SymDev a = sym_dev(SymShape(), false, 0.0, x, y, z, m, rc, rowpart, colpart, cnt, stage,
+                             wcount, status, nullptr, emit);
+    if (b.T == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kick_sym_b, dim3((unsigned)b.T), dim3(SYM_NT), 0, s, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_sym(const SymShape &h, const SymBatch *b, const double *x,
+                              const double *y, const double *z, const double *rc,
+                              const int32_t *cnt, const int32_t *stage, const int32_t *wcount,
+                              const int32_t *rowloc, const int64_t *boff, genga_pairs *pairs,
+                              hipStream_t s)
 {
     SymScatterDev d;
     d.sh = h;
+    d.b = b ? *b : SymBatch{nullptr, nullptr, nullptr, 0, 0};
     d.x = x; d.y = y; d.z = z; d.rc = rc;
     d.cnt = cnt;
     d.stage = stage;
@@ -714,7 +784,9 @@ hipError_t launch_scatter_sym(const SymShape &h, const double *x, const double *
     d.pi = pairs->i;
     d.pj = pairs->j;
     d.capacity = pairs->capacity;
-    hipLaunchKernelGGL(k_pairs_scatter_sym, dim3((unsigned)(h.T * SYM_NW)), dim3(64), 0, s, d);
+    const int64_t T = b ? b->T : h.T;
+    if (T == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairs_scatter_sym, dim3((unsigned)(T * SYM_NW)), dim3(64), 0, s, d);
     return hipGetLastError();
 }
 

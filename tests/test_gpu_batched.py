@@ -46,13 +46,16 @@ def _oracle_system(d, rc, s, rows=None):
     return np.stack([ax, ay, az]), pi + lo, pj + lo, cnt
 
 
-@pytest.mark.parametrize("block,ipt,cols", [(256, 1, 1024), (64, 1, 256), (64, 2, 512), (256, 2, 2048)])
-def test_batched_kick_matches_oracle(dev, block, ipt, cols):
+@pytest.mark.parametrize("block,ipt,cols,flags", [(256, 1, 1024, N.FLAG_DIRECTED), (64, 1, 256, N.FLAG_DIRECTED),
+                                                  (64, 2, 512, N.FLAG_DIRECTED), (256, 2, 2048, N.FLAG_DIRECTED),
+                                                  (0, 0, 0, 0)])
+def test_batched_kick_matches_oracle(dev, block, ipt, cols, flags):
+    # one-sided tile shapes, and the symmetric form (the binary64 default)
     d = W.make_batch(sizes=SMALL_SIZES)
     rc = _rc_batch(d)
     st = N.State.from_numpy(d, rc=rc)
     bt = _batch(d)
-    cfg = N.Config(G=G, block=block, ipt=ipt, tile_cols=cols)
+    cfg = N.Config(G=G, block=block, ipt=ipt, tile_cols=cols, flags=flags)
     ws = N.BatchWorkspace(bt, cfg)
     _say("plan", ws.info)
     pl = N.PairList(200000)
@@ -233,15 +236,16 @@ def test_autotune_batched_choice_is_valid(dev, tmp_path, monkeypatch):
     cfg = N.Config(G=G)
     choice = autotune.tune_batched(st, bt, cfg)
     _say("autotuned batched shape", choice)
-    assert choice["block"] in (64, 256) and choice["ipt"] in (1, 2)
-    assert choice["tile_cols"] in (256, 512, 1024, 2048) and choice["grid"] >= 0
+    if choice["form"] == "one-sided":
+        assert choice["block"] in (64, 256) and choice["ipt"] in (1, 2)
+        assert choice["tile_cols"] in (256, 512, 1024, 2048) and choice["grid"] >= 0
     assert choice["ms"] > 0.0
     # the state is untouched (zero step factor)
     assert torch.equal(st.t["x"], x0[0]) and torch.equal(st.t["vx"], x0[1])
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and lines[0].startswith("batch:")
     again = autotune.tune_batched(st, bt, cfg)                  # served from the cache
-    shape = {k: choice[k] for k in ("block", "ipt", "tile_cols", "grid")}
+    shape = {k: choice[k] for k in ("block", "ipt", "tile_cols", "grid", "flags")}
     assert {k: again[k] for k in shape} == shape
     assert again["ms"] == pytest.approx(choice["ms"], rel=1e-5)
     assert len(cache.read_text().splitlines()) == 1
