@@ -421,7 +421,10 @@ size_t genga_batch_workspace_bytes(const genga_batch *bt, const genga_params *p)
 int genga_batch_plan(const genga_batch *bt, const genga_params *p, void *ws, void *stream);
 
 /* Shape of the plan: out5 = {tiles, persistent blocks, threads per block,
- * rows per thread, columns per tile}. */
+ * rows per thread, columns per tile} of the one-sided kick.  A binary64 batch
+ * without GENGA_FLAG_DIRECTED runs the symmetric kick instead (one block of
+ * 256 threads per tile of 512 rows x 512 columns of one system; the plan
+ * holds both). */
 int genga_batch_info(const genga_batch *bt, const genga_params *p, int64_t *out5);
 
 /* Kick of every system in one persistent launch: for body i of system s,
