@@ -77,7 +77,9 @@ extern "C" {
  * it to both bodies; the one-sided form evaluates every ordered pair for its
  * first body.  Both give the same encounter list (bit for bit) and
  * accelerations that differ by summation order only.  By default the
- * symmetric form runs from n >= 8192 bodies in the all-massive kick, binary64
+ * symmetric form runs from n >= 8192 bodies (up to about 370,000: its
+ * workspace holds row and column sums that grow as n^2 / 512, 8 GiB there,
+ * 0.34 GiB at 65,536 bodies) in the all-massive kick, binary64
  * and mixed (genga_kick, genga_step and the levels' base kick), and in the
  * binary64 batch (genga_kick_batched, genga_step_batched; every system, in
  * 512-row groups and 512-column slices); the flags force one form at any n

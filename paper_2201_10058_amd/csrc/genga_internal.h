@@ -88,6 +88,9 @@ constexpr int64_t SYM_MIN_N = 8192;    // default: symmetric kick from this many
 // below this many bodies the symmetric kick's row totals are summed in
 // SYM_FOLD parts over the whole chip before the reduction (k_sym_fold)
 constexpr int64_t SYM_FOLD_BELOW = 32768;
+// default limit of the symmetric kick's row and column sums (about 370,000
+// bodies); larger systems take the one-sided form unless forced
+constexpr int64_t SYM_WS_MAX = (int64_t)8 << 30;
 constexpr int SYM_FOLD = 8;
 hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const double *x,
                            const double *y, const double *z, const double *m, const double *rc,

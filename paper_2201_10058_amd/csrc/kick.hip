@@ -1224,7 +1224,6 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
     const bool plain = !p || p->tp_mode == 0 || p->n_massive >= n;
     if (plain && !(flags & GENGA_FLAG_DIRECTED) &&
         (n >= SYM_MIN_N || (flags & GENGA_FLAG_SYMMETRIC))) {
-        c.use_sym = true;
         int W = sym_width(n);
         if (p && p->slices > 0) {
             // slices over a row group's own rows: 1, 2, 4, 8 or 16
@@ -1232,7 +1231,14 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
             while (dd * 2 <= p->slices && dd < SYM_RG / 64) dd *= 2;
             W = SYM_RG / dd;
         }
-        c.sym = sym_shape(n, W);
+        const SymShape h = sym_shape(n, W);
+        // its row and column sums grow as n^2 / SYM_RG: by default the
+        // symmetric form stays within SYM_WS_MAX bytes of them
+        const double bytes = 32.0 * ((double)h.T * SYM_RG + (double)h.coloff(h.G));
+        if ((flags & GENGA_FLAG_SYMMETRIC) || bytes <= (double)SYM_WS_MAX) {
+            c.use_sym = true;
+            c.sym = h;
+        }
     }
     return c;
 }
