@@ -29,7 +29,7 @@ namespace {
 
 constexpr int LT = 256;     // threads per block of the list kernels
 constexpr int LG = 1024;    // blocks of the grid-stride list kernels
-constexpr int LG_BIG = 64;  // workgroups of the Bulirsch-Stoer class of 257-512 bodies
+constexpr int LG_BIG = 512; // workgroups of the Bulirsch-Stoer class of 9-512 bodies (2 per CU)
 constexpr int DB = 256;     // blocks (and chunks) of the list compaction
 constexpr int ST = 1024;    // threads of the one-block scan of the adjacency tile sums
 
@@ -543,9 +543,10 @@ __global__ __launch_bounds__(LT) void k_group_rank(const int32_t *lab, const int
 
 // ---------------------------------------------------------------------------
 // Direct solver: one thread per member; groups of up to 8 bodies take 8 lanes
-// of a wave each, larger ones a workgroup of 64, 256 or 512 threads (the
-// classes of Table 1 up to 512 bodies; 512 threads hold the extrapolation
-// tableau in registers at 2 waves per SIMD and 68 KB of LDS).  The
+// of a wave each, larger ones a workgroup of 512 threads (Table 1 splits them
+// into more classes up to 512 bodies; here they are rare, and 512 threads
+// hold the extrapolation tableau in registers at 2 waves per SIMD with 68 KB
+// of LDS).  The
 // group's flow (Kepler force of the star plus the remainder R of the mutual
 // forces) is integrated over H by Bulirsch-Stoer steps: the modified
 // midpoint rule with n = 2, 4, ..., 2 KM sub-steps, polynomial extrapolation
@@ -599,12 +600,15 @@ __device__ __forceinline__ double rcp2(double x)
     return __builtin_fma(t, __builtin_fma(-x, t, 1.0), t);
 }
 
-// R = prod_l (1 - K(r; rho_l)) with y_l = r / (0.9 rho_l) - 1/9.
-__device__ __forceinline__ double bs_remainder(double r, const double *rho, int nlev)
+// R = prod_l (1 - K(r; rho_l)) with y_l = r / (0.9 rho_l) - 1/9, from
+// irho_l = 1 / rho_l = min(1 / rc_i, 1 / rc_j) (the members' reciprocal
+// critical radii are formed once per group: the radii do not change during
+// the integration).
+__device__ __forceinline__ double bs_remainder(double r, const double *irho, int nlev)
 {
     double R = 1.0;
     for (int l = 0; l < nlev; ++l) {
-        const double yv = __builtin_fma(r * rcp2(rho[l]), 10.0 / 9.0, -1.0 / 9.0);
+        const double yv = __builtin_fma(r * irho[l], 10.0 / 9.0, -1.0 / 9.0);
         R *= 1.0 - changeover_of_y(yv);
     }
     return R;
@@ -615,7 +619,7 @@ struct BsSmem {
     double px[BT], py[BT], pz[BT], m[BT];
     double pv[3][BT], R[BT];
     int32_t idx[BT];
-    double rc[GENGA_MAX_LEVELS][BT];
+    double irc[GENGA_MAX_LEVELS][BT];   // 1 / rc of each level
     double red[BT / 64];
     int ired[BT / 64];
 };
@@ -636,10 +640,10 @@ __device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, i
         const double dx = sm.px[q] - o[0], dy = sm.py[q] - o[1], dz = sm.pz[q] - o[2];
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double ir = rsq2(r2);
-        double rho[GENGA_MAX_LEVELS];
+        double irho[GENGA_MAX_LEVELS];
         for (int l = 0; l < a.nlev; ++l)
-            rho[l] = sm.rc[l][t] > sm.rc[l][q] ? sm.rc[l][t] : sm.rc[l][q];
-        const double R = bs_remainder(r2 * ir, rho, a.nlev);
+            irho[l] = sm.irc[l][t] < sm.irc[l][q] ? sm.irc[l][t] : sm.irc[l][q];
+        const double R = bs_remainder(r2 * ir, irho, a.nlev);
         const double s = a.G * sm.m[q] * R * (ir * ir * ir);
         acc[0] += s * dx;
         acc[1] += s * dy;
@@ -757,7 +761,7 @@ struct LanePol {
     double m, R;
     int32_t bidx;
     double zc[6];
-    double rc[GENGA_MAX_LEVELS];
+    double irc[GENGA_MAX_LEVELS];   // 1 / rc of each level
     __device__ bool member() const { return u < g; }
     __device__ int self() const { return u; }
     __device__ void publish(const double z[6])
@@ -808,16 +812,16 @@ struct LanePol {
         for (int q = 0; q < g; ++q) {
             const double xq = __shfl(z[0], q, GS), yq = __shfl(z[1], q, GS),
                          zq = __shfl(z[2], q, GS), mq = __shfl(m, q, GS);
-            double rho[GENGA_MAX_LEVELS];
+            double irho[GENGA_MAX_LEVELS];
             for (int l = 0; l < a.nlev; ++l) {
-                const double rq = __shfl(rc[l], q, GS);
-                rho[l] = rc[l] > rq ? rc[l] : rq;
+                const double iq = __shfl(irc[l], q, GS);
+                irho[l] = irc[l] < iq ? irc[l] : iq;
             }
             if (!mem || q == u) continue;
             const double dx = xq - z[0], dy = yq - z[1], dz = zq - z[2];
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double ir = rsq2(r2);
-            const double R = bs_remainder(r2 * ir, rho, a.nlev);
+            const double R = bs_remainder(r2 * ir, irho, a.nlev);
             const double s = a.G * mq * R * (ir * ir * ir);
             acc[0] += s * dx;
             acc[1] += s * dy;
@@ -1083,7 +1087,7 @@ __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
         P.m = 0.0;
         P.R = 0.0;
         for (int c = 0; c < 6; ++c) P.zc[c] = 0.0;
-        for (int l = 0; l < GENGA_MAX_LEVELS; ++l) P.rc[l] = 0.0;
+        for (int l = 0; l < GENGA_MAX_LEVELS; ++l) P.irc[l] = 0.0;
         const int32_t b = u < g ? a.gmem[a.gstart[root] + u] : 0;
         P.bidx = b;
         double y[6] = {0, 0, 0, 0, 0, 0};
@@ -1092,7 +1096,7 @@ __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
             for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
             P.m = a.m[b];
             P.R = a.radius ? a.radius[b] : 0.0;
-            for (int l = 0; l < a.nlev; ++l) P.rc[l] = a.rc[l][b];
+            for (int l = 0; l < a.nlev; ++l) P.irc[l] = rcp2(a.rc[l][b]);
         }
         const bool failed = bs_run(a, P, y);
         if (failed && u == 0) atomicOr(a.status, ST_NOCONV);
@@ -1134,7 +1138,7 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
             sm.m[t] = a.m[b];
             sm.R[t] = a.radius ? a.radius[b] : 0.0;
             sm.idx[t] = b;
-            for (int l = 0; l < a.nlev; ++l) sm.rc[l][t] = a.rc[l][b];
+            for (int l = 0; l < a.nlev; ++l) sm.irc[l][t] = rcp2(a.rc[l][b]);
         }
         BlockPol<BT> P{sm, t, g};
         const bool failed = bs_run(a, P, y);
@@ -1282,10 +1286,10 @@ static hipError_t direct_solve(const LevelRun &R, int l, double dt_l)
     a.coll_count = R.at<unsigned long long>(V.coll_count);
     a.coll_cap = LEVEL_COLL_CAP;
     hipLaunchKernelGGL(k_bs_lanes<BS_GS>, dim3(LG), dim3(LT), 0, R.s, a);
-    hipLaunchKernelGGL(k_bs<64>, dim3(LG), dim3(64), 0, R.s, a, BS_GS);
-    hipLaunchKernelGGL(k_bs<256>, dim3(LG), dim3(256), 0, R.s, a, 64);
-    // groups of 257-512 bodies are rare: a few workgroups walk them
-    hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG_BIG), dim3(GENGA_GROUP_MAX), 0, R.s, a, 256);
+    // groups of more than 8 bodies are rare at the deepest level: one
+    // launch of 512-thread workgroups takes all of them (an empty launch per
+    // class cost ~4.5 us per deepest sub-step)
+    hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG_BIG), dim3(GENGA_GROUP_MAX), 0, R.s, a, BS_GS);
     return hipGetLastError();
 }
 
