@@ -71,7 +71,7 @@ extern "C" {
 
 /* genga_params.flags */
 #define GENGA_FLAG_NOSYNC 1 /* genga_step: do not synchronise nor read the status     */
-/* Form of the single-system kick (Newton's third law, Sect. 2: the pair
+/* Form of the kick (Newton's third law, Sect. 2: the pair
  * force and its changeover weight K(r_ij; max(rc_i, rc_j)) are symmetric in i
  * and j).  The symmetric form evaluates each unordered pair once and applies
  * it to both bodies; the one-sided form evaluates every ordered pair for its
@@ -84,7 +84,7 @@ extern "C" {
  * binary64 batch (genga_kick_batched, genga_step_batched; every system, in
  * 512-row groups and 512-column slices); the flags force one form at any n
  * (both set: GENGA_E_INVAL).  Test-particle modes, the mixed batch and
- * genga_encounter_pairs are one-sided. */
+ * genga_encounter_pairs are one-sided whatever the flags. */
 #define GENGA_FLAG_DIRECTED  2
 #define GENGA_FLAG_SYMMETRIC 4
 
