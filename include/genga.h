@@ -12,9 +12,9 @@
  * K(r_ij; rho_ij) of Sect. 6.2 (zero below 0.1 rho, one above rho, the
  * smooth form of Chambers 1999 eq. 10 between), with rho_ij = max(rc_i, rc_j).
  * Pairs closer than rho_ij form the close-encounter list that the direct
- * solver would take (Sect. 2; list order fixed as in Appendix B, "exact
- * reproducible results").  The direct solver itself is not part of this
- * library.
+ * solver takes (Sect. 2; list order fixed as in Appendix B, "exact
+ * reproducible results").  genga_step runs the direct solver (close-encounter
+ * groups integrated by Bulirsch-Stoer extrapolation) when p->direct is set.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
