@@ -107,6 +107,7 @@ struct SymSmem {
     SymCols<MIXED> col[2];
     double acc[2][MIXED ? 4 : 3][SYM_NW][64];   // column sums of a chunk, per wave
     double nacc[MIXED ? SYM_NW : 1][3][64];      // mixed: binary64 column sums of near pairs
+    double gmax[2];    // binary64: largest rc^2 among the columns of chunk b
     int wcnt[SYM_NW];
 };
 
@@ -134,6 +135,23 @@ __device__ __forceinline__ double rotate_down(double v)
 __device__ __forceinline__ float rotate_down(float v)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+
+// Largest value over the 64 lanes of a wave (all active), in every lane;
+// fmax ignores a NaN operand.
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = __builtin_fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// A value the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
 }
 
 // Tile of launch index t: group g and slice s (s = -1: an empty diagonal slot
@@ -172,10 +190,11 @@ __device__ __forceinline__ int64_t sym_group_of(const SymShape &h, int64_t sid)
     return g;
 }
 
-// Rare path of one pair (r^2 <= max(rc_i^2, rc_j^2)): the self pair, coincident
-// bodies, the changeover band and encounter recording.  si, sj hold the fast
-// weights (m_j and m_i times r^-3) and are replaced by K-weighted ones inside
-// rho_ij; a pair exactly at rho_ij keeps them (K = 1).  1/r and 1/rho from
+// Rare path of one pair (binary64: r^2 at most the wave's gate bound, which is
+// at least max(rc_i^2, rc_j^2); mixed: r^2 <= max(rc_i^2, rc_j^2)): the self pair, coincident bodies, the changeover band
+// and encounter recording.  si, sj hold the fast weights (m_j and m_i times
+// r^-3) and are replaced by K-weighted ones inside rho_ij; a pair at or beyond
+// rho_ij keeps them (K = 1) and is not recorded.  1/r and 1/rho from
 // v_rsq_f64 with one Newton correction (relative error below 5e-15), so the
 // band variable is y = (r/rho) / 0.9 - 1/9; in the binary64 kick m_i is
 // (2/3) (3/2 m_i), to 2 ulp.  Whether a pair is inside rho_ij, and so in the
@@ -245,7 +264,7 @@ template <bool GEN>
 __device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows<false> &R,
                                           const SymCols<false> &C, int colbase, const int *mode,
                                           double &cx, double &cy, double &cz, double c53,
-                                          int64_t wave_g, int *wcnt, int lane)
+                                          double g2, int64_t wave_g, int *wcnt, int lane)
 {
     for (int k0 = 0; k0 < 64; k0 += 2) {
 #pragma unroll
@@ -253,7 +272,6 @@ __device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows<false> &R,
             const int e = lane + k0 + u;
             const double2 p = C.xy[e];
             const double2 zm = C.zm[e];
-            const double rc2c = C.rc2[e];
 #pragma unroll
             for (int q = 0; q < SYM_IPT; ++q) {
                 if (GEN && mode[q] == 0) continue;
@@ -261,7 +279,7 @@ __device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows<false> &R,
                 const double dy = p.y - R.yi[q];
                 const double dz = zm.x - R.zi[q];
                 const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                const bool cand = r2 <= vmax_f64(R.rc2i[q], rc2c);
+                const bool cand = r2 <= g2;
                 const double yv = __builtin_amdgcn_rsq(r2);
                 const double y2 = yv * yv;
                 const double pp = __builtin_fma(-r2, y2, c53);
@@ -274,7 +292,7 @@ __device__ __forceinline__ void sym_chunk(const SymDev &a, SymRows<false> &R,
                     int ee = lane;
                     asm volatile("" : "+v"(ee));
                     ee += k0 + u;
-                    sym_slow<false>(a, R, q, colbase + (ee & 63), r2, rc2c, C.m[ee], si, sj,
+                    sym_slow<false>(a, R, q, colbase + (ee & 63), r2, C.rc2[ee], C.m[ee], si, sj,
                                     wave_g, wcnt);
                 }
                 R.ax[q] = __builtin_fma(dx, si, R.ax[q]);
@@ -376,10 +394,11 @@ __device__ __forceinline__ void sym_chunk_mixed(const SymDev &a, SymRows<true> &
     }
 }
 
-// Column jg (or padding) into entries t and t + 64 of an LDS chunk.
+// Column jg (or padding) into entries t and t + 64 of an LDS chunk.  Returns
+// its rc^2 (0 for padding).
 template <bool MIXED>
-__device__ __forceinline__ void sym_put(SymCols<MIXED> &C, int t, bool real, double x, double y,
-                                        double z, double m, double rc, double widen)
+__device__ __forceinline__ double sym_put(SymCols<MIXED> &C, int t, bool real, double x, double y,
+                                          double z, double m, double rc, double widen)
 {
     if (!real) {
         x = y = z = SYM_FAR_COL;
@@ -405,6 +424,7 @@ __device__ __forceinline__ void sym_put(SymCols<MIXED> &C, int t, bool real, dou
     C.rc2[t + 64] = rc2;
     C.m[t] = m;
     C.m[t + 64] = m;
+    return rc2;
 }
 
 // Column sums of chunk cc (columns cc*64 + lane) of group g: the waves' sums
@@ -484,6 +504,18 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
             R.axf[q] = R.ayf[q] = R.azf[q] = R.magf[q] = 0.0f;
         }
     }
+    // Binary64 fast path's gate: a pair can be inside max(rc_i, rc_j) only if
+    // r^2 is at most the largest rc^2 among the wave's rows and the chunk's
+    // columns, so one compare against that wave-uniform bound replaces the
+    // per-pair max and compare, and the rare path takes the exact test.  (The
+    // mixed kernel keeps its per-pair test: the bound's registers cost it more
+    // in spills than the instruction saves.)
+    double rg = 0.0;
+    if constexpr (!MIXED) {
+#pragma unroll
+        for (int q = 0; q < SYM_IPT; ++q) rg = __builtin_fmax(rg, R.rc2i[q]);
+        rg = wave_uniform(wave_max(rg));
+    }
     int *wcnt = &sm.wcnt[w];
     if (lane == 0) __hip_atomic_store(wcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     if constexpr (MIXED) {
@@ -501,7 +533,11 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
             x = a.x[jg]; y = a.y[jg]; z = a.z[jg]; m = a.m[jg]; rc = a.rc[jg];
             if (!(rc >= 0.0 && rc < INFINITY)) atomicOr(a.status, ST_RCRIT);
         }
-        sym_put<MIXED>(sm.col[0], lane, real, x, y, z, m, rc, a.widen);
+        const double gv = sym_put<MIXED>(sm.col[0], lane, real, x, y, z, m, rc, a.widen);
+        if constexpr (!MIXED) {
+            const double gm = wave_max(gv);
+            if (lane == 0) sm.gmax[0] = gm;
+        }
     }
     __syncthreads();
 
@@ -558,12 +594,13 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
             sm.nacc[w][1][lane] = 0.0;
             sm.nacc[w][2][lane] = 0.0;
         } else {
+            const double g2 = wave_uniform(__builtin_fmax(rg, sm.gmax[b]));
             double cx = 0.0, cy = 0.0, cz = 0.0;
             if (full)
-                sym_chunk<false>(a, R, sm.col[b], colbase, mode, cx, cy, cz, c53, wave_g, wcnt,
+                sym_chunk<false>(a, R, sm.col[b], colbase, mode, cx, cy, cz, c53, g2, wave_g, wcnt,
                                  lane);
             else
-                sym_chunk<true>(a, R, sm.col[b], colbase, mode, cx, cy, cz, c53, wave_g, wcnt,
+                sym_chunk<true>(a, R, sm.col[b], colbase, mode, cx, cy, cz, c53, g2, wave_g, wcnt,
                                 lane);
             sm.acc[b][0][w][lane] = cx;
             sm.acc[b][1][w][lane] = cy;
@@ -571,7 +608,11 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
         }
         if (loader) {
             if (preal && !(prc >= 0.0 && prc < INFINITY)) atomicOr(a.status, ST_RCRIT);
-            sym_put<MIXED>(sm.col[b ^ 1], lane, preal, px, py, pz, pm, prc, a.widen);
+            const double gv = sym_put<MIXED>(sm.col[b ^ 1], lane, preal, px, py, pz, pm, prc, a.widen);
+            if constexpr (!MIXED) {
+                const double gm = wave_max(gv);
+                if (lane == 0) sm.gmax[b ^ 1] = gm;
+            }
         }
         __syncthreads();
     }
