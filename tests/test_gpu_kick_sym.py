@@ -81,6 +81,28 @@ def test_sym_disk2048_and_one_sided(dev):
     assert np.max(np.abs(P)) <= 1e-14 * (d["m"] * np.abs(a_s)).sum()
 
 
+def test_sym_outlier_radii_widen_the_wave_bound(dev):
+    # The binary64 symmetric kick gates each pair by the largest rc^2 among the
+    # wave's rows and the chunk's columns, and takes the exact test in the rare
+    # path.  One body in 97 with a critical radius of 0.8 (a unit cloud, the
+    # others 0.01) lifts that bound for its waves and chunks, so thousands of
+    # pairs outside both of their radii enter the rare path: they must keep the
+    # unweighted force and stay out of the list.
+    d = W.random_cloud(3000, seed=5, rc_scale=0.01)
+    rc = d["rc"].copy()
+    rc[::97] = 0.8
+    a, (pi, pj, cnt), code, _ = _run_kick(d, rc, SYM)
+    assert code == N.OK
+    err = _rel_err(a, _oracle_acc(d, rc))
+    _say("outlier radii: max rel err", err.max(), "pairs", cnt)
+    assert err.max() <= ACC_TOL
+    opi, opj, ocnt = oracle.pairs(d["x"], d["y"], d["z"], rc)
+    assert cnt == ocnt and np.array_equal(pi, opi) and np.array_equal(pj, opj)
+    a_d, (qi, qj, qc), code_d, _ = _run_kick(d, rc, DIR)
+    assert code_d == N.OK and qc == cnt and np.array_equal(qi, pi) and np.array_equal(qj, pj)
+    assert np.max(_rel_err(a, a_d)) <= 2 * ACC_TOL
+
+
 def test_sym_ring_overflows_staging(dev):
     # the ring test of Sect. 6.1: every body meets its 4 neighbours on each
     # side; a wave's 128 rows then hold 512 pairs of one tile, more than its
