@@ -136,4 +136,21 @@ __device__ int64_t block_excl_scan(int64_t v, int64_t *total, int64_t *smem /* N
     return off + inc - v;
 }
 
+// Largest value over the 64 lanes of a wave (all active), in every lane;
+// fmax ignores a NaN operand.
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = __builtin_fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// A value the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 }  // namespace genga

@@ -211,10 +211,13 @@ constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
 
 // One column j against the lane's rows (the hot loop body).
 //   b = (x_j, y_j, z_j, 3/2 m_j) for KM_F64, (x_j, y_j, z_j, m_j) for KM_PAIRS,
-//   (x_j, y_j, z_j, {m_j, rc2f_j}) for KM_MIXED; *mj64 = m_j.
+//   (x_j, y_j, z_j, {m_j, rc2f_j}) for KM_MIXED; *mj64 = m_j, *rc2j64 = rc_j^2.
+//   gate2 (KM_F64, KM_PAIRS): a bound on r^2, at least max(rc_i^2, rc_j^2) for
+//   every row of the lane, below which a pair takes the rare path, where the
+//   exact test is made.
 template <int IPT, int MODE>
 __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const double4 b,
-                                         const double rc2j, const int64_t jg, const double c15,
+                                         const double gate2, const int64_t jg, const double c15,
                                          const double c1875, const double c53, const int64_t wave_g,
                                          int *wcnt, const double *rc2j64,
                                          const double *mj64, const double *irj64)
@@ -270,8 +273,8 @@ __device__ __forceinline__ void interact(const KickDev &a, Rows<IPT> &R, const d
         const double dy = b.y - R.yi[q];
         const double dz = b.z - R.zi[q];
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        // candidate: inside the pair critical radius, or the self pair
-        const bool cand = r2 <= vmax_f64(R.rc2i[q], rc2j);
+        // candidate: possibly inside the pair critical radius, or the self pair
+        const bool cand = r2 <= gate2;
         double sc = 0.0;
         if (FORCES) {
             // m r^-3 from v_rsq_f64 (measured relative error below 2^-24):
@@ -320,6 +323,7 @@ struct KickSmem {
     double rc2[NT];
     double m[NT];
     double irc[NT];     // 1 / rc_j
+    double cmax[NT / 64];   // largest rc_j^2 among each staging wave's columns
     int wcnt[4];
 };
 
@@ -374,6 +378,16 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
         R.axf[q] = R.ayf[q] = R.azf[q] = R.magf[q] = 0.0f;
         R.kc[q] = 0;
     }
+    // Binary64 and pair-list gate: a pair can be inside max(rc_i, rc_j) only
+    // if r^2 is at most the largest rc^2 among the wave's rows and the tile's
+    // columns, so one compare against that wave-uniform bound replaces the
+    // per-pair max and compare (the rare path takes the exact test).
+    double rg = 0.0;
+    if (MODE != KM_MIXED) {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) rg = __builtin_fmax(rg, R.rc2i[q]);
+        rg = wave_uniform(wave_max(rg));
+    }
     int *wcnt = &sm.wcnt[w];
     if (lane == 0) __hip_atomic_store(wcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 
@@ -382,6 +396,7 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
         {
             const int q = tid;
             const int64_t jg = t0 + q;
+            double g = 0.0;
             if (jg < j1) {
                 const double rcj = a.rc[jg];
                 if (!(rcj >= 0.0 && rcj < INFINITY)) atomicOr(a.status, ST_RCRIT);
@@ -399,23 +414,33 @@ __device__ __forceinline__ void process_tile(const KickDev &a, KickSmem<NT> &sm,
                 }
                 sm.rc2[q] = rcj * rcj;
                 if (MODE != KM_PAIRS) sm.irc[q] = 1.0 / rcj;
-
+                g = rcj * rcj;
+            }
+            if (MODE != KM_MIXED) {
+                const double gm = wave_max(g);
+                if (lane == 0) sm.cmax[w] = gm;
             }
         }
         __syncthreads();
+        double g2 = 0.0;
+        if (MODE != KM_MIXED) {
+            g2 = rg;
+#pragma unroll
+            for (int v = 0; v < NT / 64; ++v) g2 = __builtin_fmax(g2, sm.cmax[v]);
+            g2 = wave_uniform(g2);
+        }
         const int tn = (int)min((int64_t)NT, j1 - t0);
         int jj = 0;
         for (; jj + 4 <= tn; jj += 4) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                interact<IPT, MODE>(a, R, t_xyzm[jj + u], MODE == KM_MIXED ? 0.0 : t_rc2[jj + u],
-                                    t0 + jj + u, c15, c1875, c53, wave_g, wcnt, t_rc2 + jj + u,
-                                    t_m + jj + u, t_irc + jj + u);
+                interact<IPT, MODE>(a, R, t_xyzm[jj + u], g2, t0 + jj + u, c15, c1875, c53,
+                                    wave_g, wcnt, t_rc2 + jj + u, t_m + jj + u, t_irc + jj + u);
             if ((jj & (FOLD - 1)) == FOLD - 4) fold<IPT, MODE>(R);
         }
         for (; jj < tn; ++jj)
-            interact<IPT, MODE>(a, R, t_xyzm[jj], MODE == KM_MIXED ? 0.0 : t_rc2[jj], t0 + jj, c15,
-                                c1875, c53, wave_g, wcnt, t_rc2 + jj, t_m + jj, t_irc + jj);
+            interact<IPT, MODE>(a, R, t_xyzm[jj], g2, t0 + jj, c15, c1875, c53, wave_g, wcnt,
+                                t_rc2 + jj, t_m + jj, t_irc + jj);
         fold<IPT, MODE>(R);
     }
 
@@ -993,8 +1018,8 @@ __global__ __launch_bounds__(RT) void k_refine_tiles(KickDev a, const int32_t *l
             __syncthreads();
             const int tn = (int)(j1 - t0 < RT ? j1 - t0 : RT);
             for (int jj = 0; jj < tn; ++jj)
-                interact<1, KM_F64>(a, R, t_xyzm[jj], t_rc2[jj], t0 + jj, c15, c1875, c53, 0,
-                                    nullptr, t_rc2 + jj, t_m + jj, t_irc + jj);
+                interact<1, KM_F64>(a, R, t_xyzm[jj], vmax_f64(R.rc2i[0], t_rc2[jj]), t0 + jj, c15,
+                                    c1875, c53, 0, nullptr, t_rc2 + jj, t_m + jj, t_irc + jj);
         }
         if (pos < cnt) {
             double *P = a.part + ((size_t)pos * S + s) * 3;

@@ -137,23 +137,6 @@ __device__ __forceinline__ float rotate_down(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
 }
 
-// Largest value over the 64 lanes of a wave (all active), in every lane;
-// fmax ignores a NaN operand.
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = __builtin_fmax(v, __shfl_xor(v, off));
-    return v;
-}
-
-// A value the same in every lane, moved to scalar registers.
-__device__ __forceinline__ double wave_uniform(double v)
-{
-    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
-    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
-    return __hiloint2double(hi, lo);
-}
-
 // Tile of launch index t: group g and slice s (s = -1: an empty diagonal slot
 // of the last group).
 __device__ __forceinline__ void sym_tile(const SymShape &h, int64_t t, int64_t &g, int64_t &s)
