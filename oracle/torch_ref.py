@@ -59,17 +59,12 @@ def hc(x, v, m, m_star, h):
     return x + h * P[None, :] / m_star
 
 
-def drift(x, v, mu, dt, iters: int = 60):
-    """Kepler drift of bound orbits by Gauss f and g in the eccentric-anomaly
-    change dE.  Kepler's equation is solved without gradient tracking; one
-    more Newton step taken with tracking gives the derivative of the exact
-    root (implicit-function theorem)."""
-    r0 = torch.linalg.norm(x, dim=1)
-    v2 = (v * v).sum(1)
-    u = (x * v).sum(1)
-    alpha = 2.0 / r0 - v2 / mu
-    if not bool((alpha > 0).all()):
-        raise ValueError("torch reference drift handles bound orbits only")
+def _drift_bound(x, v, r0, u, alpha, mu, dt, iters):
+    """Gauss f and g in the eccentric-anomaly change dE (alpha = 1/a > 0).
+    Kepler's equation n dt = dE - ec sin dE + es (1 - cos dE), ec = 1 - r0/a,
+    es = u / sqrt(mu a), is solved without gradient tracking; one more Newton
+    step taken with tracking gives the derivative of the exact root
+    (implicit-function theorem)."""
     a = 1.0 / alpha
     n = torch.sqrt(mu * alpha ** 3)
     ec = 1.0 - r0 * alpha
@@ -96,6 +91,68 @@ def drift(x, v, mu, dt, iters: int = 60):
     fd = -torch.sqrt(mu * a) * s / (r * r0)
     gd = 1.0 - (a / r) * omc
     return f[:, None] * x + g[:, None] * v, fd[:, None] * x + gd[:, None] * v
+
+
+def _drift_unbound(x, v, r0, u, alpha, mu, dt, iters):
+    """Gauss f and g in the hyperbolic-anomaly change dF (alpha = 1/a < 0,
+    A = -a > 0).  With e cosh F0 = 1 + r0/A and e sinh F0 = u / sqrt(mu A),
+    the mean-anomaly change e sinh F - F gives Kepler's equation
+    n dt = ch sinh dF + sh (cosh dF - 1) - dF, n = sqrt(mu / A^3), and
+    r = A (ch cosh dF + sh sinh dF - 1); f = 1 - (A/r0)(cosh dF - 1),
+    g = dt - (sinh dF - dF)/n, fdot = -sqrt(mu A) sinh dF / (r r0),
+    gdot = 1 - (A/r)(cosh dF - 1).  Root as in the bound case."""
+    A = -1.0 / alpha
+    n = torch.sqrt(mu / A ** 3)
+    ch = 1.0 + r0 / A
+    sh = u / torch.sqrt(mu * A)
+    M = n * dt
+
+    def F(d):
+        return ch * torch.sinh(d) + sh * (torch.cosh(d) - 1.0) - d - M
+
+    def Fp(d):
+        return ch * torch.cosh(d) + sh * torch.sinh(d) - 1.0
+
+    with torch.no_grad():
+        d = torch.asinh(M / ch)
+        for _ in range(iters):
+            d = d - F(d) / Fp(d)
+    d = d.detach()
+    d = d - F(d) / Fp(d)
+    s, c = torch.sinh(d), torch.cosh(d)
+    cm1 = 2.0 * torch.sinh(0.5 * d) ** 2
+    r = A * (ch * c + sh * s - 1.0)
+    f = 1.0 - (A / r0) * cm1
+    g = dt - (s - d) / n
+    fd = -torch.sqrt(mu * A) * s / (r * r0)
+    gd = 1.0 - (A / r) * cm1
+    return f[:, None] * x + g[:, None] * v, fd[:, None] * x + gd[:, None] * v
+
+
+def drift(x, v, mu, dt, iters: int = 60):
+    """Kepler drift about mu for dt by Gauss f and g: bound orbits in the
+    eccentric-anomaly change, unbound ones in the hyperbolic-anomaly change
+    (each body takes its own branch; a parabolic orbit, 1/a = 0, is refused)."""
+    r0 = torch.linalg.norm(x, dim=1)
+    v2 = (v * v).sum(1)
+    u = (x * v).sum(1)
+    alpha = 2.0 / r0 - v2 / mu
+    bound = alpha > 0
+    if bool((alpha == 0).any()):
+        raise ValueError("torch reference drift: parabolic orbit")
+    if bool(bound.all()):
+        return _drift_bound(x, v, r0, u, alpha, mu, dt, iters)
+    ib = torch.nonzero(bound).flatten()
+    iu = torch.nonzero(~bound).flatten()
+    xo = torch.zeros_like(x)
+    vo = torch.zeros_like(v)
+    for idx, fn in ((ib, _drift_bound), (iu, _drift_unbound)):
+        if idx.numel() == 0:
+            continue
+        xs, vs = fn(x[idx], v[idx], r0[idx], u[idx], alpha[idx], mu, dt, iters)
+        xo = xo.index_copy(0, idx, xs)
+        vo = vo.index_copy(0, idx, vs)
+    return xo, vo
 
 
 def step(x, v, m, G, m_star, dt, n1, n2):

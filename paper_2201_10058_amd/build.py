@@ -61,6 +61,10 @@ def assemble(out_dir: str, verbose: bool = False) -> list:
 
 if __name__ == "__main__":
     if "-S" in sys.argv:
-        print(assemble(os.path.join(ROOT, "_work", "asm"), verbose=True))
+        # python build.py -S OUT_DIR: the assembly of every source into OUT_DIR
+        k = sys.argv.index("-S")
+        if k + 1 >= len(sys.argv):
+            sys.exit("usage: build.py -S OUT_DIR")
+        print(assemble(sys.argv[k + 1], verbose=True))
     else:
         print(build(verbose="-v" in sys.argv))

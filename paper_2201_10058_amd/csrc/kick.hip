@@ -15,9 +15,12 @@
 //    owns IPT rows and streams the tile with broadcast LDS reads.  Per
 //    interaction the FP64 fast path is 3 sub, 3 mul/fma for r^2, v_rsq_f64
 //    with a first-order correction folded into m r^-3 (5 ops), 3 fma
-//    accumulations and one compare against max(rc_i^2, rc_j^2).  Pairs inside the pair critical
-//    radius (and the self pair) take a divergent slow path that evaluates K,
-//    records encounter pairs and detects coincident bodies.
+//    accumulations and one compare of r^2 against a wave-uniform bound (the
+//    largest rc^2 among the wave's rows and the tile's columns, which is at
+//    least max(rc_i^2, rc_j^2)).  Pairs under the bound take a divergent slow
+//    path that makes the exact test r^2 < max(rc_i^2, rc_j^2), evaluates K
+//    inside it, records encounter pairs and detects the self pair and
+//    coincident bodies.
 //  * Partial sums per column slice go to the workspace; k_kick_reduce adds
 //    them in slice order (no atomics), applies v += h a and prepares the pair
 //    offsets.

@@ -21,9 +21,9 @@
 //    column it is on.  After every step the three column sums move one lane
 //    down (v_mov_b32_dpp wave_rol:1, lane l receives lane l + 1), which hands
 //    each lane the sum of its next column; after 64 steps every sum is back
-//    in the lane of its column.  Per step and lane: 2 pairs of 21 FP64
-//    instructions and 6 moves cover 4 directed interactions (the one-sided
-//    kick spends 4 x 18).
+//    in the lane of its column.  Per step and lane: 2 pairs of 20 FP64
+//    instructions (one of them v_rsq_f64) and 6 moves cover 4 directed
+//    interactions (the one-sided kick spends 4 x 17).
 //  * Chunks over the group's own rows: a chunk after the lane's row chunk is
 //    done symmetrically, the row's own chunk one-sided (each lane sums all 64
 //    columns into its row only, self pair excluded), a chunk before it not at

@@ -109,6 +109,43 @@ def test_rcrit_hc_drift_vjp_match_autograd(dev):
     assert ex < 1e-11 and ev < 1e-11
 
 
+def test_drift_vjp_bound_and_unbound_match_autograd(dev):
+    # bound and unbound orbits in one call: the hyperbolic branch of the
+    # drift VJP against autograd of the reference's hyperbolic-anomaly drift
+    rng = np.random.default_rng(33)
+    n = 400
+    r = rng.uniform(0.3, 3.0, n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    vc = np.sqrt(G / r)
+    fac = rng.uniform(0.2, 1.9, n)
+    d = dict(x=r * np.cos(th), y=r * np.sin(th), z=rng.normal(0, 0.01, n),
+             vx=-fac * vc * np.sin(th) + rng.normal(0, 0.1, n) * vc,
+             vy=fac * vc * np.cos(th), vz=rng.normal(0, 0.02, n) * vc, m=np.zeros(n))
+    cfg = N.Config(G=G)
+    ws = N.Workspace(n, cfg)
+    for dt in (20.0, -35.0):
+        b6 = rng.normal(size=(n, 6))
+        x, v, _ = T.state_tensors(d, requires_grad=True)
+        alpha = 2.0 / torch.linalg.norm(x, dim=1) - (v * v).sum(1) / G
+        assert int((alpha < 0).sum()) > 80 and int((alpha > 0).sum()) > 80
+        x1, v1 = T.drift(x, v, G, dt)
+        L = (x1 * torch.tensor(b6[:, :3])).sum() + (v1 * torch.tensor(b6[:, 3:])).sum()
+        gx, gv = torch.autograd.grad(L, (x, v))
+        adj = N.AdjointState(n)
+        for c, k in enumerate(("x", "y", "z", "vx", "vy", "vz")):
+            adj.t[k].copy_(torch.tensor(b6[:, c]))
+        N.drift_vjp(_gpu_state(d), cfg, ws, dt, adj)
+        torch.cuda.synchronize()
+        assert N.read_status(ws) == N.OK
+        gxs = np.stack([adj.t[k].cpu().numpy() for k in "xyz"]).T
+        gvs = np.stack([adj.t[k].cpu().numpy() for k in ("vx", "vy", "vz")]).T
+        # per body, relative to the body's own gradient
+        ex = np.linalg.norm(gxs - gx.numpy(), axis=1) / np.linalg.norm(gx.numpy(), axis=1)
+        ev = np.linalg.norm(gvs - gv.numpy(), axis=1) / np.linalg.norm(gv.numpy(), axis=1)
+        _say("drift vjp, bound + unbound, dt", dt, "max rel errors", ex.max(), ev.max())
+        assert ex.max() < 1e-10 and ev.max() < 1e-10
+
+
 def _torch_dev(d):
     X = torch.tensor(np.stack([d["x"], d["y"], d["z"]]), device="cuda")
     V = torch.tensor(np.stack([d["vx"], d["vy"], d["vz"]]), device="cuda")

@@ -106,3 +106,40 @@ def test_rho_tie_routes_to_lower_index():
     rho = T.pair_rho(rc)
     g = torch.autograd.grad(rho[0, 1] + rho[1, 0], rc)[0]
     assert g.tolist() == [2.0, 0.0, 0.0]
+
+
+def _mixed_orbits(n, seed):
+    """Bound and unbound heliocentric orbits (speed 0.2-1.9 times circular)."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.3, 3.0, n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    vc = np.sqrt(G / r)
+    fac = rng.uniform(0.2, 1.9, n)
+    return dict(x=r * np.cos(th), y=r * np.sin(th), z=rng.normal(0, 0.01, n),
+                vx=-fac * vc * np.sin(th) + rng.normal(0, 0.1, n) * vc,
+                vy=fac * vc * np.cos(th), vz=rng.normal(0, 0.02, n) * vc, m=np.zeros(n))
+
+
+def test_torch_drift_unbound_matches_c_oracle():
+    # the hyperbolic branch against the C oracle's drift (itself pinned by
+    # brentq on Kepler's hyperbolic equation and by energy conservation)
+    d = _mixed_orbits(200, seed=31)
+    x, v, _ = T.state_tensors(d)
+    alpha = 2.0 / torch.linalg.norm(x, dim=1) - (v * v).sum(1) / G
+    assert int((alpha < 0).sum()) > 40 and int((alpha > 0).sum()) > 40
+    for dt in (20.0, -35.0, 300.0):
+        x1, v1 = T.drift(x, v, G, dt)
+        ref = oracle.state_copy(d)
+        assert oracle.drift(ref, G, dt) == 0
+        X = np.stack([ref["x"], ref["y"], ref["z"]]).T
+        V = np.stack([ref["vx"], ref["vy"], ref["vz"]]).T
+        ex = np.linalg.norm(x1.numpy() - X, axis=1) / np.linalg.norm(X, axis=1)
+        ev = np.linalg.norm(v1.numpy() - V, axis=1) / np.linalg.norm(V, axis=1)
+        assert ex.max() < 1e-12 and ev.max() < 1e-12, (dt, ex.max(), ev.max())
+
+
+def test_drift_gradient_fd_unbound():
+    # autograd through both branches against central differences
+    d = _mixed_orbits(40, seed=32)
+    x, v, _ = T.state_tensors(d)
+    _fd_check(lambda x_, v_: T.drift(x_, v_, G, 25.0), [x, v], seed=6)
