@@ -63,6 +63,8 @@ extern "C" {
 #define GENGA_E_RCRIT       (-7) /* a critical radius is negative or NaN               */
 #define GENGA_E_GROUP       (-8) /* a close-encounter group exceeds the direct solver's
                                     GENGA_GROUP_MAX bodies (its bodies kept their drift) */
+#define GENGA_E_SCRATCH     (-9) /* genga_kick_static: the problem needs more scratch
+                                    than GENGA_STATIC_SCRATCH_BYTES                 */
 
 /* genga_params.precision */
 #define GENGA_FP64  0 /* all pair arithmetic in binary64                              */
@@ -223,6 +225,26 @@ int genga_rcrit(const genga_bodies *b, const genga_params *p, void *ws, void *st
  * Positions of two distinct bodies that coincide set GENGA_E_NONFINITE. */
 int genga_kick(const genga_bodies *b, const genga_params *p, double h,
                double *ax, double *ay, double *az, genga_pairs *pairs, void *ws, void *stream);
+
+/* genga_kick without a workspace, for callers that cannot allocate device
+ * memory: code under HIP graph capture that may not call hipMalloc, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments, kernels
+ * and results as genga_kick (bit for bit, for the same params), except:
+ *  - scratch is a static device array of GENGA_STATIC_SCRATCH_BYTES bytes
+ *    that the library holds on every GPU it runs on until the process ends;
+ *    the call allocates nothing.  A kick that needs more (for the default
+ *    shapes: more than about 9,600 bodies) returns GENGA_E_SCRATCH at once,
+ *    with nothing enqueued;
+ *  - status (device int32, required) receives, when the stream reaches the
+ *    end of the call, GENGA_OK or the most severe code the kernels found
+ *    (GENGA_E_OVERFLOW, GENGA_E_NONFINITE, GENGA_E_RCRIT).
+ * Every call on one GPU shares that GPU's array and clears its status words
+ * first: calls that overlap on one GPU (different streams, or host threads
+ * without ordering) race and give undefined results.  The first call on a
+ * device looks up the array's device address (hipGetSymbolAddress). */
+#define GENGA_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+int genga_kick_static(const genga_bodies *b, const genga_params *p, double h, double *ax,
+                      double *ay, double *az, genga_pairs *pairs, int32_t *status, void *stream);
 
 /* Close-encounter list alone (same predicate and order as genga_kick); used
  * for the detection after the drift (Appendix A). */

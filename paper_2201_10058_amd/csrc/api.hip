@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "genga_internal.h"
@@ -129,6 +130,56 @@ static int do_kick(const genga_bodies *b, const genga_params *p, double h, doubl
     return GENGA_OK;
 }
 
+// Scratch of genga_kick_static: one array per GPU, which holds it from the
+// load of this library's code object until the process ends.  In host code
+// its name is a host-side stand-in, never a device address: the device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[GENGA_STATIC_SCRATCH_BYTES];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+static std::mutex g_static_mu;
+static void *g_static_ptr[STATIC_MAX_DEVICES];
+
+// Device address of this device's scratch array (the current device).
+static int static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return GENGA_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (!ptr) return GENGA_E_HIP;
+        g_static_ptr[dev] = ptr;
+    }
+    *out = g_static_ptr[dev];
+    return GENGA_OK;
+}
+
+// Status words at the head of the scratch (status, tile counter, refined
+// rows, padding): cleared at the start of every call.
+__global__ void k_static_begin(int32_t *head)
+{
+    if (threadIdx.x < 64) head[threadIdx.x] = 0;
+}
+
+// The call's status bits as the most severe return code, into *out.
+__global__ void k_static_end(const int32_t *head, int32_t *out)
+{
+    const int32_t st = head[0];
+    int32_t code = GENGA_OK;
+    if (st & ST_RCRIT) code = GENGA_E_RCRIT;
+    else if (st & ST_NONFINITE) code = GENGA_E_NONFINITE;
+    else if (st & ST_NOCONV) code = GENGA_E_NOCONV;
+    else if (st & ST_GROUP) code = GENGA_E_GROUP;
+    else if (st & ST_OVERFLOW) code = GENGA_E_OVERFLOW;
+    *out = code;
+}
+
 }  // namespace genga
 
 using namespace genga;
@@ -149,6 +200,8 @@ const char *genga_strerror(int code)
     case GENGA_E_NOCONV: return "Kepler solver or Bulirsch-Stoer did not converge";
     case GENGA_E_RCRIT: return "negative or non-finite critical radius";
     case GENGA_E_GROUP: return "close-encounter group larger than the direct solver's limit";
+    case GENGA_E_SCRATCH:
+        return "genga_kick_static: the kick needs more scratch than GENGA_STATIC_SCRATCH_BYTES";
     default: return "unknown error";
     }
 }
@@ -467,6 +520,30 @@ int genga_level_counts(int64_t n, const genga_params *p, void *ws, int64_t *out,
     hipError_t e = hipMemcpyAsync(out, (char *)ws + V.lcount, sizeof(int64_t) * V.L,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? GENGA_OK : hip_fail(e);
+}
+
+int genga_kick_static(const genga_bodies *b, const genga_params *p, double h, double *ax,
+                      double *ay, double *az, genga_pairs *pairs, int32_t *status, void *stream)
+{
+    int r = check_bodies(b, h != 0.0, true);
+    if (r) return r;
+    if ((r = check_params(p))) return r;
+    if ((r = check_pairs(pairs))) return r;
+    if (!status || !is_fin(h)) return GENGA_E_INVAL;
+    if ((ax || ay || az) && !(ax && ay && az)) return GENGA_E_INVAL;
+    if ((r = check_tp(b, p, true))) return r;
+    if (make_layout(b->n, choose_kick_cfg(b->n, p)).total > (size_t)GENGA_STATIC_SCRATCH_BYTES)
+        return GENGA_E_SCRATCH;
+    void *ws = nullptr;
+    if ((r = static_scratch(&ws))) return r;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_static_begin, dim3(1), dim3(64), 0, s, (int32_t *)ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+    if ((r = do_kick(b, p, h, ax, ay, az, pairs, true, ws, stream))) return r;
+    hipLaunchKernelGGL(k_static_end, dim3(1), dim3(1), 0, s, (const int32_t *)ws, status);
+    e = hipGetLastError();
     return e == hipSuccess ? GENGA_OK : hip_fail(e);
 }
 

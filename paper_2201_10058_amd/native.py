@@ -25,6 +25,7 @@ E_UNSUPPORTED = -5
 E_NOCONV = -6
 E_RCRIT = -7
 E_GROUP = -8
+E_SCRATCH = -9
 
 FP64 = 0
 MIXED = 1
@@ -79,6 +80,10 @@ SIGNATURES = {
     "genga_kick": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params), ctypes.c_double,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(Pairs), ctypes.c_void_p, ctypes.c_void_p]),
+    "genga_kick_static": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
+                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(Pairs), ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     "genga_encounter_pairs": (ctypes.c_int, [ctypes.POINTER(Bodies), ctypes.POINTER(Params),
                                              ctypes.POINTER(Pairs), ctypes.c_void_p,
                                              ctypes.c_void_p]),
@@ -306,6 +311,26 @@ class Workspace:
 
 def read_status(ws: Workspace) -> int:
     return load().genga_read_status(ctypes.c_void_p(ws.ptr), ctypes.c_void_p(_stream_ptr()))
+
+
+def kick_static(state: State, cfg: Config, h: float, acc: bool = False,
+                pairs: PairList | None = None):
+    """genga_kick_static: the kick with the library's static scratch (no
+    workspace).  Returns (a or None, status) where status is a device int32
+    tensor that receives the call's status code."""
+    b, p = state.bodies(), cfg.params()
+    a = None
+    ptrs = (None, None, None)
+    if acc:
+        a = torch.empty((3, state.n), dtype=torch.float64, device=state.t["x"].device)
+        ptrs = (a[0].data_ptr(), a[1].data_ptr(), a[2].data_ptr())
+    status = torch.full((1,), -100, dtype=torch.int32, device=state.t["x"].device)
+    ps = pairs.struct() if pairs is not None else None
+    _check(load().genga_kick_static(ctypes.byref(b), ctypes.byref(p), float(h), ptrs[0], ptrs[1],
+                                    ptrs[2], ctypes.byref(ps) if ps is not None else None,
+                                    ctypes.c_void_p(status.data_ptr()),
+                                    ctypes.c_void_p(_stream_ptr())), "genga_kick_static")
+    return a, status
 
 
 def rcrit(state: State, cfg: Config, ws: Workspace):

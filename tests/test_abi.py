@@ -203,3 +203,25 @@ def test_batch_plan_shape_on_host():
     btb = N.BatchC(len(sizes), bad.ctypes.data, dummy, dummy, dummy, dummy)
     p = N.Config(G=2.959e-4).params()
     assert lib.genga_batch_workspace_bytes(ctypes.byref(btb), ctypes.byref(p)) == 0
+
+
+def test_kick_static_host_checks():
+    # the no-workspace kick refuses, before any device work, a missing status
+    # word and a system whose kick needs more than the static scratch
+    from paper_2201_10058_amd import native
+    lib = native.load()
+    assert native.E_SCRATCH == -9
+    assert lib.genga_strerror(native.E_SCRATCH).decode().startswith("genga_kick_static")
+    fake = ctypes.c_void_p(256)     # never dereferenced by the host-side checks
+    b = native.Bodies()
+    for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rc"):
+        setattr(b, k, fake)
+    p = native.Config(G=2.959e-4).params()
+    b.n = 1000
+    assert lib.genga_kick_static(ctypes.byref(b), ctypes.byref(p), 0.0, None, None, None, None,
+                                 None, None) == native.E_INVAL
+    for n in (20000, 65536):
+        b.n = n
+        assert lib.genga_workspace_bytes(n, ctypes.byref(p)) > (96 << 20)
+        assert lib.genga_kick_static(ctypes.byref(b), ctypes.byref(p), 0.0, None, None, None, None,
+                                     fake, None) == native.E_SCRATCH
