@@ -145,6 +145,28 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// High word of an upper bound of the largest of the 64 lanes' values (all
+// lanes active, every value a non-negative double), in a scalar register:
+// the largest high word over the wave.  For non-negative doubles the high
+// word (as a signed int) orders the values, so bound_of_hi(h) (the low word
+// set to all ones) is at least every lane's value and above their maximum by
+// less than 2^-20 of it.  The maximum runs over DPP row shifts and row
+// broadcasts (no address registers, unlike a butterfly of ds_bpermute); lane
+// 63 ends with it.
+__device__ __forceinline__ int wave_max_hi(double v)
+{
+    int h = __double2hiint(v);
+    h = max(h, __builtin_amdgcn_update_dpp(h, h, 0x111, 0xf, 0xf, false));   // row_shr:1
+    h = max(h, __builtin_amdgcn_update_dpp(h, h, 0x112, 0xf, 0xf, false));   // row_shr:2
+    h = max(h, __builtin_amdgcn_update_dpp(h, h, 0x114, 0xf, 0xf, false));   // row_shr:4
+    h = max(h, __builtin_amdgcn_update_dpp(h, h, 0x118, 0xf, 0xf, false));   // row_shr:8
+    h = max(h, __builtin_amdgcn_update_dpp(h, h, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    h = max(h, __builtin_amdgcn_update_dpp(h, h, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(h, 63);
+}
+
+__device__ __forceinline__ double bound_of_hi(int h) { return __hiloint2double(h, (int)0xffffffff); }
+
 // A value the same in every lane, moved to scalar registers.
 __device__ __forceinline__ double wave_uniform(double v)
 {

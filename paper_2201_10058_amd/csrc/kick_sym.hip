@@ -75,12 +75,14 @@ struct SymDev {
     double c53;        // 5/3
     double c15, c1875; // 3/2, 15/8
     double widen;      // mixed: squared widening of the binary32 near test
+    double far_row, far_col;   // coordinates of padding rows and columns
 };
 
 // Padding rows and columns sit far away, on opposite sides (no two padding
 // bodies coincide), with mass 0 and critical radius 0: r^2 stays finite (below
 // 1.3e37, also in binary32), every weight they give or take is 0 and they
-// never reach the rare path.
+// never reach the rare path.  (Passed as kernel arguments, so that they sit in
+// scalar registers.)
 constexpr double SYM_FAR_ROW = 1e18, SYM_FAR_COL = -1e18;
 
 // One chunk of 64 columns, stored twice (entries e and e + 64 are column e).
@@ -107,7 +109,8 @@ struct SymSmem {
     SymCols<MIXED> col[2];
     double acc[2][MIXED ? 4 : 3][SYM_NW][64];   // column sums of a chunk, per wave
     double nacc[MIXED ? SYM_NW : 1][3][64];      // mixed: binary64 column sums of near pairs
-    double gmax[2];    // binary64: largest rc^2 among the columns of chunk b
+    int gmax[2];       // binary64: high word of a bound of the largest rc^2 among
+                       // the columns of chunk b (wave_max_hi)
     int wcnt[SYM_NW];
 };
 
@@ -381,10 +384,10 @@ __device__ __forceinline__ void sym_chunk_mixed(const SymDev &a, SymRows<true> &
 // its rc^2 (0 for padding).
 template <bool MIXED>
 __device__ __forceinline__ double sym_put(SymCols<MIXED> &C, int t, bool real, double x, double y,
-                                          double z, double m, double rc, double widen)
+                                          double z, double m, double rc, double widen, double far)
 {
     if (!real) {
-        x = y = z = SYM_FAR_COL;
+        x = y = z = far;
         m = 0.0;
         rc = 0.0;
     }
@@ -418,10 +421,12 @@ __device__ __forceinline__ void sym_colsum(const SymDev &a, const SymSmem<MIXED>
 {
     constexpr int NC = MIXED ? 4 : 3;
     const SymShape &h = a.sh;
-    const int64_t j = cc * 64 + lane;
+    int l = lane;   // opaque copy: the index is formed here, not kept live
+    asm volatile("" : "+v"(l));
+    const int j = (int)(cc * 64) + l;
     if (j >= h.n) return;
     const int64_t row0 = g * SYM_RG;
-    double *cp = a.colpart + (size_t)NC * h.coloff(g) + (j - row0);
+    double *cp = a.colpart + (size_t)NC * h.coloff(g) - row0 + j;
     const int64_t L = h.collen(g);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -444,7 +449,7 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
     const SymShape &h = a.sh;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int w = tid >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t n = h.n;
     const int64_t row0 = g * SYM_RG;
     const int64_t rowend = row0 + SYM_RG < n ? row0 + SYM_RG : n;
@@ -474,7 +479,7 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
             R.rc2i[q] = r * r;
             mi = a.m[i];
         } else {
-            R.xi[q] = R.yi[q] = R.zi[q] = SYM_FAR_ROW;
+            R.xi[q] = R.yi[q] = R.zi[q] = a.far_row;
             R.rc2i[q] = 0.0;
         }
         R.mw[q] = MIXED ? mi : 1.5 * mi;
@@ -489,15 +494,17 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
     }
     // Binary64 fast path's gate: a pair can be inside max(rc_i, rc_j) only if
     // r^2 is at most the largest rc^2 among the wave's rows and the chunk's
-    // columns, so one compare against that wave-uniform bound replaces the
-    // per-pair max and compare, and the rare path takes the exact test.  (The
+    // columns, so one compare against a wave-uniform bound of it (at most
+    // 2^-20 above) replaces the per-pair max and compare, and the rare path
+    // takes the exact test.  (The
     // mixed kernel keeps its per-pair test: the bound's registers cost it more
     // in spills than the instruction saves.)
-    double rg = 0.0;
+    int rg = 0;   // high word of the bound over the wave's rows
     if constexpr (!MIXED) {
+        double r2m = 0.0;
 #pragma unroll
-        for (int q = 0; q < SYM_IPT; ++q) rg = __builtin_fmax(rg, R.rc2i[q]);
-        rg = wave_uniform(wave_max(rg));
+        for (int q = 0; q < SYM_IPT; ++q) r2m = vmax_f64(r2m, R.rc2i[q]);
+        rg = wave_max_hi(r2m);
     }
     int *wcnt = &sm.wcnt[w];
     if (lane == 0) __hip_atomic_store(wcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -509,16 +516,16 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
 
     // chunk 0 by wave 0
     if (w == 0) {
-        const int64_t jg = col0 + lane;
+        const int jg = (int)col0 + lane;
         const bool real = jg < col1;
         double x = 0, y = 0, z = 0, m = 0, rc = 0;
         if (real) {
             x = a.x[jg]; y = a.y[jg]; z = a.z[jg]; m = a.m[jg]; rc = a.rc[jg];
             if (!(rc >= 0.0 && rc < INFINITY)) atomicOr(a.status, ST_RCRIT);
         }
-        const double gv = sym_put<MIXED>(sm.col[0], lane, real, x, y, z, m, rc, a.widen);
+        const double gv = sym_put<MIXED>(sm.col[0], lane, real, x, y, z, m, rc, a.widen, a.far_col);
         if constexpr (!MIXED) {
-            const double gm = wave_max(gv);
+            const int gm = wave_max_hi(gv);
             if (lane == 0) sm.gmax[0] = gm;
         }
     }
@@ -535,7 +542,7 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
         double px = 0, py = 0, pz = 0, pm = 0, prc = 0;
         bool preal = false;
         if (loader) {
-            const int64_t jg = (cc + 1) * 64 + lane;
+            const int jg = (int)((cc + 1) * 64) + lane;
             preal = jg < col1;
             if (preal) {
                 px = a.x[jg]; py = a.y[jg]; pz = a.z[jg]; pm = a.m[jg]; prc = a.rc[jg];
@@ -577,7 +584,8 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
             sm.nacc[w][1][lane] = 0.0;
             sm.nacc[w][2][lane] = 0.0;
         } else {
-            const double g2 = wave_uniform(__builtin_fmax(rg, sm.gmax[b]));
+            const double g2 =
+                bound_of_hi(max(rg, __builtin_amdgcn_readfirstlane(sm.gmax[b])));
             double cx = 0.0, cy = 0.0, cz = 0.0;
             if (full)
                 sym_chunk<false>(a, R, sm.col[b], colbase, mode, cx, cy, cz, c53, g2, wave_g, wcnt,
@@ -591,9 +599,10 @@ __device__ __forceinline__ void sym_tile_run(const SymDev &a, int64_t g, int64_t
         }
         if (loader) {
             if (preal && !(prc >= 0.0 && prc < INFINITY)) atomicOr(a.status, ST_RCRIT);
-            const double gv = sym_put<MIXED>(sm.col[b ^ 1], lane, preal, px, py, pz, pm, prc, a.widen);
+            const double gv = sym_put<MIXED>(sm.col[b ^ 1], lane, preal, px, py, pz, pm, prc,
+                                              a.widen, a.far_col);
             if constexpr (!MIXED) {
-                const double gm = wave_max(gv);
+                const int gm = wave_max_hi(gv);
                 if (lane == 0) sm.gmax[b ^ 1] = gm;
             }
         }
@@ -759,6 +768,8 @@ static SymDev sym_dev(const SymShape &h, bool mixed, double widen, const double 
     a.c15 = 1.5;
     a.c1875 = 1.875;
     a.widen = widen;
+    a.far_row = SYM_FAR_ROW;
+    a.far_col = SYM_FAR_COL;
     return a;
 }
 
