@@ -414,10 +414,12 @@ int genga_step(genga_bodies *b, const genga_params *p, genga_pairs *pairs, void 
     if (e != hipSuccess) return hip_fail(e);
     if ((r = do_kick(b, p, h, nullptr, nullptr, nullptr, levels ? &e0 : pairs, true, ws, stream)))
         return r;
-    if (!levels && !gr && p->precision == GENGA_FP64) {
-        // the plain binary64 step in fewer launches: HC + FG + the next HC's
-        // momentum sum in one kernel, the second HC fused into the second
-        // kick's reduction (the kick sees only position differences)
+    if (!levels && !gr) {
+        // the plain step in fewer launches: HC + FG + the next HC's momentum
+        // sum in one kernel, the second HC fused into the second kick's
+        // reduction (the kick sees only position differences; in mixed
+        // precision the binary64 refinement of cancelling rows, which runs
+        // after that reduction, sees the shifted positions)
         const int64_t nsum = hc_count(b, p);
         if ((e = launch_momentum(b, L, (char *)ws, s, nsum)) != hipSuccess) return hip_fail(e);
         if ((e = launch_hc_drift(b, p->m_star, h, p->G * p->m_star, p->dt, L, (char *)ws, s,

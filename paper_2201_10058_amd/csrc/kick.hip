@@ -208,7 +208,11 @@ constexpr double MIXED_NEAR = 3.0;
 // Rows whose binary32 terms sum (in magnitude) to more than MIXED_KAPPA times
 // the magnitude of their total are evaluated again in binary64: the binary32
 // terms carry relative errors of a few 2^-24, so without this the error of a
-// strongly cancelling row grows with that ratio.
+// strongly cancelling row grows with that ratio.  The error per unit of the
+// ratio depends on the arrangement: below 3e-8 on the disks (measured
+// without the refinement: initial disks of 16,384-65,536 bodies and after
+// 10-1000 steps), about 1.6e-7 for the bodies of a ring of equal masses,
+// where rounding errors add coherently; hence 10.
 constexpr double MIXED_KAPPA = 10.0;
 constexpr int FOLD = 64;   // columns per binary32 partial sum (mixed mode)
 
@@ -950,53 +954,65 @@ __global__ __launch_bounds__(FB) void k_kick_refine(RefineDev a)
     }
 }
 
-// Single system: tiles of 256 listed rows x a column slice, columns staged in
-// LDS as in the kick, so the listed rows cost what they would in the binary64
-// kick.  The number of slices is chosen on the device from the row count so
-// that the partial sums ([row][slice][3], by list position) fit the partial-
-// sum region of the workspace (cap doubles); each slice is a multiple of 64
-// columns.
-constexpr int RT = KB;        // listed rows per refine tile
-constexpr int RMAXS = 1024;   // most column slices of the refinement (a few hundred listed rows
-                              // then fill the chip: 2 row tiles x 1024 slices of 64 columns)
+// Single system: the listed rows in binary64.  A block takes a tile of 64
+// listed rows (one per lane, every wave the same rows) and a block slice of
+// the columns; its 4 waves split the slice in 4 contiguous parts, each staging
+// 64 columns at a time in its own LDS region (no block barrier in the column
+// loop), and their sums are added in wave order into the partial-sum region,
+// [row tile][block slice][3][64]; k_refine_sum adds a row's block slices in
+// order and applies v += h a.  The grids are fixed and the row count is read
+// on the device, so the launches can be captured.
+constexpr int RF_GRID = 2048;   // blocks of the refinement
 
-__device__ __forceinline__ void refine_shape(int cnt, int64_t n, int64_t cap, int &S, int64_t &len)
+struct RfSmem {
+    double4 xyzm[4][64];   // (x, y, z, 3/2 m) of a wave's staged columns
+    double rc2[4][64], m[4][64], irc[4][64];
+    double acc[4][3][64];
+};
+
+// Row tiles, block slices and the block slice length (a multiple of 128
+// columns: at least 32 per wave) for cnt listed rows; the partial sums fit
+// cap doubles.
+__device__ __forceinline__ void refine_split(int cnt, int64_t n, int64_t cap, int &RTn, int &SB,
+                                             int64_t &blen)
 {
-    int64_t sl = cap / (3 * (int64_t)(cnt > 0 ? cnt : 1));
-    sl = sl < RMAXS ? sl : RMAXS;
-    sl = sl > 1 ? sl : 1;
-    len = (((n + sl - 1) / sl) + 63) / 64 * 64;
-    S = (int)((n + len - 1) / len);
+    RTn = (cnt + 63) / 64;
+    int64_t sb = RF_GRID / RTn;
+    const int64_t most = cap / (192 * (int64_t)RTn);
+    sb = sb < most ? sb : most;
+    sb = sb > 1 ? sb : 1;
+    blen = (((n + sb - 1) / sb) + 127) / 128 * 128;
+    SB = (int)((n + blen - 1) / blen);
 }
 
-__global__ __launch_bounds__(RT) void k_refine_tiles(KickDev a, const int32_t *list,
-                                                     const int32_t *count, int64_t cap)
+__global__ __launch_bounds__(256) void k_refine_rows(KickDev a, RefineDev f, int64_t cap)
 {
-    __shared__ KickSmem<RT> sm;
-    const int tid = threadIdx.x;
-    const int cnt = *count;
-    int S;
-    int64_t len;
-    refine_shape(cnt, a.n, cap, S, len);
-    const int64_t items = (int64_t)((cnt + RT - 1) / RT) * S;
+    __shared__ RfSmem sm;
+    const int cnt = *f.count;
+    if (cnt == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int RTn, SB;
+    int64_t blen;
+    refine_split(cnt, a.n, cap, RTn, SB, blen);
+    const int items = RTn * SB;
     const int vzero = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
     const double c15 = a.c15 + (double)vzero, c1875 = a.c1875 + (double)vzero;
     const double c53 = a.c53 + (double)vzero;
-    const double4 *t_xyzm = sm.xyzm + vzero;
-    const double *t_rc2 = sm.rc2 + vzero;
-    const double *t_m = sm.m + vzero;
-    const double *t_irc = sm.irc + vzero;
-    for (int64_t t = blockIdx.x; t < items; t += gridDim.x) {
-        const int64_t pos = (t / S) * RT + tid;
-        const int s = (int)(t % S);
+    const double4 *t_xyzm = sm.xyzm[w] + vzero;
+    const double *t_rc2 = sm.rc2[w] + vzero;
+    const double *t_m = sm.m[w] + vzero;
+    const double *t_irc = sm.irc[w] + vzero;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int rt = item / SB, sb = item % SB;
+        const int pos = rt * 64 + lane;
+        int64_t i = -1;
         Rows<1> R;
-        R.ii[0] = -1;
         R.xi[0] = R.yi[0] = R.zi[0] = __builtin_nan("");
         R.rc2i[0] = 0.0;
         R.iri[0] = 0.0;
         if (pos < cnt) {
-            const int64_t i = list[pos];
-            R.ii[0] = i;
+            i = f.list[pos];
             R.xi[0] = a.x[i];
             R.yi[0] = a.y[i];
             R.zi[0] = a.z[i];
@@ -1004,51 +1020,65 @@ __global__ __launch_bounds__(RT) void k_refine_tiles(KickDev a, const int32_t *l
             R.rc2i[0] = r * r;
             R.iri[0] = 1.0 / r;
         }
+        R.ii[0] = i;
         R.ax[0] = R.ay[0] = R.az[0] = 0.0;
         R.kc[0] = 0;
-        const int64_t j0 = (int64_t)s * len;
-        const int64_t j1 = j0 + len < a.n ? j0 + len : a.n;
-        for (int64_t t0 = j0; t0 < j1; t0 += RT) {
-            __syncthreads();
-            const int64_t jg = t0 + tid;
+        const int64_t q4 = blen / 4;
+        const int64_t j0 = (int64_t)sb * blen + w * q4;
+        const int64_t j1 = j0 + q4 < a.n ? j0 + q4 : a.n;
+        for (int64_t t0 = j0; t0 < j1; t0 += 64) {
+            const int64_t jg = t0 + lane;
             if (jg < j1) {
                 const double mj = a.m[jg], rcj = a.rc[jg];
-                sm.xyzm[tid] = make_double4(a.x[jg], a.y[jg], a.z[jg], 1.5 * mj);
-                sm.m[tid] = mj;
-                sm.rc2[tid] = rcj * rcj;
-                sm.irc[tid] = 1.0 / rcj;
+                sm.xyzm[w][lane] = make_double4(a.x[jg], a.y[jg], a.z[jg], 1.5 * mj);
+                sm.m[w][lane] = mj;
+                sm.rc2[w][lane] = rcj * rcj;
+                sm.irc[w][lane] = 1.0 / rcj;
             }
-            __syncthreads();
-            const int tn = (int)(j1 - t0 < RT ? j1 - t0 : RT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int tn = (int)(j1 - t0 < 64 ? j1 - t0 : 64);
             for (int jj = 0; jj < tn; ++jj)
                 interact<1, KM_F64>(a, R, t_xyzm[jj], vmax_f64(R.rc2i[0], t_rc2[jj]), t0 + jj, c15,
                                     c1875, c53, 0, nullptr, t_rc2 + jj, t_m + jj, t_irc + jj);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (pos < cnt) {
-            double *P = a.part + ((size_t)pos * S + s) * 3;
-            P[0] = R.ax[0];
-            P[1] = R.ay[0];
-            P[2] = R.az[0];
+        sm.acc[w][0][lane] = R.ax[0];
+        sm.acc[w][1][lane] = R.ay[0];
+        sm.acc[w][2][lane] = R.az[0];
+        __syncthreads();
+        if (w == 0) {
+            double *P = a.part + ((size_t)rt * SB + sb) * 192;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                P[c * 64 + lane] = ((sm.acc[0][c][lane] + sm.acc[1][c][lane]) + sm.acc[2][c][lane]) +
+                                   sm.acc[3][c][lane];
         }
+        __syncthreads();
     }
 }
 
-// Sum each listed row's slices and apply v += h a: one wave per listed row,
-// lanes take slices l, l + 64, then a fixed xor-butterfly combines the lanes.
-__global__ __launch_bounds__(RB) void k_refine_apply(RefineDev f, const double *part, int64_t cap)
+// Sum each listed row's block-slice sums in slice order and apply v += h a:
+// one wave per listed row, lanes take slices l, l + 64, ..., then a fixed
+// xor-butterfly combines the lanes.
+__global__ __launch_bounds__(RB) void k_refine_sum(KickDev a, RefineDev f, int64_t cap)
 {
     const int cnt = *f.count;
-    int S;
-    int64_t len;
-    refine_shape(cnt, f.n, cap, S, len);
+    int RTn, SB;
+    int64_t blen;
+    refine_split(cnt, a.n, cap, RTn, SB, blen);
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (RB / 64);
     for (int64_t pos = (int64_t)blockIdx.x * (RB / 64) + (threadIdx.x >> 6); pos < cnt; pos += nw) {
         const int64_t i = f.list[pos];
+        const double *P = a.part + (size_t)(pos / 64) * SB * 192 + (pos % 64);
         double a3[3] = {0.0, 0.0, 0.0};
-        for (int s = lane; s < S; s += 64) {
+        for (int s2 = lane; s2 < SB; s2 += 64) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) a3[c] += part[((size_t)pos * S + s) * 3 + c];
+            for (int c = 0; c < 3; ++c) a3[c] += P[(size_t)s2 * 192 + c * 64];
         }
         for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -1543,12 +1573,11 @@ hipError_t launch_kick(const KickLaunch &k, const KickCfg &c, const Layout &L, c
             const int64_t cap = 5 * (int64_t)c.slices * L.npad;
             KickDev rd = d;
             rd.emit = 0;
-            hipLaunchKernelGGL(k_refine_tiles, dim3(2048), dim3(RT), 0, s, rd, f.list, f.count,
-                               cap);
+            hipLaunchKernelGGL(k_refine_rows, dim3(RF_GRID), dim3(256), 0, s, rd, f, cap);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_refine_apply, dim3((unsigned)std::min<int64_t>(L.nb, 1024)),
-                               dim3(RB), 0, s, f, d.part, cap);
+            hipLaunchKernelGGL(k_refine_sum, dim3((unsigned)std::min<int64_t>(L.nb, 1024)),
+                               dim3(RB), 0, s, rd, f, cap);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
