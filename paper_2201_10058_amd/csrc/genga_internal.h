@@ -97,6 +97,9 @@ hipError_t launch_kick_sym(const SymShape &h, bool mixed, double widen, const do
                            double *rowpart, double *colpart, int32_t *cnt, int32_t *stage,
                            int32_t *wcount, int32_t *status, int32_t *refine_cnt, bool emit,
                            hipStream_t s);
+hipError_t launch_kick_vjp_sym(const SymShape &h, const genga_bodies *b, double G, double scale,
+                               const double *abx, const double *aby, const double *abz,
+                               genga_adjoint *adj, double *part, int32_t *status, hipStream_t s);
 hipError_t launch_kick_sym_b(const SymBatch &b, const double *x, const double *y,
                              const double *z, const double *m, const double *rc, double *rowpart,
                              double *colpart, int32_t *cnt, int32_t *stage, int32_t *wcount,

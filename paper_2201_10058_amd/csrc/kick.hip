@@ -1290,9 +1290,10 @@ KickCfg choose_kick_cfg(int64_t n, const genga_params *p)
             W = SYM_RG / dd;
         }
         const SymShape h = sym_shape(n, W);
-        // its row and column sums grow as n^2 / SYM_RG: by default the
-        // symmetric form stays within SYM_WS_MAX bytes of them
-        const double bytes = 32.0 * ((double)h.T * SYM_RG + (double)h.coloff(h.G));
+        // its row and column sums (up to 5 per row and tile or group: the
+        // adjoint's) grow as n^2 / SYM_RG: by default the symmetric form stays
+        // within SYM_WS_MAX bytes of them
+        const double bytes = 40.0 * ((double)h.T * SYM_RG + (double)h.coloff(h.G));
         if ((flags & GENGA_FLAG_SYMMETRIC) || bytes <= (double)SYM_WS_MAX) {
             c.use_sym = true;
             c.sym = h;
@@ -1311,11 +1312,14 @@ Layout make_layout(int64_t n, const KickCfg &c, int64_t S)
     size_t off = 0;
     L.status = off;
     off += 256;
-    // the symmetric kick's row sums [T][3][SYM_RG] and column sums share the
-    // partial-sum region; its per-tile pair counts the count region
+    // the symmetric kick's row sums [T][3 or 4][SYM_RG] and column sums (with
+    // the row totals' parts below SYM_FOLD_BELOW bodies), or the symmetric
+    // adjoint's 5 of each, share the partial-sum region; the kick's per-tile
+    // pair counts the count region
+    const size_t symx = (size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G);
     const size_t sym_part =
-        c.use_sym ? 4 * ((size_t)c.sym.T * SYM_RG + (size_t)c.sym.coloff(c.sym.G)) +
-                        (n < SYM_FOLD_BELOW ? (size_t)SYM_FOLD * 4 * L.npad : 0)
+        c.use_sym ? std::max(4 * symx + (n < SYM_FOLD_BELOW ? (size_t)SYM_FOLD * 4 * L.npad : 0),
+                             5 * symx)
                   : 0;
     size_t sym_cnt = c.use_sym ? (size_t)c.sym.T * SYM_RG : 0;
     size_t nw = std::max<size_t>((size_t)c.nwaves, c.use_sym ? (size_t)c.sym.T * SYM_NW : 0);

@@ -304,6 +304,12 @@ hipError_t launch_kick_vjp(const genga_bodies *b, const genga_params *p, double 
                            genga_adjoint *adj, char *ws, hipStream_t s)
 {
     KickCfg c = choose_kick_cfg(b->n, p);
+    if (c.use_sym) {
+        // the symmetric form, where the kick takes it (csrc/vjp_sym.hip)
+        const Layout L = make_layout(b->n, c);
+        return launch_kick_vjp_sym(c.sym, b, p->G, scale, abx, aby, abz, adj,
+                                   (double *)(ws + L.part), (int32_t *)(ws + L.status), s);
+    }
     // one row per thread for the adjoint (its register footprint is larger)
     c.ipt = 1;
     c.gx = (int)((b->n + KB - 1) / KB);

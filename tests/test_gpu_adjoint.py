@@ -34,8 +34,12 @@ def _small_disk(n, seed):
     return W.make_disk(W.DiskSpec(f"adj{n}", n, 0.5, 1.5, 2.0 * n / 64.0, seed=seed))
 
 
-@pytest.mark.parametrize("n,scale", [(200, 0.4), (700, 0.15)])
-def test_kick_vjp_matches_autograd(dev, n, scale):
+@pytest.mark.parametrize("flags", [0, N.FLAG_SYMMETRIC])
+@pytest.mark.parametrize("n,scale", [(200, 0.4), (700, 0.15), (1100, 0.1)])
+def test_kick_vjp_matches_autograd(dev, n, scale, flags):
+    # the one-sided (gather) form and the symmetric form (each pair once,
+    # applied to both bodies; the default from 8,192 bodies); 1,100 bodies
+    # span three row groups of 512 and a ragged tail
     d = W.random_cloud(n, seed=21, rc_scale=scale)
     rng = np.random.default_rng(1)
     abar = rng.normal(size=(3, n))
@@ -47,7 +51,7 @@ def test_kick_vjp_matches_autograd(dev, n, scale):
     gx, gm, grc = torch.autograd.grad(L, (x, m, rc))
     # GPU
     st = _gpu_state(d, rc=d["rc"])
-    cfg = N.Config(G=G)
+    cfg = N.Config(G=G, flags=flags)
     ws = N.Workspace(n, cfg)
     adj = N.AdjointState(n)
     ab = [torch.tensor(abar[c], device="cuda") for c in range(3)]
@@ -60,6 +64,39 @@ def test_kick_vjp_matches_autograd(dev, n, scale):
     _say("kick vjp rel errors (x, m, rc)", e, "band rc grads", int((grc != 0).sum()))
     assert max(e) < 1e-10
     assert int((grc != 0).sum()) > 10
+
+
+@pytest.mark.parametrize("n", [16384, 65536])
+def test_kick_vjp_forms_agree_on_disks(dev, n):
+    # at the benchmark sizes (beyond the autograd reference's reach) the
+    # symmetric VJP against the one-sided gather form, which the autograd
+    # test pins at small sizes: every body, relative to its own gradient
+    d = W.make_disk(W.DISK_65536 if n == 65536 else W.DISK_MIXED[n])
+    st = _gpu_state(d)
+    c0 = N.Config(G=G)
+    N.rcrit(st, c0, N.Workspace(n, c0))
+    rng = np.random.default_rng(9)
+    ab = [torch.tensor(rng.normal(size=n), device="cuda") for _ in range(3)]
+    out = {}
+    for name, fl in (("sym", N.FLAG_SYMMETRIC), ("one", N.FLAG_DIRECTED)):
+        cfg = N.Config(G=G, flags=fl)
+        ws = N.Workspace(n, cfg)
+        adj = N.AdjointState(n)
+        N.kick_vjp(st, cfg, ws, 1.3, ab, adj)
+        torch.cuda.synchronize()
+        assert N.read_status(ws) == N.OK
+        out[name] = {k: adj.t[k].cpu().numpy() for k in ("x", "y", "z", "m", "rc")}
+    xs = np.stack([out["sym"][k] for k in "xyz"]); xo = np.stack([out["one"][k] for k in "xyz"])
+    ex = np.linalg.norm(xs - xo, axis=0) / np.linalg.norm(xo, axis=0)
+    # scalar gradients (sums of terms of both signs, some near zero): against
+    # the largest magnitude over the bodies
+    em = np.abs(out["sym"]["m"] - out["one"]["m"]) / np.abs(out["one"]["m"]).max()
+    band = out["one"]["rc"] != 0
+    er = np.abs(out["sym"]["rc"] - out["one"]["rc"]) / np.abs(out["one"]["rc"]).max()
+    _say(f"vjp forms n={n}: xbar {ex.max():.2e} mbar {em.max():.2e} rcbar {er.max():.2e} "
+         f"({int(band.sum())} band rows)")
+    assert ex.max() < 1e-10 and em.max() < 1e-12 and er.max() < 1e-12
+    assert np.array_equal(out["sym"]["rc"] != 0, band)
 
 
 def test_rcrit_hc_drift_vjp_match_autograd(dev):
