@@ -45,12 +45,19 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-kernels-only", action="store_true",
+                    help="batched section without the autotuner and the per-system comparison "
+                         "(for counter runs: the captured batched step alone)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-tp", action="store_true",
                     help="skip the test-particle mode timings")
     ap.add_argument("--no-levels", action="store_true",
                     help="skip the symplectic-level, direct-solver and GR timings")
+    ap.add_argument("--no-pairs-run", action="store_true",
+                    help="skip the 1000-step run with per-step encounter-list hashes")
+    ap.add_argument("--no-sizes", action="store_true",
+                    help="skip the binary64/mixed step timings at 16,384 and 32,768 bodies")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 2,048-body eager vs hipGraph step timing")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -61,7 +68,7 @@ def parse():
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KICK_SOURCES = ("kick.hip", "kick_sym.hip", "device_common.h", "genga_internal.h")
+KICK_SOURCES = ("kick.hip", "kick_sym.hip", "sym_common.h", "device_common.h", "genga_internal.h")
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_kick_sym_disk65536_traffic.txt")
 
 
@@ -266,13 +273,29 @@ def bench_small(N, W, torch, np, steps=100):
     with torch.cuda.graph(g):
         N.step(st, cfg, ws, pairs)
     graph = timed(g.replay)
+    # several steps captured in one graph (one launch of the whole sequence)
+    per_graph = 10
+    g10 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g10):
+        for _ in range(per_graph):
+            N.step(st, cfg, ws, pairs)
+    for _ in range(2):
+        g10.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // per_graph):
+        g10.replay()
+    torch.cuda.synchronize()
+    graph10 = (time.perf_counter() - t0) / (per_graph * (steps // per_graph))
     if N.read_status(ws) != N.OK:
         raise SystemExit("small-system status")
     inter = 2.0 * st.n * (st.n - 1)
     return {"workload": W.DISK_2048.name, "n": st.n, "steps": steps,
             "eager_step_us": round(eager * 1e6, 2), "graph_step_us": round(graph * 1e6, 2),
+            "graph_10_steps_per_replay_step_us": round(graph10 * 1e6, 2),
             "eager_ginter_s": round(inter / eager / 1e9, 3),
             "graph_ginter_s": round(inter / graph / 1e9, 3),
+            "graph_10_steps_ginter_s": round(inter / graph10 / 1e9, 3),
             "energy_rel_change_eager_steps": float((e_end[0] - e_start[0]) / abs(e_start[0])),
             "energy_k_rel_change_eager_steps": float((e_end[5] - e_start[5]) / abs(e_start[5]))}
 
@@ -383,6 +406,121 @@ def bench_gr(N, W, torch, np, steps=10):
     return out
 
 
+def bench_sizes(N, W, torch, np, steps=30):
+    """Binary64 and mixed steps of the 16,384- and 32,768-body disks (the
+    65,536-body disk is the main run), each from the same initial state:
+    time per step; the two precisions alternate twice and the faster of each
+    pair of runs is kept."""
+    out = {}
+    for n_ in (16384, 32768):
+        d = W.make_disk(W.DISK_MIXED[n_])
+        best = {}
+        for _ in range(2):
+            for name, prec in (("fp64", N.FP64), ("mixed", N.MIXED)):
+                st = N.State.from_numpy(d)
+                cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                               precision=prec, flags=N.FLAG_NOSYNC)
+                ws = N.Workspace(n_, cfg)
+                pl = N.PairList(1 << 20)
+                for _ in range(3):
+                    N.step(st, cfg, ws, pl)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    N.step(st, cfg, ws, pl)
+                torch.cuda.synchronize()
+                dt_s = (time.perf_counter() - t0) / steps
+                if N.read_status(ws) != N.OK:
+                    raise SystemExit(f"sizes {n_} status")
+                best[name] = min(best.get(name, 1e9), dt_s)
+        inter = 2.0 * n_ * (n_ - 1)
+        out[f"n{n_}"] = {"workload": d["name"],
+                         "fp64_step_ms": round(best["fp64"] * 1e3, 4),
+                         "mixed_step_ms": round(best["mixed"] * 1e3, 4),
+                         "fp64_ginter_s": round(inter / best["fp64"] / 1e9, 3),
+                         "mixed_ginter_s": round(inter / best["mixed"] / 1e9, 3),
+                         "mixed_speedup": round(best["fp64"] / best["mixed"], 4)}
+    return out
+
+
+def bench_n2_zero(N, W, torch, np, steps=10):
+    """The 65,536-body step with the critical radius of the Hill term alone
+    (n2 = 0 in eq. rcrit) beside the main run's n2 = 0.4: time per step and
+    encounter pairs of the last step."""
+    d = W.make_disk(W.DISK_65536)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=0.0,
+                   flags=N.FLAG_NOSYNC)
+    ws = N.Workspace(st.n, cfg)
+    pl = N.PairList(1 << 20)
+    for _ in range(3):
+        N.step(st, cfg, ws, pl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        N.step(st, cfg, ws, pl)
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / steps
+    if N.read_status(ws) != N.OK:
+        raise SystemExit("n2 = 0 status")
+    n = st.n
+    return {"n2": 0.0, "step_ms": round(dt_s * 1e3, 4),
+            "ginter_s": round(2.0 * n * (n - 1) / dt_s / 1e9, 3),
+            "encounter_pairs_last_step": int(pl.count.item()),
+            "encounter_pairs_sha256_last_step": pair_list_sha256(pl)}
+
+
+def pairs_run(N, W, torch, np, steps=1000):
+    """The 65,536-body disk for 1000 base steps with the encounter list of
+    every step (first half kick, positions the step starts from): per step
+    its pair count and the SHA-256 of the canonical list (int32 i then int32
+    j, little endian).  The per-step digests go to stderr; the JSON keeps the
+    counts' range and the SHA-256 over the 1000 digests in step order."""
+    import hashlib
+    d = W.make_disk(W.DISK_65536)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                   flags=N.FLAG_NOSYNC)
+    ws = N.Workspace(st.n, cfg)
+    pl = N.PairList(1 << 20)
+    chain = hashlib.sha256()
+    counts = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        N.step(st, cfg, ws, pl)
+        c = int(pl.count.item())
+        if c > pl.capacity:
+            raise SystemExit(f"pairs run: {c} pairs beyond the list capacity at step {k}")
+        dig = pair_list_sha256(pl)
+        counts.append(c)
+        chain.update(dig.encode())
+        print(f"pairs step {k}: {c} {dig}", file=sys.stderr, flush=(k % 100 == 99))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if N.read_status(ws) != N.OK:
+        raise SystemExit("pairs run status")
+    return {"workload": d["name"], "steps": steps, "count_min": min(counts),
+            "count_max": max(counts), "count_mean": round(float(np.mean(counts)), 1),
+            "count_first": counts[0], "count_last": counts[-1],
+            "sha256_of_step_digests": chain.hexdigest(), "wall_s": round(wall, 2)}
+
+
+def oracle_run_cfg0(N, W, torch, np, steps=100):
+    """The oracle's own 100-step run of the 2,048-body disk on the host (its
+    plain binary64 step, all host cores), beside the GPU's step."""
+    import oracle
+    d = W.make_disk(W.DISK_2048)
+    ref = oracle.state_copy(d)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        oracle.step(ref, d["G"], d["m_star"], d["dt"], d["n1"], d["n2"])
+    host_s = time.perf_counter() - t0
+    n = d["n"]
+    return {"workload": d["name"], "steps": steps, "cores": oracle.num_threads(),
+            "host_s": round(host_s, 3), "host_step_ms": round(host_s / steps * 1e3, 3),
+            "host_ginter_s": round(2.0 * n * (n - 1) * steps / host_s / 1e9, 3)}
+
+
 def pair_list_sha256(pairs) -> str:
     """SHA-256 of the canonical list (int32 i then int32 j, little endian)."""
     import hashlib
@@ -406,9 +544,13 @@ def bench_batched(args, N, W, torch, np):
     ws0 = N.BatchWorkspace(bt, base)
     N.step_batched(st, ws0, base)
     torch.cuda.synchronize()
-    choice = autotune.tune_batched(st, bt, base)
-    tune_ms = choice.pop("ms")
-    form = choice.pop("form")
+    if args.batch_kernels_only:
+        choice = {"block": 0, "ipt": 0, "tile_cols": 0, "grid": 0, "flags": base.flags}
+        tune_ms, form = float("nan"), "default"
+    else:
+        choice = autotune.tune_batched(st, bt, base)
+        tune_ms = choice.pop("ms")
+        form = choice.pop("form")
     cfg = N.Config(**{**base.__dict__, **choice})
     ws = N.BatchWorkspace(bt, cfg)
     pairs = N.PairList(1 << 22)
@@ -433,6 +575,9 @@ def bench_batched(args, N, W, torch, np):
     code = N.read_status(ws)
     if code != N.OK:
         raise SystemExit(f"batched status: {code}")
+    if args.batch_kernels_only:
+        return {"systems": int(d["S"]), "graph_step_ms": round(graph_s * 1e3, 4),
+                "eager_step_ms": round(eager_s * 1e3, 4), "form": "default"}
     # the other kick form on the same ensemble (captured step)
     forms = N.FLAG_DIRECTED | N.FLAG_SYMMETRIC
     other = N.FLAG_SYMMETRIC if form == "one-sided" else N.FLAG_DIRECTED
@@ -484,7 +629,7 @@ def bench_batched(args, N, W, torch, np):
                            "graph_step_ms": round(other_s * 1e3, 4)}}
 
 
-def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):
+def bench_adjoint(N, W, torch, np, d65536_state, cfg65536, kick_ms_fp64=None):
     """Adjoint: the kick VJP kernel on the 65,536-body disk, and the gradient of
     a 200-step trajectory of the 4,096-body disk (checkpoints every 20 steps)."""
     from paper_2201_10058_amd import adjoint as A
@@ -492,16 +637,24 @@ def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):
     ws = N.Workspace(n, cfg65536)
     adj = N.AdjointState(n)
     ab = [torch.randn(n, dtype=torch.float64, device="cuda") for _ in range(3)]
-    N.kick_vjp(st, cfg65536, ws, 1.0, ab, adj)
-    torch.cuda.synchronize()
-    reps = 5
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        N.kick_vjp(st, cfg65536, ws, 1.0, ab, adj)
-    e1.record()
-    e1.synchronize()
-    vjp_ms = e0.elapsed_time(e1) / reps
+    def vjp_time(cfg):
+        wsv = N.Workspace(n, cfg)
+        N.kick_vjp(st, cfg, wsv, 1.0, ab, adj)
+        torch.cuda.synchronize()
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            N.kick_vjp(st, cfg, wsv, 1.0, ab, adj)
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    vjp_ms = vjp_time(cfg65536)     # the default: the symmetric form at this size
+    vjp_one_ms = vjp_time(N.Config(**{**cfg65536.__dict__, "flags": N.FLAG_DIRECTED}))
+    kick_ms = None
+    if kick_ms_fp64 is not None:
+        kick_ms = kick_ms_fp64
     d = W.make_disk(W.DISK_ADJOINT)
     X = torch.tensor(np.stack([d["x"], d["y"], d["z"]]), device="cuda", requires_grad=True)
     V = torch.tensor(np.stack([d["vx"], d["vy"], d["vz"]]), device="cuda", requires_grad=True)
@@ -523,7 +676,10 @@ def bench_adjoint(N, W, torch, np, d65536_state, cfg65536):
     t2 = time.perf_counter()
     peak = torch.cuda.max_memory_allocated() - base
     return {"kick_vjp_ms_n65536": round(vjp_ms, 4),
+            "kick_vjp_form": "symmetric",
             "kick_vjp_ginter_s": round(n * (n - 1) / vjp_ms / 1e6, 3),
+            "kick_vjp_one_sided_ms_n65536": round(vjp_one_ms, 4),
+            "kick_vjp_over_kick_kernel": round(vjp_ms / kick_ms, 3) if kick_ms else None,
             "trajectory_n4096_200_steps_forward_s": round(t1 - t0, 4),
             "trajectory_n4096_200_steps_backward_s": round(t2 - t1, 4),
             "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
@@ -686,10 +842,22 @@ def main():
     if not args.no_small:
         out["small_system"] = bench_small(N, W, torch, np)
         print(f"small system done: {out['small_system']}", file=sys.stderr, flush=True)
+    if not args.no_sizes:
+        out["sizes"] = bench_sizes(N, W, torch, np)
+        out["sizes"]["n65536"] = {"workload": spec.name,
+                                  "fp64_step_ms": out["ms_per_step"],
+                                  "mixed_step_ms": out["mixed"]["ms_per_step"] if r32 else None}
+        print(f"sizes done: {out['sizes']}", file=sys.stderr, flush=True)
+        out["n2_zero"] = bench_n2_zero(N, W, torch, np)
+        print(f"n2 = 0 done: {out['n2_zero']}", file=sys.stderr, flush=True)
+    if not args.no_pairs_run:
+        out["pairs_1000_steps"] = pairs_run(N, W, torch, np)
+        print(f"pairs run done: {out['pairs_1000_steps']}", file=sys.stderr, flush=True)
     st_rc = r64["rc"]
     if not args.no_adjoint:
         st_adj = N.State.from_numpy(d, rc=st_rc.cpu().numpy())
-        out["adjoint"] = bench_adjoint(N, W, torch, np, st_adj, N.Config(G=G))
+        out["adjoint"] = bench_adjoint(N, W, torch, np, st_adj, N.Config(G=G),
+                                       kick_ms_fp64=r64["kick_s"] * 1e3)
         print(f"adjoint done: {out['adjoint']}", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = bench_batched(args, N, W, torch, np)
@@ -699,6 +867,7 @@ def main():
         import oracle
         rc = st_rc.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(d, rc, G, args.cpu_seconds)
+        out["cpu_baseline"]["oracle_run_disk2048_100_steps"] = oracle_run_cfg0(N, W, torch, np)
     print(json.dumps(out), flush=True)
 
 
