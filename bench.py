@@ -331,7 +331,9 @@ def bench_tp(N, W, torch, np, steps=20):
 
 
 LEVEL_CANDIDATES = ((1, 1), (2, 2), (2, 4), (3, 2), (2, 10), (3, 4))
-DIRECT_CANDIDATES = ((3, 4), (2, 10), (4, 4))
+# (1, 1) with the direct solver is the original hybrid step (one symplectic
+# level, Bulirsch-Stoer for every level-0 group): the baseline of Sect. 6.2
+DIRECT_CANDIDATES = ((1, 1), (3, 4), (2, 10), (4, 4))
 
 
 def bench_levels(N, W, torch, np, steps=10):
@@ -354,11 +356,17 @@ def bench_levels(N, W, torch, np, steps=10):
         e0 = float(N.energy(st, cfg, ws)[0].item())
         N.step(st, cfg, ws, pairs)
         torch.cuda.synchronize()
+        # the one-level direct step integrates a group of ~25,000 bodies by
+        # Bulirsch-Stoer (about a second per step): fewer timed steps
+        k_steps = 3 if (direct and L == 1) else steps
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(k_steps):
             N.step(st, cfg, ws, pairs)
+            if direct and L == 1:
+                torch.cuda.synchronize()
+                print(f"levels {L}x{s}+direct: step done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        dt_s = (time.perf_counter() - t0) / steps
+        dt_s = (time.perf_counter() - t0) / k_steps
         code = N.read_status(ws)
         if code != N.OK and not (direct and code == N.E_GROUP):
             raise SystemExit(f"levels {L}x{s}: status {code}")
@@ -366,14 +374,56 @@ def bench_levels(N, W, torch, np, steps=10):
         counts = (N.level_counts(st.n, cfg, ws).tolist() if L > 1 or direct
                   else [int(pairs.count.item())])
         rec = {"step_ms": round(dt_s * 1e3, 4), "list_sizes_last_step": counts,
-               "energy_rel_change": (e1 - e0) / abs(e0)}
+               "energy_rel_change": (e1 - e0) / abs(e0), "steps": k_steps + 1}
         if direct:
             g, gmax = N.group_stats(st.n, cfg, ws)
             rec.update({"groups_last_step": g, "largest_group": gmax,
-                        "status": "ok" if code == N.OK else "group over 256 bodies"})
+                        "status": "ok" if code == N.OK else "group over the solver's limit"})
         out["configs"][f"{L}x{s}" + ("+direct" if direct else "")] = rec
     st = N.State.from_numpy(d)
     out["tuner"] = AT.tune_levels(st, N.Config(**base), LEVEL_CANDIDATES, steps=3)
+    return out
+
+
+RING_SIZES = (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536)
+
+
+def bench_bs_ring(N, W, torch, np, steps=5):
+    """The close-encounter performance test of Sect. 6.1 (Fig. BSTime): n
+    bodies on a ring, each meeting its 8 nearest neighbours, so that all n
+    form one close-encounter group; one-level steps with the direct solver
+    (8 lanes per group up to 8 bodies, one workgroup up to 512, all
+    workgroups beyond) against the same steps without it, per n."""
+    out = {"neighbours": 8, "steps": steps, "sizes": {}}
+    for n in RING_SIZES:
+        d = W.make_bs_ring(n)
+        rec = {}
+        for direct in (1, 0):
+            st = N.State.from_numpy(d)
+            cfg = N.Config(G=d["G"], m_star=1.0, dt=d["dt"], n1=d["n1"], n2=0.0, slevels=1,
+                           substeps=1, direct=direct, flags=N.FLAG_NOSYNC,
+                           level_capacity=max(1 << 12, 16 * n))
+            ws = N.Workspace(st.n, cfg)
+            N.step(st, cfg, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                N.step(st, cfg, ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            if N.read_status(ws) != N.OK:
+                raise SystemExit(f"ring {n}: status")
+            if direct:
+                g, gmax = N.group_stats(st.n, cfg, ws)
+                if (g, gmax) != (1, n):
+                    raise SystemExit(f"ring {n}: groups {(g, gmax)}")
+                rec["direct_step_ms"] = round(ms, 4)
+            else:
+                rec["plain_step_ms"] = round(ms, 4)
+        rec["close_encounter_ms"] = round(rec["direct_step_ms"] - rec["plain_step_ms"], 4)
+        rec["solver"] = "lanes" if n <= 8 else ("workgroup" if n <= 512 else "grid")
+        out["sizes"][str(n)] = rec
+        print(f"ring {n}: {rec}", file=sys.stderr, flush=True)
     return out
 
 
@@ -836,6 +886,9 @@ def main():
     if not args.no_levels:
         out["levels"] = bench_levels(N, W, torch, np)
         print(f"levels done: {out['levels']}", file=sys.stderr, flush=True)
+    if not args.no_levels:
+        out["bs_ring"] = bench_bs_ring(N, W, torch, np)
+        print(f"ring done: {out['bs_ring']}", file=sys.stderr, flush=True)
     if not args.no_levels:
         out["gr"] = bench_gr(N, W, torch, np)
         print(f"gr done: {out['gr']}", file=sys.stderr, flush=True)

@@ -166,7 +166,10 @@ typedef struct {
 } genga_params;
 
 #define GENGA_MAX_LEVELS 8
-#define GENGA_GROUP_MAX 512 /* bodies of the largest group the direct solver takes */
+#define GENGA_GROUP_MAX 65536 /* bodies of the largest group the direct solver takes
+                                 (groups above 512 bodies spread over all compute units;
+                                 a device that cannot hold 256 workgroups of 256 threads
+                                 at once takes correspondingly fewer)                   */
 
 /* Close-encounter list (device memory). */
 typedef struct {
@@ -292,8 +295,11 @@ int genga_drift(genga_bodies *b, const genga_params *p, double dt, void *ws, voi
  * their state before the drift, integrated by Bulirsch-Stoer extrapolation of
  * the modified midpoint rule (step sequence 2, 4, ..., 16; each step accepted
  * when the last two extrapolations agree within p->bs_eps relative to the
- * state's magnitude, else halved).  One workgroup per group; a group of more
- * than GENGA_GROUP_MAX bodies sets GENGA_E_GROUP and keeps its drift.
+ * state's magnitude, else halved).  Groups of up to 8 bodies take 8 lanes of
+ * a wave, groups of up to 512 one workgroup, larger groups all workgroups of
+ * one launch together (grid-wide barriers between the force evaluations,
+ * Sect. 6.1); a group of more than GENGA_GROUP_MAX bodies sets GENGA_E_GROUP
+ * and keeps its drift.
  *
  * Collisions (Sect. 7; b->R non-null, direct = 1): after each accepted
  * Bulirsch-Stoer step the group's first pair (member order) with

@@ -283,13 +283,27 @@ struct LevelLayout {
     size_t gstart = 0;     // int32 [n]  first member slot per root
     size_t groot = 0;      // int32 [n]  roots in ascending order (one per group)
     size_t gtmp = 0;       // int32 [n]  members in arrival order
-    size_t gmem = 0;       // int32 [n]  members, ascending within each group
+    size_t gmem = 0;       // int32 [n]  members, ascending within each group of <= 512
     size_t gcount = 0;     // int32 [2]  groups, members
     size_t gstats = 0;     // int64 [2]  groups integrated, largest group (per step)
     size_t gtsum = 0;      // int64 [2][n / 256] tile sums of the group scan
     size_t coll_count = 0; // uint64     collisions of the step
     size_t coll_i = 0, coll_j = 0;   // int32 [LEVEL_COLL_CAP] survivor, absorbed
     size_t coll_du = 0;    // double [LEVEL_COLL_CAP] lost energy
+    // grid solver (groups of more than 512 bodies; n > 512 only): capacity
+    // gcap = min(n rounded up to 256, GENGA_GROUP_MAX) members
+    int64_t gcap = 0;
+    size_t gbig = 0;       // int32 [2 + n / 513]  listed groups, their roots
+    size_t gsync = 0;      // uint64 [8]  barrier arrivals, abort, reduction slots
+    size_t gpub = 0;       // double [2][6][gcap]  published member states
+    size_t gbox = 0;       // double [2][gcap / 64][8]  tile boxes
+    size_t gtrho = 0;      // double [gcap / 64]  largest deepest-level rc per tile
+    size_t gmm = 0, gmR = 0, gmrc = 0;   // double [gcap]  mass, radius, deepest rc
+    size_t gmirc = 0;      // double [L][gcap]  1 / rc per level
+    size_t gmidx = 0;      // int32 [gcap]  member bodies
+    size_t gbpart = 0;     // double [gcap / 64][4]  workgroup extents
+    size_t gccnt = 0, gcfill = 0;   // int32 [4096]  ordering cells
+    size_t gctmp = 0;      // int32 [2][gcap]  cell scratch, spatial order
     size_t total = 0;
 };
 

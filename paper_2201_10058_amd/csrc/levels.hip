@@ -17,7 +17,9 @@
 // writes).  For the kicks every list gets an adjacency structure whose
 // partners are sorted ascending per body, so each body adds its pair terms in
 // a fixed order and no floating-point atomics are used.
+#include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "device_common.h"
 #include "genga_internal.h"
@@ -30,6 +32,7 @@ namespace {
 constexpr int LT = 256;     // threads per block of the list kernels
 constexpr int LG = 1024;    // blocks of the grid-stride list kernels
 constexpr int LG_BIG = 512; // workgroups of the Bulirsch-Stoer class of 9-512 bodies (2 per CU)
+constexpr int GROUP_BLOCK = 512;   // largest group of the one-workgroup class
 constexpr int DB = 256;     // blocks (and chunks) of the list compaction
 constexpr int ST = 1024;    // threads of the one-block scan of the adjacency tile sums
 
@@ -471,7 +474,8 @@ __global__ __launch_bounds__(LT) void k_group_tiles(const int32_t *flag, const i
     }
 }
 
-__global__ __launch_bounds__(ST) void k_group_top(int64_t *tsum, int64_t ntiles, int32_t *gcount)
+__global__ __launch_bounds__(ST) void k_group_top(int64_t *tsum, int64_t ntiles, int32_t *gcount,
+                                                  int32_t *big, unsigned long long *gsync)
 {
     __shared__ int64_t sm[ST / 64];
     const int t = threadIdx.x;
@@ -495,13 +499,20 @@ __global__ __launch_bounds__(ST) void k_group_top(int64_t *tsum, int64_t ntiles,
     if (t == 0) {
         gcount[0] = (int32_t)tb;   // groups
         gcount[1] = (int32_t)ta;   // members
+        if (big) {
+            // the grid solver's list and barrier state, fresh for its launch:
+            // arrivals, abort flag, three maximum slots, three minimum slots
+            big[0] = 0;
+            for (int k = 0; k < 5; ++k) gsync[k] = 0;
+            for (int k = 5; k < 8; ++k) gsync[k] = (unsigned long long)LLONG_MAX;
+        }
     }
 }
 
 __global__ __launch_bounds__(LT) void k_group_write(const int32_t *flag, const int32_t *lab,
                                                     const int32_t *gsize, int64_t n,
                                                     const int64_t *tsum, int32_t *gstart,
-                                                    int32_t *groot)
+                                                    int32_t *groot, int32_t *big)
 {
     __shared__ int64_t sm[LT / 64];
     const int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x;
@@ -512,6 +523,8 @@ __global__ __launch_bounds__(LT) void k_group_write(const int32_t *flag, const i
     if (root) {
         gstart[k] = (int32_t)(tsum[2 * blockIdx.x] + om);
         groot[tsum[2 * blockIdx.x + 1] + orr] = (int32_t)k;
+        // groups beyond one workgroup, for the grid solver (any order)
+        if (big && gsize[k] > GROUP_BLOCK) big[1 + atomicAdd(big, 1)] = (int32_t)k;
     }
 }
 
@@ -535,6 +548,13 @@ __global__ __launch_bounds__(LT) void k_group_rank(const int32_t *lab, const int
          e += (int64_t)gridDim.x * LT) {
         const int32_t k = gtmp[e], r = lab[k];
         const int32_t s0 = gstart[r], g = gsize[r];
+        // the grid solver orders a large group's members itself (by cell,
+        // then body): its slots keep the arrival order, sparing the
+        // quadratic ranking
+        if (g > GROUP_BLOCK) {
+            gmem[e] = k;
+            continue;
+        }
         int32_t rank = 0;
         for (int32_t q = s0; q < s0 + g; ++q) rank += gtmp[q] < k;
         gmem[s0 + rank] = k;
@@ -601,14 +621,18 @@ __device__ __forceinline__ double rcp2(double x)
 }
 
 // R = prod_l (1 - K(r; rho_l)) with y_l = r / (0.9 rho_l) - 1/9, from
-// irho_l = 1 / rho_l = min(1 / rc_i, 1 / rc_j) (the members' reciprocal
-// critical radii are formed once per group: the radii do not change during
-// the integration).
-__device__ __forceinline__ double bs_remainder(double r, const double *irho, int nlev)
+// irho_l = 1 / rho_l = min(1 / rc_i, 1 / rc_j).  The members' reciprocal
+// critical radii are formed once per group (the radii do not change during
+// the integration) and read from LDS: level l of member i at ia[l * sa], of
+// member j at ib[l * sb].
+__device__ __forceinline__ double bs_remainder(double r, const double *ia, int sa, const double *ib,
+                                               int sb, int nlev)
 {
     double R = 1.0;
     for (int l = 0; l < nlev; ++l) {
-        const double yv = __builtin_fma(r * irho[l], 10.0 / 9.0, -1.0 / 9.0);
+        const double xa = ia[l * sa], xb = ib[l * sb];
+        const double irho = xa < xb ? xa : xb;
+        const double yv = __builtin_fma(r * irho, 10.0 / 9.0, -1.0 / 9.0);
         R *= 1.0 - changeover_of_y(yv);
     }
     return R;
@@ -618,10 +642,11 @@ template <int BT>
 struct BsSmem {
     double px[BT], py[BT], pz[BT], m[BT];
     double pv[3][BT], R[BT];
+    double rcd[BT];                     // deepest-level rc
     int32_t idx[BT];
     double irc[GENGA_MAX_LEVELS][BT];   // 1 / rc of each level
     double red[BT / 64];
-    int ired[BT / 64];
+    long long ired[BT / 64];
 };
 
 // Acceleration of member t at its position (o) from the positions in LDS.
@@ -639,11 +664,12 @@ __device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, i
         if (q == t) continue;
         const double dx = sm.px[q] - o[0], dy = sm.py[q] - o[1], dz = sm.pz[q] - o[2];
         const double r2 = dx * dx + dy * dy + dz * dz;
+        // beyond the larger deepest-level radius R = 0 exactly: the term is
+        // an exact zero and skipping it leaves the sum unchanged
+        const double rq = sm.rcd[t] > sm.rcd[q] ? sm.rcd[t] : sm.rcd[q];
+        if (r2 > rq * rq * (1.0 + 0x1p-18)) continue;
         const double ir = rsq2(r2);
-        double irho[GENGA_MAX_LEVELS];
-        for (int l = 0; l < a.nlev; ++l)
-            irho[l] = sm.irc[l][t] < sm.irc[l][q] ? sm.irc[l][t] : sm.irc[l][q];
-        const double R = bs_remainder(r2 * ir, irho, a.nlev);
+        const double R = bs_remainder(r2 * ir, &sm.irc[0][t], BT, &sm.irc[0][q], BT, a.nlev);
         const double s = a.G * sm.m[q] * R * (ir * ir * ir);
         acc[0] += s * dx;
         acc[1] += s * dy;
@@ -706,7 +732,9 @@ struct BlockPol {
     }
     __device__ double gmax(double v) { return bs_block_max<BT>(sm, v); }
     __device__ bool member() const { return t < g; }
+    __device__ bool owner() const { return true; }
     __device__ int self() const { return t; }
+    __device__ long long overlap(const BsDev &a, const double z[6]);
     __device__ void publish(const double z[6])
     {
         __syncthreads();
@@ -739,16 +767,16 @@ struct BlockPol {
             sm.R[t] = R;
         }
     }
-    __device__ int gmin(int v)
+    __device__ long long gmin(long long v)
     {
         for (int d = 32; d > 0; d >>= 1) {
-            const int o = __shfl_xor(v, d, 64);
+            const long long o = __shfl_xor(v, d, 64);
             v = o < v ? o : v;
         }
         __syncthreads();
         if ((threadIdx.x & 63) == 0) sm.ired[threadIdx.x >> 6] = v;
         __syncthreads();
-        int r = sm.ired[0];
+        long long r = sm.ired[0];
 #pragma unroll
         for (int w = 1; w < BT / 64; ++w) r = sm.ired[w] < r ? sm.ired[w] : r;
         return r;
@@ -761,9 +789,11 @@ struct LanePol {
     double m, R;
     int32_t bidx;
     double zc[6];
-    double irc[GENGA_MAX_LEVELS];   // 1 / rc of each level
+    const double *irc;   // 1 / rc of each level: LDS, level l at irc[l * LT]; lane q at + q - u
     __device__ bool member() const { return u < g; }
+    __device__ bool owner() const { return true; }
     __device__ int self() const { return u; }
+    __device__ long long overlap(const BsDev &a, const double z[6]);
     __device__ void publish(const double z[6])
     {
 #pragma unroll
@@ -784,10 +814,10 @@ struct LanePol {
             R = RR;
         }
     }
-    __device__ int gmin(int v)
+    __device__ long long gmin(long long v)
     {
         for (int d = GS / 2; d > 0; d >>= 1) {
-            const int o = __shfl_xor(v, d, GS);
+            const long long o = __shfl_xor(v, d, GS);
             v = o < v ? o : v;
         }
         return v;
@@ -812,16 +842,11 @@ struct LanePol {
         for (int q = 0; q < g; ++q) {
             const double xq = __shfl(z[0], q, GS), yq = __shfl(z[1], q, GS),
                          zq = __shfl(z[2], q, GS), mq = __shfl(m, q, GS);
-            double irho[GENGA_MAX_LEVELS];
-            for (int l = 0; l < a.nlev; ++l) {
-                const double iq = __shfl(irc[l], q, GS);
-                irho[l] = irc[l] < iq ? irc[l] : iq;
-            }
             if (!mem || q == u) continue;
             const double dx = xq - z[0], dy = yq - z[1], dz = zq - z[2];
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double ir = rsq2(r2);
-            const double R = bs_remainder(r2 * ir, irho, a.nlev);
+            const double R = bs_remainder(r2 * ir, irc, LT, irc + (q - u), LT, a.nlev);
             const double s = a.G * mq * R * (ir * ir * ir);
             acc[0] += s * dx;
             acc[1] += s * dy;
@@ -925,12 +950,15 @@ __device__ int bs_step(const BsDev &a, Pol &P, const double y[6], double h, doub
 }
 
 // The first overlapping pair of the group at state z (a < b, encoded as
-// a * 1024 + b), or INT_MAX.  Uniform over the group.
+// a * KEY_BASE + b), or NO_PAIR.  Uniform over the group.
+constexpr long long KEY_BASE = 65536;
+constexpr long long NO_PAIR = LLONG_MAX;
+
 template <class Pol>
-__device__ int bs_overlap(const BsDev &a, Pol &P, const double z[6])
+__device__ long long bs_overlap(const BsDev &a, Pol &P, const double z[6])
 {
     P.publish(z);
-    int key = INT_MAX;
+    long long key = NO_PAIR;
     const int u = P.self();
     const double ru = P.rad(u);
     for (int q = 0; q < P.g; ++q) {
@@ -940,9 +968,22 @@ __device__ int bs_overlap(const BsDev &a, Pol &P, const double z[6])
         if (!P.member() || q <= u) continue;
         const double rs = ru + rq;
         const double dx = o[0] - z[0], dy = o[1] - z[1], dz = o[2] - z[2];
-        if (rs > 0.0 && dx * dx + dy * dy + dz * dz < rs * rs && key == INT_MAX) key = u * 1024 + q;
+        if (rs > 0.0 && dx * dx + dy * dy + dz * dz < rs * rs && key == NO_PAIR)
+            key = (long long)u * KEY_BASE + q;
     }
     return P.gmin(key);
+}
+
+template <int BT>
+__device__ long long BlockPol<BT>::overlap(const BsDev &a, const double z[6])
+{
+    return bs_overlap(a, *this, z);
+}
+
+template <int GS>
+__device__ long long LanePol<GS>::overlap(const BsDev &a, const double z[6])
+{
+    return bs_overlap(a, *this, z);
 }
 
 // Distance of members ma, mb at state z (uniform).
@@ -986,11 +1027,13 @@ __device__ void bs_merge(const BsDev &a, Pol &P, double z[6], int ma, int mb)
             dv2 += (ya[c + 3] - yb[c + 3]) * (ya[c + 3] - yb[c + 3]);
         }
         const double du = 0.5 * m1 * m2 / M * dv2 - a.G * m1 * m2 / __builtin_sqrt(dx2);
-        const unsigned long long slot = atomicAdd(a.coll_count, 1ull);
-        if ((int64_t)slot < a.coll_cap) {
-            a.coll_i[slot] = first ? i1 : i2;
-            a.coll_j[slot] = first ? i2 : i1;
-            a.coll_du[slot] = du;
+        if (P.owner()) {
+            const unsigned long long slot = atomicAdd(a.coll_count, 1ull);
+            if ((int64_t)slot < a.coll_cap) {
+                a.coll_i[slot] = first ? i1 : i2;
+                a.coll_j[slot] = first ? i2 : i1;
+                a.coll_du[slot] = du;
+            }
         }
     } else if (u == mg) {
         z[0] = 1e6 + (double)(first ? i2 : i1);
@@ -1015,9 +1058,9 @@ __device__ bool bs_run(const BsDev &a, Pol &P, double y[6])
         double yn[6];
         const int kdone = bs_step(a, P, y, h, yn);
         if (kdone >= 0) {
-            const int key = a.radius ? bs_overlap(a, P, yn) : INT_MAX;
-            if (key != INT_MAX) {
-                const int ma = key / 1024, mb = key % 1024;
+            const long long key = a.radius ? P.overlap(a, yn) : NO_PAIR;
+            if (key != NO_PAIR) {
+                const int ma = (int)(key / KEY_BASE), mb = (int)(key % KEY_BASE);
                 const double rs = P.rad(ma) + P.rad(mb);
                 double lo = 0.0, hi = h;
                 double yh[6];
@@ -1070,6 +1113,7 @@ constexpr int BS_GS = 8;
 template <int GS>
 __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
 {
+    __shared__ double irc_sm[GENGA_MAX_LEVELS][LT];
     const int u = threadIdx.x % GS;
     const int64_t ng = a.gcount[0];
     const int64_t stride = (int64_t)gridDim.x * (LT / GS);
@@ -1087,7 +1131,7 @@ __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
         P.m = 0.0;
         P.R = 0.0;
         for (int c = 0; c < 6; ++c) P.zc[c] = 0.0;
-        for (int l = 0; l < GENGA_MAX_LEVELS; ++l) P.irc[l] = 0.0;
+        P.irc = &irc_sm[0][threadIdx.x];
         const int32_t b = u < g ? a.gmem[a.gstart[root] + u] : 0;
         P.bidx = b;
         double y[6] = {0, 0, 0, 0, 0, 0};
@@ -1096,7 +1140,7 @@ __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
             for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
             P.m = a.m[b];
             P.R = a.radius ? a.radius[b] : 0.0;
-            for (int l = 0; l < a.nlev; ++l) P.irc[l] = rcp2(a.rc[l][b]);
+            for (int l = 0; l < a.nlev; ++l) irc_sm[l][threadIdx.x] = rcp2(a.rc[l][b]);
         }
         const bool failed = bs_run(a, P, y);
         if (failed && u == 0) atomicOr(a.status, ST_NOCONV);
@@ -1110,8 +1154,8 @@ __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
     }
 }
 
-// Groups of lo < size <= BT, one workgroup each (the last class also reports
-// the oversized ones).
+// Groups of lo < size <= BT, one workgroup each (larger ones are the grid
+// solver's).
 template <int BT>
 __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
 {
@@ -1121,11 +1165,7 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
     for (int gi = blockIdx.x; gi < ng; gi += gridDim.x) {
         const int32_t root = a.groot[gi];
         const int g = a.gsize[root];
-        if (g <= lo) continue;                       // another class's group
-        if (g > BT) {
-            if (BT == GENGA_GROUP_MAX && t == 0) atomicOr(a.status, ST_GROUP);
-            continue;
-        }
+        if (g <= lo || g > BT) continue;             // another class's group
         if (t == 0) {
             atomicAdd(a.gstats, 1ull);
             atomicMax(a.gstats + 1, (unsigned long long)g);
@@ -1138,7 +1178,9 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
             sm.m[t] = a.m[b];
             sm.R[t] = a.radius ? a.radius[b] : 0.0;
             sm.idx[t] = b;
-            for (int l = 0; l < a.nlev; ++l) sm.irc[l][t] = rcp2(a.rc[l][b]);
+            for (int l = 0; l < a.nlev; ++l)
+                sm.irc[l][t] = rcp2(a.rc[l][b]);
+            sm.rcd[t] = a.rc[a.nlev - 1][b];
         }
         BlockPol<BT> P{sm, t, g};
         const bool failed = bs_run(a, P, y);
@@ -1151,6 +1193,602 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
             }
         }
         __syncthreads();   // LDS reuse by the next group
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Groups of more than GROUP_BLOCK bodies (Sect. 6.1: the method that spreads
+// one group over many thread blocks).  The paper drives each sub-step of
+// that method from the host; here one persistent launch integrates the
+// listed groups one after another, its workgroups meeting at a grid-wide
+// barrier before every evaluation that reads other members' positions and
+// at every group-wide maximum or minimum.  One thread per member (so a
+// group may hold up to GENGA_GROUP_MAX bodies with the launch's workgroups
+// all resident); the members are first ordered by a 64 x 64 cell grid over
+// the group's x-y extent (cells in Morton order, members of a cell by their
+// rank in the group), so that each wave's 64 members form a compact tile.
+// A derivative then visits, per tile, only the tiles whose bounding boxes
+// come within the larger deepest-level critical radius of the two tiles:
+// every pair of the tiles left out has R = 0 exactly (the deepest level's
+// factor 1 - K is zero at r >= rho), so its terms are exact zeros and the
+// sums equal the all-pairs ones; a member's sum runs over its partners in
+// ascending tile and slot order.
+// ---------------------------------------------------------------------------
+constexpr int GT = 256;             // threads per workgroup of the grid solver
+constexpr int GCELL = 64;           // ordering cells per axis
+// a barrier that has waited this long (wall clock, 100 MHz ticks: 2 s) gives up
+constexpr uint64_t GWAIT_TICKS = 200000000ull;
+
+struct GridDev {
+    int32_t cap;                        // members per group the launch can hold
+    const int32_t *big;                 // [0] listed groups, [1 ..] their roots
+    double *pub;                        // [2][6][cap] published states (by parity)
+    double *box;                        // [2][cap / 64][8] tile box lo, hi, max radius
+    double *trho;                       // [cap / 64] largest deepest-level rc per tile
+    double *mm, *mR;                    // [cap] member mass, radius
+    double *mirc;                       // [GENGA_MAX_LEVELS][cap] 1 / rc per level
+    double *mrc;                        // [cap] deepest-level rc
+    int32_t *midx;                      // [cap] member body
+    double *bpart;                      // [cap / 64][4] workgroup x-y extents
+    int32_t *ccnt, *cfill;              // [GCELL^2] members per cell, fill counters
+    int32_t *ctmp;                      // [cap] members by cell in arrival order
+    unsigned long long *sync;           // [0] arrivals, [1] abort, [2..4] max slots
+    long long *rmin;                    // [3] min slots
+};
+
+struct GridSmem {
+    double sx[4][64], sy[4][64], sz[4][64], sm[4][64], src[4][64];
+    double sirc[4][GENGA_MAX_LEVELS][64];
+    double oirc[GENGA_MAX_LEVELS][GT];   // own 1 / rc per level
+    double part[4][3][64];               // partial sums of the split waves
+    double red[4][4];
+    int32_t cstart[GCELL * GCELL];
+    double ext[4];
+    int64_t scan[GT / 64];
+    int dead;
+};
+
+// The grid solver's LDS (only k_bs_grid reaches it).  Declared at namespace
+// scope so that the out-of-line evaluation addresses it as LDS.
+static __shared__ GridSmem g_gsm;
+
+__device__ __forceinline__ unsigned morton6(unsigned cx, unsigned cy)
+{
+    unsigned k = 0;
+    for (int b = 0; b < 6; ++b) k |= ((cx >> b) & 1u) << (2 * b) | ((cy >> b) & 1u) << (2 * b + 1);
+    return k;
+}
+
+__device__ __forceinline__ double wave_min_all(double v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const double o = __shfl_xor(v, d, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_all(double v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const double o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct GridPol {
+    const GridDev &G;
+    int t, g, nlev, nblk;
+    int split, sub;             // waves per tile, this wave's share (0: the owner)
+    unsigned long long nbar;    // barriers passed in this launch
+    int par;                    // parity of the last publication
+    int nred;                   // reductions done in this launch
+    bool dead;
+    double m, R;                // own mass and radius
+    double rcd;                 // own deepest-level rc
+
+    __device__ bool member() const { return t < g; }
+    // the first wave of a tile writes; the others hold copies of its members
+    __device__ bool owner() const { return t < g && sub == 0; }
+    __device__ int self() const { return t; }
+
+    // Grid-wide barrier of the nblk workgroups: every arrival is counted
+    // once after a release fence; the wait polls with relaxed loads (an
+    // acquire per poll would invalidate the L2 of the poller's XCD each
+    // time) and ends with one acquire fence.  The wait is bounded in wall
+    // clock time: a barrier that times out (or finds that another workgroup
+    // gave up) marks the launch dead, after which no barrier waits and the
+    // flow fails to converge.
+    __device__ bool sync()
+    {
+        __syncthreads();
+        ++nbar;
+        if (threadIdx.x == 0) {
+            int d = dead ? 1 : 0;
+            if (!d) {
+                unsigned long long *cnt = G.sync;
+                const unsigned long long target = nbar * (unsigned long long)nblk;
+                __threadfence();
+                __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if (__hip_atomic_load(cnt + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        d = 1;
+                        break;
+                    }
+                    if (wall_clock64() - t0 > GWAIT_TICKS) {
+                        __hip_atomic_store(cnt + 1, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        d = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                __threadfence();
+            }
+            g_gsm.dead = d;
+        }
+        __syncthreads();
+        dead = g_gsm.dead != 0;
+        return !dead;
+    }
+
+    // the own tile's box (lo, hi) of positions z (members only)
+    __device__ void tile_box(const double z[3], double lo[3], double hi[3]) const
+    {
+        const bool mem = member();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = wave_min_all(mem ? z[c] : INFINITY);
+            hi[c] = wave_max_all(mem ? z[c] : -INFINITY);
+        }
+    }
+
+    __device__ void publish_n(const double z[6], int nc, double lo[3], double hi[3])
+    {
+        par ^= 1;
+        double *P = G.pub + (size_t)par * 6 * G.cap;
+        if (owner())
+            for (int c = 0; c < nc; ++c) P[(size_t)c * G.cap + t] = z[c];
+        tile_box(z, lo, hi);
+        const double rmax = wave_max_all(member() ? R : 0.0);
+        if ((threadIdx.x & 63) == 0 && owner()) {
+            double *B = G.box + ((size_t)par * (G.cap / 64) + (t >> 6)) * 8;
+            B[0] = lo[0]; B[1] = lo[1]; B[2] = lo[2];
+            B[3] = hi[0]; B[4] = hi[1]; B[5] = hi[2];
+            B[6] = rmax;
+        }
+        sync();
+    }
+
+    __device__ void publish(const double z[6])
+    {
+        double lo[3], hi[3];
+        publish_n(z, 6, lo, hi);
+    }
+
+    __device__ void get(int q, double o[6]) const
+    {
+        const double *P = G.pub + (size_t)par * 6 * G.cap;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = P[(size_t)c * G.cap + q];
+    }
+    __device__ double mass(int q) const { return G.mm[q]; }
+    __device__ double rad(int q) const { return G.mR[q]; }
+    __device__ int idx(int q) const { return G.midx[q]; }
+    __device__ void set_own(double mm, double RR)
+    {
+        if (member()) {
+            m = mm;
+            R = RR;
+            if (owner()) {
+                G.mm[t] = mm;
+                G.mR[t] = RR;
+            }
+        }
+    }
+
+    // squared gap between the own tile's box and tile J's (published) box
+    __device__ double gap2(const double lo[3], const double hi[3], const double *B) const
+    {
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double a1 = B[c] - hi[c], a2 = lo[c] - B[3 + c];
+            const double gc = a1 > a2 ? a1 : a2;
+            d2 += gc > 0.0 ? gc * gc : 0.0;
+        }
+        return d2;
+    }
+
+    // (one copy of the evaluation: bs_step reaches it from nine places; the
+    // loop works on locals and LDS only).  The split waves of a tile take
+    // every split-th tile of its list each; their partial sums are added in
+    // share order.
+    __device__ __noinline__ void deriv(const BsDev &a, const double z[6], double f[6])
+    {
+        f[0] = z[3];
+        f[1] = z[4];
+        f[2] = z[5];
+        double lo[3], hi[3];
+        publish_n(z, 3, lo, hi);
+        const double x0 = z[0], y0 = z[1], z0 = z[2];
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int me = t, ng = g, nl = nlev, S_ = split, mine = sub;
+        const int t0 = me - lane;
+        GridSmem &S = g_gsm;
+        if (!dead && t0 < ng) {
+            const double Gc = a.G, rcme = rcd;
+            const size_t cap = (size_t)G.cap;
+            const int nt = (ng + 63) >> 6;
+            const double *trho = G.trho, *mm = G.mm, *mrc = G.mrc, *mirc = G.mirc;
+            const double rhoI = trho[t0 >> 6];
+            const double *P = G.pub + (size_t)par * 6 * cap;
+            const double *Bx = G.box + (size_t)par * (cap / 64) * 8;
+            int seen = 0;   // tiles of the list met so far (wave-uniform)
+            for (int jb = 0; jb < nt; jb += 64) {
+                const int Jl = jb + lane;
+                bool near = false;
+                if (Jl < nt) {
+                    const double rr = rhoI > trho[Jl] ? rhoI : trho[Jl];
+                    // (a NaN box keeps the tile: the flow then fails as a whole)
+                    near = !(gap2(lo, hi, Bx + (size_t)Jl * 8) > rr * rr * (1.0 + 0x1p-18));
+                }
+                unsigned long long mask = __ballot(near);
+                while (mask) {
+                    const int J = jb + __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    if (seen++ % S_ != mine) continue;
+                    const int jq = J * 64 + lane;
+                    if (jq < ng) {
+                        S.sx[w][lane] = P[jq];
+                        S.sy[w][lane] = P[cap + jq];
+                        S.sz[w][lane] = P[2 * cap + jq];
+                        S.sm[w][lane] = mm[jq];
+                        S.src[w][lane] = mrc[jq];
+                        for (int l = 0; l < nl; ++l) S.sirc[w][l][lane] = mirc[(size_t)l * cap + jq];
+                    }
+                    wave_sync_lds();
+                    const int qn = ng - J * 64 < 64 ? ng - J * 64 : 64;
+                    const int qself = me - J * 64;
+                    for (int q = 0; q < qn; ++q) {
+                        if (q == qself) continue;
+                        const double dx = S.sx[w][q] - x0, dy = S.sy[w][q] - y0,
+                                     dz = S.sz[w][q] - z0;
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        const double rq = rcme > S.src[w][q] ? rcme : S.src[w][q];
+                        // beyond the larger deepest-level radius R = 0 exactly
+                        if (r2 > rq * rq * (1.0 + 0x1p-18)) continue;
+                        const double ir = rsq2(r2);
+                        const double Rw = bs_remainder(r2 * ir, &S.oirc[0][threadIdx.x], GT,
+                                                       &S.sirc[w][0][q], 64, nl);
+                        const double s = Gc * S.sm[w][q] * Rw * (ir * ir * ir);
+                        ax += s * dx;
+                        ay += s * dy;
+                        az += s * dz;
+                    }
+                    wave_sync_lds();
+                }
+            }
+        }
+        // the star's pull, then the shares' partial sums in share order
+        double kx = 0.0, ky = 0.0, kz = 0.0;
+        if (member()) {
+            const double r2s = x0 * x0 + y0 * y0 + z0 * z0;
+            const double irs = rsq2(r2s);
+            const double ks = -a.mu * (irs * irs * irs);
+            kx = ks * x0;
+            ky = ks * y0;
+            kz = ks * z0;
+        }
+        if (S_ > 1) {
+            S.part[w][0][lane] = ax;
+            S.part[w][1][lane] = ay;
+            S.part[w][2][lane] = az;
+            __syncthreads();
+            const int w0 = w - mine;
+            for (int k = 0; k < S_; ++k) {
+                kx += S.part[w0 + k][0][lane];
+                ky += S.part[w0 + k][1][lane];
+                kz += S.part[w0 + k][2][lane];
+            }
+            __syncthreads();
+        } else {
+            kx += ax;
+            ky += ay;
+            kz += az;
+        }
+        f[3] = kx;
+        f[4] = ky;
+        f[5] = kz;
+    }
+
+    // group-wide reductions through rotating slots: slot nred % 3 collects
+    // this reduction; after its barrier workgroup 0 resets slot
+    // (nred + 2) % 3, whose last readers have all passed this barrier and
+    // whose next writers come after the next one (the split waves hold the
+    // same values: a maximum or minimum counts them once)
+    __device__ void reset_slot()
+    {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const int s2 = (nred + 2) % 3;
+            __hip_atomic_store(G.sync + 2 + s2, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(G.rmin + s2, NO_PAIR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ++nred;
+    }
+
+    __device__ double gmax(double v)
+    {
+        // non-negative (or +inf) values: their bit patterns order as integers
+        v = wave_max_all(v);
+        const int s = nred % 3;
+        if ((threadIdx.x & 63) == 0 && !dead)
+            __hip_atomic_fetch_max(G.sync + 2 + s, (unsigned long long)__double_as_longlong(v),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sync();
+        double r = INFINITY;
+        if (!dead)
+            r = __longlong_as_double((long long)__hip_atomic_load(G.sync + 2 + s, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT));
+        reset_slot();
+        return r;
+    }
+
+    __device__ long long gmin(long long v)
+    {
+        for (int d = 32; d > 0; d >>= 1) {
+            const long long o = __shfl_xor(v, d, 64);
+            v = o < v ? o : v;
+        }
+        const int s = nred % 3;
+        if ((threadIdx.x & 63) == 0 && !dead && v != NO_PAIR)
+            __hip_atomic_fetch_min(G.rmin + s, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sync();
+        long long r = NO_PAIR;
+        if (!dead) r = __hip_atomic_load(G.rmin + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        reset_slot();
+        return r;
+    }
+
+    __device__ long long overlap(const BsDev &a, const double z[6]);
+};
+
+// The grid solver's overlap search: tiles whose boxes stay apart by more
+// than the sum of their largest radii hold no overlapping pair.
+__device__ long long GridPol::overlap(const BsDev &a, const double z[6])
+{
+    double lo[3], hi[3];
+    publish_n(z, 6, lo, hi);
+    long long key = NO_PAIR;
+    const int lane = threadIdx.x & 63;
+    const int t0 = t - lane;
+    if (!dead && t0 < g) {
+        const int nt = (g + 63) >> 6;
+        const double *Pp = G.pub + (size_t)par * 6 * G.cap;
+        const double *Bx = G.box + (size_t)par * (G.cap / 64) * 8;
+        const double rI = wave_max_all(member() ? R : 0.0);
+        for (int jb = 0; jb < nt; jb += 64) {
+            const int Jl = jb + lane;
+            bool near = false;
+            if (Jl < nt) {
+                const double rs = rI + Bx[(size_t)Jl * 8 + 6];
+                near = rs > 0.0 && !(gap2(lo, hi, Bx + (size_t)Jl * 8) > rs * rs * (1.0 + 0x1p-18));
+            }
+            unsigned long long mask = __ballot(near);
+            while (mask) {
+                const int J = jb + __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int qn = g - J * 64 < 64 ? g - J * 64 : 64;
+                for (int qq = 0; qq < qn; ++qq) {
+                    const int q = J * 64 + qq;
+                    if (!member() || q <= t || key != NO_PAIR) continue;
+                    const double rs = R + G.mR[q];
+                    const double dx = Pp[q] - z[0], dy = Pp[(size_t)G.cap + q] - z[1],
+                                 dz = Pp[2 * (size_t)G.cap + q] - z[2];
+                    if (rs > 0.0 && dx * dx + dy * dy + dz * dz < rs * rs)
+                        key = (long long)t * KEY_BASE + q;
+                }
+            }
+        }
+    }
+    return gmin(key);
+}
+
+// Spatial order of the group's members (see above): by cell, then by body
+// index, whatever the order of the group's slots; perm[k] = body of the k-th
+// member in that order.  Four grid barriers; only the owners contribute.
+__device__ void grid_order(const BsDev &a, GridPol &P, int32_t root, int32_t *perm)
+{
+    const GridDev &G = P.G;
+    GridSmem &S = g_gsm;
+    const int g = P.g, t = P.t;
+    const bool own = P.owner();
+    const int nthr = P.nblk * GT;
+    const int tid = blockIdx.x * GT + threadIdx.x;
+    const int32_t b = own ? a.gmem[a.gstart[root] + t] : 0;
+    double x = 0.0, y = 0.0;
+    if (own) {
+        x = a.shadow[b];
+        y = a.shadow[(size_t)a.n + b];
+    }
+    for (int c = tid; c < GCELL * GCELL; c += nthr) {
+        G.ccnt[c] = 0;
+        G.cfill[c] = 0;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    {
+        const double v[4] = {wave_min_all(own ? x : INFINITY), wave_max_all(own ? x : -INFINITY),
+                             wave_min_all(own ? y : INFINITY), wave_max_all(own ? y : -INFINITY)};
+        if (lane == 0)
+            for (int c = 0; c < 4; ++c) S.red[w][c] = v[c];
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            const int c = threadIdx.x;
+            double r = S.red[0][c];
+            for (int k = 1; k < 4; ++k) r = (c & 1) ? (S.red[k][c] > r ? S.red[k][c] : r)
+                                                    : (S.red[k][c] < r ? S.red[k][c] : r);
+            G.bpart[(size_t)blockIdx.x * 4 + c] = r;
+        }
+    }
+    P.sync();
+    // the group's extent (the same arithmetic in every workgroup)
+    double *ext = S.ext;
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        double r = G.bpart[c];
+        for (int k = 1; k < P.nblk; ++k) {
+            const double o = G.bpart[(size_t)k * 4 + c];
+            r = (c & 1) ? (o > r ? o : r) : (o < r ? o : r);
+        }
+        ext[c] = r;
+    }
+    __syncthreads();
+    unsigned cell = 0;
+    if (own) {
+        const double wx = ext[1] - ext[0], wy = ext[3] - ext[2];
+        const double fx = wx > 0.0 ? (x - ext[0]) * (GCELL / wx) : 0.0;
+        const double fy = wy > 0.0 ? (y - ext[2]) * (GCELL / wy) : 0.0;
+        int cx = fx >= 0.0 ? (int)fx : 0, cy = fy >= 0.0 ? (int)fy : 0;
+        cx = cx < GCELL - 1 ? cx : GCELL - 1;
+        cy = cy < GCELL - 1 ? cy : GCELL - 1;
+        // (NaN positions land in cell 0: the flow fails later anyway)
+        cell = morton6((unsigned)cx, (unsigned)cy);
+        atomicAdd(G.ccnt + cell, 1);
+    }
+    P.sync();
+    // exclusive scan of the cell counts, in every workgroup
+    {
+        constexpr int PER = GCELL * GCELL / GT;
+        int loc[PER], sum = 0;
+        for (int k = 0; k < PER; ++k) {
+            loc[k] = __hip_atomic_load(G.ccnt + threadIdx.x * PER + k, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            sum += loc[k];
+        }
+        int64_t tot;
+        int64_t off = block_excl_scan<GT>((int64_t)sum, &tot, S.scan);
+        for (int k = 0; k < PER; ++k) {
+            S.cstart[threadIdx.x * PER + k] = (int32_t)off;
+            off += loc[k];
+        }
+    }
+    __syncthreads();
+    if (own) G.ctmp[S.cstart[cell] + atomicAdd(G.cfill + cell, 1)] = b;
+    P.sync();
+    // within a cell by body index (the slots' arrival order is not fixed)
+    if (own) {
+        const int c0 = S.cstart[cell];
+        const int cn = __hip_atomic_load(G.ccnt + cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int rank = 0;
+        for (int k = c0; k < c0 + cn; ++k) rank += G.ctmp[k] < b;
+        perm[c0 + rank] = b;
+    }
+    P.sync();
+}
+
+// Waves per tile for a group of g members when nb workgroups (of 4 waves)
+// can take part: the most of 4, 2, 1 that fit within half of them (room to
+// spare for the barriers), else within all of them (0: the group does not
+// fit).
+__device__ inline int grid_split(int g, int nb)
+{
+    const int nt = (g + 63) / 64;
+    for (int lim : {nb / 2, nb})
+        for (int s = 4; s >= 1; s >>= 1)
+            if ((nt * s + 3) / 4 <= lim) return s;
+    return 0;
+}
+
+// All listed groups of more than GROUP_BLOCK bodies, one after another.
+// Launched with as many workgroups as are resident together (sized for two
+// per compute unit); a group takes the most waves per tile that fit, and the
+// workgroups beyond the largest group's need return at once.
+__global__ __launch_bounds__(GT, 2) void k_bs_grid(BsDev a, GridDev G)
+{
+    GridSmem &S = g_gsm;
+    const int nbig = G.big[0];
+    int need = 0;
+    for (int k = 0; k < nbig; ++k) {
+        const int g = a.gsize[G.big[1 + k]];
+        const int s = g <= G.cap ? grid_split(g, gridDim.x) : 0;
+        if (s) {
+            const int nb = ((g + 63) / 64 * s + 3) / 4;
+            need = nb > need ? nb : need;
+        } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+            atomicOr(a.status, ST_GROUP);
+        }
+    }
+    if ((int)blockIdx.x >= need) return;
+    GridPol P{G};
+    P.nlev = a.nlev;
+    P.nblk = need;
+    P.nbar = 0;
+    P.par = 0;
+    P.nred = 0;
+    P.dead = false;
+    int32_t *perm = G.ctmp + G.cap;   // second half of the cell scratch
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int k = 0; k < nbig; ++k) {
+        const int32_t root = G.big[1 + k];
+        const int g = a.gsize[root];
+        const int split = g <= G.cap ? grid_split(g, gridDim.x) : 0;
+        if (!split) continue;
+        P.g = g;
+        P.split = split;
+        P.sub = gw % split;
+        P.t = gw / split * 64 + lane;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            atomicAdd(a.gstats, 1ull);
+            atomicMax(a.gstats + 1, (unsigned long long)g);
+        }
+        grid_order(a, P, root, perm);
+        const int t = P.t;
+        const bool mem = t < g;
+        const int32_t b = mem ? perm[t] : 0;
+        double y[6] = {0, 0, 0, 0, 0, 0};
+        P.m = 0.0;
+        P.R = 0.0;
+        P.rcd = 0.0;
+        if (mem) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
+            P.m = a.m[b];
+            P.R = a.radius ? a.radius[b] : 0.0;
+            P.rcd = a.rc[a.nlev - 1][b];
+            for (int l = 0; l < a.nlev; ++l) {
+                const double ir = rcp2(a.rc[l][b]);
+                S.oirc[l][threadIdx.x] = ir;
+                if (P.owner()) G.mirc[(size_t)l * G.cap + t] = ir;
+            }
+            if (P.owner()) {
+                G.mm[t] = P.m;
+                G.mR[t] = P.R;
+                G.mrc[t] = P.rcd;
+                G.midx[t] = b;
+            }
+        }
+        const double tr = wave_max_all(mem ? P.rcd : 0.0);
+        if (lane == 0 && P.owner()) G.trho[t >> 6] = tr;
+        // (the first evaluation's barrier publishes these)
+        const bool failed = bs_run(a, P, y);
+        if (failed && t == 0) atomicOr(a.status, ST_NOCONV);
+        if (P.owner()) {
+            bs_store(a, b, y);
+            if (a.radius) {
+                a.m[b] = P.m;
+                a.radius[b] = P.R;
+            }
+        }
+        P.sync();   // scratch reuse by the next group
     }
 }
 
@@ -1239,9 +1877,11 @@ static hipError_t group_and_save(const LevelRun &R, int l)
     hipLaunchKernelGGL(k_group_union, dim3(LG), dim3(LT), 0, R.s, pi, pj, cnt, V.cap, gtmp, flag);
     hipLaunchKernelGGL(k_group_root, dim3(LG), dim3(LT), 0, R.s, gtmp, flag, lab, gsize, n);
     hipLaunchKernelGGL(k_group_tiles, dim3(nt), dim3(LT), 0, R.s, flag, lab, gsize, n, tsum);
-    hipLaunchKernelGGL(k_group_top, dim3(1), dim3(ST), 0, R.s, tsum, (int64_t)nt, gcount);
+    int32_t *big = V.gbig ? R.at<int32_t>(V.gbig) : nullptr;
+    unsigned long long *gsync = V.gbig ? R.at<unsigned long long>(V.gsync) : nullptr;
+    hipLaunchKernelGGL(k_group_top, dim3(1), dim3(ST), 0, R.s, tsum, (int64_t)nt, gcount, big, gsync);
     hipLaunchKernelGGL(k_group_write, dim3(nt), dim3(LT), 0, R.s, flag, lab, gsize, n, tsum, gstart,
-                       groot);
+                       groot, big);
     hipLaunchKernelGGL(k_group_fill, dim3(LG), dim3(LT), 0, R.s, flag, lab, gstart, gfill, gtmp, n);
     hipLaunchKernelGGL(k_group_rank, dim3(LG), dim3(LT), 0, R.s, lab, gstart, gsize, gtmp, gcount,
                        gmem);
@@ -1251,6 +1891,32 @@ static hipError_t group_and_save(const LevelRun &R, int l)
     hipLaunchKernelGGL(k_state_list, dim3(LG), dim3(LT), 0, R.s, mem, R.at<double>(V.shadow[l]), n,
                        1);
     return hipGetLastError();
+}
+
+// Workgroups of k_bs_grid that the current device holds at once (queried
+// once per device).
+static hipError_t grid_resident_blocks(int *out)
+{
+    static std::mutex mu;
+    static int cached[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (!cached[dev]) {
+        int per_cu = 0, cus = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bs_grid, GT, 0)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+            hipSuccess)
+            return e;
+        if (per_cu < 1 || cus < 1) return hipErrorLaunchFailure;
+        cached[dev] = per_cu * cus;
+    }
+    *out = cached[dev];
+    return hipSuccess;
 }
 
 // The groups of list l over dt_l from the saved state, weights of levels 0..l.
@@ -1289,7 +1955,32 @@ static hipError_t direct_solve(const LevelRun &R, int l, double dt_l)
     // groups of more than 8 bodies are rare at the deepest level: one
     // launch of 512-thread workgroups takes all of them (an empty launch per
     // class cost ~4.5 us per deepest sub-step)
-    hipLaunchKernelGGL(k_bs<GENGA_GROUP_MAX>, dim3(LG_BIG), dim3(GENGA_GROUP_MAX), 0, R.s, a, BS_GS);
+    hipLaunchKernelGGL(k_bs<GROUP_BLOCK>, dim3(LG_BIG), dim3(GROUP_BLOCK), 0, R.s, a, BS_GS);
+    if (!V.gbig) return hipGetLastError();
+    // groups beyond one workgroup: as many workgroups as fit the capacity
+    // and are resident on the device together (the barriers need them all)
+    int resident = 0;
+    hipError_t e = grid_resident_blocks(&resident);
+    if (e != hipSuccess) return e;
+    const int nb = (int)std::min<int64_t>(V.gcap / 64, resident);
+    GridDev G;
+    G.cap = (int32_t)std::min<int64_t>(V.gcap, (int64_t)nb * GT);
+    G.big = R.at<int32_t>(V.gbig);
+    G.pub = R.at<double>(V.gpub);
+    G.box = R.at<double>(V.gbox);
+    G.trho = R.at<double>(V.gtrho);
+    G.mm = R.at<double>(V.gmm);
+    G.mR = R.at<double>(V.gmR);
+    G.mrc = R.at<double>(V.gmrc);
+    G.mirc = R.at<double>(V.gmirc);
+    G.midx = R.at<int32_t>(V.gmidx);
+    G.bpart = R.at<double>(V.gbpart);
+    G.ccnt = R.at<int32_t>(V.gccnt);
+    G.cfill = R.at<int32_t>(V.gcfill);
+    G.ctmp = R.at<int32_t>(V.gctmp);
+    G.sync = R.at<unsigned long long>(V.gsync);
+    G.rmin = (long long *)(G.sync + 5);
+    hipLaunchKernelGGL(k_bs_grid, dim3(nb), dim3(GT), 0, R.s, a, G);
     return hipGetLastError();
 }
 
@@ -1399,6 +2090,25 @@ LevelLayout make_level_layout(int64_t n, const genga_params *p, size_t base)
         V.coll_j = take(sizeof(int32_t) * LEVEL_COLL_CAP);
         V.coll_du = take(sizeof(double) * LEVEL_COLL_CAP);
         V.gtsum = take(sizeof(int64_t) * 2 * (size_t)((n + LT - 1) / LT));
+        if (n > GROUP_BLOCK) {
+            const int64_t gc = (n + GT - 1) / GT * GT;
+            V.gcap = gc < GENGA_GROUP_MAX ? gc : GENGA_GROUP_MAX;
+            const size_t c = (size_t)V.gcap;
+            V.gbig = take(sizeof(int32_t) * (size_t)(2 + n / (GROUP_BLOCK + 1)));
+            V.gsync = take(sizeof(uint64_t) * 8);
+            V.gpub = take(sizeof(double) * 12 * c);
+            V.gbox = take(sizeof(double) * 2 * (c / 64) * 8);
+            V.gtrho = take(sizeof(double) * (c / 64));
+            V.gmm = take(sizeof(double) * c);
+            V.gmR = take(sizeof(double) * c);
+            V.gmrc = take(sizeof(double) * c);
+            V.gmirc = take(sizeof(double) * (size_t)V.L * c);
+            V.gmidx = take(sizeof(int32_t) * c);
+            V.gbpart = take(sizeof(double) * 4 * (c / 64));
+            V.gccnt = take(sizeof(int32_t) * GCELL * GCELL);
+            V.gcfill = take(sizeof(int32_t) * GCELL * GCELL);
+            V.gctmp = take(sizeof(int32_t) * 2 * c);
+        }
     }
     V.total = off;
     return V;

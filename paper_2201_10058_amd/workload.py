@@ -209,6 +209,40 @@ def make_ring(n: int, radius: float = 1.0, m_body: float = 1e-9, neighbours: int
                 m=np.full(n, m_body), rc=rc, n=n)
 
 
+def make_bs_ring(n: int, m_body: float | None = None, neighbours: int = 4,
+                 G: float = GAUSS_G) -> dict:
+    """The close-encounter performance test of Sect. 6.1: n equal masses
+    evenly spaced on a circular orbit of radius 1 about a unit star
+    (barycentric velocities, coplanar).  Returns the state and the n1 for
+    which the critical radius n1 R_H (n2 = 0) lies midway between the chords
+    to the k-th and (k+1)-th neighbour, k = `neighbours`: every body meets
+    2k others and the encounter graph is one chain, a single group of n.
+    Below 2k + 2 bodies every other body is a partner (rc = 2.2).
+
+    The default mass, min(1e-9, 1e-4 (2 pi / n)^2), keeps a neighbour's pull
+    below 1e-4 of the star's at every n, so that the ring stays a ring over a
+    step (a heavier dense ring clumps and the group's steps shrink): the
+    test then times the same Bulirsch-Stoer work per body at every n."""
+    if m_body is None:
+        m_body = min(1e-9, 1e-4 * (2.0 * math.pi / n) ** 2)
+    th = 2.0 * math.pi * np.arange(n, dtype=np.float64) / n
+    v = math.sqrt(G * (1.0 + m_body))
+    m = np.full(n, m_body)
+    vh = np.stack([-v * np.sin(th), v * np.cos(th), np.zeros(n)], 1)
+    vb = vh - (m[:, None] * vh).sum(0) / (1.0 + m.sum())
+    rh = (m_body / 3.0) ** (1.0 / 3.0)
+    if n <= 2 * neighbours + 1:
+        rc = 2.2
+    else:
+        def chord(q):
+            return 2.0 * math.sin(math.pi * q / n)
+        rc = 0.5 * (chord(neighbours) + chord(neighbours + 1))
+    return {"x": np.cos(th), "y": np.sin(th), "z": np.zeros(n),
+            "vx": vb[:, 0].copy(), "vy": vb[:, 1].copy(), "vz": vb[:, 2].copy(), "m": m,
+            "n": n, "n1": rc / rh, "G": G, "m_star": 1.0, "dt": 6.0,
+            "name": f"bs_ring_n{n}_k{neighbours}"}
+
+
 def random_cloud(n: int, seed: int, spread: float = 1.0, rc_scale: float = 0.2,
                  m_scale: float = 1e-6) -> dict:
     """Uniform random bodies in a cube, random masses and critical radii.

@@ -117,11 +117,57 @@ def test_direct_disk2048_one_level(dev):
     assert ep < 1e-11 and ev < 1e-11
 
 
-def test_oversized_group_is_reported(dev):
-    # a ring of 600 neighbours in one chain: more than GENGA_GROUP_MAX = 512
-    ring = ring_chain(600)
+@pytest.mark.parametrize("L,s", [(1, 1), (2, 2)])
+def test_direct_grid_group_ring1024(dev, L, s):
+    # Sect. 6.1's ring test: 1,024 bodies, each inside the critical radius of
+    # its nearest neighbours, form one group; more than one workgroup holds,
+    # so all workgroups of the grid solver integrate it together (with two
+    # levels, over each level-1 sub-step with both levels' weights)
+    n = 1024
+    ring = ring_chain(n)
     st = N.State.from_numpy(ring)
-    cfg = N.Config(G=G, slevels=1, substeps=1, level_capacity=4096, direct=1, n1=3.0, n2=0.0)
+    cfg = N.Config(G=G, slevels=L, substeps=s, level_capacity=16 * n, direct=1, n1=3.0, n2=0.0)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(ring)
+    _say(f"ring {n} {L}x{s}: grid solver step")
+    assert N.step(st, cfg, ws) == N.OK
+    gs = N.group_stats(st.n, cfg, ws)
+    r = oracle.step_direct(ref, G, 1.0, 6.0, 3.0, 0.0, L, s, rk_steps=200)
+    assert r[6] == 0 and gs == r[5] and gs[1] == n, (gs, r[5])
+    out = st.numpy()
+    ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
+    _say(f"ring {n} {L}x{s}: groups {gs}, position {ep:.2e} velocity {ev:.2e}")
+    assert ep < 1e-11 and ev < 1e-11
+
+
+def test_direct_disk4096_one_level_grid_group(dev):
+    # without levels the 4,096-body disk's level-0 list links 1,916 bodies
+    # into one group (379 groups in all): the grid solver with the members in
+    # spatial order and tile culling, against the oracle's all-pairs flow
+    d = W.make_disk(W.DISK_ADJOINT)
+    st = N.State.from_numpy(d)
+    cfg = _cfg(1, 1)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(d)
+    _say("disk4096 one level: grid solver step")
+    assert N.step(st, cfg, ws) == N.OK
+    gs = N.group_stats(st.n, cfg, ws)
+    r = oracle.step_direct(ref, G, 1.0, 6.0, 3.0, 0.4, 1, 1, rk_steps=200)
+    assert r[6] == 0 and gs == r[5], (gs, r[5])
+    out = st.numpy()
+    ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
+    _say(f"disk4096 one level: groups {gs}, position {ep:.2e} velocity {ev:.2e}")
+    assert gs[1] > 512
+    assert ep < 1e-11 and ev < 1e-11
+
+
+def test_oversized_group_is_reported(dev):
+    # a ring of 70,000 bodies in one chain (m = 3e-12: 3 R_H = 3e-4 AU
+    # against a spacing of 9.0e-5 AU): more than GENGA_GROUP_MAX = 65,536
+    n = 70000
+    ring = ring_chain(n, m=3e-12)
+    st = N.State.from_numpy(ring)
+    cfg = N.Config(G=G, slevels=1, substeps=1, level_capacity=1 << 19, direct=1, n1=3.0, n2=0.0)
     ws = N.Workspace(st.n, cfg)
     assert N.step(st, cfg, ws) == N.E_GROUP
 
