@@ -638,11 +638,45 @@ __device__ __forceinline__ double bs_remainder(double r, const double *ia, int s
     return R;
 }
 
+__device__ __forceinline__ double wave_min_all(double v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const double o = __shfl_xor(v, d, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_all(double v)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const double o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Squared gap between the box (lo, hi) and the box B = (lo, hi) of another
+// tile: a lower bound of the squared distance of any two of their members.
+__device__ __forceinline__ double box_gap2(const double lo[3], const double hi[3], const double *B)
+{
+    double d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double a1 = B[c] - hi[c], a2 = lo[c] - B[3 + c];
+        const double gc = a1 > a2 ? a1 : a2;
+        d2 += gc > 0.0 ? gc * gc : 0.0;
+    }
+    return d2;
+}
+
 template <int BT>
 struct BsSmem {
     double px[BT], py[BT], pz[BT], m[BT];
     double pv[3][BT], R[BT];
     double rcd[BT];                     // deepest-level rc
+    double box[BT / 64][8];             // each wave's box of its members' positions
+    double trho[BT / 64];               // each wave's largest deepest-level rc
     int32_t idx[BT];
     double irc[GENGA_MAX_LEVELS][BT];   // 1 / rc of each level
     double red[BT / 64];
@@ -650,50 +684,75 @@ struct BsSmem {
 };
 
 // Acceleration of member t at its position (o) from the positions in LDS.
+// The partners come by waves of 64: a wave whose box stays beyond the larger
+// deepest-level critical radius of the two waves from the own wave's box
+// holds no partner with R > 0 and is skipped (its terms are exact zeros), as
+// is each single partner beyond that radius; the sum runs over the partners
+// in ascending order.
 template <int BT>
 __device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, int t, int g,
                                          const double o[3], double acc[3])
 {
+    const double *BI = sm.box[t >> 6];
+    const double lo[3] = {BI[0], BI[1], BI[2]}, hi[3] = {BI[3], BI[4], BI[5]};
     const double r2s = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
     const double irs = rsq2(r2s);
     const double ks = -a.mu * (irs * irs * irs);
     acc[0] = ks * o[0];
     acc[1] = ks * o[1];
     acc[2] = ks * o[2];
-    for (int q = 0; q < g; ++q) {
-        if (q == t) continue;
-        const double dx = sm.px[q] - o[0], dy = sm.py[q] - o[1], dz = sm.pz[q] - o[2];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        // beyond the larger deepest-level radius R = 0 exactly: the term is
-        // an exact zero and skipping it leaves the sum unchanged
-        const double rq = sm.rcd[t] > sm.rcd[q] ? sm.rcd[t] : sm.rcd[q];
-        if (r2 > rq * rq * (1.0 + 0x1p-18)) continue;
-        const double ir = rsq2(r2);
-        const double R = bs_remainder(r2 * ir, &sm.irc[0][t], BT, &sm.irc[0][q], BT, a.nlev);
-        const double s = a.G * sm.m[q] * R * (ir * ir * ir);
-        acc[0] += s * dx;
-        acc[1] += s * dy;
-        acc[2] += s * dz;
+    const int nw = (g + 63) >> 6;
+    const double rhoI = sm.trho[t >> 6];
+    for (int J = 0; J < nw; ++J) {
+        const double rr = rhoI > sm.trho[J] ? rhoI : sm.trho[J];
+        if (box_gap2(lo, hi, sm.box[J]) > rr * rr * (1.0 + 0x1p-18)) continue;
+        const int q1 = g < J * 64 + 64 ? g : J * 64 + 64;
+        for (int q = J * 64; q < q1; ++q) {
+            if (q == t) continue;
+            const double dx = sm.px[q] - o[0], dy = sm.py[q] - o[1], dz = sm.pz[q] - o[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            // beyond the larger deepest-level radius R = 0 exactly: the term
+            // is an exact zero and skipping it leaves the sum unchanged
+            const double rq = sm.rcd[t] > sm.rcd[q] ? sm.rcd[t] : sm.rcd[q];
+            if (r2 > rq * rq * (1.0 + 0x1p-18)) continue;
+            const double ir = rsq2(r2);
+            const double R = bs_remainder(r2 * ir, &sm.irc[0][t], BT, &sm.irc[0][q], BT, a.nlev);
+            const double s = a.G * sm.m[q] * R * (ir * ir * ir);
+            acc[0] += s * dx;
+            acc[1] += s * dy;
+            acc[2] += s * dz;
+        }
     }
 }
 
-// Publish positions, then every member's derivative at them.
+// Publish positions (and each wave's box), then every member's derivative
+// at them.
 template <int BT>
 __device__ __forceinline__ void bs_deriv(const BsDev &a, BsSmem<BT> &sm, int t, int g,
                                          const double z[6], double f[6])
 {
     __syncthreads();   // the previous evaluation has finished reading
-    if (t < g) {
+    const bool mem = t < g;
+    if (mem) {
         sm.px[t] = z[0];
         sm.py[t] = z[1];
         sm.pz[t] = z[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double lo = wave_min_all(mem ? z[c] : INFINITY);
+        const double hi = wave_max_all(mem ? z[c] : -INFINITY);
+        if ((t & 63) == 0 && mem) {
+            sm.box[t >> 6][c] = lo;
+            sm.box[t >> 6][3 + c] = hi;
+        }
     }
     __syncthreads();
     f[0] = z[3];
     f[1] = z[4];
     f[2] = z[5];
     double acc[3] = {0.0, 0.0, 0.0};
-    if (t < g) bs_accel<BT>(a, sm, t, g, z, acc);
+    if (mem) bs_accel<BT>(a, sm, t, g, z, acc);
     f[3] = acc[0];
     f[4] = acc[1];
     f[5] = acc[2];
@@ -1182,6 +1241,10 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
                 sm.irc[l][t] = rcp2(a.rc[l][b]);
             sm.rcd[t] = a.rc[a.nlev - 1][b];
         }
+        {
+            const double tr = wave_max_all(t < g ? sm.rcd[t] : 0.0);
+            if ((t & 63) == 0 && t < g) sm.trho[t >> 6] = tr;
+        }
         BlockPol<BT> P{sm, t, g};
         const bool failed = bs_run(a, P, y);
         if (failed && t == 0) atomicOr(a.status, ST_NOCONV);
@@ -1257,24 +1320,6 @@ __device__ __forceinline__ unsigned morton6(unsigned cx, unsigned cy)
     unsigned k = 0;
     for (int b = 0; b < 6; ++b) k |= ((cx >> b) & 1u) << (2 * b) | ((cy >> b) & 1u) << (2 * b + 1);
     return k;
-}
-
-__device__ __forceinline__ double wave_min_all(double v)
-{
-    for (int d = 32; d > 0; d >>= 1) {
-        const double o = __shfl_xor(v, d, 64);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ double wave_max_all(double v)
-{
-    for (int d = 32; d > 0; d >>= 1) {
-        const double o = __shfl_xor(v, d, 64);
-        v = o > v ? o : v;
-    }
-    return v;
 }
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -1395,18 +1440,6 @@ struct GridPol {
         }
     }
 
-    // squared gap between the own tile's box and tile J's (published) box
-    __device__ double gap2(const double lo[3], const double hi[3], const double *B) const
-    {
-        double d2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double a1 = B[c] - hi[c], a2 = lo[c] - B[3 + c];
-            const double gc = a1 > a2 ? a1 : a2;
-            d2 += gc > 0.0 ? gc * gc : 0.0;
-        }
-        return d2;
-    }
 
     // (one copy of the evaluation: bs_step reaches it from nine places; the
     // loop works on locals and LDS only).  The split waves of a tile take
@@ -1440,7 +1473,7 @@ struct GridPol {
                 if (Jl < nt) {
                     const double rr = rhoI > trho[Jl] ? rhoI : trho[Jl];
                     // (a NaN box keeps the tile: the flow then fails as a whole)
-                    near = !(gap2(lo, hi, Bx + (size_t)Jl * 8) > rr * rr * (1.0 + 0x1p-18));
+                    near = !(box_gap2(lo, hi, Bx + (size_t)Jl * 8) > rr * rr * (1.0 + 0x1p-18));
                 }
                 unsigned long long mask = __ballot(near);
                 while (mask) {
@@ -1581,7 +1614,7 @@ __device__ long long GridPol::overlap(const BsDev &a, const double z[6])
             bool near = false;
             if (Jl < nt) {
                 const double rs = rI + Bx[(size_t)Jl * 8 + 6];
-                near = rs > 0.0 && !(gap2(lo, hi, Bx + (size_t)Jl * 8) > rs * rs * (1.0 + 0x1p-18));
+                near = rs > 0.0 && !(box_gap2(lo, hi, Bx + (size_t)Jl * 8) > rs * rs * (1.0 + 0x1p-18));
             }
             unsigned long long mask = __ballot(near);
             while (mask) {

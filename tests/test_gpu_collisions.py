@@ -71,3 +71,47 @@ def test_no_collision_without_radii(dev):
     assert N.step(state, cfg, ws) == N.OK
     assert N.collisions(state.n, cfg, ws)[0] == 0
     assert np.array_equal(state.numpy()["m"], st["m"])
+
+
+def _ring_collision(n=600, dv=1e-3, R=0.004):
+    # a ring of n bodies in one group (more than one workgroup holds: the
+    # grid solver); body 300 is sped up by dv along its orbit and, with
+    # body 301, given radius R (the gap of 0.0025 AU closes in ~2.5 days)
+    from encounter_fixture import ring_chain
+    st = ring_chain(n)
+    th = 2 * np.pi * 300 / n
+    st["vx"][300] += -dv * np.sin(th)
+    st["vy"][300] += dv * np.cos(th)
+    st["R"] = np.full(n, 1e-6)
+    st["R"][300] = st["R"][301] = R
+    return st
+
+
+def test_merger_in_grid_group_matches_oracle(dev):
+    st = _ring_collision()
+    state = N.State.from_numpy(st, radius=st["R"])
+    cfg = N.Config(G=G, slevels=1, substeps=1, direct=1, level_capacity=1 << 14, n1=3.0, n2=0.0)
+    ws = N.Workspace(state.n, cfg)
+    _say("ring 600 with a merger: grid solver step")
+    assert N.step(state, cfg, ws) == N.OK
+    gs = N.group_stats(state.n, cfg, ws)
+    recs = N.collisions(state.n, cfg, ws)[1]
+    out = state.numpy()
+    ref = {k: v.copy() for k, v in st.items()}
+    r = oracle.step_coll(ref, G, 1.0, 6.0, 3.0, 0.0, 1, 1, rk_steps=200)
+    _say(f"grid group merger: groups {gs} oracle {r[2]}, gpu {recs} oracle {r[3]}")
+    assert r[4] == 0 and gs == r[2] == (1, 600)
+    assert len(recs) == 1 and len(r[3]) == 1
+    (gi, gj, gdu), (oi, oj, odu) = recs[0], r[3][0]
+    assert (gi, gj) == (oi, oj) == (300, 301)
+    assert abs(gdu - odu) <= 1e-6 * abs(odu)
+    ep = max(np.abs(out[k] - ref[k]).max() for k in ("x", "y", "z"))
+    ev = max(np.abs(out[k] - ref[k]).max() for k in ("vx", "vy", "vz"))
+    _say(f"grid group merger: position {ep:.2e} AU velocity {ev:.2e} AU/day")
+    # both sides locate the contact only to coll_tol = 1e-6 of R_a + R_b:
+    # ~1e-6 * 0.008 / 1e-3 = 8e-6 days at this closing speed; the pair's
+    # mutual pull at contact (~1.4e-5 AU/day^2) over that time bounds the
+    # velocity difference by ~1e-10 AU/day
+    assert ep < 1e-10 and ev < 1e-10
+    assert out["m"][gi] == ref["m"][gi] and out["m"][gj] == 0.0
+    assert abs(out["R"][gi] - ref["R"][gi]) <= 1e-15 * ref["R"][gi] and out["R"][gj] == 0.0
