@@ -402,13 +402,43 @@ __device__ __forceinline__ int32_t uf_load(const int32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int32_t uf_find(const int32_t *parent, int32_t x)
+// Root of x, halving the path on the way: a non-root's parent may be
+// replaced by any of its ancestors (parents only point to smaller bodies and
+// a non-root never becomes a root again), so plain atomic stores of the
+// grandparent are safe under concurrent hooks and keep the chains short (a
+// ring's chain is as long as the ring otherwise).
+__device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x)
 {
     for (;;) {
         const int32_t p = uf_load(parent + x);
         if (p == x) return x;
-        x = p;     // parents only point to smaller bodies: the walk ends
+        const int32_t gp = uf_load(parent + p);
+        if (gp != p) __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
     }
+}
+
+// atomicAdd(ctr + key, 1) for every active lane, one atomic per distinct key
+// of the wave; returns the lane's slot (the old value plus its rank among
+// the wave's lanes with the same key).
+__device__ __forceinline__ int32_t wave_add_by_key(int32_t *ctr, int32_t key, bool active)
+{
+    unsigned long long todo = __ballot(active);
+    int32_t slot = 0;
+    while (todo) {
+        const int lead = __builtin_ctzll(todo);
+        const int32_t k = __shfl(key, lead, 64);
+        const unsigned long long same = __ballot(active && key == k);
+        int32_t base = 0;
+        if ((int)(threadIdx.x & 63) == lead) base = atomicAdd(ctr + k, __popcll(same));
+        base = __shfl(base, lead, 64);
+        if (active && key == k) {
+            const unsigned long long lower = same & ((1ull << (threadIdx.x & 63)) - 1ull);
+            slot = base + __popcll(lower);
+        }
+        todo &= ~same;
+    }
+    return slot;
 }
 
 __global__ __launch_bounds__(LT) void k_group_init(int32_t *parent, int32_t *flag, int32_t *gsize,
@@ -447,14 +477,18 @@ __global__ __launch_bounds__(LT) void k_group_union(const int32_t *pi, const int
 }
 
 // Root of every listed body (into lab), members counted per root.
-__global__ __launch_bounds__(LT) void k_group_root(const int32_t *parent, const int32_t *flag,
+__global__ __launch_bounds__(LT) void k_group_root(int32_t *parent, const int32_t *flag,
                                                    int32_t *lab, int32_t *gsize, int64_t n)
 {
-    for (int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x; k < n; k += (int64_t)gridDim.x * LT) {
-        if (!flag[k]) continue;
-        const int32_t r = uf_find(parent, (int32_t)k);
-        lab[k] = r;
-        atomicAdd(gsize + r, 1);
+    for (int64_t k0 = (int64_t)blockIdx.x * LT; k0 < n; k0 += (int64_t)gridDim.x * LT) {
+        const int64_t k = k0 + threadIdx.x;
+        const bool on = k < n && flag[k];
+        int32_t r = 0;
+        if (on) {
+            r = uf_find(parent, (int32_t)k);
+            lab[k] = r;
+        }
+        wave_add_by_key(gsize, r, on);
     }
 }
 
@@ -532,10 +566,12 @@ __global__ __launch_bounds__(LT) void k_group_fill(const int32_t *flag, const in
                                                    const int32_t *gstart, int32_t *gfill,
                                                    int32_t *gtmp, int64_t n)
 {
-    for (int64_t k = (int64_t)blockIdx.x * LT + threadIdx.x; k < n; k += (int64_t)gridDim.x * LT) {
-        if (!flag[k]) continue;
-        const int32_t r = lab[k];
-        gtmp[gstart[r] + atomicAdd(gfill + r, 1)] = (int32_t)k;
+    for (int64_t k0 = (int64_t)blockIdx.x * LT; k0 < n; k0 += (int64_t)gridDim.x * LT) {
+        const int64_t k = k0 + threadIdx.x;
+        const bool on = k < n && flag[k];
+        const int32_t r = on ? lab[k] : 0;
+        const int32_t slot = wave_add_by_key(gfill, r, on);
+        if (on) gtmp[gstart[r] + slot] = (int32_t)k;
     }
 }
 
