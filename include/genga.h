@@ -115,7 +115,9 @@ typedef struct {
     int ipt;       /* kick rows per thread (1 or 2); 0 = library choice         */
     int slices;    /* single system: kick column slices; 0 = library choice.
                       Symmetric kick: slices of 512 / d columns with d the
-                      largest power of two <= min(slices, 8)               */
+                      largest power of two <= min(slices, 8) (a binary64
+                      batch: <= min(slices, 4); 0 = the width whose tiles
+                      finish first by the batch plan's schedule model)     */
     int block;     /* batch: kick threads per block (64 or 256); 0 = 256         */
     int tile_cols; /* batch: columns per kick tile (rounded up to 64); 0 = 1024  */
     int grid;      /* batch: persistent kick blocks; 0 = library choice         */
@@ -491,9 +493,9 @@ size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga
 
 /* Batched kick.  Candidates: the one-sided form with block {64, 256} x rows
  * per thread {1, 2} x tile_cols {256, 512, 1024, 2048} x grid {library
- * choice, 32 waves per CU}, and (binary64) the symmetric form.  Writes
- * p->block, p->ipt, p->tile_cols, p->grid (p->slices = 0) and the form flag
- * in p->flags.  On return
+ * choice, 32 waves per CU}, and (binary64) the symmetric form with 1, 2 or 4
+ * column slices per 512-row group.  Writes p->block, p->ipt, p->tile_cols,
+ * p->grid, p->slices and the form flag in p->flags.  On return
  * ws holds the plan of the chosen shape (as after genga_batch_plan).
  * ws_bytes >= genga_autotune_batched_workspace_bytes(bt, p), else candidates
  * that do not fit are skipped.  GENGA_E_UNSUPPORTED if no candidate ran. */

@@ -136,8 +136,8 @@ double time_ms(F &&call, hipStream_t s, int reps)
     return (double)t[t.size() / 2];
 }
 
-// One-sided tile shapes, and (binary64) the symmetric form, whose shape is
-// fixed (512-row groups, 512-column slices).
+// One-sided tile shapes, and (binary64) the symmetric form with 1, 2 or 4
+// column slices per 512-row group (slice widths 512, 256, 128).
 std::vector<Shape> batch_candidates(const genga_params *p)
 {
     std::vector<Shape> v;
@@ -154,11 +154,13 @@ std::vector<Shape> batch_candidates(const genga_params *p)
                     s.flags = GENGA_FLAG_DIRECTED;
                     v.push_back(s);
                 }
-    if (p->precision == GENGA_FP64) {
-        Shape s;
-        s.flags = GENGA_FLAG_SYMMETRIC;
-        v.push_back(s);
-    }
+    if (p->precision == GENGA_FP64)
+        for (int sl : {1, 2, 4}) {
+            Shape s;
+            s.slices = sl;
+            s.flags = GENGA_FLAG_SYMMETRIC;
+            v.push_back(s);
+        }
     return v;
 }
 

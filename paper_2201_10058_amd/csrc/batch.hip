@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
+#include <queue>
 #include <vector>
 
 #include "genga_internal.h"
@@ -37,6 +39,87 @@ struct BatchShape {
     int64_t ntot = 0;
     int64_t cols = 0;     // columns per tile (multiple of 64)
 };
+
+// Symmetric kick of a batch: the critical path of one tile, in units of one
+// 64-row slot's pass over a 64-column chunk.  At each chunk the block waits
+// for its busiest wave: off the diagonal both slots of every wave run the
+// chunk (padding rows included); on a diagonal tile a slot works on the
+// chunks from its own on and padding slots are skipped.  Each chunk and each
+// tile also carry a fixed cost (staging, barriers, sums).
+static double sym_tile_cost(const SymShape &h, int64_t g, int64_t s)
+{
+    const int64_t row0 = g * SYM_RG;
+    const int64_t rowend = std::min<int64_t>(row0 + SYM_RG, h.n);
+    const int64_t col0 = row0 + s * h.W;
+    const int64_t col1 = std::min<int64_t>(col0 + h.W, h.n);
+    const int64_t nch = (col1 - col0 + 63) / 64;
+    double t = 0.5;
+    for (int64_t kc = 0; kc < nch; ++kc) {
+        const int64_t cc = (col0 >> 6) + kc;
+        int busiest = 0;
+        for (int w = 0; w < SYM_NW; ++w) {
+            int c = 0;
+            for (int q = 0; q < SYM_IPT; ++q) {
+                const int64_t slot = (int64_t)q * SYM_NW + w;
+                if (s >= h.d) {
+                    ++c;
+                } else if (row0 + slot * 64 < rowend && cc >= (row0 >> 6) + slot) {
+                    ++c;
+                }
+            }
+            busiest = std::max(busiest, c);
+        }
+        t += busiest + 0.15;
+    }
+    return t;
+}
+
+// Longest total, over the resident blocks, of the tiles handed out in
+// decreasing cost as blocks free up (the launch's order and schedule).
+static double sym_makespan(std::vector<double> &cost, int slots)
+{
+    std::sort(cost.begin(), cost.end(), std::greater<double>());
+    std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+    for (int k = 0; k < slots; ++k) q.push(0.0);
+    for (double c : cost) {
+        const double m = q.top();
+        q.pop();
+        q.push(m + c);
+    }
+    double mx = 0.0;
+    while (!q.empty()) {
+        mx = std::max(mx, q.top());
+        q.pop();
+    }
+    return mx;
+}
+
+// Columns per slice for a batch in the symmetric kick: of 512, 256 and 128
+// (one, two or four slices per 512-row group), the width whose tiles finish
+// first on the device's resident blocks by the model above (narrower slices
+// balance the blocks better but add tiles and row sums).  The 512-system
+// ensemble of 16-4,096 bodies takes 256 (0.803 against 0.839 ms per step
+// for 512 and 0.834 for 128).
+static int sym_batch_width(const genga_batch *bt)
+{
+    const int slots = 4 * cu_count();   // blocks of 4 waves at 4 waves per SIMD
+    int best = SYM_RG;
+    double best_t = 0.0;
+    for (int W : {SYM_RG, SYM_RG / 2, SYM_RG / 4}) {
+        std::vector<double> cost;
+        for (int64_t q = 0; q < bt->S; ++q) {
+            const SymShape h = sym_shape(bt->offsets[q + 1] - bt->offsets[q], W);
+            for (int64_t g = 0; g < h.G; ++g)
+                for (int64_t k = 0; k < h.ns(g); ++k) cost.push_back(sym_tile_cost(h, g, k));
+        }
+        const double t = sym_makespan(cost, slots);
+        if (W == SYM_RG || t < best_t) {
+            best = W;
+            best_t = t;
+        }
+    }
+    return best;
+}
 
 // Validate the batch and derive the launch shape (O(S) host work).
 static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape &sh)
@@ -74,15 +157,20 @@ static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape 
     int64_t grid = (p && p->grid > 0) ? p->grid : (int64_t)cu_count() * per_cu;
     if (grid > ntiles) grid = ntiles;
     c.grid = (int)grid;
-    // binary64: the symmetric kick over every system (slices of SYM_RG
-    // columns, so system s has G_s (G_s + 1) / 2 tiles)
+    // binary64: the symmetric kick over every system (512-row groups and
+    // slices of symb_W columns, the same width for every system)
     if ((!p || p->precision == GENGA_FP64) && !(p && (p->flags & GENGA_FLAG_DIRECTED))) {
+        const int sl = p ? p->slices : 0;
+        if (sl < 0) return GENGA_E_INVAL;
+        int d = 1;
+        while (2 * d <= sl && 2 * d <= 4) d *= 2;
         c.use_symb = true;
+        c.symb_W = sl ? SYM_RG / d : sym_batch_width(bt);
         c.symb_S = bt->S;
         c.symb_T = 0;
         c.symb_cols = 0;
         for (int64_t q = 0; q < bt->S; ++q) {
-            const SymShape h = sym_shape(bt->offsets[q + 1] - bt->offsets[q], SYM_RG);
+            const SymShape h = sym_shape(bt->offsets[q + 1] - bt->offsets[q], c.symb_W);
             c.symb_T += h.T;
             c.symb_cols += h.coloff(h.G);
         }
@@ -92,29 +180,26 @@ static int batch_shape(const genga_batch *bt, const genga_params *p, BatchShape 
 
 // Symmetric kick of a batch: per-system shapes and offsets, tiles in storage
 // order (system by system, tb(g) + s within a system) and the launch order
-// (decreasing work: rows x columns, halved on the diagonal).
+// (decreasing critical path, sym_tile_cost).
 static void build_sym_plan(const genga_batch *bt, const BatchShape &sh, std::vector<SymSys> &sys,
                            std::vector<SymTileB> &tiles, std::vector<int32_t> &order)
 {
     sys.assign((size_t)bt->S, SymSys{});
     tiles.clear();
     tiles.reserve((size_t)sh.cfg.symb_T);
-    std::vector<int64_t> cost;
+    std::vector<double> cost;
     cost.reserve((size_t)sh.cfg.symb_T);
     int64_t tbase = 0, cbase = 0;
     for (int64_t q = 0; q < bt->S; ++q) {
         SymSys &ss = sys[(size_t)q];
         ss.o = bt->offsets[q];
-        ss.sh = sym_shape(bt->offsets[q + 1] - ss.o, SYM_RG);
+        ss.sh = sym_shape(bt->offsets[q + 1] - ss.o, sh.cfg.symb_W);
         ss.tbase = tbase;
         ss.cbase = cbase;
-        const int64_t n = ss.sh.n;
         for (int64_t g = 0; g < ss.sh.G; ++g) {
-            const int64_t rows = std::min<int64_t>(SYM_RG, n - g * SYM_RG);
             for (int64_t k = 0; k < ss.sh.ns(g); ++k) {
-                const int64_t cols = std::min<int64_t>(ss.sh.W, n - g * SYM_RG - k * ss.sh.W);
                 tiles.push_back(SymTileB{(int32_t)q, (int32_t)g, (int32_t)k, 0});
-                cost.push_back(k < ss.sh.d ? rows * cols / 2 : rows * cols);
+                cost.push_back(sym_tile_cost(ss.sh, g, k));
             }
         }
         tbase += ss.sh.T;

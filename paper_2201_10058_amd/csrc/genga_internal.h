@@ -141,6 +141,7 @@ struct KickCfg {
     // component) of all systems
     bool use_symb = false;
     int64_t symb_S = 0, symb_T = 0, symb_cols = 0;
+    int symb_W = 0;           // columns per slice of every system (512, 256 or 128)
 };
 
 // Byte offsets of the workspace regions.
