@@ -676,7 +676,44 @@ def bench_batched(args, N, W, torch, np):
                               if form == "one-sided" else {}),
                            "autotuned_kick_ms": round(tune_ms, 4)},
             "other_form": {"form": "symmetric" if form == "one-sided" else "one-sided",
-                           "graph_step_ms": round(other_s * 1e3, 4)}}
+                           "graph_step_ms": round(other_s * 1e3, 4)},
+            "tuner_by_size": tune_by_size(N, W, torch, np, d)}
+
+
+SIZE_BUCKETS = ((16, 64), (64, 256), (256, 1024), (1024, 4096))
+
+
+def tune_by_size(N, W, torch, np, d):
+    """The batched autotuner's choice for the ensemble's systems of each size
+    bucket (N_s in [lo, hi)), each bucket tuned as an ensemble of its own
+    (fresh, not from the cache), with the time of its tuned kick."""
+    from paper_2201_10058_amd import autotune
+    sizes = np.diff(d["offsets"])
+    out = {}
+    for lo, hi in SIZE_BUCKETS:
+        idx = [k for k in range(d["S"]) if lo <= sizes[k] < hi]
+        if not idx:
+            continue
+        parts = {f: np.concatenate([d[f][d["offsets"][k]:d["offsets"][k + 1]] for k in idx])
+                 for f in ("x", "y", "z", "vx", "vy", "vz", "m")}
+        offs = np.zeros(len(idx) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum(sizes[idx])
+        bt = N.Batch(offs, d["m_star"][idx], d["dt"][idx], d["n1"][idx], d["n2"][idx])
+        st = N.State.from_numpy(parts)
+        cfg = N.Config(G=d["G"], flags=N.FLAG_NOSYNC)
+        N.step_batched(st, N.BatchWorkspace(bt, cfg), cfg)   # radii for the kicks
+        torch.cuda.synchronize()
+        ch = autotune.tune_batched(st, bt, cfg, use_cache=False)
+        inter = float(np.sum(sizes[idx] * (sizes[idx] - 1)))
+        rec = {"systems": len(idx), "bodies": int(offs[-1]), "form": ch["form"],
+               "kick_ms": round(ch["ms"], 4), "kick_ginter_s": round(inter / ch["ms"] / 1e6, 1)}
+        if ch["form"] == "symmetric":
+            rec["slice_columns"] = 512 // max(1, ch["slices"])
+        else:
+            rec.update(block=ch["block"], ipt=ch["ipt"], tile_cols=ch["tile_cols"], grid=ch["grid"])
+        out[f"{lo}-{hi}"] = rec
+        print(f"tuner, systems of {lo}-{hi} bodies: {rec}", file=sys.stderr, flush=True)
+    return out
 
 
 def bench_adjoint(N, W, torch, np, d65536_state, cfg65536, kick_ms_fp64=None):

@@ -491,11 +491,13 @@ int genga_step_batched(genga_bodies *b, const genga_batch *bt, const genga_param
 /* Workspace for genga_autotune_batched: the largest any candidate needs. */
 size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga_params *p);
 
-/* Batched kick.  Candidates: the one-sided form with block {64, 256} x rows
- * per thread {1, 2} x tile_cols {256, 512, 1024, 2048} x grid {library
- * choice, 32 waves per CU}, and (binary64) the symmetric form with 1, 2 or 4
- * column slices per 512-row group.  Writes p->block, p->ipt, p->tile_cols,
- * p->grid, p->slices and the form flag in p->flags.  On return
+/* Batched kick.  Candidates, in this order: (binary64) the symmetric form
+ * with the plan's own slice width (p->slices = 0) and with 1, 2 or 4 column
+ * slices per 512-row group, then the one-sided form with block {64, 256} x
+ * rows per thread {1, 2} x tile_cols {256, 512, 1024, 2048} x grid {library
+ * choice, 32 waves per CU}; each timed 5 times (median), a later candidate
+ * chosen only if more than 1 % faster.  Writes p->block, p->ipt,
+ * p->tile_cols, p->grid, p->slices and the form flag in p->flags.  On return
  * ws holds the plan of the chosen shape (as after genga_batch_plan).
  * ws_bytes >= genga_autotune_batched_workspace_bytes(bt, p), else candidates
  * that do not fit are skipped.  GENGA_E_UNSUPPORTED if no candidate ran. */

@@ -30,8 +30,9 @@ def cache_path() -> str:
 
 
 def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool = True) -> dict:
-    """Pick the batched kick's form and, for the one-sided form, (block, ipt,
-    tile_cols, grid); returns the choice (with the time of one kick in "ms")."""
+    """Pick the batched kick's form and its shape: (block, ipt, tile_cols,
+    grid) for the one-sided form, the column slices per 512-row group for the
+    symmetric one; returns the choice (with the time of one kick in "ms")."""
     lib = N.load()
     bt = batch.struct()
     p = cfg.params()
@@ -48,7 +49,7 @@ def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool 
              "genga_autotune_batched")
     form = "symmetric" if p.flags & N.FLAG_SYMMETRIC else "one-sided"
     return dict(form=form, block=p.block, ipt=p.ipt, tile_cols=p.tile_cols, grid=p.grid,
-                flags=p.flags, ms=ms.value)
+                slices=p.slices, flags=p.flags, ms=ms.value)
 
 
 def tune_single(state: N.State, cfg: N.Config, use_cache: bool = True) -> dict:

@@ -136,11 +136,19 @@ double time_ms(F &&call, hipStream_t s, int reps)
     return (double)t[t.size() / 2];
 }
 
-// One-sided tile shapes, and (binary64) the symmetric form with 1, 2 or 4
-// column slices per 512-row group (slice widths 512, 256, 128).
+// (binary64) the symmetric form with the plan's own slice width first, then
+// with 1, 2 or 4 column slices per 512-row group (widths 512, 256, 128), and
+// the one-sided tile shapes.
 std::vector<Shape> batch_candidates(const genga_params *p)
 {
     std::vector<Shape> v;
+    if (p->precision == GENGA_FP64)
+        for (int sl : {0, 1, 2, 4}) {
+            Shape s;
+            s.slices = sl;
+            s.flags = GENGA_FLAG_SYMMETRIC;
+            v.push_back(s);
+        }
     const int cu = cus();
     for (int block : {64, KB})
         for (int ipt : {1, 2})
@@ -154,13 +162,6 @@ std::vector<Shape> batch_candidates(const genga_params *p)
                     s.flags = GENGA_FLAG_DIRECTED;
                     v.push_back(s);
                 }
-    if (p->precision == GENGA_FP64)
-        for (int sl : {1, 2, 4}) {
-            Shape s;
-            s.slices = sl;
-            s.flags = GENGA_FLAG_SYMMETRIC;
-            v.push_back(s);
-        }
     return v;
 }
 
@@ -241,8 +242,10 @@ int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_p
                     return genga_kick_batched(b, bt, &q, 0.0, nullptr, nullptr, nullptr, nullptr,
                                               ws, stream);
                 },
-                s, 3);
-            if (ms >= 0.0 && (best_ms < 0.0 || ms < best_ms)) {
+                s, 5);
+            // a later candidate has to be faster by more than the timing's
+            // noise (1 %): the plan's own choice, timed first, wins ties
+            if (ms >= 0.0 && (best_ms < 0.0 || ms < 0.99 * best_ms)) {
                 best_ms = ms;
                 best = c;
             }

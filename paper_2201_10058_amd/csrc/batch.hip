@@ -12,7 +12,9 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <queue>
+#include <unordered_map>
 #include <vector>
 
 #include "genga_internal.h"
@@ -100,9 +102,8 @@ static double sym_makespan(std::vector<double> &cost, int slots)
 // balance the blocks better but add tiles and row sums).  The 512-system
 // ensemble of 16-4,096 bodies takes 256 (0.803 against 0.839 ms per step
 // for 512 and 0.834 for 128).
-static int sym_batch_width(const genga_batch *bt)
+static int sym_batch_width_uncached(const genga_batch *bt, int slots)
 {
-    const int slots = 4 * cu_count();   // blocks of 4 waves at 4 waves per SIMD
     int best = SYM_RG;
     double best_t = 0.0;
     for (int W : {SYM_RG, SYM_RG / 2, SYM_RG / 4}) {
@@ -119,6 +120,28 @@ static int sym_batch_width(const genga_batch *bt)
         }
     }
     return best;
+}
+
+// The same, remembered per (system sizes, resident blocks): the simulation
+// takes tens of microseconds of host time, and every batched call derives
+// its shape again.
+static int sym_batch_width(const genga_batch *bt)
+{
+    const int slots = 4 * cu_count();   // blocks of 4 waves at 4 waves per SIMD
+    uint64_t h = 1469598103934665603ull ^ (uint64_t)slots;
+    for (int64_t q = 0; q <= bt->S; ++q) h = (h ^ (uint64_t)bt->offsets[q]) * 1099511628211ull;
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, int> memo;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = memo.find(h);
+        if (it != memo.end()) return it->second;
+    }
+    const int W = sym_batch_width_uncached(bt, slots);
+    std::lock_guard<std::mutex> lk(mu);
+    if (memo.size() > 4096) memo.clear();
+    memo[h] = W;
+    return W;
 }
 
 // Validate the batch and derive the launch shape (O(S) host work).

@@ -260,13 +260,15 @@ def test_autotune_batched_choice_is_valid(dev, tmp_path, monkeypatch):
     if choice["form"] == "one-sided":
         assert choice["block"] in (64, 256) and choice["ipt"] in (1, 2)
         assert choice["tile_cols"] in (256, 512, 1024, 2048) and choice["grid"] >= 0
+    else:
+        assert choice["flags"] & N.FLAG_SYMMETRIC and choice["slices"] in (0, 1, 2, 4)
     assert choice["ms"] > 0.0
     # the state is untouched (zero step factor)
     assert torch.equal(st.t["x"], x0[0]) and torch.equal(st.t["vx"], x0[1])
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and lines[0].startswith("batch:")
     again = autotune.tune_batched(st, bt, cfg)                  # served from the cache
-    shape = {k: choice[k] for k in ("block", "ipt", "tile_cols", "grid", "flags")}
+    shape = {k: choice[k] for k in ("block", "ipt", "tile_cols", "grid", "slices", "flags")}
     assert {k: again[k] for k in shape} == shape
     assert again["ms"] == pytest.approx(choice["ms"], rel=1e-5)
     assert len(cache.read_text().splitlines()) == 1
