@@ -101,6 +101,25 @@ def test_sym_outlier_radii_widen_the_wave_bound(dev):
     a_d, (qi, qj, qc), code_d, _ = _run_kick(d, rc, DIR)
     assert code_d == N.OK and qc == cnt and np.array_equal(qi, pi) and np.array_equal(qj, pj)
     assert np.max(_rel_err(a, a_d)) <= 2 * ACC_TOL
+    # the one-sided form with two rows per lane and the pairs-only call share
+    # the wave-uniform gate
+    st = N.State.from_numpy(d, rc=rc)
+    cfg2 = N.Config(G=G, flags=DIR, ipt=2)
+    ws2 = N.Workspace(st.n, cfg2)
+    pl2 = N.PairList(max(16, ocnt))
+    a2 = N.kick(st, cfg2, ws2, 0.0, acc=True, pairs=pl2).cpu().numpy()
+    ri, rj, rcnt = pl2.result()
+    assert N.read_status(ws2) == N.OK
+    assert np.max(_rel_err(a2, _oracle_acc(d, rc))) <= ACC_TOL
+    assert rcnt == ocnt and np.array_equal(ri, opi) and np.array_equal(rj, opj)
+    for flags in (DIR, SYM):
+        cfgp = N.Config(G=G, flags=flags)
+        wsp = N.Workspace(st.n, cfgp)
+        plp = N.PairList(max(16, ocnt))
+        N.encounter_pairs(st, cfgp, wsp, plp)
+        si, sj, scnt = plp.result()
+        assert N.read_status(wsp) == N.OK
+        assert scnt == ocnt and np.array_equal(si, opi) and np.array_equal(sj, opj), flags
 
 
 def test_sym_ring_overflows_staging(dev):
