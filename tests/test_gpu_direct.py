@@ -217,3 +217,57 @@ def test_direct_cuts_the_energy_error(dev):
         err[direct] = e
     _say("energy error over 40 steps, 3 x 4 levels: without / with the direct solver", err)
     assert err[1] < 0.1 * err[0]
+
+
+@pytest.mark.parametrize("n", [20000, 40000])
+def test_grid_solver_keeps_the_ring_symmetric(dev, n):
+    # Sect. 6.1's ring at sizes whose group the grid solver splits over 2
+    # waves per tile (20,000 bodies) and runs on one (40,000): the ring is
+    # invariant under rotation by 2 pi / n, so after a step every body must
+    # have the same radius, radial and tangential velocity and angle advance
+    # up to rounding.  A partner lost or counted twice at a tile or share
+    # boundary moves the bodies there by ~1e-7 AU; the oracle cannot
+    # integrate a group this large in seconds, the symmetry holds at any size.
+    d = W.make_bs_ring(n)
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=d["G"], m_star=1.0, dt=d["dt"], n1=d["n1"], n2=0.0, slevels=1, substeps=1,
+                   direct=1, level_capacity=16 * n)
+    ws = N.Workspace(st.n, cfg)
+    _say(f"ring {n}: grid solver step")
+    assert N.step(st, cfg, ws) == N.OK
+    assert N.group_stats(st.n, cfg, ws) == (1, n)
+    out = st.numpy()
+    th0 = 2 * np.pi * np.arange(n) / n
+    r = np.hypot(out["x"], out["y"])
+    dth = np.angle(np.exp(1j * (np.arctan2(out["y"], out["x"]) - th0)))
+    c, s = np.cos(th0 + dth), np.sin(th0 + dth)
+    vr = out["vx"] * c + out["vy"] * s
+    vt = -out["vx"] * s + out["vy"] * c
+    spread = {k: float(np.ptp(v)) for k, v in (("r", r), ("angle", dth), ("v_r", vr), ("v_t", vt))}
+    _say(f"ring {n}: spread over the bodies {spread}, mean angle advance {dth.mean():.6f}")
+    assert dth.mean() > 0.05                         # the ring moved along its orbit
+    assert spread["r"] < 1e-12 and spread["angle"] < 1e-12
+    assert spread["v_t"] < 1e-11 * np.abs(vt).mean() and spread["v_r"] < 1e-13
+    assert np.all(np.abs(out["z"]) == 0.0)
+
+
+def test_grid_solver_two_groups_in_one_launch(dev):
+    # two rings of 600 bodies at 1.0 and 1.6 AU (0.6 AU apart, far beyond
+    # their 0.03 and 0.05 AU critical radii): two groups of more than 512
+    # bodies, which the grid solver's one launch integrates one after the
+    # other, reusing its scratch
+    r1, r2 = ring_chain(600, a=1.0), ring_chain(600, a=1.6)
+    d = {k: np.concatenate([r1[k], r2[k]]) for k in r1}
+    st = N.State.from_numpy(d)
+    cfg = N.Config(G=G, slevels=1, substeps=1, level_capacity=1 << 14, direct=1, n1=3.0, n2=0.0)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(d)
+    _say("two rings of 600: grid solver step")
+    assert N.step(st, cfg, ws) == N.OK
+    gs = N.group_stats(st.n, cfg, ws)
+    r = oracle.step_direct(ref, G, 1.0, 6.0, 3.0, 0.0, 1, 1, rk_steps=200)
+    assert r[6] == 0 and gs == r[5] == (2, 600), (gs, r[5])
+    out = st.numpy()
+    ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
+    _say(f"two rings of 600: position {ep:.2e} velocity {ev:.2e}")
+    assert ep < 1e-11 and ev < 1e-11
