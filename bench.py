@@ -382,6 +382,44 @@ def bench_levels(N, W, torch, np, steps=10):
         out["configs"][f"{L}x{s}" + ("+direct" if direct else "")] = rec
     st = N.State.from_numpy(d)
     out["tuner"] = AT.tune_levels(st, N.Config(**base), LEVEL_CANDIDATES, steps=3)
+    out["direct_by_n"] = levels_by_n(N, W, torch)
+    return out
+
+
+LEVELS_BY_N = (2048, 4096, 8192, 16384, 32768)
+
+
+def levels_by_n(N, W, torch, steps=3):
+    """Sect. 6.2's comparison across N: disks of the benchmark's kind (0.5-4 AU,
+    5 M_earth, seeds 40 + k) stepped by the original hybrid integrator (one
+    level, every level-0 group by Bulirsch-Stoer) and with levels (3 x 4 and
+    2 x 10, the direct solver on the deepest level): ms per step (after one
+    untimed step) and the largest group of the last step."""
+    out = {}
+    for k, n_ in enumerate(LEVELS_BY_N):
+        d = W.make_disk(W.DiskSpec(f"disk_n{n_}_a0.5-4_5Mearth_s{40 + k}", n_, 0.5, 4.0, 5.0,
+                                   seed=40 + k))
+        base = dict(G=d["G"], m_star=d["m_star"], dt=d["dt"], n1=d["n1"], n2=d["n2"],
+                    flags=N.FLAG_NOSYNC, level_capacity=1 << 20, direct=1)
+        rec = {}
+        for L, s in ((1, 1), (3, 4), (2, 10)):
+            st = N.State.from_numpy(d)
+            cfg = N.Config(**base, slevels=L, substeps=s)
+            ws = N.Workspace(st.n, cfg)
+            N.step(st, cfg, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                N.step(st, cfg, ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            if N.read_status(ws) != N.OK:
+                raise SystemExit(f"levels by N {n_} {L}x{s}: status")
+            g, gmax = N.group_stats(st.n, cfg, ws)
+            rec[f"{L}x{s}+direct"] = {"step_ms": round(ms, 4), "largest_group": gmax}
+        rec["levels_speedup_3x4"] = round(rec["1x1+direct"]["step_ms"] / rec["3x4+direct"]["step_ms"], 3)
+        out[str(n_)] = rec
+        print(f"levels by N, {n_} bodies: {rec}", file=sys.stderr, flush=True)
     return out
 
 
