@@ -719,31 +719,25 @@ struct BsSmem {
     long long ired[BT / 64];
 };
 
-// Acceleration of member t at its position (o) from the positions in LDS.
-// The partners come by waves of 64: a wave whose box stays beyond the larger
-// deepest-level critical radius of the two waves from the own wave's box
-// holds no partner with R > 0 and is skipped (its terms are exact zeros), as
-// is each single partner beyond that radius; the sum runs over the partners
-// in ascending order.
+// Partner sum of member t at its position (o) from the positions in LDS,
+// over share `sub` of S: the partners q = sub, sub + S, ... of every partner
+// wave that is not skipped.  The partners come by waves of 64: a wave whose
+// box stays beyond the larger deepest-level critical radius of the two waves
+// from the own wave's box holds no partner with R > 0 and is skipped (its
+// terms are exact zeros), as is each single partner beyond that radius.
 template <int BT>
 __device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, int t, int g,
-                                         const double o[3], double acc[3])
+                                         int S, int sub, const double o[3], double acc[3])
 {
     const double *BI = sm.box[t >> 6];
     const double lo[3] = {BI[0], BI[1], BI[2]}, hi[3] = {BI[3], BI[4], BI[5]};
-    const double r2s = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
-    const double irs = rsq2(r2s);
-    const double ks = -a.mu * (irs * irs * irs);
-    acc[0] = ks * o[0];
-    acc[1] = ks * o[1];
-    acc[2] = ks * o[2];
     const int nw = (g + 63) >> 6;
     const double rhoI = sm.trho[t >> 6];
     for (int J = 0; J < nw; ++J) {
         const double rr = rhoI > sm.trho[J] ? rhoI : sm.trho[J];
         if (box_gap2(lo, hi, sm.box[J]) > rr * rr * (1.0 + 0x1p-18)) continue;
         const int q1 = g < J * 64 + 64 ? g : J * 64 + 64;
-        for (int q = J * 64; q < q1; ++q) {
+        for (int q = J * 64 + sub; q < q1; q += S) {
             if (q == t) continue;
             const double dx = sm.px[q] - o[0], dy = sm.py[q] - o[1], dz = sm.pz[q] - o[2];
             const double r2 = dx * dx + dy * dy + dz * dz;
@@ -762,14 +756,16 @@ __device__ __forceinline__ void bs_accel(const BsDev &a, const BsSmem<BT> &sm, i
 }
 
 // Publish positions (and each wave's box), then every member's derivative
-// at them.
+// at them: the star's pull plus the S shares' partner sums, added in share
+// order (the waves of a share hold copies of the same members; only share 0
+// writes).  The shares' sums pass through pv, which no evaluation uses.
 template <int BT>
-__device__ __forceinline__ void bs_deriv(const BsDev &a, BsSmem<BT> &sm, int t, int g,
-                                         const double z[6], double f[6])
+__device__ __forceinline__ void bs_deriv(const BsDev &a, BsSmem<BT> &sm, int t, int g, int S,
+                                         int sub, const double z[6], double f[6])
 {
     __syncthreads();   // the previous evaluation has finished reading
-    const bool mem = t < g;
-    if (mem) {
+    const bool mem = t < g, own = mem && sub == 0;
+    if (own) {
         sm.px[t] = z[0];
         sm.py[t] = z[1];
         sm.pz[t] = z[2];
@@ -778,7 +774,7 @@ __device__ __forceinline__ void bs_deriv(const BsDev &a, BsSmem<BT> &sm, int t, 
     for (int c = 0; c < 3; ++c) {
         const double lo = wave_min_all(mem ? z[c] : INFINITY);
         const double hi = wave_max_all(mem ? z[c] : -INFINITY);
-        if ((t & 63) == 0 && mem) {
+        if ((threadIdx.x & 63) == 0 && own) {
             sm.box[t >> 6][c] = lo;
             sm.box[t >> 6][3 + c] = hi;
         }
@@ -787,11 +783,32 @@ __device__ __forceinline__ void bs_deriv(const BsDev &a, BsSmem<BT> &sm, int t, 
     f[0] = z[3];
     f[1] = z[4];
     f[2] = z[5];
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (mem) bs_accel<BT>(a, sm, t, g, z, acc);
-    f[3] = acc[0];
-    f[4] = acc[1];
-    f[5] = acc[2];
+    double p[3] = {0.0, 0.0, 0.0};
+    if (mem) bs_accel<BT>(a, sm, t, g, S, sub, z, p);
+    double k[3] = {0.0, 0.0, 0.0};
+    if (mem) {
+        const double r2s = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+        const double irs = rsq2(r2s);
+        const double ks = -a.mu * (irs * irs * irs);
+        k[0] = ks * z[0];
+        k[1] = ks * z[1];
+        k[2] = ks * z[2];
+    }
+    if (S > 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sm.pv[c][threadIdx.x] = p[c];
+        __syncthreads();
+        const int w0 = (threadIdx.x >> 6) - sub, lane = threadIdx.x & 63;
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) k[c] += sm.pv[c][(w0 + s) * 64 + lane];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) k[c] += p[c];
+    }
+    f[3] = k[0];
+    f[4] = k[1];
+    f[5] = k[2];
 }
 
 template <int BT>
@@ -821,19 +838,20 @@ template <int BT>
 struct BlockPol {
     BsSmem<BT> &sm;
     int t, g;
+    int S, sub;   // waves per member (the group's shares), this wave's share
     __device__ void deriv(const BsDev &a, const double z[6], double f[6])
     {
-        bs_deriv<BT>(a, sm, t, g, z, f);
+        bs_deriv<BT>(a, sm, t, g, S, sub, z, f);
     }
     __device__ double gmax(double v) { return bs_block_max<BT>(sm, v); }
     __device__ bool member() const { return t < g; }
-    __device__ bool owner() const { return true; }
+    __device__ bool owner() const { return t < g && sub == 0; }
     __device__ int self() const { return t; }
     __device__ long long overlap(const BsDev &a, const double z[6]);
     __device__ void publish(const double z[6])
     {
         __syncthreads();
-        if (t < g) {
+        if (owner()) {
             sm.px[t] = z[0];
             sm.py[t] = z[1];
             sm.pz[t] = z[2];
@@ -857,7 +875,7 @@ struct BlockPol {
     __device__ int idx(int q) const { return sm.idx[q]; }
     __device__ void set_own(double m, double R)
     {
-        if (t < g) {
+        if (owner()) {
             sm.m[t] = m;
             sm.R[t] = R;
         }
@@ -1250,41 +1268,54 @@ __global__ __launch_bounds__(LT) void k_bs_lanes(BsDev a)
 }
 
 // Groups of lo < size <= BT, one workgroup each (larger ones are the grid
-// solver's).
+// solver's).  A group of fewer members than threads spreads each member over
+// S waves (S = BT / 64 over the member waves, a power of two): the waves of
+// member wave I are I * S ... I * S + S - 1, each taking one share of the
+// partners, and the first of them (the owner) alone writes.
 template <int BT>
 __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
 {
     __shared__ BsSmem<BT> sm;
-    const int t = threadIdx.x;
+    // (the wave index is uniform: the partner loops then run on scalar registers)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int ng = a.gcount[0];
     for (int gi = blockIdx.x; gi < ng; gi += gridDim.x) {
         const int32_t root = a.groot[gi];
         const int g = a.gsize[root];
         if (g <= lo || g > BT) continue;             // another class's group
-        if (t == 0) {
+        if (threadIdx.x == 0) {
             atomicAdd(a.gstats, 1ull);
             atomicMax(a.gstats + 1, (unsigned long long)g);
         }
+        const int nw = (g + 63) >> 6;
+        int S = 1;
+        while (nw * S * 2 <= BT / 64) S *= 2;
+        const int t = (w / S) * 64 + lane, sub = w % S;
+        BlockPol<BT> P{sm, t, g, S, sub};
         const int32_t b = t < g ? a.gmem[a.gstart[root] + t] : 0;
         double y[6] = {0, 0, 0, 0, 0, 0};
+        double rcd = 0.0;
         if (t < g) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) y[c] = a.shadow[(size_t)c * a.n + b];
+            rcd = a.rc[a.nlev - 1][b];
+        }
+        if (P.owner()) {
             sm.m[t] = a.m[b];
             sm.R[t] = a.radius ? a.radius[b] : 0.0;
             sm.idx[t] = b;
             for (int l = 0; l < a.nlev; ++l)
                 sm.irc[l][t] = rcp2(a.rc[l][b]);
-            sm.rcd[t] = a.rc[a.nlev - 1][b];
+            sm.rcd[t] = rcd;
         }
         {
-            const double tr = wave_max_all(t < g ? sm.rcd[t] : 0.0);
-            if ((t & 63) == 0 && t < g) sm.trho[t >> 6] = tr;
+            const double tr = wave_max_all(rcd);
+            if (lane == 0 && P.owner()) sm.trho[t >> 6] = tr;
         }
-        BlockPol<BT> P{sm, t, g};
-        const bool failed = bs_run(a, P, y);
-        if (failed && t == 0) atomicOr(a.status, ST_NOCONV);
-        if (t < g) {
+        bool failed;
+        [[clang::always_inline]] failed = bs_run(a, P, y);
+        if (failed && threadIdx.x == 0) atomicOr(a.status, ST_NOCONV);
+        if (P.owner()) {
             bs_store(a, b, y);
             if (a.radius) {
                 a.m[b] = sm.m[t];
@@ -1679,7 +1710,7 @@ __device__ void grid_order(const BsDev &a, GridPol &P, int32_t root, int32_t *pe
 {
     const GridDev &G = P.G;
     GridSmem &S = g_gsm;
-    const int g = P.g, t = P.t;
+    const int t = P.t;
     const bool own = P.owner();
     const int nthr = P.nblk * GT;
     const int tid = blockIdx.x * GT + threadIdx.x;
