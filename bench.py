@@ -34,7 +34,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the kick kernel settles within ~15 launches of a fresh process (2.0 ms
+    # on the first, 1.6 ms from about the twelfth on): 10 untimed steps by default
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=65536, help="bodies (default: the 65,536-body disk)")
     ap.add_argument("--ipt", type=int, default=0)
     ap.add_argument("--slices", type=int, default=0)

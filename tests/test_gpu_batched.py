@@ -80,6 +80,36 @@ def test_batched_kick_matches_oracle(dev, block, ipt, cols, flags):
     assert cnt == len(oi) and np.array_equal(pi, oi) and np.array_equal(pj, oj)
 
 
+@pytest.mark.parametrize("slices", [1, 2, 4])
+def test_batched_symmetric_widths_match_oracle(dev, slices):
+    # the symmetric kick with 512-, 256- and 128-column slices (up to 24
+    # tiles per 512-row group here, so the reduction adds up to 24 row sums
+    # per row before the column sums); a second launch gives the same bits
+    d = W.make_batch(sizes=SMALL_SIZES)
+    rc = _rc_batch(d)
+    st = N.State.from_numpy(d, rc=rc)
+    bt = _batch(d)
+    cfg = N.Config(G=G, slices=slices, flags=N.FLAG_SYMMETRIC)
+    ws = N.BatchWorkspace(bt, cfg)
+    _say("plan", ws.info)
+    pl = N.PairList(200000)
+    a = N.kick_batched(st, ws, cfg, 0.0, acc=True, pairs=pl).cpu().numpy()
+    a2 = N.kick_batched(st, ws, cfg, 0.0, acc=True).cpu().numpy()
+    torch.cuda.synchronize()
+    assert N.read_status(ws) == N.OK
+    assert np.array_equal(a, a2)
+    pi, pj, cnt = pl.result()
+    all_i, all_j = [], []
+    for s in range(d["S"]):
+        lo, hi = d["offsets"][s], d["offsets"][s + 1]
+        ref, opi, opj, _ = _oracle_system(d, rc, s)
+        err = np.linalg.norm(a[:, lo:hi] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert err.max() <= 1e-12, (s, err.max())
+        all_i.append(opi); all_j.append(opj)
+    oi, oj = np.concatenate(all_i), np.concatenate(all_j)
+    assert cnt == len(oi) and np.array_equal(pi, oi) and np.array_equal(pj, oj)
+
+
 def test_batched_step_matches_oracle_and_single(dev):
     d = W.make_batch(sizes=SMALL_SIZES)
     bt = _batch(d)
@@ -117,10 +147,16 @@ def test_batched_step_matches_oracle_and_single(dev):
             assert np.max(np.abs(out[k][lo:hi] - single[k])) <= 1e-12 * scale, (s, k)
 
 
-def test_batched_graph_replay_bitwise(dev):
-    d = W.make_batch(sizes=SMALL_SIZES[:10])
+@pytest.mark.parametrize("form", ["one-sided", "symmetric"])
+def test_batched_graph_replay_bitwise(dev, form):
+    if form == "one-sided":
+        d = W.make_batch(sizes=SMALL_SIZES[:10])
+        cfg = N.Config(G=G, flags=N.FLAG_NOSYNC, block=64, tile_cols=512)
+    else:
+        # 128-column slices, systems of 16 to 3,001 bodies
+        d = W.make_batch(sizes=SMALL_SIZES)
+        cfg = N.Config(G=G, flags=N.FLAG_NOSYNC | N.FLAG_SYMMETRIC, slices=4)
     bt = _batch(d)
-    cfg = N.Config(G=G, flags=N.FLAG_NOSYNC, block=64, tile_cols=512)
     st_g = N.State.from_numpy(d)
     st_e = N.State.from_numpy(d)
     ws_g = N.BatchWorkspace(bt, cfg)
