@@ -1509,9 +1509,11 @@ struct GridPol {
 
 
     // (one copy of the evaluation: bs_step reaches it from nine places; the
-    // loop works on locals and LDS only).  The split waves of a tile take
-    // every split-th tile of its list each; their partial sums are added in
-    // share order.
+    // loop works on locals and LDS only).  A partner tile is visited if its
+    // box comes within the larger deepest-level radius of the own tile's box
+    // and of some member's own position (both tests skip only exact zeros).
+    // The split waves of a tile take every split-th tile of its list each;
+    // their partial sums are added in share order.
     __device__ __noinline__ void deriv(const BsDev &a, const double z[6], double f[6])
     {
         f[0] = z[3];
@@ -1533,19 +1535,37 @@ struct GridPol {
             const double rhoI = trho[t0 >> 6];
             const double *P = G.pub + (size_t)par * 6 * cap;
             const double *Bx = G.box + (size_t)par * (cap / 64) * 8;
+            const double pos[3] = {x0, y0, z0};
+            const bool mem = me < ng;
             int seen = 0;   // tiles of the list met so far (wave-uniform)
             for (int jb = 0; jb < nt; jb += 64) {
                 const int Jl = jb + lane;
                 bool near = false;
+                double bj[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, rj = 0.0;
                 if (Jl < nt) {
-                    const double rr = rhoI > trho[Jl] ? rhoI : trho[Jl];
+                    const double *B = Bx + (size_t)Jl * 8;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) bj[c] = B[c];
+                    rj = trho[Jl];
+                    const double rr = rhoI > rj ? rhoI : rj;
                     // (a NaN box keeps the tile: the flow then fails as a whole)
-                    near = !(box_gap2(lo, hi, Bx + (size_t)Jl * 8) > rr * rr * (1.0 + 0x1p-18));
+                    near = !(box_gap2(lo, hi, bj) > rr * rr * (1.0 + 0x1p-18));
                 }
                 unsigned long long mask = __ballot(near);
                 while (mask) {
-                    const int J = jb + __builtin_ctzll(mask);
+                    const int src = __builtin_ctzll(mask);
+                    const int J = jb + src;
                     mask &= mask - 1;
+                    // the same test for each member's own position: a tile whose
+                    // box is large (members from distant cells) passes the box
+                    // test against many tiles, of which few come near a member
+                    double bJ[6];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) bJ[c] = __shfl(bj[c], src, 64);
+                    const double rJ = __shfl(rj, src, 64);
+                    const double rm = rcme > rJ ? rcme : rJ;
+                    const bool close = mem && !(box_gap2(pos, pos, bJ) > rm * rm * (1.0 + 0x1p-18));
+                    if (__ballot(close) == 0ull) continue;
                     if (seen++ % S_ != mine) continue;
                     const int jq = J * 64 + lane;
                     if (jq < ng) {
