@@ -1335,7 +1335,7 @@ __global__ __launch_bounds__(BT) void k_bs(BsDev a, int lo)
 // at every group-wide maximum or minimum.  One thread per member (so a
 // group may hold up to GENGA_GROUP_MAX bodies with the launch's workgroups
 // all resident); the members are first ordered by a 64 x 64 cell grid over
-// the group's x-y extent (cells in Morton order, members of a cell by their
+// the group's x-y extent (cells along Hilbert's curve, members of a cell by their
 // rank in the group), so that each wave's 64 members form a compact tile.
 // A derivative then visits, per tile, only the tiles whose bounding boxes
 // come within the larger deepest-level critical radius of the two tiles:
@@ -1382,11 +1382,27 @@ struct GridSmem {
 // scope so that the out-of-line evaluation addresses it as LDS.
 static __shared__ GridSmem g_gsm;
 
-__device__ __forceinline__ unsigned morton6(unsigned cx, unsigned cy)
+// Position of cell (x, y) of the GCELL x GCELL grid along Hilbert's curve
+// (the usual construction: at each scale s the quadrant's number goes into
+// the index, then the coordinates are turned into that quadrant's frame),
+// so that consecutive cells along the order are always neighbours.
+__device__ __forceinline__ unsigned hilbert_cell(unsigned x, unsigned y)
 {
-    unsigned k = 0;
-    for (int b = 0; b < 6; ++b) k |= ((cx >> b) & 1u) << (2 * b) | ((cy >> b) & 1u) << (2 * b + 1);
-    return k;
+    unsigned d = 0;
+    for (unsigned s = GCELL / 2; s > 0; s >>= 1) {
+        const unsigned rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = GCELL - 1 - x;
+                y = GCELL - 1 - y;
+            }
+            const unsigned tmp = x;
+            x = y;
+            y = tmp;
+        }
+    }
+    return d;
 }
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -1781,7 +1797,7 @@ __device__ void grid_order(const BsDev &a, GridPol &P, int32_t root, int32_t *pe
         cx = cx < GCELL - 1 ? cx : GCELL - 1;
         cy = cy < GCELL - 1 ? cy : GCELL - 1;
         // (NaN positions land in cell 0: the flow fails later anyway)
-        cell = morton6((unsigned)cx, (unsigned)cy);
+        cell = hilbert_cell((unsigned)cx, (unsigned)cy);
         atomicAdd(G.ccnt + cell, 1);
     }
     P.sync();
