@@ -1832,15 +1832,13 @@ __device__ void grid_order(const BsDev &a, GridPol &P, int32_t root, int32_t *pe
 }
 
 // Waves per tile for a group of g members when nb workgroups (of 4 waves)
-// can take part: the most of 4, 2, 1 that fit within half of them (room to
-// spare for the barriers), else within all of them (0: the group does not
+// can take part: the most of 4, 2, 1 that fit in them (0: the group does not
 // fit).
 __device__ inline int grid_split(int g, int nb)
 {
     const int nt = (g + 63) / 64;
-    for (int lim : {nb / 2, nb})
-        for (int s = 4; s >= 1; s >>= 1)
-            if ((nt * s + 3) / 4 <= lim) return s;
+    for (int s = 4; s >= 1; s >>= 1)
+        if ((nt * s + 3) / 4 <= nb) return s;
     return 0;
 }
 

@@ -221,8 +221,10 @@ def test_direct_cuts_the_energy_error(dev):
 
 @pytest.mark.parametrize("n", [20000, 40000])
 def test_grid_solver_keeps_the_ring_symmetric(dev, n):
-    # Sect. 6.1's ring at sizes whose group the grid solver splits over 2
-    # waves per tile (20,000 bodies) and runs on one (40,000): the ring is
+    # Sect. 6.1's ring at sizes whose group the grid solver splits over 4
+    # waves per tile (20,000 bodies) and over 2 (40,000) on the MI355X's 512
+    # resident workgroups (one wave per tile needs more than 2,048 tiles of 64
+    # there, beyond the 65,536-body limit): the ring is
     # invariant under rotation by 2 pi / n, so after a step every body must
     # have the same radius, radial and tangential velocity and angle advance
     # up to rounding.  A partner lost or counted twice at a tile or share
