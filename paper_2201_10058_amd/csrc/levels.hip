@@ -1444,7 +1444,7 @@ struct GridPol {
             if (!d) {
                 unsigned long long *cnt = G.sync;
                 const unsigned long long target = nbar * (unsigned long long)nblk;
-                __threadfence();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint64_t t0 = wall_clock64();
                 while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -1459,7 +1459,7 @@ struct GridPol {
                     }
                     __builtin_amdgcn_s_sleep(4);
                 }
-                __threadfence();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             g_gsm.dead = d;
         }
