@@ -397,9 +397,15 @@ __global__ __launch_bounds__(LT) void k_level_kick(LevelKickDev k)
 // per-root sizes, a scan over the roots in ascending order, and the members
 // of each group placed in ascending order (rank among the group's members).
 // ---------------------------------------------------------------------------
+// A parent read through the caches (workgroup scope) may be an older value:
+// every value a body's parent ever held is still one of its ancestors (trees
+// only merge) and a root's parent was itself until it was hooked, so an old
+// value only makes a walk stop early, at a node that was a root; the hook's
+// exchange then fails and returns the current parent.  (Reads at device
+// scope, from memory, made the 65,536-body ring's unions 1.5 ms.)
 __device__ __forceinline__ int32_t uf_load(const int32_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Root of x, halving the path on the way: a non-root's parent may be
@@ -461,17 +467,23 @@ __global__ __launch_bounds__(LT) void k_group_union(const int32_t *pi, const int
         const int32_t i = pi[p], j = pj[p];
         flag[i] = 1;
         flag[j] = 1;
+        int32_t a0 = i, b0 = j;
         for (;;) {
-            int32_t ra = uf_find(parent, i), rb = uf_find(parent, j);
-            if (ra == rb) break;
+            int32_t ra = uf_find(parent, a0), rb = uf_find(parent, b0);
+            if (ra == rb) break;   // a common ancestor: one tree
             if (ra < rb) {
                 const int32_t t = ra;
                 ra = rb;
                 rb = t;
             }
-            // hook the larger root under the smaller; a failed exchange means
-            // ra stopped being a root meanwhile: look again
-            if (atomicCAS(parent + ra, ra, rb) == ra) break;
+            // hook the larger root under the smaller (a root is the smallest
+            // body of its tree, so rb < ra lies in another tree); a failed
+            // exchange means ra was hooked meanwhile: go on from its current
+            // parent, which the exchange returns
+            const int32_t old = atomicCAS(parent + ra, ra, rb);
+            if (old == ra) break;
+            a0 = old;
+            b0 = rb;
         }
     }
 }
