@@ -855,7 +855,7 @@ __global__ __launch_bounds__(FT) void k_fold_massive(ReduceDev r)
 // Mixed mode: binary64 kick of the rows listed by k_kick_reduce, with the
 // arithmetic of the binary64 kick.  Batched systems: one block per row
 // (threads stride over the row's system, then a fixed-order block sum).
-// Single system: k_refine_tiles / k_refine_apply below.  The grids are fixed
+// Single system: k_refine_rows / k_refine_sum below.  The grids are fixed
 // (the row count is read on the device), so the launches can be captured.
 struct RefineDev {
     const double *x, *y, *z, *m, *rc;
