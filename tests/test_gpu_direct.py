@@ -98,6 +98,30 @@ def test_direct_group_of_hundreds(dev, n):
     assert ep < 1e-11 and ev < 1e-11
 
 
+@pytest.mark.parametrize("n", [40, 100])
+def test_direct_small_ring_members_over_several_waves(dev, n):
+    # Sect. 6.1's ring of n bodies, each meeting its 8 nearest neighbours: one
+    # group that the 512-thread class spreads over 8 waves per member (up to
+    # 64 bodies) or 4 (up to 128), each wave summing a share of the partners;
+    # against the oracle's RK4 group flow
+    d = W.make_bs_ring(n)
+    ring = {k: d[k] for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
+    st = N.State.from_numpy(ring)
+    cfg = N.Config(G=d["G"], m_star=1.0, dt=d["dt"], n1=d["n1"], n2=0.0, slevels=1, substeps=1,
+                   direct=1, level_capacity=16 * n)
+    ws = N.Workspace(st.n, cfg)
+    ref = oracle.state_copy(ring)
+    for _ in range(2):
+        assert N.step(st, cfg, ws) == N.OK
+        gs = N.group_stats(st.n, cfg, ws)
+        r = oracle.step_direct(ref, d["G"], 1.0, d["dt"], d["n1"], 0.0, 1, 1, rk_steps=200)
+        assert r[6] == 0 and gs == r[5] == (1, n), (gs, r[5])
+    out = st.numpy()
+    ep, ev = _rel(out, ref, ("x", "y", "z")), _rel(out, ref, ("vx", "vy", "vz"))
+    _say(f"ring of {n}: position {ep:.2e} velocity {ev:.2e}")
+    assert ep < 1e-11 and ev < 1e-11
+
+
 def test_direct_disk2048_one_level(dev):
     # without levels the 2,048-body disk's level-0 list forms groups of up to
     # 337 bodies, all within the direct solver's reach
