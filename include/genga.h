@@ -485,18 +485,23 @@ int genga_step_batched(genga_bodies *b, const genga_batch *bt, const genga_param
  * problem, key = kind, device architecture, precision and problem signature
  * (N rounded up to a power of two; or S, total N and a histogram of the system
  * sizes); the last line of a key wins.  ms_out (nullable) receives the time
- * of one kick with the chosen shape.  Synchronises the stream.
+ * of one kick with the chosen shape (genga_autotune_batched: of a step's two
+ * kicks, one without and one with the encounter list).  Synchronises the
+ * stream.
  * ------------------------------------------------------------------------ */
 
-/* Workspace for genga_autotune_batched: the largest any candidate needs. */
+/* Workspace for genga_autotune_batched: the largest any candidate needs,
+ * then room for the tuner's own encounter list (16 pairs per body). */
 size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga_params *p);
 
 /* Batched kick.  Candidates, in this order: (binary64) the symmetric form
  * with the plan's own slice width (p->slices = 0) and with 1, 2 or 4 column
  * slices per 512-row group, then the one-sided form with block {64, 256} x
  * rows per thread {1, 2} x tile_cols {256, 512, 1024, 2048} x grid {library
- * choice, 32 waves per CU}; each timed 5 times (median), a later candidate
- * chosen only if more than 1 % faster.  Writes p->block, p->ipt,
+ * choice, 32 waves per CU}; each timed 5 times (median) over a kick without
+ * and a kick with an encounter list (the list placed after the largest
+ * candidate's workspace; both kicks without it if ws_bytes leaves no room),
+ * a later candidate chosen only if more than 1 % faster.  Writes p->block, p->ipt,
  * p->tile_cols, p->grid, p->slices and the form flag in p->flags.  On return
  * ws holds the plan of the chosen shape (as after genga_batch_plan).
  * ws_bytes >= genga_autotune_batched_workspace_bytes(bt, p), else candidates

@@ -32,7 +32,8 @@ def cache_path() -> str:
 def tune_batched(state: N.State, batch: N.Batch, cfg: N.Config, use_cache: bool = True) -> dict:
     """Pick the batched kick's form and its shape: (block, ipt, tile_cols,
     grid) for the one-sided form, the column slices per 512-row group for the
-    symmetric one; returns the choice (with the time of one kick in "ms")."""
+    symmetric one; returns the choice (with the time of a step's two kicks,
+    one without and one with the encounter list, in "ms")."""
     lib = N.load()
     bt = batch.struct()
     p = cfg.params()

@@ -52,7 +52,7 @@ std::string batch_key(const genga_batch *bt, int precision)
         hist[std::min(std::max(b, 0), 7)] += 1;
     }
     char buf[256];
-    snprintf(buf, sizeof buf, "batch:%s:p%d:S%lld:N%lld:h%d.%d.%d.%d.%d.%d.%d.%d",
+    snprintf(buf, sizeof buf, "batch:two-kicks:%s:p%d:S%lld:N%lld:h%d.%d.%d.%d.%d.%d.%d.%d",
              arch_name().c_str(), precision, (long long)bt->S, (long long)bt->offsets[bt->S],
              hist[0], hist[1], hist[2], hist[3], hist[4], hist[5], hist[6], hist[7]);
     return buf;
@@ -205,9 +205,9 @@ using namespace genga;
 
 extern "C" {
 
-size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga_params *p)
+// The largest workspace any batched candidate needs.
+static size_t batch_candidates_bytes(const genga_batch *bt, const genga_params *p)
 {
-    if (!p) return 0;
     size_t most = 0;
     for (const Shape &s : batch_candidates(p)) {
         genga_params q = *p;
@@ -218,6 +218,26 @@ size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga
     return most;
 }
 
+// The batched tuner's encounter list, after the candidates' workspace: one
+// int64 count, then TUNE_PAIRS_PER_BODY pairs per body (a list that
+// overflows still counts its pairs and times the same work).
+constexpr int64_t TUNE_PAIRS_PER_BODY = 16;
+
+static size_t align_256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static size_t tune_pair_bytes(const genga_batch *bt)
+{
+    const int64_t cap = TUNE_PAIRS_PER_BODY * std::max<int64_t>(bt->offsets[bt->S], 1);
+    return 256 + 2 * align_256(sizeof(int32_t) * (size_t)cap);
+}
+
+size_t genga_autotune_batched_workspace_bytes(const genga_batch *bt, const genga_params *p)
+{
+    if (!p || !bt || !bt->offsets || bt->S < 1) return 0;
+    const size_t most = batch_candidates_bytes(bt, p);
+    return most ? align_256(most) + tune_pair_bytes(bt) : 0;
+}
+
 int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_params *p,
                            void *ws, size_t ws_bytes, const char *cache_path, double *ms_out,
                            void *stream)
@@ -226,6 +246,22 @@ int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_p
     if (genga_batch_workspace_bytes(bt, p) == 0) return GENGA_E_INVAL;
     hipStream_t s = (hipStream_t)stream;
     const std::string key = batch_key(bt, p->precision);
+    // a step's two kicks: one without the encounter list and one with it
+    // (the list costs the symmetric form more the narrower its slices); the
+    // list sits after the largest candidate's workspace when it fits, else
+    // both timed kicks go without it
+    const size_t lo = align_256(batch_candidates_bytes(bt, p));
+    genga_pairs list{nullptr, nullptr, 0, nullptr};
+    genga_pairs *plist = nullptr;
+    if (lo > 0 && ws_bytes >= lo + tune_pair_bytes(bt)) {
+        char *w = (char *)ws + lo;
+        const int64_t cap = TUNE_PAIRS_PER_BODY * std::max<int64_t>(bt->offsets[bt->S], 1);
+        list.count = (int64_t *)w;
+        list.i = (int32_t *)(w + 256);
+        list.j = (int32_t *)(w + 256 + align_256(sizeof(int32_t) * (size_t)cap));
+        list.capacity = cap;
+        plist = &list;
+    }
     Shape best;
     double best_ms = -1.0;
     if (!cache_lookup(cache_path, key, best, best_ms)) {
@@ -235,11 +271,14 @@ int genga_autotune_batched(const genga_bodies *b, const genga_batch *bt, genga_p
             apply(c, &q);
             q.flags = (p->flags & ~FORM_FLAGS) | c.flags;
             const size_t need = genga_batch_workspace_bytes(bt, &q);
-            if (need == 0 || need > ws_bytes) continue;
+            if (need == 0 || need > ws_bytes || (plist && need > lo)) continue;
             if (genga_batch_plan(bt, &q, ws, stream) != GENGA_OK) continue;
             const double ms = time_ms(
                 [&] {
-                    return genga_kick_batched(b, bt, &q, 0.0, nullptr, nullptr, nullptr, nullptr,
+                    const int r = genga_kick_batched(b, bt, &q, 0.0, nullptr, nullptr, nullptr,
+                                                     nullptr, ws, stream);
+                    if (r != GENGA_OK) return r;
+                    return genga_kick_batched(b, bt, &q, 0.0, nullptr, nullptr, nullptr, plist,
                                               ws, stream);
                 },
                 s, 5);
